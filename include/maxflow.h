@@ -1,0 +1,173 @@
+/*
+ * maxflow.h -- C ABI of the MI355X (gfx950) continuous max-flow / min-cut
+ * solver for the methods of Sun, Tai and Yuan, "Efficient ADMM and Splitting
+ * Methods for Continuous Min-cut and Max-flow Problems" (arXiv 2004.11227).
+ *
+ * Models (Section 2.1):
+ *   MF_TWO_LABEL  relaxed min-cut, eq. seg:chanvese, and its dual max-flow,
+ *                 eq. two-label-mf:  max sum p_s  s.t. |q| <= alpha,
+ *                 p_s <= C_s, p_t <= C_t, p_t - p_s + div q = 0
+ *                 (the sign convention of the augmented Lagrangian
+ *                 eq. augfunc:twolabel).
+ *   MF_POTTS      relaxed Potts model, eq. relaxed-potts, and its dual,
+ *                 eq. potts-mf:  max sum p_s  s.t. |q_i| <= alpha,
+ *                 p_i <= C_i, div q_i - p_s + p_i = 0.
+ * Methods (Section 3):
+ *   MF_RPADMM_FG  rpADMMI, relaxed preconditioned ADMM of Fortin-Glowinski
+ *                 type (eq. rpADMMI; multi-label eq. multi:fg:4).
+ *   MF_RPADMM_EB  rpADMMII, relaxed preconditioned ADMM of Eckstein-Bertsekas
+ *                 type (eq. rpADMMII; multi-label component-wise scheme of the
+ *                 multi-phase EB subsection, with coefficient 1 on
+ *                 (p_i^{k+1} - p_s^{k+1}) in the multiplier step as in the
+ *                 general EB update eq. update:two:sun:lag).
+ *   MF_RPDRQ      rPDRQ, relaxed Douglas-Rachford with a symmetric red-black
+ *                 Gauss-Seidel preconditioner (eq. iteration:quadratic:seg;
+ *                 multi-label eq. pdrq:4labels for general n, T_0 of Lemma 1).
+ *
+ * Discretisation: forward-difference gradient with Neumann boundary,
+ * div = -grad^*, unit spacing; 2-D or 3-D grids (3-D uses a = 12).
+ *
+ * Memory: every pointer marked "device" is HIP device memory on the current
+ * device.  The caller owns the capacities, the workspace and every output
+ * buffer.  The library never allocates device memory: the workspace given to
+ * create() holds all solver state, sized by maxflow_workspace_bytes().
+ * Layout of grid fields: planar, one contiguous plane per scalar component,
+ * row-major with x (last shape entry) fastest; multi-plane fields are
+ * [plane][z][y][x].
+ *
+ * Errors: every call returns an mf_status; no exception crosses the ABI.
+ * On a negative status maxflow_last_error() returns a thread-local message.
+ * A handle may be used from one host thread at a time.  All GPU work is
+ * enqueued on the stream given at create(); calls that return data to the
+ * host synchronise that stream.
+ */
+#ifndef MAXFLOW_H
+#define MAXFLOW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MF_OK = 0,
+  MF_ENOTCONV = 1,   /* iteration cap reached before the tolerance: not an error */
+  MF_EINVAL = -1,    /* invalid argument (shape, parameter range, model/labels)  */
+  MF_ENOMEM = -2,    /* workspace too small / pool budget exceeded               */
+  MF_EDEVICE = -3,   /* HIP runtime error                                        */
+  MF_EDIVERGED = -4  /* NaN or Inf in the primal-dual gap                        */
+} mf_status;
+
+typedef enum { MF_TWO_LABEL = 0, MF_POTTS = 1 } mf_model;
+typedef enum { MF_RPADMM_FG = 0, MF_RPADMM_EB = 1, MF_RPDRQ = 2 } mf_method;
+/* MF_TV_ISO: pointwise Euclidean |q(x)| <= alpha, the P_alpha of eq.
+ * (projections).  MF_TV_ANISO: per-component |q_k(x)| <= alpha (l1 TV). */
+typedef enum { MF_TV_ISO = 0, MF_TV_ANISO = 1 } mf_tv;
+/* MF_BF16: flows (q, p_s, p_t / p_i and the rPDRQ reflected variables) and
+ * capacities stored as bfloat16 (round to nearest even); u and all
+ * arithmetic stay FP32; gap reductions are FP64 in both modes. */
+typedef enum { MF_F32 = 0, MF_BF16 = 1 } mf_storage;
+/* MF_FUSED: one kernel per iteration (LDS tile with halo).  MF_UNFUSED: the
+ * baseline, one kernel per operator; bitwise identical results. */
+typedef enum { MF_FUSED = 0, MF_UNFUSED = 1 } mf_variant;
+
+typedef struct {
+  int32_t ndim;          /* 2 or 3                                                    */
+  int64_t shape[3];      /* (H, W) or (D, H, W); W fastest; each >= 1                 */
+  int32_t model;         /* mf_model                                                  */
+  int32_t method;        /* mf_method                                                 */
+  int32_t tv;            /* mf_tv                                                     */
+  int32_t storage;       /* mf_storage                                                */
+  int32_t variant;       /* mf_variant                                                */
+  int32_t nlabels;       /* 2 for MF_TWO_LABEL; 2..8 for MF_POTTS                     */
+  double alpha;          /* TV weight, >= 0                                           */
+  double c;              /* ADMM step c > 0;             0 -> 0.3                     */
+  double relax;          /* FG r in (0, 1.618..); EB rho in (0, 2); DR rho in (0, 2);
+                            0 -> 1.618 (FG), 1.9 (EB, DR)                             */
+  double sigma, tau;     /* rPDRQ steps; 0 -> (0.2, 1.0) two-label, (5, 0.4) Potts    */
+  double a;              /* q preconditioner N = a c I; 0 -> 4*ndim; < 4*ndim: EINVAL */
+  double a_tilde;        /* two-label M = a~ c I_2; 0 -> 2; < 2: EINVAL               */
+  double a1, a2;         /* Potts M = c diag(a1 I.., a2 I); 0 -> 2, 2n; smaller: EINVAL*/
+  int32_t max_iter;      /* iteration cap for maxflow_solve (>= 0)                   */
+  double tol;            /* relative primal-dual gap tolerance for maxflow_solve      */
+  int32_t check_every;   /* gap cadence in iterations; 0 -> 10                        */
+  int32_t tile_rows;     /* fused 2-D tile height (8, 16 or 32); 0 -> tuned default   */
+} mf_params;
+
+/* Gap at an iterate.  primal = P(u) at clip(u,0,1) (two-label) or the pointwise
+ * simplex projection of u (Potts); dual = sum_x min(C_s, C_t + div q) or
+ * sum_x min_i(C_i + div q_i); rel_gap = (primal - dual) / max(|primal|,|dual|);
+ * resid_rms = RMS of the conservation residual; flow = sum p_s.  For rPDRQ the
+ * flows are the resolvent outputs of the last iteration. */
+typedef struct {
+  int64_t iter;
+  double primal, dual, rel_gap, resid_rms, flow;
+  int32_t status;
+} mf_gap;
+
+typedef struct mf_solver mf_solver;
+
+/* Bytes of workspace create() needs for these parameters (0 on invalid
+ * parameters; see maxflow_last_error()). */
+size_t maxflow_workspace_bytes(const mf_params* p);
+
+/* Validate p, lay out the workspace, copy the capacities (device, FP32,
+ * TWO_LABEL: planes [C_s, C_t]; POTTS: planes [C_1..C_n]) into it, converting
+ * to BF16 if requested, and set the initial point (q = 0, u = 0, source and
+ * sink flows at the pointwise minimum capacity).  The caller may free `cap`
+ * once this returns.  `workspace` (device, >= maxflow_workspace_bytes(p)
+ * bytes, 256-byte aligned) must outlive the solver.  `hip_stream` is a
+ * hipStream_t (NULL = default stream). */
+mf_status maxflow_create(const mf_params* p, const float* cap, void* workspace,
+                         size_t ws_bytes, void* hip_stream, mf_solver** out);
+
+/* Re-initialise the iterate (iteration count 0). */
+mf_status maxflow_reset(mf_solver* s);
+
+/* Enqueue `iters` iterations; asynchronous, no host synchronisation. */
+mf_status maxflow_step(mf_solver* s, int32_t iters);
+
+/* Evaluate the gap at the current iterate (FP64 reduction on the GPU);
+ * synchronises the stream. */
+mf_status maxflow_gap(mf_solver* s, mf_gap* out);
+
+/* Iterate until the relative gap at a multiple of check_every is <= tol or
+ * max_iter is reached; the state is left at the iterate whose gap was
+ * accepted.  Returns MF_OK, MF_ENOTCONV or MF_EDIVERGED; fills *out. */
+mf_status maxflow_solve(mf_solver* s, mf_gap* out);
+
+/* Current iteration count. */
+int64_t maxflow_iter(const mf_solver* s);
+
+/* Copy the current u (device, FP32, 1 plane two-label / n planes Potts). */
+mf_status maxflow_read_u(mf_solver* s, float* dst);
+
+/* Labels (device, int32, one plane): two-label u > 1/2; Potts argmax_i u_i
+ * with the lowest index on ties. */
+mf_status maxflow_labels(mf_solver* s, int32_t* dst);
+
+/* Field access in FP32 for checking and restarts.  Fields: 0 = u (L planes),
+ * 1 = q (L*ndim planes, label-major then component x, y, z), 2 = p_s (1 plane),
+ * 3 = p (L planes: p_t for two-label, p_1..p_n for Potts).  For rPDRQ,
+ * q, p_s, p are the reflected variables (q-bar, p-bar) and fields 4, 5, 6 are
+ * the resolvent outputs of the last iteration (same shapes as 1, 2, 3).
+ * L = 1 (two-label) or n.  `dst`/`src` are device pointers. */
+mf_status maxflow_read_field(mf_solver* s, int32_t field, float* dst);
+mf_status maxflow_write_field(mf_solver* s, int32_t field, const float* src);
+
+/* Raw state snapshot (device bytes; size maxflow_state_bytes). */
+size_t maxflow_state_bytes(const mf_solver* s);
+mf_status maxflow_export_state(mf_solver* s, void* dst);
+mf_status maxflow_import_state(mf_solver* s, const void* src, int64_t iter);
+
+mf_status maxflow_destroy(mf_solver* s);
+
+/* Thread-local message describing the last error. */
+const char* maxflow_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MAXFLOW_H */

@@ -1,0 +1,569 @@
+// Host runtime behind include/maxflow.h: parameter validation, workspace
+// layout, launch schedules and the device-side convergence protocol.
+//
+// Ping-pong state: iterate k of an rpADMM solve lives in state buffer k % 2.
+// A "check" evaluates the gap of iterate k (fused into the sweep k -> k+1 for
+// the two-label fused pass, otherwise a standalone reduction before it) and a
+// one-thread bookkeeping kernel decides on the GPU whether the solve stops at
+// k; every later sweep of the same solve reads that decision and exits at
+// once, so buffer k % 2 keeps iterate k.  The host only polls the decision to
+// stop enqueueing work; it never has to wait for a gap before continuing.
+// rPDRQ updates its state in place and evaluates the gap on the output of
+// the check iteration, so it needs no rollback.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/maxflow.h"
+#include "mf_kernels.h"
+
+using namespace mf;
+
+namespace {
+
+thread_local std::string g_err;
+
+mf_status fail(mf_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      return fail(MF_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));           \
+  } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Resolved {
+  mf_params p;
+  int nl;         // labels carried (1 two-label, n Potts)
+  int ncap;       // capacity planes
+  Geom g;
+  size_t esz;     // bytes per flow / capacity element
+  int nq;         // q planes per state
+};
+
+// Fill defaults and validate; returns an error message or "".
+std::string resolve(const mf_params* in, Resolved& r) {
+  if (!in) return "null params";
+  r.p = *in;
+  mf_params& p = r.p;
+  if (p.ndim != 2 && p.ndim != 3) return "ndim must be 2 or 3";
+  for (int i = 0; i < p.ndim; i++)
+    if (p.shape[i] < 1 || p.shape[i] > (1LL << 30)) return "shape entries must be >= 1";
+  if (p.model != MF_TWO_LABEL && p.model != MF_POTTS) return "unknown model";
+  if (p.method < MF_RPADMM_FG || p.method > MF_RPDRQ) return "unknown method";
+  if (p.tv != MF_TV_ISO && p.tv != MF_TV_ANISO) return "unknown tv";
+  if (p.storage != MF_F32 && p.storage != MF_BF16) return "unknown storage";
+  if (p.variant != MF_FUSED && p.variant != MF_UNFUSED) return "unknown variant";
+  if (p.model == MF_TWO_LABEL) {
+    if (p.nlabels != 0 && p.nlabels != 2) return "two-label model needs nlabels = 2";
+    p.nlabels = 2;
+  } else if (!(p.nlabels == 2 || p.nlabels == 3 || p.nlabels == 4 || p.nlabels == 8)) {
+    return "Potts nlabels must be 2, 3, 4 or 8";
+  }
+  if (!(p.alpha >= 0.0) || !std::isfinite(p.alpha)) return "alpha must be finite and >= 0";
+  if (p.c == 0.0) p.c = 0.3;
+  if (!(p.c > 0.0) || !std::isfinite(p.c)) return "c must be > 0";
+  if (p.relax == 0.0) p.relax = p.method == MF_RPADMM_FG ? 1.618 : 1.9;
+  if (p.method == MF_RPADMM_FG) {
+    if (!(p.relax > 0.0 && p.relax < 0.5 * (1.0 + std::sqrt(5.0)))) return "FG relaxation r must be in (0, 1.618..)";
+  } else if (!(p.relax > 0.0 && p.relax < 2.0)) {
+    return "relaxation rho must be in (0, 2)";
+  }
+  const bool two = p.model == MF_TWO_LABEL;
+  if (p.sigma == 0.0) p.sigma = two ? 0.2 : 5.0;
+  if (p.tau == 0.0) p.tau = two ? 1.0 : 0.4;
+  if (!(p.sigma > 0.0) || !(p.tau > 0.0)) return "sigma and tau must be > 0";
+  const double amin = 4.0 * p.ndim;
+  if (p.a == 0.0) p.a = amin;
+  if (p.a < amin) return "a must be >= 4*ndim (||div^* div|| bound)";
+  if (p.a_tilde == 0.0) p.a_tilde = 2.0;
+  if (p.a_tilde < 2.0) return "a_tilde must be >= 2";
+  if (p.a1 == 0.0) p.a1 = 2.0;
+  if (p.a2 == 0.0) p.a2 = 2.0 * p.nlabels;
+  if (p.a1 < 2.0) return "a1 must be >= 2";
+  if (p.a2 < 2.0 * p.nlabels) return "a2 must be >= 2 n";
+  if (p.max_iter < 0) return "max_iter must be >= 0";
+  if (!(p.tol >= 0.0)) return "tol must be >= 0";
+  if (p.check_every == 0) p.check_every = 10;
+  if (p.check_every < 1) return "check_every must be >= 1";
+  if (p.tile_rows == 0) p.tile_rows = two ? 16 : 8;
+  if (p.tile_rows != 8 && p.tile_rows != 16 && p.tile_rows != 32) return "tile_rows must be 8, 16 or 32";
+  r.nl = two ? 1 : p.nlabels;
+  r.ncap = two ? 2 : p.nlabels;
+  r.g.ndim = p.ndim;
+  if (p.ndim == 2) {
+    r.g.H = (int)p.shape[0];
+    r.g.W = (int)p.shape[1];
+    r.g.D = 1;
+  } else {
+    r.g.D = (int)p.shape[0];
+    r.g.H = (int)p.shape[1];
+    r.g.W = (int)p.shape[2];
+  }
+  const long long n = r.g.npix();
+  if (n > (1LL << 34)) return "grid too large";
+  r.g.plane = (long long)align_up((size_t)n, 128);
+  r.esz = p.storage == MF_BF16 ? 2 : 4;
+  r.nq = r.nl * p.ndim;
+  return "";
+}
+
+struct Layout {
+  size_t ctrl, cap, state[2], stz, wbuf, total;
+  size_t state_bytes;
+};
+
+Layout plan(const Resolved& r) {
+  Layout L{};
+  const size_t P = (size_t)r.g.plane;
+  size_t off = 0;
+  L.ctrl = off;
+  off = align_up(off + sizeof(Ctrl), 256);
+  L.cap = off;
+  off = align_up(off + (size_t)r.ncap * P * r.esz, 256);
+  // state: u (nl f32) + q (nq) + ps (1) + p (nl) in storage type
+  L.state_bytes = align_up((size_t)r.nl * P * 4, 256) + align_up((size_t)r.nq * P * r.esz, 256) +
+                  align_up(P * r.esz, 256) + align_up((size_t)r.nl * P * r.esz, 256);
+  L.state[0] = off;
+  off += L.state_bytes;
+  const bool dr = r.p.method == MF_RPDRQ;
+  if (!dr) {
+    L.state[1] = off;
+    off += L.state_bytes;
+  } else {
+    L.state[1] = L.state[0];
+  }
+  // rPDRQ resolvent outputs (same shape as q, ps, p)
+  L.stz = off;
+  if (dr) off += L.state_bytes;
+  // scratch planes: unfused w, or rPDRQ b
+  L.wbuf = off;
+  if (dr || r.p.variant == MF_UNFUSED) off = align_up(off + (size_t)r.nl * P * 4, 256);
+  L.total = off;
+  return L;
+}
+
+StateView view(char* base, size_t off, const Resolved& r) {
+  const size_t P = (size_t)r.g.plane;
+  StateView v;
+  char* b = base + off;
+  v.u = (float*)b;
+  b += align_up((size_t)r.nl * P * 4, 256);
+  v.q = b;
+  b += align_up((size_t)r.nq * P * r.esz, 256);
+  v.ps = b;
+  b += align_up(P * r.esz, 256);
+  v.p = b;
+  return v;
+}
+
+}  // namespace
+
+struct mf_solver {
+  Resolved r;
+  Layout L;
+  char* ws;
+  hipStream_t stream;
+  Ctrl* ctrl;
+  void* cap;
+  StateView st[2];
+  StateView z;
+  float* wbuf;
+  int64_t iter;
+  int* host_done;   // pinned polling slots
+  hipEvent_t ev[8];
+  int dev;
+};
+
+namespace {
+
+Coef coef_of(const Resolved& r) {
+  const mf_params& p = r.p;
+  Coef k;
+  k.alpha = (float)p.alpha;
+  k.inv_c = (float)(1.0 / p.c);
+  k.c = (float)p.c;
+  const bool eb = p.method == MF_RPADMM_EB;
+  k.rho = eb ? (float)p.relax : 1.f;
+  k.omr = eb ? (float)(1.0 - p.relax) : 0.f;
+  k.ku = eb ? (float)p.c : (float)(p.relax * p.c);
+  k.inv_a = (float)(1.0 / p.a);
+  if (p.model == MF_TWO_LABEL) {
+    k.inv_a1 = (float)(1.0 / p.a_tilde);
+    k.inv_a2 = (float)(1.0 / p.a_tilde);
+  } else {
+    k.inv_a1 = (float)(1.0 / p.a1);
+    k.inv_a2 = (float)(1.0 / p.a2);
+  }
+  return k;
+}
+
+bool fused_gap(const mf_solver* s) {
+  return s->r.p.variant == MF_FUSED && s->r.p.model == MF_TWO_LABEL && s->r.g.ndim == 2;
+}
+
+// One rpADMM sweep from iterate k (buffer k%2) to k+1.
+hipError_t admm_sweep(mf_solver* s, int64_t k, bool check, bool write, const int* done) {
+  SweepDesc d;
+  d.g = s->r.g;
+  d.nl = s->r.nl;
+  d.two = s->r.p.model == MF_TWO_LABEL;
+  d.bf16 = s->r.p.storage == MF_BF16;
+  d.iso = s->r.p.tv == MF_TV_ISO;
+  d.check = check;
+  d.write = write;
+  d.tile_rows = s->r.p.tile_rows;
+  d.cap = s->cap;
+  d.in = s->st[k & 1];
+  d.out = s->st[(k + 1) & 1];
+  d.wbuf = s->wbuf;
+  d.k = coef_of(s->r);
+  d.acc = s->ctrl->acc;
+  d.done = done;
+  if (s->r.p.variant == MF_UNFUSED) return launch_unfused(d, s->stream);
+  return launch_fused(d, s->stream);
+}
+
+hipError_t dr_iter(mf_solver* s, bool keep_z, const int* done) {
+  PdrqDesc d;
+  d.g = s->r.g;
+  d.nl = s->r.nl;
+  d.two = s->r.p.model == MF_TWO_LABEL;
+  d.bf16 = s->r.p.storage == MF_BF16;
+  d.iso = s->r.p.tv == MF_TV_ISO;
+  d.cap = s->cap;
+  d.st = s->st[0];
+  d.z = s->z;
+  d.b = s->wbuf;
+  d.sigma = (float)s->r.p.sigma;
+  d.tau = (float)s->r.p.tau;
+  d.rho = (float)s->r.p.relax;
+  d.inv_st = (float)(1.0 / (s->r.p.sigma * s->r.p.tau));
+  d.alpha = (float)s->r.p.alpha;
+  d.keep_z = keep_z;
+  d.done = done;
+  return launch_pdrq_iter(d, s->stream);
+}
+
+// Standalone gap of the current iterate into ctrl->acc.
+hipError_t gap_of(mf_solver* s, int64_t k, const int* done) {
+  GapDesc d;
+  d.g = s->r.g;
+  d.nl = s->r.nl;
+  d.two = s->r.p.model == MF_TWO_LABEL;
+  d.bf16 = s->r.p.storage == MF_BF16;
+  d.iso = s->r.p.tv == MF_TV_ISO;
+  d.cap = s->cap;
+  if (s->r.p.method == MF_RPDRQ) {
+    d.st = s->z;
+    d.st.u = s->st[0].u;
+  } else {
+    d.st = s->st[k & 1];
+  }
+  d.acc = s->ctrl->acc;
+  d.done = done;
+  return launch_gap(d, s->stream);
+}
+
+long long nres(const mf_solver* s) { return s->r.g.npix() * s->r.nl; }
+
+mf_status init_state(mf_solver* s) {
+  HIP_TRY(launch_init(s->r.g, s->r.nl, s->r.p.model == MF_TWO_LABEL, s->r.p.storage == MF_BF16, s->cap,
+                      s->st[0], s->stream));
+  if (s->r.p.method == MF_RPDRQ) {
+    StateView z = s->z;
+    // resolvent outputs of "iteration 0" := the initial flows
+    HIP_TRY(launch_init(s->r.g, s->r.nl, s->r.p.model == MF_TWO_LABEL, s->r.p.storage == MF_BF16, s->cap,
+                        StateView{s->wbuf, z.q, z.ps, z.p}, s->stream));
+  }
+  HIP_TRY(launch_ctrl_reset(s->ctrl, s->stream));
+  s->iter = 0;
+  return MF_OK;
+}
+
+void fill_gap(const Ctrl& c, int64_t iter, mf_gap* out, int32_t status) {
+  if (!out) return;
+  out->iter = iter;
+  out->primal = c.last[0];
+  out->dual = c.last[1];
+  out->rel_gap = c.last[2];
+  out->resid_rms = c.last[3];
+  out->flow = c.last[4];
+  out->status = status;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* maxflow_last_error(void) { return g_err.c_str(); }
+
+size_t maxflow_workspace_bytes(const mf_params* p) {
+  Resolved r;
+  const std::string e = resolve(p, r);
+  if (!e.empty()) {
+    g_err = e;
+    return 0;
+  }
+  return plan(r).total;
+}
+
+mf_status maxflow_create(const mf_params* p, const float* cap, void* workspace, size_t ws_bytes,
+                         void* hip_stream, mf_solver** out) {
+  if (!out) return fail(MF_EINVAL, "out is null");
+  *out = nullptr;
+  Resolved r;
+  const std::string e = resolve(p, r);
+  if (!e.empty()) return fail(MF_EINVAL, e);
+  if (!cap || !workspace) return fail(MF_EINVAL, "cap and workspace must be device pointers");
+  if (((uintptr_t)workspace) & 255) return fail(MF_EINVAL, "workspace must be 256-byte aligned");
+  const Layout L = plan(r);
+  if (ws_bytes < L.total)
+    return fail(MF_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+  mf_solver* s = new (std::nothrow) mf_solver();
+  if (!s) return fail(MF_ENOMEM, "host allocation failed");
+  s->r = r;
+  s->L = L;
+  s->ws = (char*)workspace;
+  s->stream = (hipStream_t)hip_stream;
+  s->ctrl = (Ctrl*)(s->ws + L.ctrl);
+  s->cap = s->ws + L.cap;
+  s->st[0] = view(s->ws, L.state[0], r);
+  s->st[1] = view(s->ws, L.state[1], r);
+  s->z = view(s->ws, L.stz, r);
+  s->wbuf = (float*)(s->ws + L.wbuf);
+  if (hipGetDevice(&s->dev) != hipSuccess) {
+    delete s;
+    return fail(MF_EDEVICE, "hipGetDevice failed");
+  }
+  if (hipHostMalloc((void**)&s->host_done, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    delete s;
+    return fail(MF_EDEVICE, "pinned host allocation failed");
+  }
+  for (int i = 0; i < 8; i++) {
+    if (hipEventCreateWithFlags(&s->ev[i], hipEventDisableTiming) != hipSuccess) {
+      for (int j = 0; j < i; j++) hipEventDestroy(s->ev[j]);
+      hipHostFree(s->host_done);
+      delete s;
+      return fail(MF_EDEVICE, "event creation failed");
+    }
+  }
+  hipError_t he = launch_convert_caps(cap, s->cap, r.g.npix(), r.ncap, r.g.plane, r.p.storage == MF_BF16,
+                                      s->stream);
+  if (he != hipSuccess) {
+    maxflow_destroy(s);
+    return fail(MF_EDEVICE, std::string("capacity copy: ") + hipGetErrorString(he));
+  }
+  mf_status st = init_state(s);
+  if (st != MF_OK) {
+    maxflow_destroy(s);
+    return st;
+  }
+  // the caller may free `cap` on return: make the copy complete
+  if (hipStreamSynchronize(s->stream) != hipSuccess) {
+    maxflow_destroy(s);
+    return fail(MF_EDEVICE, "stream synchronize failed");
+  }
+  *out = s;
+  return MF_OK;
+}
+
+mf_status maxflow_reset(mf_solver* s) {
+  if (!s) return fail(MF_EINVAL, "null solver");
+  return init_state(s);
+}
+
+int64_t maxflow_iter(const mf_solver* s) { return s ? s->iter : -1; }
+
+mf_status maxflow_step(mf_solver* s, int32_t iters) {
+  if (!s) return fail(MF_EINVAL, "null solver");
+  if (iters < 0) return fail(MF_EINVAL, "iters must be >= 0");
+  for (int32_t i = 0; i < iters; i++) {
+    if (s->r.p.method == MF_RPDRQ) {
+      HIP_TRY(dr_iter(s, i == iters - 1, nullptr));
+    } else {
+      HIP_TRY(admm_sweep(s, s->iter, false, true, nullptr));
+    }
+    s->iter += 1;
+  }
+  return MF_OK;
+}
+
+mf_status maxflow_gap(mf_solver* s, mf_gap* out) {
+  if (!s) return fail(MF_EINVAL, "null solver");
+  HIP_TRY(launch_ctrl_reset(s->ctrl, s->stream));
+  HIP_TRY(gap_of(s, s->iter, nullptr));
+  HIP_TRY(launch_bookkeep(s->ctrl, s->iter, s->r.p.alpha, 0.0, nres(s), 0, 0, s->stream));
+  Ctrl c;
+  HIP_TRY(hipMemcpyAsync(&c, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  const bool bad = !std::isfinite(c.last[0]) || !std::isfinite(c.last[1]);
+  fill_gap(c, s->iter, out, bad ? MF_EDIVERGED : MF_OK);
+  return bad ? fail(MF_EDIVERGED, "non-finite gap") : MF_OK;
+}
+
+mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
+  if (!s) return fail(MF_EINVAL, "null solver");
+  const mf_params& p = s->r.p;
+  const int64_t max_iter = std::max<int64_t>(p.max_iter, s->iter);
+  const int ce = p.check_every;
+  const bool dr = p.method == MF_RPDRQ;
+  const int* done = &s->ctrl->done;
+  HIP_TRY(launch_ctrl_reset(s->ctrl, s->stream));
+  int64_t k = s->iter;
+  // polling ring: after each check, copy `done` to pinned memory + event
+  int issued = 0, observed = 0;
+  const int lookahead = 3;
+  bool stop = false;
+  while (!stop) {
+    // ---- gap of iterate k and the decision
+    const bool final_check = k >= max_iter;
+    if (dr) {
+      HIP_TRY(gap_of(s, k, done));
+    } else if (fused_gap(s)) {
+      HIP_TRY(admm_sweep(s, k, true, !final_check, done));
+    } else {
+      HIP_TRY(gap_of(s, k, done));
+      if (!final_check) HIP_TRY(admm_sweep(s, k, false, true, done));
+    }
+    HIP_TRY(launch_bookkeep(s->ctrl, k, p.alpha, p.tol, nres(s), final_check ? 1 : 0, 1, s->stream));
+    if (final_check) break;
+    // ---- the rest of the chunk
+    const int64_t n = std::min<int64_t>(ce, max_iter - k);
+    if (dr) {
+      for (int64_t j = 0; j < n; j++) HIP_TRY(dr_iter(s, j == n - 1, done));
+    } else {
+      for (int64_t j = 1; j < n; j++) HIP_TRY(admm_sweep(s, k + j, false, true, done));
+    }
+    k += n;
+    // ---- poll the decision without stalling the queue
+    const int slot = issued & 7;
+    HIP_TRY(hipMemcpyAsync(s->host_done + slot, done, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipEventRecord(s->ev[slot], s->stream));
+    issued++;
+    while (observed < issued) {
+      const int os = observed & 7;
+      hipError_t q = (issued - observed > lookahead) ? hipEventSynchronize(s->ev[os]) : hipEventQuery(s->ev[os]);
+      if (q == hipErrorNotReady) break;
+      if (q != hipSuccess) return fail(MF_EDEVICE, std::string("event: ") + hipGetErrorString(q));
+      if (s->host_done[os]) stop = true;
+      observed++;
+    }
+  }
+  Ctrl c;
+  HIP_TRY(hipMemcpyAsync(&c, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (!c.done) return fail(MF_EDEVICE, "solve ended without a decision");
+  s->iter = c.iter;
+  const mf_status st = (mf_status)c.status;
+  fill_gap(c, s->iter, out, st);
+  if (st == MF_EDIVERGED) return fail(MF_EDIVERGED, "non-finite gap");
+  return st;
+}
+
+mf_status maxflow_read_u(mf_solver* s, float* dst) { return maxflow_read_field(s, 0, dst); }
+
+mf_status maxflow_labels(mf_solver* s, int32_t* dst) {
+  if (!s || !dst) return fail(MF_EINVAL, "null argument");
+  const StateView& v = s->r.p.method == MF_RPDRQ ? s->st[0] : s->st[s->iter & 1];
+  HIP_TRY(launch_labels(s->r.g, s->r.nl, s->r.p.model == MF_TWO_LABEL, v.u, dst, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return MF_OK;
+}
+
+static mf_status field_ptr(mf_solver* s, int32_t field, void** ptr, int* np, bool* is_u) {
+  const bool dr = s->r.p.method == MF_RPDRQ;
+  const StateView& v = dr ? s->st[0] : s->st[s->iter & 1];
+  *is_u = false;
+  switch (field) {
+    case 0: *ptr = v.u; *np = s->r.nl; *is_u = true; return MF_OK;
+    case 1: *ptr = v.q; *np = s->r.nq; return MF_OK;
+    case 2: *ptr = v.ps; *np = 1; return MF_OK;
+    case 3: *ptr = v.p; *np = s->r.nl; return MF_OK;
+    case 4: case 5: case 6:
+      if (!dr) return fail(MF_EINVAL, "resolvent fields exist only for rPDRQ");
+      *ptr = field == 4 ? s->z.q : (field == 5 ? s->z.ps : s->z.p);
+      *np = field == 4 ? s->r.nq : (field == 5 ? 1 : s->r.nl);
+      return MF_OK;
+    default: return fail(MF_EINVAL, "unknown field");
+  }
+}
+
+mf_status maxflow_read_field(mf_solver* s, int32_t field, float* dst) {
+  if (!s || !dst) return fail(MF_EINVAL, "null argument");
+  void* ptr;
+  int np;
+  bool is_u;
+  mf_status e = field_ptr(s, field, &ptr, &np, &is_u);
+  if (e != MF_OK) return e;
+  HIP_TRY(launch_read_planes(ptr, is_u ? false : s->r.p.storage == MF_BF16, dst, s->r.g.npix(), np,
+                             s->r.g.plane, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return MF_OK;
+}
+
+mf_status maxflow_write_field(mf_solver* s, int32_t field, const float* src) {
+  if (!s || !src) return fail(MF_EINVAL, "null argument");
+  void* ptr;
+  int np;
+  bool is_u;
+  mf_status e = field_ptr(s, field, &ptr, &np, &is_u);
+  if (e != MF_OK) return e;
+  HIP_TRY(launch_write_planes(src, ptr, is_u ? false : s->r.p.storage == MF_BF16, s->r.g.npix(), np,
+                              s->r.g.plane, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return MF_OK;
+}
+
+size_t maxflow_state_bytes(const mf_solver* s) {
+  if (!s) return 0;
+  return s->r.p.method == MF_RPDRQ ? 2 * s->L.state_bytes : s->L.state_bytes;
+}
+
+mf_status maxflow_export_state(mf_solver* s, void* dst) {
+  if (!s || !dst) return fail(MF_EINVAL, "null argument");
+  const bool dr = s->r.p.method == MF_RPDRQ;
+  const size_t off = dr ? s->L.state[0] : s->L.state[s->iter & 1];
+  HIP_TRY(hipMemcpyAsync(dst, s->ws + off, s->L.state_bytes, hipMemcpyDeviceToDevice, s->stream));
+  if (dr)
+    HIP_TRY(hipMemcpyAsync((char*)dst + s->L.state_bytes, s->ws + s->L.stz, s->L.state_bytes,
+                           hipMemcpyDeviceToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return MF_OK;
+}
+
+mf_status maxflow_import_state(mf_solver* s, const void* src, int64_t iter) {
+  if (!s || !src) return fail(MF_EINVAL, "null argument");
+  if (iter < 0) return fail(MF_EINVAL, "iter must be >= 0");
+  const bool dr = s->r.p.method == MF_RPDRQ;
+  s->iter = iter;
+  const size_t off = dr ? s->L.state[0] : s->L.state[iter & 1];
+  HIP_TRY(hipMemcpyAsync(s->ws + off, src, s->L.state_bytes, hipMemcpyDeviceToDevice, s->stream));
+  if (dr)
+    HIP_TRY(hipMemcpyAsync(s->ws + s->L.stz, (const char*)src + s->L.state_bytes, s->L.state_bytes,
+                           hipMemcpyDeviceToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return MF_OK;
+}
+
+mf_status maxflow_destroy(mf_solver* s) {
+  if (!s) return MF_OK;
+  hipStreamSynchronize(s->stream);
+  for (int i = 0; i < 8; i++)
+    if (s->ev[i]) hipEventDestroy(s->ev[i]);
+  if (s->host_done) hipHostFree(s->host_done);
+  delete s;
+  return MF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,258 @@
+// rPDRQ: relaxed, preconditioned Douglas-Rachford with one symmetric
+// red-black Gauss-Seidel sweep as preconditioner (eq. iteration:quadratic:seg
+// for two labels, eq. pdrq:4labels for n labels with T_0 of Lemma 1).
+//
+// The u-step u^{k+1} = u^k + M^{-1}(b^k - st T u^k), M the symmetric GS
+// matrix of st T = st(-Delta + m I) in red-black order, is one in-place
+// red, black, red sweep of
+//     u(x) <- (b(x)/st + sum_{y ~ x} u(y)) / (|N(x)| + m),
+// m = 2 (two-label) or n + 1 (Potts, per label).  Each colour needs every
+// update of the other colour, so an iteration is three launches:
+//   R1 : b^k at every cell (-> b planes), red cells updated in place
+//   B  : black cells updated in place
+//   R2F: red cells recomputed from the final black cells (every thread that
+//        needs a red value computes it, so red values are never read from
+//        memory in this launch), red u written in place, then the flows
+//        y = y-bar + tau K u and the relaxed reflection
+//        y-bar += rho (prox(2y - y-bar) - y) in place (each cell touches only
+//        its own flows; b is read from its plane, not recomputed).
+#include "mf_kernels.h"
+
+namespace mf {
+
+template <typename TS>
+struct KD {
+  int W, H, D;
+  long long P, n;
+  const TS* cap;
+  float* u;
+  TS* qb;
+  TS* psb;
+  TS* pb;
+  TS* zq;
+  TS* zs;
+  TS* zp;
+  float* b;
+  float sigma, tau, rho, inv_st, alpha, m;
+  int iso, keep_z;
+  const int* done;
+};
+
+struct Cell {
+  int x, y, z;
+};
+
+template <int NDIM>
+__device__ __forceinline__ Cell cell_of(long long idx, int W, int H) {
+  Cell c;
+  c.x = (int)(idx % W);
+  c.y = (int)((idx / W) % H);
+  c.z = NDIM == 3 ? (int)(idx / ((long long)W * H)) : 0;
+  return c;
+}
+
+__device__ __forceinline__ bool is_red(const Cell& c) { return ((c.x + c.y + c.z) & 1) == 0; }
+
+// Gauss-Seidel value at one cell from its neighbours in `u` (one label).
+template <int NDIM>
+__device__ __forceinline__ float gs_value(const float* u, const float* b, long long idx, const Cell& c, int W,
+                                          int H, int D, float inv_st, float m) {
+  const long long sz = (long long)W * H;
+  float s = 0.f;
+  float nb = 0.f;
+  if (c.x > 0) { s += u[idx - 1]; nb += 1.f; }
+  if (c.x + 1 < W) { s += u[idx + 1]; nb += 1.f; }
+  if (c.y > 0) { s += u[idx - W]; nb += 1.f; }
+  if (c.y + 1 < H) { s += u[idx + W]; nb += 1.f; }
+  if (NDIM == 3) {
+    if (c.z > 0) { s += u[idx - sz]; nb += 1.f; }
+    if (c.z + 1 < D) { s += u[idx + sz]; nb += 1.f; }
+  }
+  return (b[idx] * inv_st + s) / (nb + m);
+}
+
+template <int NL, bool TWO, int NDIM, typename TS>
+__global__ __launch_bounds__(256) void k_dr_r1(const KD<TS> A) {
+  if (A.done && *A.done) return;
+  const long long sz = (long long)A.W * A.H;
+  for (long long idx = blockIdx.x * 256LL + threadIdx.x; idx < A.n; idx += (long long)gridDim.x * 256) {
+    const Cell c = cell_of<NDIM>(idx, A.W, A.H);
+    const float psb = ld(A.psb, idx);
+    float usum = 0.f;
+    float uk[NL];
+#pragma unroll
+    for (int l = 0; l < NL; l++) {
+      uk[l] = A.u[(long long)l * A.P + idx];
+      usum += uk[l];
+    }
+#pragma unroll
+    for (int l = 0; l < NL; l++) {
+      const TS* q = A.qb + (long long)(NDIM * l) * A.P;
+      float d = ((c.x + 1 < A.W ? ld(q, idx) : 0.f) - (c.x > 0 ? ld(q, idx - 1) : 0.f)) +
+                ((c.y + 1 < A.H ? ld(q + A.P, idx) : 0.f) - (c.y > 0 ? ld(q + A.P, idx - A.W) : 0.f));
+      if (NDIM == 3)
+        d += (c.z + 1 < A.D ? ld(q + 2 * A.P, idx) : 0.f) - (c.z > 0 ? ld(q + 2 * A.P, idx - sz) : 0.f);
+      float bl = -A.sigma * ((d + ld(A.pb + (long long)l * A.P, idx)) - psb);
+      // Potts: + st ((n-1) u_i - sum_{j != i} u_j) = st (n u_i - sum_j u_j)
+      if (!TWO) bl += (A.sigma * A.tau) * ((float)NL * uk[l] - usum);
+      float* bp = A.b + (long long)l * A.P;
+      bp[idx] = bl;
+    }
+    if (is_red(c)) {
+#pragma unroll
+      for (int l = 0; l < NL; l++) {
+        float* ul = A.u + (long long)l * A.P;
+        ul[idx] = gs_value<NDIM>(ul, A.b + (long long)l * A.P, idx, c, A.W, A.H, A.D, A.inv_st, A.m);
+      }
+    }
+  }
+}
+
+template <int NL, int NDIM, typename TS>
+__global__ __launch_bounds__(256) void k_dr_b(const KD<TS> A) {
+  if (A.done && *A.done) return;
+  for (long long idx = blockIdx.x * 256LL + threadIdx.x; idx < A.n; idx += (long long)gridDim.x * 256) {
+    const Cell c = cell_of<NDIM>(idx, A.W, A.H);
+    if (is_red(c)) continue;
+#pragma unroll
+    for (int l = 0; l < NL; l++) {
+      float* ul = A.u + (long long)l * A.P;
+      ul[idx] = gs_value<NDIM>(ul, A.b + (long long)l * A.P, idx, c, A.W, A.H, A.D, A.inv_st, A.m);
+    }
+  }
+}
+
+template <int NDIM>
+__device__ __forceinline__ float u_final(const float* ul, const float* bl, long long idx, const Cell& c, int W,
+                                         int H, int D, float inv_st, float m) {
+  return is_red(c) ? gs_value<NDIM>(ul, bl, idx, c, W, H, D, inv_st, m) : ul[idx];
+}
+
+template <int NL, bool TWO, int NDIM, typename TS>
+__global__ __launch_bounds__(256) void k_dr_r2f(const KD<TS> A) {
+  if (A.done && *A.done) return;
+  const long long sz = (long long)A.W * A.H;
+  const float tau = A.tau, rho = A.rho;
+  for (long long idx = blockIdx.x * 256LL + threadIdx.x; idx < A.n; idx += (long long)gridDim.x * 256) {
+    const Cell c = cell_of<NDIM>(idx, A.W, A.H);
+    float un[NL];
+    float usum = 0.f;
+#pragma unroll
+    for (int l = 0; l < NL; l++) {
+      const float* ul = A.u + (long long)l * A.P;
+      const float* bl = A.b + (long long)l * A.P;
+      const float u0 = u_final<NDIM>(ul, bl, idx, c, A.W, A.H, A.D, A.inv_st, A.m);
+      un[l] = u0;
+      usum += u0;
+      // grad u^{k+1} with the forward neighbours' final values
+      float g[3] = {0.f, 0.f, 0.f};
+      if (c.x + 1 < A.W) {
+        Cell cn = c;
+        cn.x += 1;
+        g[0] = u_final<NDIM>(ul, bl, idx + 1, cn, A.W, A.H, A.D, A.inv_st, A.m) - u0;
+      }
+      if (c.y + 1 < A.H) {
+        Cell cn = c;
+        cn.y += 1;
+        g[1] = u_final<NDIM>(ul, bl, idx + A.W, cn, A.W, A.H, A.D, A.inv_st, A.m) - u0;
+      }
+      if (NDIM == 3 && c.z + 1 < A.D) {
+        Cell cn = c;
+        cn.z += 1;
+        g[2] = u_final<NDIM>(ul, bl, idx + sz, cn, A.W, A.H, A.D, A.inv_st, A.m) - u0;
+      }
+      // q = q-bar - tau grad u;  z_q = P_alpha(2q - q-bar);  q-bar += rho (z_q - q)
+      TS* q = A.qb + (long long)(NDIM * l) * A.P;
+      float qbv[3], qv[3], zv[3];
+#pragma unroll
+      for (int k = 0; k < NDIM; k++) {
+        qbv[k] = ld(q + (long long)k * A.P, idx);
+        qv[k] = qbv[k] - tau * g[k];
+        zv[k] = 2.f * qv[k] - qbv[k];
+      }
+      if (NDIM == 2) {
+        if (A.iso) proj2<true>(zv[0], zv[1], A.alpha);
+        else proj2<false>(zv[0], zv[1], A.alpha);
+      } else {
+        if (A.iso) proj3<true>(zv[0], zv[1], zv[2], A.alpha);
+        else proj3<false>(zv[0], zv[1], zv[2], A.alpha);
+      }
+#pragma unroll
+      for (int k = 0; k < NDIM; k++) {
+        st(q + (long long)k * A.P, idx, qbv[k] + rho * (zv[k] - qv[k]));
+        if (A.keep_z) st(A.zq + (long long)(NDIM * l + k) * A.P, idx, zv[k]);
+      }
+      // p_i = p-bar_i + tau u_i;  z = min(C_i, 2 p_i - p-bar_i);  p-bar_i += rho (z - p_i)
+      TS* pbl = A.pb + (long long)l * A.P;
+      const float pbv = ld(pbl, idx);
+      const float pv = pbv + tau * u0;
+      const float zpv = fminf(ld(A.cap + (long long)(TWO ? 1 : l) * A.P, idx), 2.f * pv - pbv);
+      st(pbl, idx, pbv + rho * (zpv - pv));
+      if (A.keep_z) st(A.zp + (long long)l * A.P, idx, zpv);
+    }
+    // p_s = p-bar_s - tau sum_i u_i;  z_s = (min(C_s,) 2 p_s - p-bar_s + tau)
+    const float psbv = ld(A.psb, idx);
+    const float psv = psbv - tau * usum;
+    float zsv = (2.f * psv - psbv) + tau;
+    if (TWO) zsv = fminf(ld(A.cap, idx), zsv);
+    st(A.psb, idx, psbv + rho * (zsv - psv));
+    if (A.keep_z) st(A.zs, idx, zsv);
+    if (is_red(c)) {
+#pragma unroll
+      for (int l = 0; l < NL; l++) A.u[(long long)l * A.P + idx] = un[l];
+    }
+  }
+}
+
+template <int NL, bool TWO, int NDIM, typename TS>
+static hipError_t dr_nl(const PdrqDesc& d, hipStream_t s) {
+  KD<TS> a;
+  a.W = d.g.W;
+  a.H = d.g.H;
+  a.D = d.g.D;
+  a.P = d.g.plane;
+  a.n = d.g.npix();
+  a.cap = (const TS*)d.cap;
+  a.u = d.st.u;
+  a.qb = (TS*)d.st.q;
+  a.psb = (TS*)d.st.ps;
+  a.pb = (TS*)d.st.p;
+  a.zq = (TS*)d.z.q;
+  a.zs = (TS*)d.z.ps;
+  a.zp = (TS*)d.z.p;
+  a.b = d.b;
+  a.sigma = d.sigma;
+  a.tau = d.tau;
+  a.rho = d.rho;
+  a.inv_st = d.inv_st;
+  a.alpha = d.alpha;
+  a.m = TWO ? 2.f : (float)(NL + 1);
+  a.iso = d.iso ? 1 : 0;
+  a.keep_z = d.keep_z ? 1 : 0;
+  a.done = d.done;
+  long long nb = (a.n + 255) / 256;
+  if (nb > 16384) nb = 16384;
+  hipLaunchKernelGGL((k_dr_r1<NL, TWO, NDIM, TS>), dim3((int)nb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_dr_b<NL, NDIM, TS>), dim3((int)nb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_dr_r2f<NL, TWO, NDIM, TS>), dim3((int)nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int NDIM, typename TS>
+static hipError_t dr_ts(const PdrqDesc& d, hipStream_t s) {
+  if (d.two) return dr_nl<1, true, NDIM, TS>(d, s);
+  switch (d.nl) {
+    case 2: return dr_nl<2, false, NDIM, TS>(d, s);
+    case 3: return dr_nl<3, false, NDIM, TS>(d, s);
+    case 4: return dr_nl<4, false, NDIM, TS>(d, s);
+    case 8: return dr_nl<8, false, NDIM, TS>(d, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_pdrq_iter(const PdrqDesc& d, hipStream_t s) {
+  if (d.g.ndim == 2) return d.bf16 ? dr_ts<2, bf16_t>(d, s) : dr_ts<2, float>(d, s);
+  return d.bf16 ? dr_ts<3, bf16_t>(d, s) : dr_ts<3, float>(d, s);
+}
+
+}  // namespace mf

@@ -1,0 +1,309 @@
+// Gap reduction, initial point, labels, field copies and the per-solve
+// bookkeeping kernel.
+#include "mf_kernels.h"
+
+namespace mf {
+
+hipError_t launch_fused2d(const SweepDesc& d, hipStream_t s);
+hipError_t launch_fused3d(const SweepDesc& d, hipStream_t s);
+
+hipError_t launch_fused(const SweepDesc& d, hipStream_t s) {
+  return d.g.ndim == 2 ? launch_fused2d(d, s) : launch_fused3d(d, s);
+}
+
+// ------------------------------------------------------------------ gap
+template <typename TS>
+struct KG {
+  int W, H, D;
+  long long P, n;
+  const TS* cap;
+  const float* u;
+  const TS* q;
+  const TS* ps;
+  const TS* p;
+  double* acc;
+  const int* done;
+  int iso;
+};
+
+__device__ __forceinline__ double clip01(float v) { return fmin(1.0, fmax(0.0, (double)v)); }
+
+// Per pixel, in FP64: primal data and TV terms at the projected u, the dual
+// term (min(C_s, C_t + div q) or min_i(C_i + div q_i)), the squared
+// conservation residual and p_s.  Relaxed min-cut (eq. seg:chanvese) /
+// relaxed Potts (eq. relaxed-potts) and their max-flow duals (eqs.
+// two-label-mf, potts-mf).
+template <int NL, bool TWO, int NDIM, typename TS>
+__global__ __launch_bounds__(256) void k_gap(const KG<TS> A) {
+  __shared__ double sred[4 * 5];
+  if (A.done && *A.done) return;
+  double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const long long sz = (long long)A.W * A.H;
+  for (long long idx = blockIdx.x * 256LL + threadIdx.x; idx < A.n; idx += (long long)gridDim.x * 256) {
+    const int x = (int)(idx % A.W);
+    const int y = (int)((idx / A.W) % A.H);
+    const int z = (int)(idx / sz);
+    const bool hx = x + 1 < A.W, hy = y + 1 < A.H, hz = NDIM == 3 && z + 1 < A.D;
+    const double ps = (double)ld(A.ps, idx);
+    double dq[NL];
+#pragma unroll
+    for (int l = 0; l < NL; l++) {
+      const TS* q = A.q + (long long)(NDIM * l) * A.P;
+      double d = ((hx ? (double)ld(q, idx) : 0.0) - (x > 0 ? (double)ld(q, idx - 1) : 0.0)) +
+                 ((hy ? (double)ld(q + A.P, idx) : 0.0) - (y > 0 ? (double)ld(q + A.P, idx - A.W) : 0.0));
+      if (NDIM == 3)
+        d += (hz ? (double)ld(q + 2 * A.P, idx) : 0.0) - (z > 0 ? (double)ld(q + 2 * A.P, idx - sz) : 0.0);
+      dq[l] = d;
+    }
+    if (TWO) {
+      const double Cs = (double)ld(A.cap, idx), Ct = (double)ld(A.cap + A.P, idx);
+      const double u0 = clip01(A.u[idx]);
+      const double gx = hx ? clip01(A.u[idx + 1]) - u0 : 0.0;
+      const double gy = hy ? clip01(A.u[idx + A.W]) - u0 : 0.0;
+      const double gz = hz ? clip01(A.u[idx + sz]) - u0 : 0.0;
+      g[0] += (1.0 - u0) * Cs + u0 * Ct;
+      g[1] += A.iso ? sqrt((gx * gx + gy * gy) + gz * gz) : (fabs(gx) + fabs(gy)) + fabs(gz);
+      g[2] += fmin(Cs, Ct + dq[0]);
+      const double r = ((double)ld(A.p, idx) - ps) + dq[0];
+      g[3] += r * r;
+    } else {
+      double v[NL], w0[NL], wx[NL], wy[NL], wz[NL];
+#pragma unroll
+      for (int l = 0; l < NL; l++) v[l] = (double)A.u[(long long)l * A.P + idx];
+      simplex_proj<NL>(v, w0);
+#pragma unroll
+      for (int l = 0; l < NL; l++) v[l] = hx ? (double)A.u[(long long)l * A.P + idx + 1] : 0.0;
+      simplex_proj<NL>(v, wx);
+#pragma unroll
+      for (int l = 0; l < NL; l++) v[l] = hy ? (double)A.u[(long long)l * A.P + idx + A.W] : 0.0;
+      simplex_proj<NL>(v, wy);
+      if (NDIM == 3) {
+#pragma unroll
+        for (int l = 0; l < NL; l++) v[l] = hz ? (double)A.u[(long long)l * A.P + idx + sz] : 0.0;
+        simplex_proj<NL>(v, wz);
+      }
+      double mn = 1e300;
+#pragma unroll
+      for (int l = 0; l < NL; l++) {
+        const double C = (double)ld(A.cap + (long long)l * A.P, idx);
+        g[0] += w0[l] * C;
+        const double gx = hx ? wx[l] - w0[l] : 0.0;
+        const double gy = hy ? wy[l] - w0[l] : 0.0;
+        const double gz = (NDIM == 3 && hz) ? wz[l] - w0[l] : 0.0;
+        g[1] += A.iso ? sqrt((gx * gx + gy * gy) + gz * gz) : (fabs(gx) + fabs(gy)) + fabs(gz);
+        const double t = C + dq[l];
+        mn = t < mn ? t : mn;
+        const double r = (dq[l] + (double)ld(A.p + (long long)l * A.P, idx)) - ps;
+        g[3] += r * r;
+      }
+      g[2] += mn;
+    }
+    g[4] += ps;
+  }
+  block_accumulate<5, 4>(g, A.acc, sred);
+}
+
+template <int NL, bool TWO, int NDIM, typename TS>
+static hipError_t gap_nl(const GapDesc& d, hipStream_t s) {
+  KG<TS> a;
+  a.W = d.g.W;
+  a.H = d.g.H;
+  a.D = d.g.D;
+  a.P = d.g.plane;
+  a.n = d.g.npix();
+  a.cap = (const TS*)d.cap;
+  a.u = d.st.u;
+  a.q = (const TS*)d.st.q;
+  a.ps = (const TS*)d.st.ps;
+  a.p = (const TS*)d.st.p;
+  a.acc = d.acc;
+  a.done = d.done;
+  a.iso = d.iso ? 1 : 0;
+  long long nb = (a.n + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL((k_gap<NL, TWO, NDIM, TS>), dim3((int)nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int NDIM, typename TS>
+static hipError_t gap_ts(const GapDesc& d, hipStream_t s) {
+  if (d.two) return gap_nl<1, true, NDIM, TS>(d, s);
+  switch (d.nl) {
+    case 2: return gap_nl<2, false, NDIM, TS>(d, s);
+    case 3: return gap_nl<3, false, NDIM, TS>(d, s);
+    case 4: return gap_nl<4, false, NDIM, TS>(d, s);
+    case 8: return gap_nl<8, false, NDIM, TS>(d, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_gap(const GapDesc& d, hipStream_t s) {
+  if (d.g.ndim == 2) return d.bf16 ? gap_ts<2, bf16_t>(d, s) : gap_ts<2, float>(d, s);
+  return d.bf16 ? gap_ts<3, bf16_t>(d, s) : gap_ts<3, float>(d, s);
+}
+
+// ------------------------------------------------------------------ init
+// q = 0, u = 0, p_s and every p_i (p_t) at the pointwise minimum capacity.
+template <typename TS>
+__global__ __launch_bounds__(256) void k_init(int nl, int ncap, int ndim, long long n, long long P,
+                                              const TS* cap, float* u, TS* q, TS* ps, TS* p) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    float m = ld(cap, i);
+    for (int c = 1; c < ncap; c++) m = fminf(m, ld(cap + (long long)c * P, i));
+    st(ps, i, m);
+    for (int l = 0; l < nl; l++) {
+      u[(long long)l * P + i] = 0.f;
+      st(p + (long long)l * P, i, m);
+      for (int k = 0; k < ndim; k++) st(q + (long long)(l * ndim + k) * P, i, 0.f);
+    }
+  }
+}
+
+static int blocks_for(long long n) {
+  long long nb = (n + 255) / 256;
+  return (int)(nb > 8192 ? 8192 : (nb < 1 ? 1 : nb));
+}
+
+hipError_t launch_init(const Geom& g, int nl, bool two, bool bf16, const void* cap, StateView st,
+                       hipStream_t s) {
+  const int ncap = two ? 2 : nl;
+  const long long n = g.npix();
+  if (bf16)
+    hipLaunchKernelGGL(k_init<bf16_t>, dim3(blocks_for(n)), dim3(256), 0, s, nl, ncap, g.ndim, n, g.plane,
+                       (const bf16_t*)cap, st.u, (bf16_t*)st.q, (bf16_t*)st.ps, (bf16_t*)st.p);
+  else
+    hipLaunchKernelGGL(k_init<float>, dim3(blocks_for(n)), dim3(256), 0, s, nl, ncap, g.ndim, n, g.plane,
+                       (const float*)cap, st.u, (float*)st.q, (float*)st.ps, (float*)st.p);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ copies
+template <typename TS>
+__global__ __launch_bounds__(256) void k_to_storage(const float* src, TS* dst, long long n, int np,
+                                                    long long psrc, long long pdst) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    for (int c = 0; c < np; c++) st(dst + (long long)c * pdst, i, src[(long long)c * psrc + i]);
+}
+template <typename TS>
+__global__ __launch_bounds__(256) void k_from_storage(const TS* src, float* dst, long long n, int np,
+                                                      long long psrc, long long pdst) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    for (int c = 0; c < np; c++) dst[(long long)c * pdst + i] = ld(src + (long long)c * psrc, i);
+}
+
+hipError_t launch_convert_caps(const float* src, void* dst, long long n, int np, long long plane,
+                               bool bf16, hipStream_t s) {
+  if (bf16)
+    hipLaunchKernelGGL(k_to_storage<bf16_t>, dim3(blocks_for(n)), dim3(256), 0, s, src, (bf16_t*)dst, n, np, n,
+                       plane);
+  else
+    hipLaunchKernelGGL(k_to_storage<float>, dim3(blocks_for(n)), dim3(256), 0, s, src, (float*)dst, n, np, n,
+                       plane);
+  return hipGetLastError();
+}
+hipError_t launch_write_planes(const float* src, void* dst, bool bf16, long long n, int np, long long plane,
+                               hipStream_t s) {
+  return launch_convert_caps(src, dst, n, np, plane, bf16, s);
+}
+hipError_t launch_read_planes(const void* src, bool bf16, float* dst, long long n, int np, long long plane,
+                              hipStream_t s) {
+  if (bf16)
+    hipLaunchKernelGGL(k_from_storage<bf16_t>, dim3(blocks_for(n)), dim3(256), 0, s, (const bf16_t*)src, dst, n,
+                       np, plane, n);
+  else
+    hipLaunchKernelGGL(k_from_storage<float>, dim3(blocks_for(n)), dim3(256), 0, s, (const float*)src, dst, n,
+                       np, plane, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ labels
+__global__ __launch_bounds__(256) void k_labels(int nl, int two, long long n, long long P, const float* u,
+                                                int32_t* lab) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    if (two) {
+      lab[i] = u[i] > 0.5f ? 1 : 0;
+    } else {
+      int best = 0;
+      float bv = u[i];
+      for (int l = 1; l < nl; l++) {
+        const float v = u[(long long)l * P + i];
+        if (v > bv) {
+          bv = v;
+          best = l;
+        }
+      }
+      lab[i] = best;
+    }
+  }
+}
+
+hipError_t launch_labels(const Geom& g, int nl, bool two, const float* u, int32_t* lab, hipStream_t s) {
+  const long long n = g.npix();
+  hipLaunchKernelGGL(k_labels, dim3(blocks_for(n)), dim3(256), 0, s, nl, two ? 1 : 0, n, g.plane, u, lab);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ control
+__global__ void k_ctrl_reset(Ctrl* c) {
+  const int t = threadIdx.x;
+  if (t < 8) {
+    c->acc[t] = 0.0;
+    c->last[t] = 0.0;
+  }
+  if (t == 0) {
+    c->iter = 0;
+    c->done = 0;
+    c->status = 0;
+    c->checks = 0;
+  }
+}
+
+hipError_t launch_ctrl_reset(Ctrl* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_ctrl_reset, dim3(1), dim3(64), 0, s, c);
+  return hipGetLastError();
+}
+
+// Turns the accumulated sums into the gap at iterate k, decides (when
+// `decide`) whether the solve stops there, and clears the accumulators.
+// Status codes follow mf_status: 0 converged, 1 cap reached, -4 diverged.
+__global__ void k_bookkeep(Ctrl* c, long long k, double alpha, double tol, long long nres, int final_check,
+                           int decide) {
+  if (threadIdx.x != 0) return;
+  if (c->done) return;
+  const double P = c->acc[0] + alpha * c->acc[1];
+  const double D = c->acc[2];
+  const double m = fmax(fmax(fabs(P), fabs(D)), 1e-300);
+  const double rel = (P - D) / m;
+  c->last[0] = P;
+  c->last[1] = D;
+  c->last[2] = rel;
+  c->last[3] = sqrt(c->acc[3] / (double)nres);
+  c->last[4] = c->acc[4];
+  c->last[5] = (double)k;
+  c->checks += 1;
+  if (decide) {
+    const bool bad = !isfinite(P) || !isfinite(D) || !isfinite(c->acc[3]);
+    if (bad) {
+      c->done = 1;
+      c->status = -4;
+      c->iter = k;
+    } else if (rel <= tol) {
+      c->done = 1;
+      c->status = 0;
+      c->iter = k;
+    } else if (final_check) {
+      c->done = 1;
+      c->status = 1;
+      c->iter = k;
+    }
+  }
+  for (int j = 0; j < 8; j++) c->acc[j] = 0.0;
+}
+
+hipError_t launch_bookkeep(Ctrl* c, long long k, double alpha, double tol, long long nres, int final_check,
+                           int decide, hipStream_t s) {
+  hipLaunchKernelGGL(k_bookkeep, dim3(1), dim3(64), 0, s, c, k, alpha, tol, nres, final_check, decide);
+  return hipGetLastError();
+}
+
+}  // namespace mf

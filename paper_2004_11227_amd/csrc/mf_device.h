@@ -1,0 +1,197 @@
+// Device-side building blocks of the max-flow sweeps (gfx950).
+//
+// Every kernel variant (fused tile, unfused baseline, batched) evaluates the
+// method through these inline functions, in the same operation order, and
+// the library is compiled with -ffp-contract=off: variants that compute the
+// same iterate therefore agree bit for bit.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mf {
+
+// ---------------------------------------------------------------- storage
+// bfloat16 is kept as raw 16-bit words.  Widening is exact (shift into the
+// high half of an FP32 word); narrowing rounds to nearest, ties to even, and
+// keeps NaNs quiet.
+typedef uint16_t bf16_t;
+
+__device__ __forceinline__ float ld(const float* p, long long i) { return p[i]; }
+__device__ __forceinline__ float ld(const bf16_t* p, long long i) {
+  return __uint_as_float(((uint32_t)p[i]) << 16);
+}
+__device__ __forceinline__ bf16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (bf16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16_t)(u >> 16);
+}
+__device__ __forceinline__ void st(float* p, long long i, float v) { p[i] = v; }
+__device__ __forceinline__ void st(bf16_t* p, long long i, float v) { p[i] = f2bf(v); }
+
+// ---------------------------------------------------------------- scalars
+struct Coef {
+  float alpha;      // TV weight
+  float inv_c;      // 1/c
+  float c;          // c
+  float ku;         // multiplier-step factor: r c (FG) or c (EB)
+  float rho;        // EB relaxation rho (1 for FG)
+  float omr;        // 1 - rho
+  float inv_a;      // 1/a   (q preconditioner N = a c I)
+  float inv_a1;     // 1/a1  (two-label: 1/a~)
+  float inv_a2;     // 1/a2  (two-label: 1/a~)
+};
+
+// P_alpha: isotropic (pointwise Euclidean ball, eq. projections) or
+// anisotropic (per-component clamp).  A vector inside the ball is returned
+// unchanged; outside it is scaled by alpha/|q|.
+template <bool ISO>
+__device__ __forceinline__ void proj2(float& x, float& y, float alpha) {
+  if (ISO) {
+    const float n = sqrtf(x * x + y * y);
+    if (n > alpha) {
+      const float s = alpha / n;
+      x = x * s;
+      y = y * s;
+    }
+  } else {
+    x = fminf(alpha, fmaxf(-alpha, x));
+    y = fminf(alpha, fmaxf(-alpha, y));
+  }
+}
+template <bool ISO>
+__device__ __forceinline__ void proj3(float& x, float& y, float& z, float alpha) {
+  if (ISO) {
+    const float n = sqrtf((x * x + y * y) + z * z);
+    if (n > alpha) {
+      const float s = alpha / n;
+      x = x * s;
+      y = y * s;
+      z = z * s;
+    }
+  } else {
+    x = fminf(alpha, fmaxf(-alpha, x));
+    y = fminf(alpha, fmaxf(-alpha, y));
+    z = fminf(alpha, fmaxf(-alpha, z));
+  }
+}
+
+// Divergence at a pixel from its own flux and the flux of its backward
+// neighbours; `hi_k` says the forward neighbour along axis k exists, `lo_k`
+// that the backward one does (zero flux through the boundary).
+__device__ __forceinline__ float div2(float qx, float qx_w, float qy, float qy_n,
+                                      bool hix, bool lox, bool hiy, bool loy) {
+  return ((hix ? qx : 0.f) - (lox ? qx_w : 0.f)) + ((hiy ? qy : 0.f) - (loy ? qy_n : 0.f));
+}
+__device__ __forceinline__ float div3(float qx, float qx_w, float qy, float qy_n, float qz,
+                                      float qz_b, bool hix, bool lox, bool hiy, bool loy,
+                                      bool hiz, bool loz) {
+  return (((hix ? qx : 0.f) - (lox ? qx_w : 0.f)) + ((hiy ? qy : 0.f) - (loy ? qy_n : 0.f))) +
+         ((hiz ? qz : 0.f) - (loz ? qz_b : 0.f));
+}
+
+// v = (p_i - p_s) - u_i / c; the q-step argument is w = div q^k + v, and
+// q^{k+1} = P_alpha(q^k + grad(w) / a)  (the (I - div^*div / a) q^k +
+// grad(p - p_s - u/c) / a form of the q-updates of Section 3).
+__device__ __forceinline__ float vterm(float p, float ps, float u, float inv_c) {
+  return (p - ps) - u * inv_c;
+}
+__device__ __forceinline__ float wterm(float dq, float v) { return dq + v; }
+__device__ __forceinline__ float qstep(float q, float wn, float w, bool inside, float inv_a) {
+  return q + inv_a * (inside ? (wn - w) : 0.f);
+}
+
+// Per-label part of the p and u updates (rpADMMI / rpADMMII, two-label and
+// Potts; the two-label model is the one-label case with p = p_t, a1 = a2 = a~
+// and an extra clip of p_s at C_s):
+//   r_i   = rho (p_i - p_s) - u_i / c
+//   p_i'  = min(C_i, p_i - (r_i + rho d_i) / a1)
+//   t_i   = u_i - ku ((rho d_i + p_i') - (1 - rho)(p_i - p_s))
+// and the sums sum_d += rho d_i, sum_r += r_i.  The p_s and final u steps are
+// finish_ps / finish_u (u_i' = t_i + ku p_s').  EB (rpADMMII) uses rho and
+// ku = c; FG (rpADMMI) is the same expression with rho = 1, 1 - rho = 0 and
+// ku = r c (the relaxation acts on the multiplier step only).
+__device__ __forceinline__ void label_update(const Coef& k, float u, float p, float ps, float d,
+                                             float C, float& pn, float& t, float& sum_d,
+                                             float& sum_r) {
+  const float dpp = p - ps;
+  const float r = k.rho * dpp - u * k.inv_c;
+  const float rd = k.rho * d;
+  pn = fminf(C, p - (r + rd) * k.inv_a1);
+  t = u - k.ku * ((rd + pn) - k.omr * dpp);
+  sum_d += rd;
+  sum_r += r;
+}
+__device__ __forceinline__ float finish_ps(const Coef& k, float ps, float sum_d, float sum_r,
+                                           bool two, float Cs) {
+  const float v = ps + ((sum_d + sum_r) + k.inv_c) * k.inv_a2;
+  return two ? fminf(Cs, v) : v;
+}
+__device__ __forceinline__ float finish_u(const Coef& k, float t, float psn) {
+  return t + k.ku * psn;
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum of NQ doubles, then one atomic per quantity per block.
+template <int NQ, int NWAVES>
+__device__ __forceinline__ void block_accumulate(double (&v)[NQ], double* dst, double* sred) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (threadIdx.x + threadIdx.y * blockDim.x) >> 6;
+#pragma unroll
+  for (int j = 0; j < NQ; j++) v[j] = wave_sum(v[j]);
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < NQ; j++) sred[wave * NQ + j] = v[j];
+  }
+  __syncthreads();
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  if (tid < NQ) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NWAVES; w++) s += sred[w * NQ + tid];
+    atomicAdd(dst + tid, s);
+  }
+}
+
+// Euclidean projection of (v_0..v_{n-1}) onto the probability simplex: the
+// threshold is theta = max_j (S_j - 1) / k_j, where S_j and k_j are the sum
+// and count of the entries ranked at or above v_j (ties broken by index);
+// the projection is max(v - theta, 0).  Rank form without a sort, so the
+// arrays stay in registers.
+template <int N>
+__device__ __forceinline__ void simplex_proj(const double (&v)[N], double (&w)[N]) {
+  double theta = -1e300;
+#pragma unroll
+  for (int j = 0; j < N; j++) {
+    double s = 0.0;
+    double k = 0.0;
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+      const bool above = (v[i] > v[j]) || (v[i] == v[j] && i <= j);
+      s += above ? v[i] : 0.0;
+      k += above ? 1.0 : 0.0;
+    }
+    const double t = (s - 1.0) / k;
+    theta = t > theta ? t : theta;
+  }
+#pragma unroll
+  for (int i = 0; i < N; i++) w[i] = v[i] - theta > 0.0 ? v[i] - theta : 0.0;
+}
+
+// XCD-aware tile order: consecutive workgroup ids are dispatched round-robin
+// over the 8 XCDs, so map the workgroups that land on one XCD to one
+// contiguous run of tiles; neighbouring tiles then share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  if (nb < 8) return b;
+  const int x = b & 7, slot = b >> 3;
+  const int base = nb >> 3, rem = nb & 7;
+  return x * base + (x < rem ? x : rem) + slot;
+}
+
+}  // namespace mf

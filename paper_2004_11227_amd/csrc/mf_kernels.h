@@ -1,0 +1,99 @@
+// Kernel launch descriptors shared by the host runtime (capi.cpp) and the
+// kernel translation units.  Only plain pointers and sizes cross this line.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mf_device.h"
+
+namespace mf {
+
+// Device control block of one solve: gap accumulators, the last evaluated
+// gap and the convergence decision.  Written only by the bookkeeping kernel
+// (decision) and by the gap reductions (atomics into acc); sweeps read `done`.
+struct Ctrl {
+  double acc[8];     // data, tv, dual, residual^2, flow (FP64 partial sums)
+  double last[8];    // primal, dual, rel_gap, resid_rms, flow, iter
+  long long iter;    // iterate at which the solve stopped
+  int done;          // 0 running, 1 stopped
+  int status;        // MF_OK / MF_ENOTCONV / MF_EDIVERGED when done
+  long long checks;  // number of gap evaluations so far
+  int pad[6];
+};
+
+struct Geom {
+  int ndim;
+  int W, H, D;       // D = 1 in 2-D
+  long long plane;   // element stride between planes
+  long long npix() const { return (long long)W * H * D; }
+};
+
+// One state buffer (all planes of one iterate).
+struct StateView {
+  float* u;    // NL planes (FP32 always)
+  void* q;     // NL * ndim planes (storage type)
+  void* ps;    // 1 plane
+  void* p;     // NL planes
+};
+
+struct SweepDesc {
+  Geom g;
+  int nl;          // 1 for the two-label model, n for Potts
+  bool two;        // two-label model (p = p_t, extra clip of p_s at C_s)
+  bool bf16;       // storage type of flows and capacities
+  bool iso;        // isotropic projection
+  bool check;      // accumulate the gap of the input iterate (fused only)
+  bool write;      // write the output iterate
+  int tile_rows;   // fused 2-D tile height
+  const void* cap;
+  StateView in, out;
+  float* wbuf;     // unfused: NL planes of w
+  Coef k;
+  double* acc;     // Ctrl::acc of this solve
+  const int* done; // Ctrl::done of this solve, or nullptr
+};
+
+struct GapDesc {
+  Geom g;
+  int nl;
+  bool two, bf16, iso;
+  const void* cap;
+  StateView st;    // iterate (for rPDRQ: u plus the resolvent outputs)
+  double* acc;
+  const int* done;
+};
+
+struct PdrqDesc {
+  Geom g;
+  int nl;
+  bool two, bf16, iso;
+  const void* cap;
+  StateView st;        // u and the reflected variables (q-bar, p_s-bar, p-bar), in place
+  StateView z;         // resolvent outputs (written when `keep_z`)
+  float* b;            // NL planes of the right-hand side b^k
+  float sigma, tau, rho, inv_st, alpha;
+  bool keep_z;
+  const int* done;
+};
+
+hipError_t launch_fused(const SweepDesc& d, hipStream_t s);
+hipError_t launch_unfused(const SweepDesc& d, hipStream_t s);
+hipError_t launch_gap(const GapDesc& d, hipStream_t s);
+hipError_t launch_pdrq_iter(const PdrqDesc& d, hipStream_t s);
+
+// misc kernels
+hipError_t launch_init(const Geom& g, int nl, bool two, bool bf16, const void* cap,
+                       StateView st, hipStream_t s);
+hipError_t launch_convert_caps(const float* src, void* dst, long long n_per_plane, int nplanes,
+                               long long plane, bool bf16, hipStream_t s);
+hipError_t launch_labels(const Geom& g, int nl, bool two, const float* u, int32_t* lab,
+                         hipStream_t s);
+hipError_t launch_read_planes(const void* src, bool bf16, float* dst, long long n, int nplanes,
+                              long long plane, hipStream_t s);
+hipError_t launch_write_planes(const float* src, void* dst, bool bf16, long long n, int nplanes,
+                               long long plane, hipStream_t s);
+hipError_t launch_ctrl_reset(Ctrl* c, hipStream_t s);
+hipError_t launch_bookkeep(Ctrl* c, long long k, double alpha, double tol, long long nres,
+                           int final_check, int decide, hipStream_t s);
+
+}  // namespace mf

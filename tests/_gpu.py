@@ -1,0 +1,73 @@
+"""Shared helpers for the GPU parity tests: run the HIP solver and the FP64
+oracle on the same seeded inputs and compare."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+try:  # the binding must load the real library; there is no fallback
+    from paper_2004_11227_amd import maxflow as mfx
+except Exception:  # pragma: no cover
+    mfx = None
+
+
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    mfx.lib()
+
+
+def banner(msg: str):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def gpu_solver(caps: np.ndarray, **kw):
+    t = torch.from_numpy(np.ascontiguousarray(caps, dtype=np.float32)).cuda()
+    return mfx.Solver(t, **kw)
+
+
+def oracle_problem(shape, kw) -> oracle.Problem:
+    return oracle.Problem(shape, model=kw.get("model", "two"), method=kw.get("method", "eb"),
+                          tv=kw.get("tv", "iso"), nlabels=kw.get("nlabels", 2),
+                          alpha=kw.get("alpha", 0.5), c=kw.get("c", 0.0), relax=kw.get("relax", 0.0),
+                          sigma=kw.get("sigma", 0.0), tau=kw.get("tau", 0.0))
+
+
+def gpu_fields(s) -> dict:
+    out = {f: s.read(f).double().cpu().numpy() for f in ("u", "q", "ps", "p")}
+    out["q"] = out["q"].reshape((s.L, s.ndim) + s.shape)
+    out["ps"] = out["ps"].reshape(s.shape)
+    if s.params.method == 2:
+        for f in ("zq", "zs", "zp"):
+            out[f] = s.read(f).double().cpu().numpy()
+        out["zq"] = out["zq"].reshape((s.L, s.ndim) + s.shape)
+        out["zs"] = out["zs"].reshape(s.shape)
+    return out
+
+
+def label_disagreement(u_gpu, u_or, model) -> float:
+    if model == "two":
+        a, b = u_gpu[0] > 0.5, u_or[0] > 0.5
+    else:
+        a, b = np.argmax(u_gpu, 0), np.argmax(u_or, 0)
+    return float(np.mean(a != b))
+
+
+def compare_run(caps, iters, **kw):
+    """Run `iters` iterations on both sides from the initial point; return
+    (max |u - u_oracle|, label disagreement, gpu fields, oracle state)."""
+    shape = caps.shape[1:]
+    s = gpu_solver(caps, **kw)
+    s.step(iters)
+    torch.cuda.synchronize()
+    g = gpu_fields(s)
+    pr = oracle_problem(shape, kw)
+    st = oracle.init_state(pr, caps.astype(np.float32).astype(np.float64))
+    oracle.step(pr, caps.astype(np.float32).astype(np.float64), st, iters)
+    du = float(np.max(np.abs(g["u"] - st.u)))
+    dis = label_disagreement(g["u"], st.u, kw.get("model", "two"))
+    s.close()
+    return du, dis, g, st

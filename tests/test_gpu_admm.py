@@ -1,0 +1,229 @@
+"""GPU parity of the rpADMM sweeps (rpADMMI = fg, rpADMMII = eb) against the
+FP64 oracle, through the C ABI.
+
+Bar (FP32 storage): after the same number of iterations from the same initial
+point, max |u - u_oracle| <= 1e-4 and thresholded-label disagreement <= 0.1 %.
+Fused and unfused passes, and every tile height, must agree bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2004_11227_amd import synth
+
+from _gpu import banner, compare_run, gpu_fields, gpu_solver, need_gpu, oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL_U = 1e-4
+TOL_LAB = 1e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.mark.parametrize("method", ["fg", "eb"])
+@pytest.mark.parametrize("variant", ["fused", "unfused"])
+def test_config0_two_label(method, variant):
+    """128x128 ellipses, alpha 0.5, relaxation 1.5, 300 iterations."""
+    banner(f"c0 two-label {method} {variant}")
+    inp = synth.config_inputs("c0")
+    du, dis, _, _ = compare_run(inp["caps"], 300, model="two", method=method, relax=1.5,
+                                alpha=0.5, variant=variant)
+    print(f"max|du|={du:.3e} label disagreement={dis:.2e}")
+    assert du <= TOL_U and dis <= TOL_LAB
+
+
+@pytest.mark.parametrize("shape", [(77, 131), (1, 200), (150, 1), (65, 64), (64, 65), (3, 3), (1, 1)])
+@pytest.mark.parametrize("tv", ["iso", "aniso"])
+def test_ragged_shapes(shape, tv):
+    banner(f"ragged {shape} {tv}")
+    rng = np.random.default_rng(sum(shape))
+    caps = synth.two_label_caps(rng.uniform(0, 1, size=shape))
+    du, dis, _, _ = compare_run(caps, 120, model="two", method="eb", relax=1.5, alpha=0.3, tv=tv)
+    assert du <= TOL_U and dis <= TOL_LAB
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 8])
+@pytest.mark.parametrize("method", ["fg", "eb"])
+def test_potts_2d(n, method):
+    banner(f"potts n={n} {method}")
+    img, _ = synth.voronoi_image(96, 130, n, 0.15, 2000 + n, ncells=16)
+    caps = synth.potts_caps(img, n)
+    du, dis, _, _ = compare_run(caps, 200, model="potts", nlabels=n, method=method, alpha=0.3)
+    print(f"max|du|={du:.3e} label disagreement={dis:.2e}")
+    assert du <= TOL_U and dis <= TOL_LAB
+
+
+@pytest.mark.parametrize("model,n", [("two", 2), ("potts", 3)])
+def test_3d_unfused(model, n):
+    banner(f"3d unfused {model} n={n}")
+    vol = synth.ellipsoid_volume(20, 22, 37, 4, 0.1, 3001)
+    caps = synth.two_label_caps(vol) if model == "two" else synth.potts_caps(vol, n)
+    du, dis, _, _ = compare_run(caps, 100, model=model, nlabels=n, method="eb", relax=1.5,
+                                alpha=0.4, variant="unfused")
+    assert du <= TOL_U and dis <= TOL_LAB
+
+
+def _bits(g):
+    return {k: v.copy() for k, v in g.items()}
+
+
+@pytest.mark.parametrize("model,n,storage", [("two", 2, "f32"), ("two", 2, "bf16"),
+                                             ("potts", 4, "f32"), ("potts", 8, "bf16")])
+def test_fused_unfused_tiles_bitwise(model, n, storage):
+    banner(f"bitwise fused/unfused/tiles {model} n={n} {storage}")
+    if model == "two":
+        caps = synth.config_inputs("c0", size=(70, 150))["caps"]
+    else:
+        img, _ = synth.voronoi_image(70, 150, n, 0.15, 7, ncells=12)
+        caps = synth.potts_caps(img, n)
+    ref = None
+    for variant, tr in [("unfused", 0), ("fused", 8), ("fused", 16), ("fused", 32)]:
+        s = gpu_solver(caps, model=model, nlabels=n, method="eb", relax=1.5, alpha=0.4,
+                       storage=storage, variant=variant, tile_rows=tr)
+        s.step(37)
+        torch.cuda.synchronize()
+        g = gpu_fields(s)
+        s.close()
+        if ref is None:
+            ref = g
+            continue
+        for f in ref:
+            assert np.array_equal(ref[f], g[f]), f"{variant} tile {tr} differs in {f}"
+
+
+def test_one_step_full_size_random_state():
+    """2048x2048 (the two-label benchmark size), one iteration from a seeded
+    random admissible state written through the ABI, all fields compared."""
+    banner("one step 2048^2 random state")
+    inp = synth.config_inputs("c1")
+    caps = inp["caps"].astype(np.float32).astype(np.float64)
+    shape = caps.shape[1:]
+    rs = synth.random_state(shape, 2, "two", 0.5, caps, seed=99)
+    f32 = {k: v.astype(np.float32).astype(np.float64) for k, v in rs.items()}
+    for method in ("fg", "eb"):
+        s = gpu_solver(caps, model="two", method=method, relax=1.5, alpha=0.5)
+        for f in ("u", "q", "ps", "p"):
+            s.write(f, torch.from_numpy(f32[f].astype(np.float32)))
+        s.step(1)
+        g = gpu_fields(s)
+        s.close()
+        pr = oracle_problem(shape, dict(model="two", method=method, relax=1.5, alpha=0.5))
+        st = oracle.state_from_arrays(pr, f32["u"], f32["q"], f32["ps"], f32["p"])
+        oracle.step(pr, caps, st, 1)
+        for f in ("u", "q", "ps", "p"):
+            err = np.max(np.abs(g[f] - getattr(st, f)))
+            assert err < 2e-5, (method, f, err)
+
+
+def test_full_size_100_iterations():
+    """2048x2048 config, 100 iterations of rpADMMII with relaxation 1.5."""
+    banner("c1 2048^2 100 its")
+    inp = synth.config_inputs("c1")
+    du, dis, _, _ = compare_run(inp["caps"], 100, model="two", method="eb", relax=1.5, alpha=0.5)
+    print(f"max|du|={du:.3e} label disagreement={dis:.2e}")
+    assert du <= TOL_U and dis <= TOL_LAB
+
+
+def test_config1_generator_512_full_500_iterations():
+    banner("c1 generator 512^2 500 its")
+    inp = synth.config_inputs("c1", size=(512, 512))
+    du, dis, _, _ = compare_run(inp["caps"], 500, model="two", method="eb", relax=1.5, alpha=0.5)
+    print(f"max|du|={du:.3e} label disagreement={dis:.2e}")
+    assert du <= TOL_U and dis <= TOL_LAB
+
+
+@pytest.mark.parametrize("model,n", [("two", 2), ("potts", 3), ("potts", 8)])
+def test_gap_matches_oracle_on_random_state(model, n):
+    banner(f"gap on random state {model} n={n}")
+    shape = (57, 91)
+    rng = np.random.default_rng(5)
+    img = rng.uniform(0, 1, size=shape)
+    caps = synth.two_label_caps(img) if model == "two" else synth.potts_caps(img, n)
+    caps = caps.astype(np.float32).astype(np.float64)
+    rs = synth.random_state(shape, n, model, 0.4, caps, seed=17)
+    f32 = {k: v.astype(np.float32).astype(np.float64) for k, v in rs.items()}
+    for tv in ("iso", "aniso"):
+        s = gpu_solver(caps, model=model, nlabels=n, alpha=0.4, tv=tv)
+        for f in ("u", "q", "ps", "p"):
+            s.write(f, torch.from_numpy(f32[f].astype(np.float32)))
+        g = s.gap()
+        s.close()
+        pr = oracle_problem(shape, dict(model=model, nlabels=n, alpha=0.4, tv=tv))
+        e = oracle.energy(pr, caps, oracle.state_from_arrays(pr, f32["u"], f32["q"], f32["ps"], f32["p"]))
+        for key in ("primal", "dual", "flow"):
+            assert abs(g[key] - e[key]) <= 1e-9 * max(1.0, abs(e[key])), (tv, key, g[key], e[key])
+        assert abs(g["resid_rms"] - e["resid_rms"]) <= 1e-9 * max(1.0, e["resid_rms"])
+
+
+@pytest.mark.parametrize("variant", ["fused", "unfused"])
+def test_solve_stops_at_checked_iterate(variant):
+    """solve() stops at the first multiple of check_every whose gap <= tol and
+    leaves the state at that iterate."""
+    banner(f"solve stop {variant}")
+    inp = synth.config_inputs("c0", size=(64, 96))
+    caps = inp["caps"].astype(np.float32).astype(np.float64)
+    kw = dict(model="two", method="eb", relax=1.5, alpha=0.5, tol=1e-3, max_iter=2000,
+              check_every=10, variant=variant)
+    s = gpu_solver(caps, **kw)
+    res = s.solve()
+    assert res["status"] == 0 and res["iter"] % 10 == 0 and res["rel_gap"] <= 1e-3
+    k = res["iter"]
+    g = gpu_fields(s)
+    assert s.iter == k
+    s.close()
+    pr = oracle_problem(caps.shape[1:], kw)
+    st, hist = oracle.solve(pr, caps, 2000, check_every=10, tol=1e-3)
+    ks = [kk for kk, _ in hist]
+    assert abs(ks[-1] - k) <= 10          # same stop up to one check of FP32 drift
+    st_k = oracle.init_state(pr, caps)
+    oracle.step(pr, caps, st_k, k)
+    assert np.max(np.abs(g["u"] - st_k.u)) <= TOL_U
+    e = oracle.energy(pr, caps, st_k)
+    assert abs(res["rel_gap"] - e["rel_gap"]) < 1e-5
+
+
+def test_solve_cap_and_zero_iterations():
+    banner("solve cap")
+    caps = synth.config_inputs("c0", size=(40, 40))["caps"]
+    s = gpu_solver(caps, model="two", method="fg", alpha=0.5, tol=0.0, max_iter=25, check_every=10)
+    res = s.solve()
+    assert res["status"] == 1 and res["iter"] == 25 and s.iter == 25
+    s.close()
+    s = gpu_solver(caps, model="two", method="fg", alpha=0.5, tol=0.0, max_iter=0)
+    res = s.solve()
+    assert res["status"] == 1 and res["iter"] == 0
+    s.close()
+
+
+def test_invalid_parameters_rejected():
+    caps = torch.ones((2, 8, 8), device="cuda")
+    from paper_2004_11227_amd import maxflow as mfx
+    for kw in [dict(alpha=-1.0), dict(relax=2.5), dict(a=3.0), dict(method="fg", relax=1.7),
+               dict(model="potts", nlabels=5), dict(tile_rows=12)]:
+        with pytest.raises(mfx.MaxflowError):
+            mfx.Solver(caps if kw.get("model") != "potts" else torch.ones((5, 8, 8), device="cuda"), **kw)
+
+
+def test_export_import_resume_bitwise():
+    banner("checkpoint resume")
+    caps = synth.config_inputs("c0", size=(50, 70))["caps"]
+    kw = dict(model="two", method="eb", relax=1.5, alpha=0.5)
+    a = gpu_solver(caps, **kw)
+    a.step(40)
+    ga = gpu_fields(a)
+    b = gpu_solver(caps, **kw)
+    b.step(17)
+    blob = b.export_state()
+    c = gpu_solver(caps, **kw)
+    c.import_state(blob, 17)
+    c.step(23)
+    gc = gpu_fields(c)
+    for f in ga:
+        assert np.array_equal(ga[f], gc[f])
+    for s in (a, b, c):
+        s.close()
