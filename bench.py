@@ -1,0 +1,235 @@
+"""Benchmark: two-label continuous max-flow, 2048x2048, rpADMMII, FP32.
+
+One step = one complete solve of the two-label 2048x2048 workload (seeded
+ellipse image, 40 ellipses, noise 0.15, alpha 0.5, relaxation 1.5): initial
+point, 500 iterations of the fused sweep with the FP64 primal-dual gap every
+10 iterations (tolerance 0, so all 500 iterations run) and label extraction.
+Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line.  value = pixels * labels * iterations / second with
+labels = 2 for the two-label model.  `roofline` reports the dominant kernel
+(the fused sweep without the gap reduction): algorithmic bytes per launch
+(48 B per pixel: read u, q_x, q_y, p_s, p_t, C_s, C_t; write u, q_x, q_y,
+p_s, p_t; FP32) divided by its average duration measured with HIP events on
+the solver's stream over a run of back-to-back sweeps.  `cpu_baseline` times
+the FP64 oracle on a bounded sample of the same workload on the host cores.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py --profile-mode    # for rocprofv3: copy calibration + sweeps
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12          # MI355X HBM3E, bytes/s
+WORKLOAD = dict(name="two_label_2d_2048", shape=(2048, 2048), iters=500, method="eb", relax=1.5,
+                alpha=0.5, check_every=10)
+
+
+def alg_bytes(model: str, n: int, ndim: int, storage: str) -> int:
+    """Minimum HBM bytes per pixel and iteration of one fused sweep: read the
+    state (u, q, p_s, p / p_t) and the capacities once, write the state once.
+    u is always FP32; flows and capacities take the storage type."""
+    L = 1 if model == "two" else n
+    ncap = 2 if model == "two" else n
+    e = 4 if storage == "f32" else 2
+    u = 2 * L * 4
+    flows = (L * ndim + 1 + L) * 2 * e
+    return u + flows + ncap * e
+
+
+BYTES_PER_PX = {"f32": alg_bytes("two", 2, 2, "f32"), "bf16": alg_bytes("two", 2, 2, "bf16")}
+KERNEL_SOURCES = ["paper_2004_11227_amd/csrc/k2d.hip", "paper_2004_11227_amd/csrc/mf_device.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused2d_two_label_2048_traffic.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--kernel-sweeps", type=int, default=400)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--profile-mode", action="store_true")
+    return ap.parse_args()
+
+
+def make_solver(torch, maxflow, caps_t, stream, **kw):
+    return maxflow.Solver(caps_t, stream=stream, **kw)
+
+
+def time_sweeps(torch, solver, stream, n):
+    """Average duration of one plain sweep, HIP events on the solver's stream."""
+    solver.step(20)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    solver.step(n)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / n
+
+
+def cpu_baseline(caps64, wl):
+    import oracle
+    shape = wl["shape"]
+    pr = oracle.Problem(shape, model="two", method=wl["method"], relax=wl["relax"], alpha=wl["alpha"])
+    st = oracle.init_state(pr, caps64)
+    oracle.step(pr, caps64, st, 1)
+    iters = 40
+    t0 = time.perf_counter()
+    oracle.step(pr, caps64, st, iters)
+    dt = time.perf_counter() - t0
+    n = shape[0] * shape[1]
+    return {"value": n * 2 * iters / dt, "unit": "pixel*label*iterations/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{iters} of the {wl['iters']} iterations of the {shape[0]}x{shape[1]} two-label "
+                      f"rpADMMII workload, FP64, OpenMP threads={oracle.num_threads()}, {dt:.1f} s"}
+
+
+def traffic_for(launch_bytes):
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    d = json.load(open(TRAFFIC_FILE))
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU; multi-GPU runs are not supported "
+              "(the solver is single-device; see DESIGN.md for the sharding design)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2004_11227_amd import maxflow, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    wl = WORKLOAD
+    inp = synth.config_inputs("c1")
+    caps64 = inp["caps"]
+    caps_t = torch.from_numpy(caps64.astype(np.float32)).to(dev)
+    stream = torch.cuda.Stream(device=dev)
+    H, W = wl["shape"]
+    npx = H * W
+    kw = dict(model="two", method=wl["method"], relax=wl["relax"], alpha=wl["alpha"], tol=0.0,
+              max_iter=wl["iters"], check_every=wl["check_every"])
+
+    if args.profile_mode:
+        # known-size copy for counter calibration, then plain sweeps
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        s = make_solver(torch, maxflow, caps_t, stream, **kw)
+        s.step(30)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_mode": True, "copy_bytes": src.numel() * 4, "sweeps": 30}))
+        return
+
+    s = make_solver(torch, maxflow, caps_t, stream, **kw)
+
+    def one_step():
+        s.reset()
+        res = s.solve()
+        s.labels()
+        return res
+
+    for _ in range(args.warmup):
+        res = one_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = one_step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    assert res["iter"] == wl["iters"], res
+    value = npx * 2 * wl["iters"] / dt
+
+    # dominant kernel: fused sweep, average duration over back-to-back launches
+    t_sweep = time_sweeps(torch, s, stream, args.kernel_sweeps)
+    launch_bytes = BYTES_PER_PX["f32"] * npx
+    achieved = launch_bytes / t_sweep
+    roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM, "traffic": traffic_for(launch_bytes),
+            "kernel": "k_fused2d<two-label,f32,16 rows>", "bytes_per_launch": launch_bytes,
+            "avg_launch_us": t_sweep * 1e6}
+    s.close()
+
+    extra = {}
+    if not args.no_extra:
+        extra = secondary(torch, maxflow, synth, np, dev, stream)
+
+    out = {"metric": "pixel*label ADMM iterations/s (two-label 2048^2, rpADMMII, FP32)",
+           "value": value, "unit": "pixel*label*iterations/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": wl["name"], "shape": list(wl["shape"]), "iterations": wl["iters"],
+                      "method": "rpADMMII", "relax": wl["relax"], "alpha": wl["alpha"],
+                      "gap_every": wl["check_every"], "labels": 2, "parallelism": "single GPU"},
+           "roofline": roof}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(caps64, wl)
+    if extra:
+        out["extra"] = extra
+    print(json.dumps(out), flush=True)
+
+
+def secondary(torch, maxflow, synth, np, dev, stream):
+    """Per-sweep bandwidth of other rows of the hot path (not the headline value)."""
+    res = {}
+
+    def sweep_rate(name, caps, nbytes_px, iters=200, **kw):
+        t = torch.from_numpy(caps.astype(np.float32)).to(dev)
+        s = maxflow.Solver(t, stream=stream, **kw)
+        dt = time_sweeps(torch, s, stream, iters)
+        npx = int(np.prod(caps.shape[1:]))
+        L = 2 if kw.get("model", "two") == "two" else kw["nlabels"]
+        res[name] = {"us_per_iter": dt * 1e6, "px_label_it_per_s": npx * L / dt,
+                     "alg_GBps": nbytes_px * npx / dt / 1e9, "frac_hbm": nbytes_px * npx / dt / PEAK_HBM}
+        s.close()
+        del t
+
+    c1 = synth.config_inputs("c1")["caps"]
+    b2 = alg_bytes("two", 2, 2, "f32")
+    sweep_rate("two_2048_unfused_f32", c1, b2, model="two", method="eb", relax=1.5, variant="unfused")
+    sweep_rate("two_2048_fused_bf16", c1, alg_bytes("two", 2, 2, "bf16"), model="two", method="eb",
+               relax=1.5, storage="bf16")
+    sweep_rate("two_2048_pdrq_f32", c1, b2, model="two", method="dr")
+    big = synth.config_inputs("c1", size=(4096, 4096))["caps"]
+    sweep_rate("two_4096_fused_f32", big, b2, iters=100, model="two", method="eb", relax=1.5)
+    del big
+    for n in (4, 8):
+        img, _ = synth.voronoi_image(1024, 1024, n, 0.15, 2000)
+        caps = synth.potts_caps(img, n)
+        for stg in ("f32", "bf16"):
+            sweep_rate(f"potts{n}_1024_fused_{stg}", caps, alg_bytes("potts", n, 2, stg),
+                       model="potts", nlabels=n, method="eb", alpha=0.3, storage=stg)
+    vol = synth.config_inputs("c3", size=(128, 128, 128))["caps"]
+    sweep_rate("two_3d_128_unfused_f32", vol, alg_bytes("two", 2, 3, "f32"), model="two", method="eb",
+               relax=1.5, alpha=0.4, variant="unfused")
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -228,7 +228,7 @@ hipError_t admm_sweep(mf_solver* s, int64_t k, bool check, bool write, const int
   d.out = s->st[(k + 1) & 1];
   d.wbuf = s->wbuf;
   d.k = coef_of(s->r);
-  d.acc = s->ctrl->acc;
+  d.acc = &s->ctrl->acc[0][0];
   d.done = done;
   if (s->r.p.variant == MF_UNFUSED) return launch_unfused(d, s->stream);
   return launch_fused(d, s->stream);
@@ -270,7 +270,7 @@ hipError_t gap_of(mf_solver* s, int64_t k, const int* done) {
   } else {
     d.st = s->st[k & 1];
   }
-  d.acc = s->ctrl->acc;
+  d.acc = &s->ctrl->acc[0][0];
   d.done = done;
   return launch_gap(d, s->stream);
 }

@@ -65,38 +65,60 @@ __device__ __forceinline__ void gap_two_px(double (&g)[5], float u0f, float uxf,
   g[4] += (double)ps;
 }
 
-template <int NL, bool TWO, typename TS, bool CHECK, int TY>
+// Tile of 64 x TY outputs, 256 threads (1-D block).  Owner mapping: thread t
+// owns V consecutive columns c0 = (t % (64/V)) * V of rows t / (64/V) + j *
+// (4V), j < RPT, so every interior global access is one V-wide vector
+// access per lane (16 B for FP32 and V = 4).  LDS column c of the tile is
+// stored at index c + 4 so those groups stay 16-byte aligned.
+template <int NL, bool TWO, typename TS, bool CHECK, int TY, bool VEC>
 __global__ __launch_bounds__(256) void k_fused2d(const K2<TS> A) {
-  constexpr int TX = 64, BY = 4, RY = TY / BY;
-  constexpr int SW = TX + 4;   // cols -2 .. TX+1
-  constexpr int SH = TY + 3;   // rows -2 .. TY
-  __shared__ float sqx[SH][SW];
-  __shared__ float sqy[SH][SW];
-  __shared__ float sw[SH][SW];
-  __shared__ float su[CHECK ? SH : 1][CHECK ? SW : 1];
+  constexpr int TX = 64;
+  constexpr int V = TY >= 16 ? 4 : 2;
+  constexpr int TPR = TX / V;        // threads per tile row
+  constexpr int RSTEP = 256 / TPR;   // tile rows covered by one pass of the block
+  constexpr int RPT = TY / RSTEP;    // rows per thread
+  constexpr int OX = 4;              // LDS column offset
+  constexpr int SW = TX + 8;         // cols -4 .. TX+3
+  constexpr int SH = TY + 3;         // rows -2 .. TY
+  __shared__ __align__(16) float sqx[SH][SW];
+  __shared__ __align__(16) float sqy[SH][SW];
+  __shared__ __align__(16) float sw[SH][SW];
+  __shared__ __align__(16) float su[CHECK ? SH : 1][CHECK ? SW : 1];
   __shared__ double sred[4 * 5];
 
   if (A.done && *A.done) return;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % A.tiles_x) * TX;
   const int y0 = (tile / A.tiles_x) * TY;
-  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
+  const int tid = threadIdx.x;
   const int W = A.W, H = A.H;
   const long long P = A.P;
-  const int gx = x0 + tx;
-  const bool colin = gx < W;
+  const int c0 = (tid % TPR) * V;
+  const int rr0 = tid / TPR;
+  const int gx0 = x0 + c0;
+  const int nvx = W - gx0 < 0 ? 0 : (W - gx0 > V ? V : W - gx0);
+  constexpr bool vec = VEC;   // W % V == 0: interior groups are whole vectors
   const Coef k = A.k;
 
-  float t[RY][NL];
-  float ps[RY], sumd[RY], sumr[RY];
+  float t[RPT][NL][V];
+  float ps[RPT][V], sumd[RPT][V], sumr[RPT][V];
+  float capt[RPT][V], caps[RPT][V];
   double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int j = 0; j < RY; j++) {
-    const int gy = y0 + ty + BY * j;
-    const bool in = colin && gy < H;
-    ps[j] = in ? ld(A.ps_in, (long long)gy * W + gx) : 0.f;
-    sumd[j] = 0.f;
-    sumr[j] = 0.f;
+  for (int j = 0; j < RPT; j++) {
+    const int gy = y0 + rr0 + RSTEP * j;
+    const int nv = gy < H ? nvx : 0;
+    const long long idx = (long long)gy * W + gx0;
+    ldg<V>(A.ps_in, idx, nv, vec, ps[j]);
+    if (TWO) {
+      ldg<V>(A.cap, idx, nv, vec, caps[j]);
+      ldg<V>(A.cap + P, idx, nv, vec, capt[j]);
+    }
+#pragma unroll
+    for (int e = 0; e < V; e++) {
+      sumd[j][e] = 0.f;
+      sumr[j][e] = 0.f;
+    }
   }
 
 #pragma unroll
@@ -105,20 +127,26 @@ __global__ __launch_bounds__(256) void k_fused2d(const K2<TS> A) {
     const TS* qy_in = qx_in + P;
     const float* u_in = A.u_in + (long long)l * P;
     const TS* p_in = A.p_in + (long long)l * P;
-    float ul[RY], pl[RY];
+    float ul[RPT][V], pl[RPT][V];
     // ---- stage q^k and v = (p - p_s) - u/c: interior by the owning threads
 #pragma unroll
-    for (int j = 0; j < RY; j++) {
-      const int r = ty + BY * j;
+    for (int j = 0; j < RPT; j++) {
+      const int r = rr0 + RSTEP * j;
       const int gy = y0 + r;
-      const bool in = colin && gy < H;
-      const long long idx = (long long)gy * W + gx;
-      sqx[r + 2][tx + 2] = in ? ld(qx_in, idx) : 0.f;
-      sqy[r + 2][tx + 2] = in ? ld(qy_in, idx) : 0.f;
-      ul[j] = in ? u_in[idx] : 0.f;
-      pl[j] = in ? ld(p_in, idx) : 0.f;
-      sw[r + 2][tx + 2] = vterm(pl[j], ps[j], ul[j], k.inv_c);
-      if (CHECK) su[r + 2][tx + 2] = ul[j];
+      const int nv = gy < H ? nvx : 0;
+      const long long idx = (long long)gy * W + gx0;
+      float qxv[V], qyv[V];
+      ldg<V>(qx_in, idx, nv, vec, qxv);
+      ldg<V>(qy_in, idx, nv, vec, qyv);
+      ldg<V>(u_in, idx, nv, vec, ul[j]);
+      ldg<V>(p_in, idx, nv, vec, pl[j]);
+#pragma unroll
+      for (int e = 0; e < V; e++) {
+        sqx[r + 2][c0 + OX + e] = qxv[e];
+        sqy[r + 2][c0 + OX + e] = qyv[e];
+        sw[r + 2][c0 + OX + e] = vterm(pl[j][e], ps[j][e], ul[j][e], k.inv_c);
+        if (CHECK) su[r + 2][c0 + OX + e] = ul[j][e];
+      }
     }
     // q halo: rows {-2,-1,TY} x cols -2..TX, then cols {-2,-1,TX} x rows 0..TY-1
     for (int h = tid; h < 3 * (TX + 3) + 3 * TY; h += 256) {
@@ -136,8 +164,8 @@ __global__ __launch_bounds__(256) void k_fused2d(const K2<TS> A) {
       const int hx = x0 + c, hy = y0 + r;
       const bool in = hx >= 0 && hx < W && hy >= 0 && hy < H;
       const long long idx = (long long)hy * W + hx;
-      sqx[r + 2][c + 2] = in ? ld(qx_in, idx) : 0.f;
-      sqy[r + 2][c + 2] = in ? ld(qy_in, idx) : 0.f;
+      sqx[r + 2][c + OX] = in ? ld(qx_in, idx) : 0.f;
+      sqy[r + 2][c + OX] = in ? ld(qy_in, idx) : 0.f;
     }
     // v halo: rows {-1,TY} x cols -1..TX, then cols {-1,TX} x rows 0..TY-1
     for (int h = tid; h < 2 * (TX + 2) + 2 * TY; h += 256) {
@@ -156,23 +184,27 @@ __global__ __launch_bounds__(256) void k_fused2d(const K2<TS> A) {
       const float uu = in ? u_in[idx] : 0.f;
       const float pp = in ? ld(p_in, idx) : 0.f;
       const float ss = in ? ld(A.ps_in, idx) : 0.f;
-      sw[r + 2][c + 2] = vterm(pp, ss, uu, k.inv_c);
-      if (CHECK) su[r + 2][c + 2] = uu;
+      sw[r + 2][c + OX] = vterm(pp, ss, uu, k.inv_c);
+      if (CHECK) su[r + 2][c + OX] = uu;
     }
     __syncthreads();
     // ---- gap of the input iterate (two-label; q^k is still intact in LDS)
     if (CHECK) {
 #pragma unroll
-      for (int j = 0; j < RY; j++) {
-        const int r = ty + BY * j;
+      for (int j = 0; j < RPT; j++) {
+        const int r = rr0 + RSTEP * j;
         const int gy = y0 + r;
-        if (colin && gy < H) {
-          const long long idx = (long long)gy * W + gx;
-          const double dq =
-              (((gx + 1 < W) ? (double)sqx[r + 2][tx + 2] : 0.0) - ((gx > 0) ? (double)sqx[r + 2][tx + 1] : 0.0)) +
-              (((gy + 1 < H) ? (double)sqy[r + 2][tx + 2] : 0.0) - ((gy > 0) ? (double)sqy[r + 1][tx + 2] : 0.0));
-          gap_two_px(g, su[r + 2][tx + 2], su[r + 2][tx + 3], su[r + 3][tx + 2], gx + 1 < W,
-                     gy + 1 < H, dq, ld(A.cap, idx), ld(A.cap + P, idx), ps[j], pl[j], A.iso);
+        const int nv = gy < H ? nvx : 0;
+#pragma unroll
+        for (int e = 0; e < V; e++) {
+          if (e < nv) {
+            const int gx = gx0 + e, c = c0 + OX + e;
+            const double dq =
+                (((gx + 1 < W) ? (double)sqx[r + 2][c] : 0.0) - ((gx > 0) ? (double)sqx[r + 2][c - 1] : 0.0)) +
+                (((gy + 1 < H) ? (double)sqy[r + 2][c] : 0.0) - ((gy > 0) ? (double)sqy[r + 1][c] : 0.0));
+            gap_two_px(g, su[r + 2][c], su[r + 2][c + 1], su[r + 3][c], gx + 1 < W, gy + 1 < H, dq,
+                       caps[j][e], capt[j][e], ps[j][e], pl[j][e], A.iso);
+          }
         }
       }
     }
@@ -180,45 +212,55 @@ __global__ __launch_bounds__(256) void k_fused2d(const K2<TS> A) {
     for (int h = tid; h < (TY + 2) * (TX + 2); h += 256) {
       const int r = h / (TX + 2) - 1, c = h % (TX + 2) - 1;
       const int hx = x0 + c, hy = y0 + r;
-      const float d = div2(sqx[r + 2][c + 2], sqx[r + 2][c + 1], sqy[r + 2][c + 2],
-                           sqy[r + 1][c + 2], hx + 1 < W, hx > 0, hy + 1 < H, hy > 0);
-      sw[r + 2][c + 2] = wterm(d, sw[r + 2][c + 2]);
+      const float d = div2(sqx[r + 2][c + OX], sqx[r + 2][c + OX - 1], sqy[r + 2][c + OX],
+                           sqy[r + 1][c + OX], hx + 1 < W, hx > 0, hy + 1 < H, hy > 0);
+      sw[r + 2][c + OX] = wterm(d, sw[r + 2][c + OX]);
     }
     __syncthreads();
     // ---- q^{k+1} = P_alpha(q^k + grad(w)/a) on rows -1..TY-1, cols -1..TX-1 (in place)
     for (int h = tid; h < (TY + 1) * (TX + 1); h += 256) {
       const int r = h / (TX + 1) - 1, c = h % (TX + 1) - 1;
       const int hx = x0 + c, hy = y0 + r;
-      const float w0 = sw[r + 2][c + 2];
-      float qx = qstep(sqx[r + 2][c + 2], sw[r + 2][c + 3], w0, hx + 1 < W, k.inv_a);
-      float qy = qstep(sqy[r + 2][c + 2], sw[r + 3][c + 2], w0, hy + 1 < H, k.inv_a);
+      const float w0 = sw[r + 2][c + OX];
+      float qx = qstep(sqx[r + 2][c + OX], sw[r + 2][c + OX + 1], w0, hx + 1 < W, k.inv_a);
+      float qy = qstep(sqy[r + 2][c + OX], sw[r + 3][c + OX], w0, hy + 1 < H, k.inv_a);
       proj(qx, qy, k.alpha, A.iso);
-      sqx[r + 2][c + 2] = quant<TS>(qx);
-      sqy[r + 2][c + 2] = quant<TS>(qy);
+      sqx[r + 2][c + OX] = quant<TS>(qx);
+      sqy[r + 2][c + OX] = quant<TS>(qy);
     }
     __syncthreads();
-    // ---- interior: d = div q^{k+1}, store q^{k+1}, per-label p and u parts
+    // ---- owned groups: d = div q^{k+1}, store q^{k+1}, per-label p and u parts
     {
       TS* qx_out = A.q_out + (long long)(2 * l) * P;
       TS* qy_out = qx_out + P;
       TS* p_out = A.p_out + (long long)l * P;
       const TS* capl = A.cap + (long long)(TWO ? 1 : l) * P;
 #pragma unroll
-      for (int j = 0; j < RY; j++) {
-        const int r = ty + BY * j;
+      for (int j = 0; j < RPT; j++) {
+        const int r = rr0 + RSTEP * j;
         const int gy = y0 + r;
-        const bool in = colin && gy < H;
-        const long long idx = (long long)gy * W + gx;
-        const float qx = sqx[r + 2][tx + 2], qy = sqy[r + 2][tx + 2];
-        const float d = div2(qx, sqx[r + 2][tx + 1], qy, sqy[r + 1][tx + 2], gx + 1 < W, gx > 0,
-                             gy + 1 < H, gy > 0);
-        const float C = in ? ld(capl, idx) : 0.f;
-        float pn;
-        label_update(k, ul[j], pl[j], ps[j], d, C, pn, t[j][l], sumd[j], sumr[j]);
-        if (A.write && in) {
-          st(qx_out, idx, qx);
-          st(qy_out, idx, qy);
-          st(p_out, idx, pn);
+        const int nv = gy < H ? nvx : 0;
+        const long long idx = (long long)gy * W + gx0;
+        float C[V], qxv[V], qyv[V], pn[V];
+        if (TWO) {
+#pragma unroll
+          for (int e = 0; e < V; e++) C[e] = capt[j][e];
+        } else {
+          ldg<V>(capl, idx, nv, vec, C);
+        }
+#pragma unroll
+        for (int e = 0; e < V; e++) {
+          const int gx = gx0 + e, c = c0 + OX + e;
+          qxv[e] = sqx[r + 2][c];
+          qyv[e] = sqy[r + 2][c];
+          const float d = div2(qxv[e], sqx[r + 2][c - 1], qyv[e], sqy[r + 1][c], gx + 1 < W, gx > 0,
+                               gy + 1 < H, gy > 0);
+          label_update(k, ul[j][e], pl[j][e], ps[j][e], d, C[e], pn[e], t[j][l][e], sumd[j][e], sumr[j][e]);
+        }
+        if (A.write) {
+          stg<V>(qx_out, idx, nv, vec, qxv);
+          stg<V>(qy_out, idx, nv, vec, qyv);
+          stg<V>(p_out, idx, nv, vec, pn);
         }
       }
     }
@@ -226,16 +268,22 @@ __global__ __launch_bounds__(256) void k_fused2d(const K2<TS> A) {
   }
   // ---- p_s and u
 #pragma unroll
-  for (int j = 0; j < RY; j++) {
-    const int gy = y0 + ty + BY * j;
-    const bool in = colin && gy < H;
-    const long long idx = (long long)gy * W + gx;
-    const float Cs = (TWO && in) ? ld(A.cap, idx) : 0.f;
-    const float psn = finish_ps(k, ps[j], sumd[j], sumr[j], TWO, Cs);
-    if (A.write && in) {
-      st(A.ps_out, idx, psn);
+  for (int j = 0; j < RPT; j++) {
+    const int gy = y0 + rr0 + RSTEP * j;
+    const int nv = gy < H ? nvx : 0;
+    const long long idx = (long long)gy * W + gx0;
+    float psn[V];
 #pragma unroll
-      for (int l = 0; l < NL; l++) A.u_out[(long long)l * P + idx] = finish_u(k, t[j][l], psn);
+    for (int e = 0; e < V; e++) psn[e] = finish_ps(k, ps[j][e], sumd[j][e], sumr[j][e], TWO, TWO ? caps[j][e] : 0.f);
+    if (A.write) {
+      stg<V>(A.ps_out, idx, nv, vec, psn);
+#pragma unroll
+      for (int l = 0; l < NL; l++) {
+        float un[V];
+#pragma unroll
+        for (int e = 0; e < V; e++) un[e] = finish_u(k, t[j][l][e], psn[e]);
+        stg<V>(A.u_out + (long long)l * P, idx, nv, vec, un);
+      }
     }
   }
   if (CHECK) block_accumulate<5, 4>(g, A.acc, sred);
@@ -267,22 +315,24 @@ static K2<TS> make_k2(const SweepDesc& d) {
   return a;
 }
 
+template <int NL, bool TWO, typename TS, bool CHECK, int TY>
+static hipError_t fused_launch(const K2<TS>& a, int H, hipStream_t s) {
+  constexpr int V = TY >= 16 ? 4 : 2;
+  const int nb = a.tiles_x * ((H + TY - 1) / TY);
+  if (a.W % V == 0)
+    hipLaunchKernelGGL((k_fused2d<NL, TWO, TS, CHECK, TY, true>), dim3(nb), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_fused2d<NL, TWO, TS, CHECK, TY, false>), dim3(nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 template <int NL, bool TWO, typename TS, bool CHECK>
 static hipError_t fused_ty(const SweepDesc& d, hipStream_t s) {
   const K2<TS> a = make_k2<TS>(d);
-  const dim3 blk(64, 4);
   const int tr = d.tile_rows;
-  if (tr == 8) {
-    const int nb = a.tiles_x * ((d.g.H + 7) / 8);
-    hipLaunchKernelGGL((k_fused2d<NL, TWO, TS, CHECK, 8>), dim3(nb), blk, 0, s, a);
-  } else if (tr == 32 && NL <= 4) {
-    const int nb = a.tiles_x * ((d.g.H + 31) / 32);
-    hipLaunchKernelGGL((k_fused2d<NL, TWO, TS, CHECK, (NL <= 4 ? 32 : 8)>), dim3(nb), blk, 0, s, a);
-  } else {
-    const int nb = a.tiles_x * ((d.g.H + 15) / 16);
-    hipLaunchKernelGGL((k_fused2d<NL, TWO, TS, CHECK, 16>), dim3(nb), blk, 0, s, a);
-  }
-  return hipGetLastError();
+  if (tr == 8) return fused_launch<NL, TWO, TS, CHECK, 8>(a, d.g.H, s);
+  if (tr == 32 && NL <= 4) return fused_launch<NL, TWO, TS, CHECK, (NL <= 4 ? 32 : 16)>(a, d.g.H, s);
+  return fused_launch<NL, TWO, TS, CHECK, 16>(a, d.g.H, s);
 }
 
 template <int NL, bool TWO, typename TS>

@@ -246,10 +246,8 @@ hipError_t launch_labels(const Geom& g, int nl, bool two, const float* u, int32_
 // ------------------------------------------------------------------ control
 __global__ void k_ctrl_reset(Ctrl* c) {
   const int t = threadIdx.x;
-  if (t < 8) {
-    c->acc[t] = 0.0;
-    c->last[t] = 0.0;
-  }
+  for (int j = t; j < kAccSlots * 8; j += blockDim.x) c->acc[j / 8][j % 8] = 0.0;
+  if (t < 8) c->last[t] = 0.0;
   if (t == 0) {
     c->iter = 0;
     c->done = 0;
@@ -268,21 +266,30 @@ hipError_t launch_ctrl_reset(Ctrl* c, hipStream_t s) {
 // Status codes follow mf_status: 0 converged, 1 cap reached, -4 diverged.
 __global__ void k_bookkeep(Ctrl* c, long long k, double alpha, double tol, long long nres, int final_check,
                            int decide) {
-  if (threadIdx.x != 0) return;
+  __shared__ double tot[8];
+  const int t = threadIdx.x;
   if (c->done) return;
-  const double P = c->acc[0] + alpha * c->acc[1];
-  const double D = c->acc[2];
+  if (t < 8) {
+    double s = 0.0;
+    for (int j = 0; j < kAccSlots; j++) s += c->acc[j][t];
+    tot[t] = s;
+  }
+  __syncthreads();
+  for (int j = t; j < kAccSlots * 8; j += blockDim.x) c->acc[j / 8][j % 8] = 0.0;
+  if (t != 0) return;
+  const double P = tot[0] + alpha * tot[1];
+  const double D = tot[2];
   const double m = fmax(fmax(fabs(P), fabs(D)), 1e-300);
   const double rel = (P - D) / m;
   c->last[0] = P;
   c->last[1] = D;
   c->last[2] = rel;
-  c->last[3] = sqrt(c->acc[3] / (double)nres);
-  c->last[4] = c->acc[4];
+  c->last[3] = sqrt(tot[3] / (double)nres);
+  c->last[4] = tot[4];
   c->last[5] = (double)k;
   c->checks += 1;
   if (decide) {
-    const bool bad = !isfinite(P) || !isfinite(D) || !isfinite(c->acc[3]);
+    const bool bad = !isfinite(P) || !isfinite(D) || !isfinite(tot[3]);
     if (bad) {
       c->done = 1;
       c->status = -4;
@@ -297,7 +304,6 @@ __global__ void k_bookkeep(Ctrl* c, long long k, double alpha, double tol, long 
       c->iter = k;
     }
   }
-  for (int j = 0; j < 8; j++) c->acc[j] = 0.0;
 }
 
 hipError_t launch_bookkeep(Ctrl* c, long long k, double alpha, double tol, long long nres, int final_check,

@@ -28,6 +28,85 @@ __device__ __forceinline__ bf16_t f2bf(float f) {
 }
 __device__ __forceinline__ void st(float* p, long long i, float v) { p[i] = v; }
 __device__ __forceinline__ void st(bf16_t* p, long long i, float v) { p[i] = f2bf(v); }
+__device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+__device__ __forceinline__ uint32_t bf_pack(float a, float b) {
+  return (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16);
+}
+
+// V consecutive elements starting at p[i] (i a multiple of V, 4*V-byte
+// aligned): one vector memory instruction per lane.
+template <int V>
+__device__ __forceinline__ void ldv(const float* p, long long i, float (&o)[V]) {
+  if constexpr (V == 4) {
+    const float4 t = *reinterpret_cast<const float4*>(p + i);
+    o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w;
+  } else if constexpr (V == 2) {
+    const float2 t = *reinterpret_cast<const float2*>(p + i);
+    o[0] = t.x; o[1] = t.y;
+  } else {
+    o[0] = p[i];
+  }
+}
+template <int V>
+__device__ __forceinline__ void ldv(const bf16_t* p, long long i, float (&o)[V]) {
+  if constexpr (V == 4) {
+    const uint2 t = *reinterpret_cast<const uint2*>(p + i);
+    o[0] = bf_lo(t.x); o[1] = bf_hi(t.x); o[2] = bf_lo(t.y); o[3] = bf_hi(t.y);
+  } else if constexpr (V == 2) {
+    const uint32_t t = *reinterpret_cast<const uint32_t*>(p + i);
+    o[0] = bf_lo(t); o[1] = bf_hi(t);
+  } else {
+    o[0] = ld(p, i);
+  }
+}
+template <int V>
+__device__ __forceinline__ void stv(float* p, long long i, const float (&v)[V]) {
+  if constexpr (V == 4) {
+    *reinterpret_cast<float4*>(p + i) = make_float4(v[0], v[1], v[2], v[3]);
+  } else if constexpr (V == 2) {
+    *reinterpret_cast<float2*>(p + i) = make_float2(v[0], v[1]);
+  } else {
+    p[i] = v[0];
+  }
+}
+template <int V>
+__device__ __forceinline__ void stv(bf16_t* p, long long i, const float (&v)[V]) {
+  if constexpr (V == 4) {
+    *reinterpret_cast<uint2*>(p + i) = make_uint2(bf_pack(v[0], v[1]), bf_pack(v[2], v[3]));
+  } else if constexpr (V == 2) {
+    *reinterpret_cast<uint32_t*>(p + i) = bf_pack(v[0], v[1]);
+  } else {
+    st(p, i, v[0]);
+  }
+}
+// Group of V elements of one row, `nv` of them inside the grid (0..V): a
+// vector access when the whole group is inside and rows are V-aligned
+// (`vec`), element accesses otherwise; elements outside read as 0.
+template <int V, typename T>
+__device__ __forceinline__ void ldg(const T* p, long long i, int nv, bool vec, float (&o)[V]) {
+  if (vec) {  // rows are V-aligned: a group is either fully inside or fully outside
+    if (nv == V) {
+      ldv<V>(p, i, o);
+    } else {
+#pragma unroll
+      for (int e = 0; e < V; e++) o[e] = 0.f;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < V; e++) o[e] = e < nv ? ld(p, i + e) : 0.f;
+  }
+}
+template <int V, typename T>
+__device__ __forceinline__ void stg(T* p, long long i, int nv, bool vec, const float (&v)[V]) {
+  if (vec) {
+    if (nv == V) stv<V>(p, i, v);
+  } else {
+#pragma unroll
+    for (int e = 0; e < V; e++)
+      if (e < nv) st(p, i + e, v[e]);
+  }
+}
 
 // ---------------------------------------------------------------- scalars
 struct Coef {
@@ -138,7 +217,10 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Block-wide sum of NQ doubles, then one atomic per quantity per block.
+// Block-wide sum of NQ doubles, then one hardware FP64 atomic per quantity per
+// block into slot (block id mod 64) of `dst` (rows of 8 doubles), so that
+// thousands of blocks do not serialise on one address; the slots are summed
+// in a fixed order by the bookkeeping kernel.
 template <int NQ, int NWAVES>
 __device__ __forceinline__ void block_accumulate(double (&v)[NQ], double* dst, double* sred) {
   const int lane = threadIdx.x & 63;
@@ -155,7 +237,7 @@ __device__ __forceinline__ void block_accumulate(double (&v)[NQ], double* dst, d
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < NWAVES; w++) s += sred[w * NQ + tid];
-    atomicAdd(dst + tid, s);
+    unsafeAtomicAdd(dst + (blockIdx.x & 63) * 8 + tid, s);
   }
 }
 

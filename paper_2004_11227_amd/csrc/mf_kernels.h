@@ -11,8 +11,10 @@ namespace mf {
 // Device control block of one solve: gap accumulators, the last evaluated
 // gap and the convergence decision.  Written only by the bookkeeping kernel
 // (decision) and by the gap reductions (atomics into acc); sweeps read `done`.
+constexpr int kAccSlots = 64;   // blocks spread their atomics over this many slots
+
 struct Ctrl {
-  double acc[8];     // data, tv, dual, residual^2, flow (FP64 partial sums)
+  double acc[kAccSlots][8];  // per slot: data, tv, dual, residual^2, flow (FP64 partial sums)
   double last[8];    // primal, dual, rel_gap, resid_rms, flow, iter
   long long iter;    // iterate at which the solve stopped
   int done;          // 0 running, 1 stopped
