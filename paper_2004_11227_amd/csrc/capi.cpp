@@ -148,7 +148,8 @@ Layout plan(const Resolved& r) {
   if (dr) off += L.state_bytes;
   // scratch planes: unfused w, or rPDRQ b
   L.wbuf = off;
-  if (dr || r.p.variant == MF_UNFUSED) off = align_up(off + (size_t)r.nl * P * 4, 256);
+  const bool unfused = r.p.variant == MF_UNFUSED || (r.p.ndim == 3 && r.p.model == MF_POTTS);
+  if (dr || unfused) off = align_up(off + (size_t)r.nl * P * 4, 256);
   L.total = off;
   return L;
 }
@@ -209,7 +210,7 @@ Coef coef_of(const Resolved& r) {
 }
 
 bool fused_gap(const mf_solver* s) {
-  return s->r.p.variant == MF_FUSED && s->r.p.model == MF_TWO_LABEL && s->r.g.ndim == 2;
+  return s->r.p.variant == MF_FUSED && s->r.p.model == MF_TWO_LABEL;
 }
 
 // One rpADMM sweep from iterate k (buffer k%2) to k+1.
@@ -230,7 +231,9 @@ hipError_t admm_sweep(mf_solver* s, int64_t k, bool check, bool write, const int
   d.k = coef_of(s->r);
   d.acc = &s->ctrl->acc[0][0];
   d.done = done;
-  if (s->r.p.variant == MF_UNFUSED) return launch_unfused(d, s->stream);
+  // Potts 3-D has no fused pass: it always runs the per-operator kernels
+  if (s->r.p.variant == MF_UNFUSED || (s->r.g.ndim == 3 && s->r.p.model == MF_POTTS))
+    return launch_unfused(d, s->stream);
   return launch_fused(d, s->stream);
 }
 

@@ -1,0 +1,102 @@
+"""Turn rocprofv3 CSV output into the short summaries kept under profiles/.
+
+    python -m paper_2004_11227_amd.profiling KTRACE_DIR FETCH_DIR WRITE_DIR OUT_PREFIX KERNEL_SUBSTR
+        [--copy-bytes N] [--launch-bytes N] [--command "..."]
+
+KTRACE_DIR holds `*_kernel_stats.csv` of a `--kernel-trace --stats` run;
+FETCH_DIR / WRITE_DIR hold `*_counter_collection.csv` of `--pmc FETCH_SIZE` /
+`--pmc WRITE_SIZE` runs of a program that first copies COPY_BYTES with a
+plain copy kernel (the counter calibration) and then runs the kernel of
+interest.  Writes OUT_PREFIX.md (human summary) and OUT_PREFIX_traffic.json
+(per-launch HBM bytes of the kernel of interest, scaled by the copy
+calibration, with the source hash of the kernel it was measured on).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def source_hash(files) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _one(pattern):
+    files = glob.glob(pattern, recursive=True)
+    if not files:
+        raise FileNotFoundError(pattern)
+    return files[0]
+
+
+def kernel_stats(d):
+    rows = list(csv.DictReader(open(_one(os.path.join(d, "**", "*kernel_stats.csv")))))
+    return [(r["Name"], int(r["Calls"]), float(r["AverageNs"]), float(r["Percentage"])) for r in rows]
+
+
+def counters(d):
+    rows = list(csv.DictReader(open(_one(os.path.join(d, "**", "*counter_collection.csv")))))
+    agg = {}
+    for r in rows:
+        agg.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return {k: (len(v), sum(v) / len(v)) for k, v in agg.items()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("ktrace")
+    ap.add_argument("fetch")
+    ap.add_argument("write")
+    ap.add_argument("out")
+    ap.add_argument("kernel")
+    ap.add_argument("--copy-bytes", type=int, default=256 << 20)
+    ap.add_argument("--launch-bytes", type=int, default=0)
+    ap.add_argument("--command", default="")
+    ap.add_argument("--sources", nargs="*", default=[])
+    a = ap.parse_args()
+    ks = kernel_stats(a.ktrace)
+    fe, wr = counters(a.fetch), counters(a.write)
+    copy_k = [k for k in fe if "copyBuffer" in k or "copy" in k.lower()]
+    ck = copy_k[0]
+    exp_kib = a.copy_bytes / 1024.0
+    f_fetch = exp_kib / fe[ck][1]
+    f_write = exp_kib / wr[ck][1]
+    kk = [k for k in fe if a.kernel in k]
+    target = kk[0]
+    fetch_b = fe[target][1] * 1024.0 * f_fetch
+    write_b = wr[target][1] * 1024.0 * f_write
+    lines = [f"# rocprofv3 summary: {a.kernel}", "", f"Command: `{a.command}`", "",
+             "## Kernel trace (--kernel-trace --stats)", "",
+             "| kernel | calls | average us | % time |", "|---|---|---|---|"]
+    for name, calls, avg, pct in ks[:12]:
+        lines.append(f"| `{name[:110]}` | {calls} | {avg / 1e3:.2f} | {pct:.2f} |")
+    lines += ["", "## HBM traffic (--pmc FETCH_SIZE, --pmc WRITE_SIZE; KiB per dispatch)", "",
+              f"Calibration: copy kernel `{ck[:60]}` of {a.copy_bytes} B read + write: "
+              f"FETCH_SIZE {fe[ck][1]:.0f} KiB (factor {f_fetch:.3f}), WRITE_SIZE {wr[ck][1]:.0f} KiB "
+              f"(factor {f_write:.3f}).", "",
+              "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB |", "|---|---|---|---|"]
+    for k in fe:
+        lines.append(f"| `{k[:110]}` | {fe[k][0]} | {fe[k][1]:.1f} | {wr.get(k, (0, 0))[1]:.1f} |")
+    lines += ["", f"Kernel of interest `{target[:100]}`: calibrated traffic per launch "
+              f"{fetch_b / 1e6:.2f} MB read + {write_b / 1e6:.2f} MB written = {(fetch_b + write_b) / 1e6:.2f} MB"]
+    if a.launch_bytes:
+        lines.append(f"(algorithmic {a.launch_bytes / 1e6:.2f} MB per launch; ratio "
+                     f"{(fetch_b + write_b) / a.launch_bytes:.3f})")
+    open(a.out + ".md", "w").write("\n".join(lines) + "\n")
+    json.dump({"kernel": target, "kernel_hash": source_hash(a.sources) if a.sources else None,
+               "bytes_per_launch": fetch_b + write_b, "fetch_bytes": fetch_b, "write_bytes": write_b,
+               "fetch_factor": f_fetch, "write_factor": f_write, "command": a.command},
+              open(a.out + "_traffic.json", "w"), indent=1)
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()

@@ -68,6 +68,60 @@ def test_3d_unfused(model, n):
     assert du <= TOL_U and dis <= TOL_LAB
 
 
+@pytest.mark.parametrize("shape", [(20, 22, 37), (9, 8, 64), (1, 13, 70), (33, 5, 3)])
+@pytest.mark.parametrize("method", ["fg", "eb"])
+def test_3d_fused_two_label(shape, method):
+    banner(f"3d fused {shape} {method}")
+    vol = synth.ellipsoid_volume(*shape, 4, 0.1, 3003)
+    caps = synth.two_label_caps(vol)
+    du, dis, _, _ = compare_run(caps, 100, model="two", method=method, relax=1.5, alpha=0.4)
+    assert du <= TOL_U and dis <= TOL_LAB
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("shape", [(19, 21, 70), (40, 16, 64)])
+def test_3d_fused_equals_unfused_bitwise(storage, shape):
+    banner(f"3d bitwise {shape} {storage}")
+    caps = synth.two_label_caps(synth.ellipsoid_volume(*shape, 5, 0.1, 3004))
+    ref = None
+    for variant in ("unfused", "fused"):
+        s = gpu_solver(caps, model="two", method="eb", relax=1.5, alpha=0.4, storage=storage, variant=variant)
+        s.step(23)
+        torch.cuda.synchronize()
+        g = gpu_fields(s)
+        s.close()
+        if ref is None:
+            ref = g
+        else:
+            for f in ref:
+                assert np.array_equal(ref[f], g[f]), f
+
+
+def test_3d_fused_gap_and_solve():
+    banner("3d fused solve")
+    caps = synth.two_label_caps(synth.ellipsoid_volume(24, 26, 30, 4, 0.1, 3005)).astype(np.float32).astype(np.float64)
+    kw = dict(model="two", method="eb", relax=1.5, alpha=0.4, tol=1e-3, max_iter=3000, check_every=10)
+    s = gpu_solver(caps, **kw)
+    res = s.solve()
+    assert res["status"] == 0 and res["iter"] % 10 == 0
+    g = gpu_fields(s)
+    s.close()
+    pr = oracle_problem(caps.shape[1:], kw)
+    st = oracle.init_state(pr, caps)
+    oracle.step(pr, caps, st, res["iter"])
+    e = oracle.energy(pr, caps, st)
+    assert abs(res["rel_gap"] - e["rel_gap"]) < 1e-5
+    assert np.max(np.abs(g["u"] - st.u)) <= TOL_U
+
+
+def test_potts_3d_fused_request_runs_unfused():
+    banner("potts 3d")
+    vol = synth.ellipsoid_volume(12, 14, 18, 3, 0.1, 3006)
+    caps = synth.potts_caps(vol, 4)
+    du, dis, _, _ = compare_run(caps, 60, model="potts", nlabels=4, method="eb", alpha=0.4)
+    assert du <= TOL_U and dis <= TOL_LAB
+
+
 def _bits(g):
     return {k: v.copy() for k, v in g.items()}
 
