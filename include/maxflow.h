@@ -94,6 +94,12 @@ typedef struct {
   double tol;            /* relative primal-dual gap tolerance for maxflow_solve      */
   int32_t check_every;   /* gap cadence in iterations; 0 -> 10                        */
   int32_t tile_rows;     /* fused 2-D tile height (8, 16 or 32); 0 -> tuned default   */
+  /* Pool only, BF16 storage: a solve whose gap at a check is <= promote_gap,
+   * or that reaches iteration promote_iter, is frozen at that iterate and
+   * continued with FP32 flows (BF16 rounding floors the reachable gap near
+   * 1e-3 for Potts problems).  0 disables either trigger. */
+  double promote_gap;
+  int32_t promote_iter;
 } mf_params;
 
 /* Gap at an iterate.  primal = P(u) at clip(u,0,1) (two-label) or the pointwise
@@ -164,8 +170,67 @@ mf_status maxflow_import_state(mf_solver* s, const void* src, int64_t iter);
 
 mf_status maxflow_destroy(mf_solver* s);
 
-/* Thread-local message describing the last error. */
+/* Thread-local message describing the last error (solver and pool calls). */
 const char* maxflow_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Batched pool (continuous batching of many solves on one device).
+ *
+ * The pool keeps many rpADMM solves resident in one caller-owned device arena
+ * and advances all of them together.  Each solve is cut into tiles; one
+ * persistent kernel per model class walks a device-resident work list of
+ * (solve, tile) items drawn from grids of any size, and every running solve
+ * advances one iteration per super-step with its own iteration counter, gap
+ * cadence and convergence decision (all on the GPU).  `steps_per_advance`
+ * super-steps are captured once into a hipGraph; admission and retirement
+ * edit the device tables between replays, so the graph never changes.  A
+ * solve's iterates are bit-identical alone, in any mix, and through the
+ * single-solve API with the same storage (tiles of 64 x 16 two-label, 64 x 8
+ * Potts).  Supported: methods FG and EB; 2-D two-label and Potts (n = 2, 3,
+ * 4, 8); 3-D two-label; FP32 or BF16 storage.  Convergence follows the same
+ * rule as maxflow_solve (gap at multiples of check_every, tolerance tol, cap
+ * max_iter) and the state stays at the accepted iterate.
+ * ---------------------------------------------------------------------- */
+typedef struct mf_pool mf_pool;
+
+/* Bytes one admitted solve occupies in the arena (capacities + two states);
+ * 0 on invalid or unsupported parameters. */
+size_t mf_pool_footprint(const mf_params* p);
+
+/* Bytes of arena the pool's own device tables take. */
+size_t mf_pool_table_bytes(int32_t max_slots, int32_t max_tiles);
+
+/* `arena`: device, 256-byte aligned, caller-owned, outlives the pool;
+ * `max_slots`: resident solves at most; `max_tiles`: work-list capacity per
+ * class; `hip_stream`: a created (non-default) hipStream_t. */
+mf_status mf_pool_create(void* arena, size_t arena_bytes, int32_t max_slots, int32_t max_tiles,
+                         int32_t steps_per_advance, void* hip_stream, mf_pool** out);
+
+/* Admit one solve: copies `cap` (device, FP32, layout as maxflow_create) into
+ * the arena (converting to BF16 if asked) and sets the initial point.
+ * MF_ENOMEM when the arena, the slot table or the class work list is full
+ * (retry after retiring solves); MF_EINVAL on invalid/unsupported params. */
+mf_status mf_pool_admit(mf_pool* pool, const mf_params* p, const float* cap, int64_t* solve_id);
+
+/* Enqueue steps_per_advance super-steps (one graph replay); asynchronous. */
+mf_status mf_pool_advance(mf_pool* pool);
+
+/* Synchronise and report solves that finished since the last poll: up to
+ * `cap` ids into done_ids and their gaps (iter = accepted iterate, status
+ * MF_OK / MF_ENOTCONV / MF_EDIVERGED) into gaps; *ndone = count. */
+mf_status mf_pool_poll(mf_pool* pool, int64_t* done_ids, mf_gap* gaps, int32_t cap, int32_t* ndone);
+
+/* Copy a solve's u (device FP32, L planes) and/or labels (device int32) and
+ * release its arena block and slot.  Either output may be NULL. */
+mf_status mf_pool_retire(mf_pool* pool, int64_t solve_id, float* u_dst, int32_t* labels_dst);
+
+/* Resident solves, arena bytes in use, and the largest free arena block. */
+mf_status mf_pool_stats(mf_pool* pool, int32_t* active, size_t* bytes_in_use, size_t* largest_free);
+
+/* Number of BF16 -> FP32 promotions performed so far. */
+int64_t mf_pool_promotions(const mf_pool* pool);
+
+mf_status mf_pool_destroy(mf_pool* pool);
 
 #ifdef __cplusplus
 }

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmaxflow.so")
 ARCH = os.environ.get("MAXFLOW_ARCH", "gfx950")
-SOURCES = ["k2d.hip", "k3d.hip", "kuf.hip", "kdr.hip", "kmisc.hip", "capi.cpp"]
+SOURCES = ["k2d.hip", "k3d.hip", "kuf.hip", "kdr.hip", "kmisc.hip", "kpool.hip", "capi.cpp", "pool.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument", "-I", os.path.join(HERE, "..", "include")]

@@ -33,6 +33,14 @@ mf_status fail(mf_status s, const std::string& msg) {
   return s;
 }
 
+}  // namespace
+
+namespace mf {
+void set_error(const std::string& m) { g_err = m; }
+}  // namespace mf
+
+namespace {
+
 #define HIP_TRY(expr)                                                                       \
   do {                                                                                      \
     hipError_t _e = (expr);                                                                 \
@@ -98,6 +106,7 @@ std::string resolve(const mf_params* in, Resolved& r) {
   if (p.check_every < 1) return "check_every must be >= 1";
   if (p.tile_rows == 0) p.tile_rows = two ? 16 : 8;
   if (p.tile_rows != 8 && p.tile_rows != 16 && p.tile_rows != 32) return "tile_rows must be 8, 16 or 32";
+  if (!(p.promote_gap >= 0.0) || p.promote_iter < 0) return "promote_gap and promote_iter must be >= 0";
   r.nl = two ? 1 : p.nlabels;
   r.ncap = two ? 2 : p.nlabels;
   r.g.ndim = p.ndim;
@@ -169,6 +178,20 @@ StateView view(char* base, size_t off, const Resolved& r) {
 }
 
 }  // namespace
+
+namespace mf {
+// Parameter resolution shared with the pool.
+std::string resolve_params(const mf_params* in, mf_params& out, Geom& g, int& nl, int& ncap) {
+  Resolved r;
+  const std::string e = resolve(in, r);
+  if (!e.empty()) return e;
+  out = r.p;
+  g = r.g;
+  nl = r.nl;
+  ncap = r.ncap;
+  return "";
+}
+}  // namespace mf
 
 struct mf_solver {
   Resolved r;

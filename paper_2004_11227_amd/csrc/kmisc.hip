@@ -1,6 +1,6 @@
 // Gap reduction, initial point, labels, field copies and the per-solve
 // bookkeeping kernel.
-#include "mf_kernels.h"
+#include "gap.h"
 
 namespace mf {
 
@@ -12,27 +12,8 @@ hipError_t launch_fused(const SweepDesc& d, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ gap
-template <typename TS>
-struct KG {
-  int W, H, D;
-  long long P, n;
-  const TS* cap;
-  const float* u;
-  const TS* q;
-  const TS* ps;
-  const TS* p;
-  double* acc;
-  const int* done;
-  int iso;
-};
 
-__device__ __forceinline__ double clip01(float v) { return fmin(1.0, fmax(0.0, (double)v)); }
-
-// Per pixel, in FP64: primal data and TV terms at the projected u, the dual
-// term (min(C_s, C_t + div q) or min_i(C_i + div q_i)), the squared
-// conservation residual and p_s.  Relaxed min-cut (eq. seg:chanvese) /
-// relaxed Potts (eq. relaxed-potts) and their max-flow duals (eqs.
-// two-label-mf, potts-mf).
+// Standalone FP64 gap of an iterate (grid-stride over pixels).
 template <int NL, bool TWO, int NDIM, typename TS>
 __global__ __launch_bounds__(256) void k_gap(const KG<TS> A) {
   __shared__ double sred[4 * 5];
@@ -43,62 +24,7 @@ __global__ __launch_bounds__(256) void k_gap(const KG<TS> A) {
     const int x = (int)(idx % A.W);
     const int y = (int)((idx / A.W) % A.H);
     const int z = (int)(idx / sz);
-    const bool hx = x + 1 < A.W, hy = y + 1 < A.H, hz = NDIM == 3 && z + 1 < A.D;
-    const double ps = (double)ld(A.ps, idx);
-    double dq[NL];
-#pragma unroll
-    for (int l = 0; l < NL; l++) {
-      const TS* q = A.q + (long long)(NDIM * l) * A.P;
-      double d = ((hx ? (double)ld(q, idx) : 0.0) - (x > 0 ? (double)ld(q, idx - 1) : 0.0)) +
-                 ((hy ? (double)ld(q + A.P, idx) : 0.0) - (y > 0 ? (double)ld(q + A.P, idx - A.W) : 0.0));
-      if (NDIM == 3)
-        d += (hz ? (double)ld(q + 2 * A.P, idx) : 0.0) - (z > 0 ? (double)ld(q + 2 * A.P, idx - sz) : 0.0);
-      dq[l] = d;
-    }
-    if (TWO) {
-      const double Cs = (double)ld(A.cap, idx), Ct = (double)ld(A.cap + A.P, idx);
-      const double u0 = clip01(A.u[idx]);
-      const double gx = hx ? clip01(A.u[idx + 1]) - u0 : 0.0;
-      const double gy = hy ? clip01(A.u[idx + A.W]) - u0 : 0.0;
-      const double gz = hz ? clip01(A.u[idx + sz]) - u0 : 0.0;
-      g[0] += (1.0 - u0) * Cs + u0 * Ct;
-      g[1] += A.iso ? sqrt((gx * gx + gy * gy) + gz * gz) : (fabs(gx) + fabs(gy)) + fabs(gz);
-      g[2] += fmin(Cs, Ct + dq[0]);
-      const double r = ((double)ld(A.p, idx) - ps) + dq[0];
-      g[3] += r * r;
-    } else {
-      double v[NL], w0[NL], wx[NL], wy[NL], wz[NL];
-#pragma unroll
-      for (int l = 0; l < NL; l++) v[l] = (double)A.u[(long long)l * A.P + idx];
-      simplex_proj<NL>(v, w0);
-#pragma unroll
-      for (int l = 0; l < NL; l++) v[l] = hx ? (double)A.u[(long long)l * A.P + idx + 1] : 0.0;
-      simplex_proj<NL>(v, wx);
-#pragma unroll
-      for (int l = 0; l < NL; l++) v[l] = hy ? (double)A.u[(long long)l * A.P + idx + A.W] : 0.0;
-      simplex_proj<NL>(v, wy);
-      if (NDIM == 3) {
-#pragma unroll
-        for (int l = 0; l < NL; l++) v[l] = hz ? (double)A.u[(long long)l * A.P + idx + sz] : 0.0;
-        simplex_proj<NL>(v, wz);
-      }
-      double mn = 1e300;
-#pragma unroll
-      for (int l = 0; l < NL; l++) {
-        const double C = (double)ld(A.cap + (long long)l * A.P, idx);
-        g[0] += w0[l] * C;
-        const double gx = hx ? wx[l] - w0[l] : 0.0;
-        const double gy = hy ? wy[l] - w0[l] : 0.0;
-        const double gz = (NDIM == 3 && hz) ? wz[l] - w0[l] : 0.0;
-        g[1] += A.iso ? sqrt((gx * gx + gy * gy) + gz * gz) : (fabs(gx) + fabs(gy)) + fabs(gz);
-        const double t = C + dq[l];
-        mn = t < mn ? t : mn;
-        const double r = (dq[l] + (double)ld(A.p + (long long)l * A.P, idx)) - ps;
-        g[3] += r * r;
-      }
-      g[2] += mn;
-    }
-    g[4] += ps;
+    gap_px<NL, TWO, NDIM, TS>(A, idx, x, y, z, g);
   }
   block_accumulate<5, 4>(g, A.acc, sred);
 }
@@ -213,6 +139,23 @@ hipError_t launch_read_planes(const void* src, bool bf16, float* dst, long long 
   else
     hipLaunchKernelGGL(k_from_storage<float>, dim3(blocks_for(n)), dim3(256), 0, s, (const float*)src, dst, n,
                        np, plane, n);
+  return hipGetLastError();
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_convert(const TI* src, TO* dst, long long n, int np, long long ss,
+                                                 long long ds) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+    for (int c = 0; c < np; c++) st(dst + (long long)c * ds, i, ld(src + (long long)c * ss, i));
+}
+
+hipError_t launch_convert_planes(const void* src, bool sb, void* dst, bool db, long long n, int np, long long ss,
+                                 long long ds, hipStream_t s) {
+  const dim3 g(blocks_for(n)), b(256);
+  if (sb && db) hipLaunchKernelGGL((k_convert<bf16_t, bf16_t>), g, b, 0, s, (const bf16_t*)src, (bf16_t*)dst, n, np, ss, ds);
+  else if (sb) hipLaunchKernelGGL((k_convert<bf16_t, float>), g, b, 0, s, (const bf16_t*)src, (float*)dst, n, np, ss, ds);
+  else if (db) hipLaunchKernelGGL((k_convert<float, bf16_t>), g, b, 0, s, (const float*)src, (bf16_t*)dst, n, np, ss, ds);
+  else hipLaunchKernelGGL((k_convert<float, float>), g, b, 0, s, (const float*)src, (float*)dst, n, np, ss, ds);
   return hipGetLastError();
 }
 

@@ -1,0 +1,295 @@
+// Persistent pool kernels: one launch per class walks that class's work list
+// of (solve, tile) items drawn from many grids of different sizes, and
+// advances every running solve by one iteration; the bookkeeping launch then
+// takes each solve's gap decision and advances its counter.  The tile bodies
+// are the same device functions as the single-solve kernels, so a solve
+// produces the same bits in the pool, alone or in any mix, and through the
+// single-solve API with the same tile shape.
+#include "mf_pool.h"
+#include "tile2d.h"
+#include "tile3d.h"
+#include "gap.h"
+
+namespace mf {
+
+// Item range of this workgroup: the list is cut into 8 contiguous chunks and
+// the workgroups dispatched to one XCD (block b runs on XCD b & 7) walk one
+// chunk, so neighbouring tiles of a grid share that XCD's L2.  The grid is a
+// multiple of 8 workgroups.
+__device__ __forceinline__ void xcd_range(int n, int& it0, int& it1, int& step) {
+  const int G = gridDim.x, b = blockIdx.x;
+  const int x = b & 7, lb = b >> 3, per = G >> 3;
+  it0 = (int)((long long)n * x / 8) + lb;
+  it1 = (int)((long long)n * (x + 1) / 8);
+  step = per;
+}
+
+template <typename TS>
+__device__ __forceinline__ K2<TS> slot_k2(const PoolSlot& sl) {
+  K2<TS> a;
+  const int src = (int)(sl.iter & 1), dst = src ^ 1;
+  a.W = sl.W;
+  a.H = sl.H;
+  a.P = sl.P;
+  a.tiles_x = sl.tiles_x;
+  a.cap = (const TS*)sl.cap;
+  a.u_in = sl.st[src].u;
+  a.u_out = sl.st[dst].u;
+  a.q_in = (const TS*)sl.st[src].q;
+  a.q_out = (TS*)sl.st[dst].q;
+  a.ps_in = (const TS*)sl.st[src].ps;
+  a.ps_out = (TS*)sl.st[dst].ps;
+  a.p_in = (const TS*)sl.st[src].p;
+  a.p_out = (TS*)sl.st[dst].p;
+  a.wbuf = nullptr;
+  a.k = sl.k;
+  a.acc = nullptr;
+  a.done = nullptr;
+  a.write = sl.iter < sl.max_iter ? 1 : 0;
+  a.iso = sl.iso;
+  return a;
+}
+
+// CHECK selects the items this launch processes: the sweeps that also
+// accumulate the (two-label, fused) gap of their input iterate, or all the
+// others.  Two specialised launches keep the common no-gap body lean.
+template <int NL, bool TWO, typename TS, int TY, bool CHECK, bool VEC>
+__global__ __launch_bounds__(256) void k_pool2d(PoolDev d, int cls) {
+  __shared__ Smem2<TY, CHECK> S;
+  constexpr int V = TY >= 16 ? 4 : 2;
+  const int n = d.counts[cls];
+  int it0, it1, step;
+  xcd_range(n, it0, it1, step);
+  for (int it = it0; it < it1; it += step) {
+    const WorkItem w = d.items[cls][it];
+    PoolSlot* sl = d.slots + w.slot;
+    if (sl->state != SLOT_RUNNING) continue;
+    // two-label gaps are fused into the sweep; Potts gaps run in k_pool_gap2d
+    const bool check = TWO && sl->check_now != 0;
+    if (check != CHECK || ((sl->W % V) == 0) != VEC) continue;
+    const K2<TS> A = slot_k2<TS>(*sl);
+    double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    tile2d<NL, TWO, TS, CHECK, TY, VEC, CHECK>(A, w.x0, w.y0, S, g);
+    if (CHECK) block_accumulate<5, 4>(g, &sl->acc[0][0], S.sred);
+    __syncthreads();
+  }
+}
+
+template <typename TS, bool CHECK, bool VEC>
+__global__ __launch_bounds__(256) void k_pool3d(PoolDev d, int cls) {
+  __shared__ Smem3<CHECK> S;
+  const int n = d.counts[cls];
+  int it0, it1, step;
+  xcd_range(n, it0, it1, step);
+  for (int it = it0; it < it1; it += step) {
+    const WorkItem w = d.items[cls][it];
+    PoolSlot* sl = d.slots + w.slot;
+    if (sl->state != SLOT_RUNNING) continue;
+    if ((sl->check_now != 0) != CHECK || ((sl->W % 2) == 0) != VEC) continue;
+    K3<TS> A;
+    const int src = (int)(sl->iter & 1), dst = src ^ 1;
+    A.W = sl->W;
+    A.H = sl->H;
+    A.D = sl->D;
+    A.P = sl->P;
+    A.SZ = (long long)sl->W * sl->H;
+    A.tiles_x = sl->tiles_x;
+    A.tiles_y = sl->tiles_y;
+    A.tz = sl->tz;
+    A.cap = (const TS*)sl->cap;
+    A.u_in = sl->st[src].u;
+    A.u_out = sl->st[dst].u;
+    A.q_in = (const TS*)sl->st[src].q;
+    A.q_out = (TS*)sl->st[dst].q;
+    A.ps_in = (const TS*)sl->st[src].ps;
+    A.ps_out = (TS*)sl->st[dst].ps;
+    A.p_in = (const TS*)sl->st[src].p;
+    A.p_out = (TS*)sl->st[dst].p;
+    A.k = sl->k;
+    A.acc = nullptr;
+    A.done = nullptr;
+    A.write = sl->iter < sl->max_iter ? 1 : 0;
+    A.iso = sl->iso;
+    const int z1 = min(w.z0 + A.tz, A.D);
+    double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    tile3d<TS, CHECK, VEC, CHECK>(A, w.x0, w.y0, w.z0, z1, S, g);
+    if (CHECK) block_accumulate<5, 4>(g, &sl->acc[0][0], S.sred);
+    __syncthreads();
+  }
+}
+
+// Gap of iterate k of every checking Potts solve, tile by tile.  It reads
+// state buffer k & 1, which the concurrent sweep k -> k+1 does not write.
+template <int NL, typename TS, int TY>
+__global__ __launch_bounds__(256) void k_pool_gap2d(PoolDev d, int cls) {
+  __shared__ double sred[4 * 5];
+  const int n = d.counts[cls];
+  int it0, it1, step;
+  xcd_range(n, it0, it1, step);
+  for (int it = it0; it < it1; it += step) {
+    const WorkItem w = d.items[cls][it];
+    PoolSlot* sl = d.slots + w.slot;
+    if (sl->state != SLOT_RUNNING || !sl->check_now) continue;
+    KG<TS> A;
+    const int src = (int)(sl->iter & 1);
+    A.W = sl->W;
+    A.H = sl->H;
+    A.D = 1;
+    A.P = sl->P;
+    A.n = (long long)sl->W * sl->H;
+    A.cap = (const TS*)sl->cap;
+    A.u = sl->st[src].u;
+    A.q = (const TS*)sl->st[src].q;
+    A.ps = (const TS*)sl->st[src].ps;
+    A.p = (const TS*)sl->st[src].p;
+    A.acc = nullptr;
+    A.done = nullptr;
+    A.iso = sl->iso;
+    double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int e = threadIdx.x; e < 64 * TY; e += 256) {
+      const int x = w.x0 + (e & 63), y = w.y0 + (e >> 6);
+      if (x < A.W && y < A.H) gap_px<NL, false, 2, TS>(A, (long long)y * A.W + x, x, y, 0, g);
+    }
+    block_accumulate<5, 4>(g, &sl->acc[0][0], sred);
+    __syncthreads();
+  }
+}
+
+// One workgroup (64 threads) per slot: sum the 64 accumulator rows, decide,
+// clear them, advance the iteration counter and publish the status.  Status
+// codes follow mf_status: 0 converged, 1 cap reached, -4 diverged.
+__global__ __launch_bounds__(64) void k_pool_book(PoolDev d) {
+  PoolSlot* sl = d.slots + blockIdx.x;
+  const int t = threadIdx.x;
+
+  if (sl->state != SLOT_RUNNING) return;
+  const bool check = sl->check_now != 0;
+  double v[5];
+#pragma unroll
+  for (int j = 0; j < 5; j++) v[j] = check ? wave_sum(sl->acc[t][j]) : 0.0;
+  if (check) {
+#pragma unroll
+    for (int j = 0; j < 8; j++) sl->acc[t][j] = 0.0;
+  }
+  if (t != 0) return;
+  const long long k = sl->iter;
+  int state = SLOT_RUNNING;
+  if (check) {
+    const double P = v[0] + sl->alpha * v[1];
+    const double D = v[2];
+    const double m = fmax(fmax(fabs(P), fabs(D)), 1e-300);
+    const double rel = (P - D) / m;
+    PoolStat& ps = d.stats[blockIdx.x];
+    ps.last[0] = P;
+    ps.last[1] = D;
+    ps.last[2] = rel;
+    ps.last[3] = sqrt(v[3] / (double)sl->nres);
+    ps.last[4] = v[4];
+    ps.last[5] = (double)k;
+    const bool bad = !isfinite(P) || !isfinite(D) || !isfinite(v[3]);
+    if (bad) {
+      state = SLOT_DONE;
+      sl->status = -4;
+    } else if (rel <= sl->tol) {
+      state = SLOT_DONE;
+      sl->status = 0;
+    } else if (k >= sl->max_iter) {
+      state = SLOT_DONE;
+      sl->status = 1;
+    } else if (sl->bf16 && ((sl->promote_gap > 0.0 && rel <= sl->promote_gap) ||
+                            (sl->promote_iter > 0 && k >= sl->promote_iter))) {
+      state = SLOT_PROMOTE;   // frozen at k until the host moves it to FP32 storage
+    }
+  }
+  if (state == SLOT_RUNNING) {
+    const long long kn = k + 1;
+    sl->iter = kn;
+    sl->check_now = (kn % sl->check_every == 0 || kn >= sl->max_iter) ? 1 : 0;
+  }
+  sl->state = state;
+  d.stats[blockIdx.x].state = state;
+  d.stats[blockIdx.x].status = sl->status;
+  d.stats[blockIdx.x].iter = sl->iter;
+}
+
+// Kernel of one (class, gap-carrying, vector-aligned) launch.
+template <typename TS, bool CHECK, bool VEC>
+static const void* pool_kernel_ts(int model) {
+  if (CHECK) {
+    if (model == 0) return (const void*)k_pool2d<1, true, TS, 16, true, VEC>;
+    if (model == 5) return (const void*)k_pool3d<TS, true, VEC>;
+    return nullptr;   // Potts sweeps never carry the gap
+  }
+  switch (model) {
+    case 0: return (const void*)k_pool2d<1, true, TS, 16, false, VEC>;
+    case 1: return (const void*)k_pool2d<2, false, TS, 8, false, VEC>;
+    case 2: return (const void*)k_pool2d<3, false, TS, 8, false, VEC>;
+    case 3: return (const void*)k_pool2d<4, false, TS, 8, false, VEC>;
+    case 4: return (const void*)k_pool2d<8, false, TS, 8, false, VEC>;
+    default: return (const void*)k_pool3d<TS, false, VEC>;
+  }
+}
+
+static const void* pool_kernel(int cls, bool check, bool vec) {
+  const int model = cls % kPoolModels;
+  const bool bf16 = cls >= kPoolModels;
+  if (bf16) {
+    if (check) return vec ? pool_kernel_ts<bf16_t, true, true>(model) : pool_kernel_ts<bf16_t, true, false>(model);
+    return vec ? pool_kernel_ts<bf16_t, false, true>(model) : pool_kernel_ts<bf16_t, false, false>(model);
+  }
+  if (check) return vec ? pool_kernel_ts<float, true, true>(model) : pool_kernel_ts<float, true, false>(model);
+  return vec ? pool_kernel_ts<float, false, true>(model) : pool_kernel_ts<float, false, false>(model);
+}
+
+// Workgroups of a persistent launch: as many as can be resident at once on
+// the device (occupancy x CUs), a multiple of 8 for the XCD partition.
+int pool_grid(int cls, bool check, bool vec) {
+  const void* k = pool_kernel(cls, check, vec);
+  if (!k) return 0;
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  int g = per_cu * cus;
+  g = g < 8 ? 8 : g - g % 8;
+  return g;
+}
+
+hipError_t launch_pool_class(const PoolDev& d, int cls, int grid, bool check, bool vec, hipStream_t s) {
+  const void* k = pool_kernel(cls, check, vec);
+  if (!k || grid <= 0) return hipSuccess;
+  PoolDev dd = d;
+  int c = cls;
+  void* args[] = {&dd, &c};
+  return hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, s);
+}
+
+hipError_t launch_pool_gap(const PoolDev& d, int cls, int grid, hipStream_t s) {
+  const int model = cls % kPoolModels;
+  const bool bf16 = cls >= kPoolModels;
+  const dim3 g(grid), b(256);
+  if (model == 0 || model == 5) return hipSuccess;   // two-label gaps are fused
+  if (bf16) {
+    switch (model) {
+      case 1: hipLaunchKernelGGL((k_pool_gap2d<2, bf16_t, 8>), g, b, 0, s, d, cls); break;
+      case 2: hipLaunchKernelGGL((k_pool_gap2d<3, bf16_t, 8>), g, b, 0, s, d, cls); break;
+      case 3: hipLaunchKernelGGL((k_pool_gap2d<4, bf16_t, 8>), g, b, 0, s, d, cls); break;
+      default: hipLaunchKernelGGL((k_pool_gap2d<8, bf16_t, 8>), g, b, 0, s, d, cls); break;
+    }
+  } else {
+    switch (model) {
+      case 1: hipLaunchKernelGGL((k_pool_gap2d<2, float, 8>), g, b, 0, s, d, cls); break;
+      case 2: hipLaunchKernelGGL((k_pool_gap2d<3, float, 8>), g, b, 0, s, d, cls); break;
+      case 3: hipLaunchKernelGGL((k_pool_gap2d<4, float, 8>), g, b, 0, s, d, cls); break;
+      default: hipLaunchKernelGGL((k_pool_gap2d<8, float, 8>), g, b, 0, s, d, cls); break;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pool_book(const PoolDev& d, int max_slots, hipStream_t s) {
+  hipLaunchKernelGGL(k_pool_book, dim3(max_slots), dim3(64), 0, s, d);
+  return hipGetLastError();
+}
+
+}  // namespace mf

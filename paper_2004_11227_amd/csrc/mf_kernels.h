@@ -94,6 +94,8 @@ hipError_t launch_read_planes(const void* src, bool bf16, float* dst, long long 
                               long long plane, hipStream_t s);
 hipError_t launch_write_planes(const float* src, void* dst, bool bf16, long long n, int nplanes,
                                long long plane, hipStream_t s);
+hipError_t launch_convert_planes(const void* src, bool src_bf16, void* dst, bool dst_bf16, long long n, int nplanes,
+                                 long long src_stride, long long dst_stride, hipStream_t s);
 hipError_t launch_ctrl_reset(Ctrl* c, hipStream_t s);
 hipError_t launch_bookkeep(Ctrl* c, long long k, double alpha, double tol, long long nres,
                            int final_check, int decide, hipStream_t s);

@@ -1,0 +1,68 @@
+// Device-resident tables of the batched solver pool.
+//
+// The pool keeps many solves resident at once.  Each solve owns a slot in a
+// device table (geometry, state buffers, iteration counter, gap
+// accumulators, decision) and its tiles are items of a per-class device work
+// list.  A super-step is one launch of a persistent kernel per class -- each
+// walks its work list and advances every running solve by one iteration,
+// reading the solve's own iteration parity and gap cadence from its slot --
+// followed by one bookkeeping launch that takes every solve's convergence
+// decision and advances its counter.  Because all of this state lives in
+// device memory, one captured hipGraph of the super-step sequence serves any
+// mix; admission and retirement only edit the tables between replays.
+#pragma once
+#include "mf_kernels.h"
+
+namespace mf {
+
+enum { SLOT_FREE = 0, SLOT_RUNNING = 1, SLOT_DONE = 2, SLOT_PROMOTE = 3 };
+
+// Classes: two-label 2-D, Potts n = 2, 3, 4, 8 (2-D), two-label 3-D; x2 storage.
+constexpr int kPoolModels = 6;
+constexpr int kPoolClasses = 2 * kPoolModels;
+
+struct PoolSlot {
+  int state;          // SLOT_*
+  int cls;
+  int W, H, D, ndim;
+  int nl, two, bf16, iso;
+  long long P;        // plane stride (elements)
+  int tiles_x, tiles_y, tz, check_every;
+  const void* cap;
+  StateView st[2];
+  Coef k;
+  double alpha, tol;
+  long long iter, max_iter, nres;
+  int check_now, status;
+  double promote_gap;       // BF16 -> FP32 promotion triggers (0: off)
+  long long promote_iter;
+  double acc[kAccSlots][8];
+};
+
+// Compact per-slot status the host polls.
+struct PoolStat {
+  int state, status;
+  long long iter;
+  double last[6];     // primal, dual, rel_gap, resid_rms, flow, iter
+};
+
+struct WorkItem {
+  int slot, x0, y0, z0;
+};
+
+struct PoolDev {
+  PoolSlot* slots;
+  PoolStat* stats;
+  WorkItem* items[kPoolClasses];
+  int* counts;        // kPoolClasses entries
+};
+
+hipError_t launch_pool_class(const PoolDev& d, int cls, int grid, bool check, bool vec, hipStream_t s);
+int pool_grid(int cls, bool check, bool vec);
+hipError_t launch_pool_gap(const PoolDev& d, int cls, int grid, hipStream_t s);
+hipError_t launch_pool_book(const PoolDev& d, int max_slots, hipStream_t s);
+
+// Tile height of each pool class (2-D) and the z-slab depth of 3-D solves.
+constexpr int pool_tile_rows(int model) { return model == 0 ? 16 : 8; }
+
+}  // namespace mf

@@ -1,0 +1,576 @@
+// Batched solver pool behind the mf_pool_* part of include/maxflow.h.
+//
+// The caller hands the pool one device arena.  Its head holds the device
+// tables (slot table, per-slot status, per-class work lists and counts); the
+// rest is carved first-fit into one block per admitted solve (capacities and
+// two state buffers), so admission is decided exactly by footprint.  A
+// super-step launches, for every class, the persistent sweep kernel over the
+// class work list (and, for Potts classes, the per-tile gap kernel) on its own
+// branch, then the bookkeeping kernel; `steps_per_advance` super-steps are
+// captured once into a hipGraph and replayed by every mf_pool_advance.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/maxflow.h"
+#include "mf_pool.h"
+
+using namespace mf;
+
+namespace mf {
+// from capi.cpp
+std::string resolve_params(const mf_params* in, mf_params& out, Geom& g, int& nl, int& ncap);
+void set_error(const std::string& m);
+}  // namespace mf
+
+namespace {
+
+mf_status pfail(mf_status s, const std::string& m) {
+  set_error(m);
+  return s;
+}
+
+#define PHIP(expr)                                                                            \
+  do {                                                                                        \
+    hipError_t _e = (expr);                                                                   \
+    if (_e != hipSuccess) return pfail(MF_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+size_t al(size_t v) { return (v + 255) / 256 * 256; }
+
+struct Footprint {
+  mf_params p;
+  Geom g;
+  int nl, ncap, cls, model;
+  size_t esz, cap_bytes, state_bytes, total;
+};
+
+std::string plan_solve(const mf_params* in, Footprint& f) {
+  std::string e = resolve_params(in, f.p, f.g, f.nl, f.ncap);
+  if (!e.empty()) return e;
+  if (f.p.method == MF_RPDRQ) return "the pool runs the rpADMM methods (fg, eb)";
+  if (f.g.ndim == 3 && f.p.model != MF_TWO_LABEL) return "the pool runs 3-D solves of the two-label model only";
+  if (f.g.ndim == 3) {
+    f.model = 5;
+  } else if (f.p.model == MF_TWO_LABEL) {
+    f.model = 0;
+  } else {
+    f.model = f.p.nlabels == 2 ? 1 : f.p.nlabels == 3 ? 2 : f.p.nlabels == 4 ? 3 : 4;
+  }
+  f.cls = f.model + (f.p.storage == MF_BF16 ? kPoolModels : 0);
+  f.esz = f.p.storage == MF_BF16 ? 2 : 4;
+  const size_t P = (size_t)f.g.plane;
+  f.cap_bytes = al((size_t)f.ncap * P * f.esz);
+  f.state_bytes = al((size_t)f.nl * P * 4) + al((size_t)f.nl * f.g.ndim * P * f.esz) + al(P * f.esz) +
+                  al((size_t)f.nl * P * f.esz);
+  f.total = f.cap_bytes + 2 * f.state_bytes;
+  return "";
+}
+
+StateView carve(char* b, const Footprint& f) {
+  const size_t P = (size_t)f.g.plane;
+  StateView v;
+  v.u = (float*)b;
+  b += al((size_t)f.nl * P * 4);
+  v.q = b;
+  b += al((size_t)f.nl * f.g.ndim * P * f.esz);
+  v.ps = b;
+  b += al(P * f.esz);
+  v.p = b;
+  return v;
+}
+
+Coef coef_for(const mf_params& p) {
+  Coef k;
+  k.alpha = (float)p.alpha;
+  k.inv_c = (float)(1.0 / p.c);
+  k.c = (float)p.c;
+  const bool eb = p.method == MF_RPADMM_EB;
+  k.rho = eb ? (float)p.relax : 1.f;
+  k.omr = eb ? (float)(1.0 - p.relax) : 0.f;
+  k.ku = eb ? (float)p.c : (float)(p.relax * p.c);
+  k.inv_a = (float)(1.0 / p.a);
+  if (p.model == MF_TWO_LABEL) {
+    k.inv_a1 = k.inv_a2 = (float)(1.0 / p.a_tilde);
+  } else {
+    k.inv_a1 = (float)(1.0 / p.a1);
+    k.inv_a2 = (float)(1.0 / p.a2);
+  }
+  return k;
+}
+
+struct HostSlot {
+  bool used = false;
+  bool reported = false;
+  int64_t id = -1;
+  Footprint f;
+  size_t off = 0;
+  StateView st[2];
+};
+
+}  // namespace
+
+struct mf_pool {
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  hipStream_t stream = nullptr;
+  int max_slots = 0, max_tiles = 0, steps = 0;
+  PoolDev dev;
+  size_t data_off = 0;
+  std::vector<std::pair<size_t, size_t>> free_list;   // (offset, size), sorted
+  std::vector<HostSlot> slots;
+  std::vector<PoolSlot> slot_img;                       // host images for uploads
+  std::vector<std::vector<WorkItem>> lists;
+  std::vector<int> counts;
+  PoolStat* stats_h = nullptr;                          // pinned
+  hipStream_t side[kPoolClasses] = {};
+  hipEvent_t fork = nullptr, join[kPoolClasses] = {};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_mask = -1;                                  // classes the graph launches
+  long long promotions = 0;
+  int64_t next_id = 1;
+  size_t in_use = 0;
+};
+
+namespace {
+
+bool alloc_block(mf_pool* P, size_t bytes, size_t& off) {
+  for (size_t i = 0; i < P->free_list.size(); i++) {
+    auto& fb = P->free_list[i];
+    if (fb.second >= bytes) {
+      off = fb.first;
+      fb.first += bytes;
+      fb.second -= bytes;
+      if (fb.second == 0) P->free_list.erase(P->free_list.begin() + i);
+      return true;
+    }
+  }
+  return false;
+}
+
+void free_block(mf_pool* P, size_t off, size_t bytes) {
+  auto& fl = P->free_list;
+  auto it = std::lower_bound(fl.begin(), fl.end(), std::make_pair(off, (size_t)0));
+  it = fl.insert(it, {off, bytes});
+  size_t i = it - fl.begin();
+  if (i + 1 < fl.size() && fl[i].first + fl[i].second == fl[i + 1].first) {
+    fl[i].second += fl[i + 1].second;
+    fl.erase(fl.begin() + i + 1);
+  }
+  if (i > 0 && fl[i - 1].first + fl[i - 1].second == fl[i].first) {
+    fl[i - 1].second += fl[i].second;
+    fl.erase(fl.begin() + i);
+  }
+}
+
+mf_status upload_list(mf_pool* P, int cls) {
+  const auto& L = P->lists[cls];
+  if (!L.empty())
+    PHIP(hipMemcpyAsync(P->dev.items[cls], L.data(), L.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
+                        P->stream));
+  P->counts[cls] = (int)L.size();
+  PHIP(hipMemcpyAsync(P->dev.counts + cls, &P->counts[cls], sizeof(int), hipMemcpyHostToDevice, P->stream));
+  return MF_OK;
+}
+
+int class_mask(const mf_pool* P) {
+  int m = 0;
+  for (int c = 0; c < kPoolClasses; c++)
+    if (!P->lists[c].empty()) m |= 1 << c;
+  return m;
+}
+
+// Capture `steps` super-steps for the classes in `mask`: per class, on its own
+// branch, the no-gap sweep, the gap-carrying sweep (two-label classes) and
+// the per-tile gap (Potts classes); then the bookkeeping launch.
+mf_status capture(mf_pool* P, int mask) {
+  if (P->exec) {
+    hipGraphExecDestroy(P->exec);
+    P->exec = nullptr;
+  }
+  if (P->graph) {
+    hipGraphDestroy(P->graph);
+    P->graph = nullptr;
+  }
+  PHIP(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+  for (int s = 0; s < P->steps; s++) {
+    hipError_t e = hipEventRecord(P->fork, P->stream);
+    for (int c = 0; c < kPoolClasses && e == hipSuccess; c++) {
+      if (!(mask & (1 << c))) continue;
+      const int model = c % kPoolModels;
+      e = hipStreamWaitEvent(P->side[c], P->fork, 0);
+      for (int v = 0; v < 2 && e == hipSuccess; v++) {
+        e = launch_pool_class(P->dev, c, pool_grid(c, false, v), false, v, P->side[c]);
+        if (e == hipSuccess && (model == 0 || model == 5))
+          e = launch_pool_class(P->dev, c, pool_grid(c, true, v), true, v, P->side[c]);
+      }
+      if (e == hipSuccess) e = launch_pool_gap(P->dev, c, 512, P->side[c]);
+      if (e == hipSuccess) e = hipEventRecord(P->join[c], P->side[c]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(P->stream, P->join[c], 0);
+    }
+    if (e == hipSuccess) e = launch_pool_book(P->dev, P->max_slots, P->stream);
+    if (e != hipSuccess) {
+      hipGraph_t g = nullptr;
+      hipStreamEndCapture(P->stream, &g);
+      if (g) hipGraphDestroy(g);
+      return pfail(MF_EDEVICE, std::string("pool graph capture: ") + hipGetErrorString(e));
+    }
+  }
+  PHIP(hipStreamEndCapture(P->stream, &P->graph));
+  PHIP(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
+  P->graph_mask = mask;
+  return MF_OK;
+}
+
+// Device image of a slot from its host record, at iterate `iter`.
+void fill_image(mf_pool* P, int slot, long long iter) {
+  HostSlot& H = P->slots[slot];
+  const Footprint& f = H.f;
+  PoolSlot& S = P->slot_img[slot];
+  std::memset(&S, 0, sizeof(S));
+  S.state = SLOT_RUNNING;
+  S.cls = f.cls;
+  S.W = f.g.W;
+  S.H = f.g.H;
+  S.D = f.g.D;
+  S.ndim = f.g.ndim;
+  S.nl = f.nl;
+  S.two = f.p.model == MF_TWO_LABEL;
+  S.bf16 = f.p.storage == MF_BF16;
+  S.iso = f.p.tv == MF_TV_ISO;
+  S.P = f.g.plane;
+  S.tiles_x = (f.g.W + 63) / 64;
+  S.tiles_y = f.g.ndim == 2 ? (f.g.H + pool_tile_rows(f.model) - 1) / pool_tile_rows(f.model) : (f.g.H + 7) / 8;
+  S.tz = f.g.ndim == 3 ? std::min(f.g.D, 16) : 1;
+  S.check_every = f.p.check_every;
+  S.cap = P->arena + H.off;
+  S.st[0] = H.st[0];
+  S.st[1] = H.st[1];
+  S.k = coef_for(f.p);
+  S.alpha = f.p.alpha;
+  S.tol = f.p.tol;
+  S.iter = iter;
+  S.max_iter = f.p.max_iter;
+  S.nres = f.g.npix() * f.nl;
+  S.check_now = (iter % f.p.check_every == 0 || iter >= f.p.max_iter) ? 1 : 0;
+  S.status = 0;
+  S.promote_gap = f.p.promote_gap;
+  S.promote_iter = f.p.promote_iter;
+}
+
+// Move a solve frozen at iterate k from BF16 to FP32 storage: widen its
+// capacities and iterate k into a new arena block (exact), point its slot at
+// it, move its tiles to the FP32 class and release the BF16 block.  The
+// solve resumes at k with the gap re-evaluated there, so the trajectory does
+// not depend on when the host gets to it.
+mf_status promote(mf_pool* P, int slot, long long k, bool& moved) {
+  moved = false;
+  HostSlot& H = P->slots[slot];
+  mf_params p32 = H.f.p;
+  p32.storage = MF_F32;
+  Footprint f2;
+  const std::string e = plan_solve(&p32, f2);
+  if (!e.empty()) return pfail(MF_EINVAL, e);
+  size_t off;
+  if (!alloc_block(P, f2.total, off)) return MF_OK;   // no room yet: stays frozen
+  char* base = P->arena + off;
+  StateView n0 = carve(base + f2.cap_bytes, f2), n1 = carve(base + f2.cap_bytes + f2.state_bytes, f2);
+  const StateView src = H.st[k & 1];
+  const StateView& dst = (k & 1) ? n1 : n0;
+  const long long n = H.f.g.npix(), pl = H.f.g.plane;
+  PHIP(launch_convert_planes(P->arena + H.off, true, base, false, n, H.f.ncap, pl, pl, P->stream));
+  PHIP(launch_convert_planes(src.u, false, dst.u, false, n, H.f.nl, pl, pl, P->stream));
+  PHIP(launch_convert_planes(src.q, true, dst.q, false, n, H.f.nl * H.f.g.ndim, pl, pl, P->stream));
+  PHIP(launch_convert_planes(src.ps, true, dst.ps, false, n, 1, pl, pl, P->stream));
+  PHIP(launch_convert_planes(src.p, true, dst.p, false, n, H.f.nl, pl, pl, P->stream));
+  const int old_cls = H.f.cls;
+  const size_t old_off = H.off, old_total = H.f.total;
+  H.f = f2;
+  H.off = off;
+  H.st[0] = n0;
+  H.st[1] = n1;
+  fill_image(P, slot, k);
+  PHIP(hipMemcpyAsync(P->dev.slots + slot, &P->slot_img[slot], sizeof(PoolSlot), hipMemcpyHostToDevice,
+                      P->stream));
+  PoolStat st;
+  std::memset(&st, 0, sizeof(st));
+  st.state = SLOT_RUNNING;
+  st.iter = k;
+  PHIP(hipMemcpyAsync(P->dev.stats + slot, &st, sizeof(st), hipMemcpyHostToDevice, P->stream));
+  auto& Lo = P->lists[old_cls];
+  auto& Ln = P->lists[f2.cls];
+  for (const WorkItem& w : Lo)
+    if (w.slot == slot) Ln.push_back(w);
+  Lo.erase(std::remove_if(Lo.begin(), Lo.end(), [&](const WorkItem& w) { return w.slot == slot; }), Lo.end());
+  mf_status ms = upload_list(P, old_cls);
+  if (ms == MF_OK) ms = upload_list(P, f2.cls);
+  if (ms != MF_OK) return ms;
+  PHIP(hipStreamSynchronize(P->stream));
+  free_block(P, old_off, old_total);
+  P->in_use += f2.total;
+  P->in_use -= old_total;
+  P->promotions++;
+  moved = true;
+  return MF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mf_pool_footprint(const mf_params* p) {
+  Footprint f;
+  const std::string e = plan_solve(p, f);
+  if (!e.empty()) {
+    set_error(e);
+    return 0;
+  }
+  return f.total;
+}
+
+size_t mf_pool_table_bytes(int32_t max_slots, int32_t max_tiles) {
+  return al(sizeof(PoolSlot) * (size_t)max_slots) + al(sizeof(PoolStat) * (size_t)max_slots) +
+         (size_t)kPoolClasses * al(sizeof(WorkItem) * (size_t)max_tiles) + al(sizeof(int) * kPoolClasses);
+}
+
+mf_status mf_pool_create(void* arena, size_t arena_bytes, int32_t max_slots, int32_t max_tiles,
+                         int32_t steps_per_advance, void* hip_stream, mf_pool** out) {
+  if (!out) return pfail(MF_EINVAL, "out is null");
+  *out = nullptr;
+  if (!arena || ((uintptr_t)arena & 255)) return pfail(MF_EINVAL, "arena must be a 256-byte aligned device pointer");
+  if (!hip_stream) return pfail(MF_EINVAL, "the pool needs a created (non-default) stream for graph capture");
+  if (max_slots < 1 || max_slots > 65536 || max_tiles < 1 || steps_per_advance < 1)
+    return pfail(MF_EINVAL, "max_slots in [1, 65536], max_tiles >= 1, steps_per_advance >= 1");
+  const size_t tb = mf_pool_table_bytes(max_slots, max_tiles);
+  if (arena_bytes <= tb) return pfail(MF_ENOMEM, "arena smaller than the pool tables");
+  mf_pool* P = new (std::nothrow) mf_pool();
+  if (!P) return pfail(MF_ENOMEM, "host allocation failed");
+  P->arena = (char*)arena;
+  P->arena_bytes = arena_bytes;
+  P->stream = (hipStream_t)hip_stream;
+  P->max_slots = max_slots;
+  P->max_tiles = max_tiles;
+  P->steps = steps_per_advance;
+  size_t off = 0;
+  P->dev.slots = (PoolSlot*)(P->arena + off);
+  off += al(sizeof(PoolSlot) * (size_t)max_slots);
+  P->dev.stats = (PoolStat*)(P->arena + off);
+  off += al(sizeof(PoolStat) * (size_t)max_slots);
+  for (int c = 0; c < kPoolClasses; c++) {
+    P->dev.items[c] = (WorkItem*)(P->arena + off);
+    off += al(sizeof(WorkItem) * (size_t)max_tiles);
+  }
+  P->dev.counts = (int*)(P->arena + off);
+  off += al(sizeof(int) * kPoolClasses);
+  P->data_off = off;
+  P->free_list.push_back({off, arena_bytes - off});
+  P->slots.resize(max_slots);
+  P->slot_img.resize(max_slots);
+  P->lists.resize(kPoolClasses);
+  for (auto& l : P->lists) l.reserve(1024);
+  P->counts.assign(kPoolClasses, 0);
+  std::vector<PoolSlot> zero(max_slots);
+  std::memset(zero.data(), 0, zero.size() * sizeof(PoolSlot));
+  std::vector<PoolStat> zs(max_slots);
+  std::memset(zs.data(), 0, zs.size() * sizeof(PoolStat));
+  hipError_t e = hipMemcpyAsync(P->dev.slots, zero.data(), zero.size() * sizeof(PoolSlot), hipMemcpyHostToDevice,
+                                P->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(P->dev.stats, zs.data(), zs.size() * sizeof(PoolStat), hipMemcpyHostToDevice, P->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(P->dev.counts, P->counts.data(), sizeof(int) * kPoolClasses, hipMemcpyHostToDevice,
+                       P->stream);
+
+  if (e == hipSuccess) e = hipHostMalloc((void**)&P->stats_h, sizeof(PoolStat) * (size_t)max_slots, hipHostMallocDefault);
+  for (int c = 0; c < kPoolClasses && e == hipSuccess; c++) {
+    e = hipStreamCreateWithFlags(&P->side[c], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->join[c], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&P->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+  if (e != hipSuccess) {
+    mf_pool_destroy(P);
+    return pfail(MF_EDEVICE, std::string("pool create: ") + hipGetErrorString(e));
+  }
+  *out = P;
+  return MF_OK;
+}
+
+mf_status mf_pool_admit(mf_pool* P, const mf_params* p, const float* cap, int64_t* solve_id) {
+  if (!P || !cap || !solve_id) return pfail(MF_EINVAL, "null argument");
+  Footprint f;
+  const std::string e = plan_solve(p, f);
+  if (!e.empty()) return pfail(MF_EINVAL, e);
+  int slot = -1;
+  for (int i = 0; i < P->max_slots; i++)
+    if (!P->slots[i].used) {
+      slot = i;
+      break;
+    }
+  if (slot < 0) return pfail(MF_ENOMEM, "no free slot");
+  // work items of this solve
+  std::vector<WorkItem> items;
+  const int tx = (f.g.W + 63) / 64;
+  if (f.g.ndim == 2) {
+    const int TY = pool_tile_rows(f.model);
+    const int ty = (f.g.H + TY - 1) / TY;
+    for (int y = 0; y < ty; y++)
+      for (int x = 0; x < tx; x++) items.push_back({slot, x * 64, y * TY, 0});
+  } else {
+    const int ty = (f.g.H + 7) / 8;
+    const int tz = std::min(f.g.D, 16);
+    const int nz = (f.g.D + tz - 1) / tz;
+    for (int z = 0; z < nz; z++)
+      for (int y = 0; y < ty; y++)
+        for (int x = 0; x < tx; x++) items.push_back({slot, x * 64, y * 8, z * tz});
+  }
+  auto& L = P->lists[f.cls];
+  if ((long long)L.size() + (long long)items.size() > P->max_tiles) return pfail(MF_ENOMEM, "work list full");
+  size_t off;
+  if (!alloc_block(P, f.total, off)) return pfail(MF_ENOMEM, "arena full");
+  HostSlot& H = P->slots[slot];
+  H.used = true;
+  H.reported = false;
+  H.id = P->next_id++;
+  H.f = f;
+  H.off = off;
+  char* base = P->arena + off;
+  H.st[0] = carve(base + f.cap_bytes, f);
+  H.st[1] = carve(base + f.cap_bytes + f.state_bytes, f);
+  P->in_use += f.total;
+  const bool bf16 = f.p.storage == MF_BF16;
+  PHIP(launch_convert_caps(cap, base, f.g.npix(), f.ncap, f.g.plane, bf16, P->stream));
+  PHIP(launch_init(f.g, f.nl, f.p.model == MF_TWO_LABEL, bf16, base, H.st[0], P->stream));
+  fill_image(P, slot, 0);
+  PoolSlot& S = P->slot_img[slot];
+  PHIP(hipMemcpyAsync(P->dev.slots + slot, &S, sizeof(S), hipMemcpyHostToDevice, P->stream));
+  PoolStat st;
+  std::memset(&st, 0, sizeof(st));
+  st.state = SLOT_RUNNING;
+  PHIP(hipMemcpyAsync(P->dev.stats + slot, &st, sizeof(st), hipMemcpyHostToDevice, P->stream));
+  L.insert(L.end(), items.begin(), items.end());
+  mf_status ms = upload_list(P, f.cls);
+  if (ms != MF_OK) return ms;
+  // the host images above are the sources of the copies: let them complete
+  PHIP(hipStreamSynchronize(P->stream));
+  *solve_id = H.id;
+  return MF_OK;
+}
+
+mf_status mf_pool_advance(mf_pool* P) {
+  if (!P) return pfail(MF_EINVAL, "null pool");
+  const int mask = class_mask(P);
+  if (!P->exec || mask != P->graph_mask) {
+    mf_status s = capture(P, mask);
+    if (s != MF_OK) return s;
+  }
+  PHIP(hipGraphLaunch(P->exec, P->stream));
+  return MF_OK;
+}
+
+mf_status mf_pool_poll(mf_pool* P, int64_t* done_ids, mf_gap* gaps, int32_t cap, int32_t* ndone) {
+  if (!P || !ndone) return pfail(MF_EINVAL, "null argument");
+  *ndone = 0;
+  PHIP(hipMemcpyAsync(P->stats_h, P->dev.stats, sizeof(PoolStat) * (size_t)P->max_slots, hipMemcpyDeviceToHost,
+                      P->stream));
+  PHIP(hipStreamSynchronize(P->stream));
+  for (int i = 0; i < P->max_slots; i++) {
+    if (P->slots[i].used && P->stats_h[i].state == SLOT_PROMOTE) {
+      bool moved;
+      mf_status ms = promote(P, i, P->stats_h[i].iter, moved);
+      if (ms != MF_OK) return ms;
+    }
+  }
+  for (int i = 0; i < P->max_slots && *ndone < cap; i++) {
+    HostSlot& H = P->slots[i];
+    if (!H.used || H.reported) continue;
+    const PoolStat& s = P->stats_h[i];
+    if (s.state != SLOT_DONE) continue;
+    H.reported = true;
+    if (done_ids) done_ids[*ndone] = H.id;
+    if (gaps) {
+      mf_gap& g = gaps[*ndone];
+      g.iter = s.iter;
+      g.primal = s.last[0];
+      g.dual = s.last[1];
+      g.rel_gap = s.last[2];
+      g.resid_rms = s.last[3];
+      g.flow = s.last[4];
+      g.status = s.status;
+    }
+    (*ndone)++;
+  }
+  return MF_OK;
+}
+
+mf_status mf_pool_retire(mf_pool* P, int64_t solve_id, float* u_dst, int32_t* labels_dst) {
+  if (!P) return pfail(MF_EINVAL, "null pool");
+  int slot = -1;
+  for (int i = 0; i < P->max_slots; i++)
+    if (P->slots[i].used && P->slots[i].id == solve_id) {
+      slot = i;
+      break;
+    }
+  if (slot < 0) return pfail(MF_EINVAL, "unknown solve id");
+  HostSlot& H = P->slots[slot];
+  // make the last decision visible (the solve may be retired before a poll)
+  PHIP(hipMemcpyAsync(P->stats_h + slot, P->dev.stats + slot, sizeof(PoolStat), hipMemcpyDeviceToHost, P->stream));
+  PHIP(hipStreamSynchronize(P->stream));
+  const long long it = P->stats_h[slot].iter;
+  const StateView& v = H.st[it & 1];
+  if (u_dst) PHIP(launch_read_planes(v.u, false, u_dst, H.f.g.npix(), H.f.nl, H.f.g.plane, P->stream));
+  if (labels_dst) PHIP(launch_labels(H.f.g, H.f.nl, H.f.p.model == MF_TWO_LABEL, v.u, labels_dst, P->stream));
+  // free the slot on the device and drop its tiles
+  int zero = SLOT_FREE;
+  PHIP(hipMemcpyAsync(&P->dev.slots[slot].state, &zero, sizeof(int), hipMemcpyHostToDevice, P->stream));
+  PHIP(hipMemcpyAsync(&P->dev.stats[slot].state, &zero, sizeof(int), hipMemcpyHostToDevice, P->stream));
+  auto& L = P->lists[H.f.cls];
+  L.erase(std::remove_if(L.begin(), L.end(), [&](const WorkItem& w) { return w.slot == slot; }), L.end());
+  mf_status ms = upload_list(P, H.f.cls);
+  if (ms != MF_OK) return ms;
+  PHIP(hipStreamSynchronize(P->stream));
+  free_block(P, H.off, H.f.total);
+  P->in_use -= H.f.total;
+  H.used = false;
+  H.id = -1;
+  return MF_OK;
+}
+
+int64_t mf_pool_promotions(const mf_pool* P) { return P ? P->promotions : -1; }
+
+mf_status mf_pool_stats(mf_pool* P, int32_t* active, size_t* bytes_in_use, size_t* bytes_free) {
+  if (!P) return pfail(MF_EINVAL, "null pool");
+  int n = 0;
+  for (auto& h : P->slots) n += h.used ? 1 : 0;
+  if (active) *active = n;
+  if (bytes_in_use) *bytes_in_use = P->in_use;
+  if (bytes_free) {
+    size_t m = 0;
+    for (auto& fb : P->free_list) m = std::max(m, fb.second);
+    *bytes_free = m;
+  }
+  return MF_OK;
+}
+
+mf_status mf_pool_destroy(mf_pool* P) {
+  if (!P) return MF_OK;
+  if (P->stream) hipStreamSynchronize(P->stream);
+  if (P->exec) hipGraphExecDestroy(P->exec);
+  if (P->graph) hipGraphDestroy(P->graph);
+  for (int c = 0; c < kPoolClasses; c++) {
+    if (P->side[c]) hipStreamDestroy(P->side[c]);
+    if (P->join[c]) hipEventDestroy(P->join[c]);
+  }
+  if (P->fork) hipEventDestroy(P->fork);
+  if (P->stats_h) hipHostFree(P->stats_h);
+  delete P;
+  return MF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,296 @@
+// Fused 2-D rpADMM tile: the body shared by the single-solve kernel and the
+// persistent pool kernel.
+//
+// One iteration of rpADMMI / rpADMMII (two-label and Potts) is, per label i,
+//   w_i   = div q_i^k + (p_i^k - p_s^k) - u_i^k / c
+//   q_i'  = P_alpha(q_i^k + grad(w_i) / a)
+//   d_i   = div q_i'
+// followed by the pointwise p, p_s and u updates (label_update/finish_*).
+// q_i'(x) depends on q^k up to two cells behind x and one ahead, so a tile of
+// 64 x TY outputs stages q^k on (TY+3) x 67 cells, w on (TY+2) x 66 and
+// produces q' on (TY+1) x 65 cells in LDS.
+#pragma once
+#include "mf_kernels.h"
+
+namespace mf {
+
+template <typename TS>
+__device__ __forceinline__ float quant(float v);
+template <>
+__device__ __forceinline__ float quant<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ float quant<bf16_t>(float v) {
+  return __uint_as_float(((uint32_t)f2bf(v)) << 16);
+}
+
+template <typename TS>
+struct K2 {
+  int W, H;
+  long long P;        // plane stride
+  int tiles_x;
+  const TS* cap;
+  const float* u_in;
+  float* u_out;
+  const TS* q_in;
+  TS* q_out;
+  const TS* ps_in;
+  TS* ps_out;
+  const TS* p_in;
+  TS* p_out;
+  float* wbuf;
+  Coef k;
+  double* acc;
+  const int* done;
+  int write;
+  int iso;
+};
+
+__device__ __forceinline__ void proj(float& x, float& y, float alpha, int iso) {
+  if (iso) proj2<true>(x, y, alpha);
+  else proj2<false>(x, y, alpha);
+}
+
+// FP64 gap terms of the two-label model at one pixel:
+// data (1-u)C_s + u C_t and TV at u = clip(u,0,1), dual min(C_s, C_t + div q),
+// residual p_t - p_s + div q, flow p_s.
+__device__ __forceinline__ void gap_two_px(double (&g)[5], float u0f, float uxf, float uyf,
+                                           bool hx, bool hy, double dq, float Cs, float Ct,
+                                           float ps, float pt, int iso) {
+  const double u0 = fmin(1.0, fmax(0.0, (double)u0f));
+  const double gx = hx ? fmin(1.0, fmax(0.0, (double)uxf)) - u0 : 0.0;
+  const double gy = hy ? fmin(1.0, fmax(0.0, (double)uyf)) - u0 : 0.0;
+  g[0] += (1.0 - u0) * (double)Cs + u0 * (double)Ct;
+  g[1] += iso ? sqrt(gx * gx + gy * gy) : fabs(gx) + fabs(gy);
+  g[2] += fmin((double)Cs, (double)Ct + dq);
+  const double r = ((double)pt - (double)ps) + dq;
+  g[3] += r * r;
+  g[4] += (double)ps;
+}
+
+// Tile of 64 x TY outputs, 256 threads (1-D block).  Owner mapping: thread t
+// owns V consecutive columns c0 = (t % (64/V)) * V of rows t / (64/V) + j *
+// (4V), j < RPT, so every interior global access is one V-wide vector
+// access per lane (16 B for FP32 and V = 4).  LDS column c of the tile is
+// stored at index c + 4 so those groups stay 16-byte aligned.
+template <int TY, bool CHECK>
+struct Smem2 {
+  static constexpr int SW = 64 + 8;   // cols -4 .. 67
+  static constexpr int SH = TY + 3;   // rows -2 .. TY
+  __align__(16) float sqx[SH][SW];
+  __align__(16) float sqy[SH][SW];
+  __align__(16) float sw[SH][SW];
+  __align__(16) float su[CHECK ? SH : 1][CHECK ? SW : 1];
+  double sred[4 * 5];
+};
+
+template <int NL, bool TWO, typename TS, bool CHECK, int TY, bool VEC, bool SU>
+__device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY, SU>& S, double (&g)[5]) {
+  static_assert(!CHECK || SU, "the gap needs the u staging array");
+  constexpr int TX = 64;
+  constexpr int V = TY >= 16 ? 4 : 2;
+  constexpr int TPR = TX / V;        // threads per tile row
+  constexpr int RSTEP = 256 / TPR;   // tile rows covered by one pass of the block
+  constexpr int RPT = TY / RSTEP;    // rows per thread
+  constexpr int OX = 4;              // LDS column offset
+  auto& sqx = S.sqx;
+  auto& sqy = S.sqy;
+  auto& sw = S.sw;
+  auto& su = S.su;
+  const int tid = threadIdx.x;
+  const int W = A.W, H = A.H;
+  const long long P = A.P;
+  const int c0 = (tid % TPR) * V;
+  const int rr0 = tid / TPR;
+  const int gx0 = x0 + c0;
+  const int nvx = W - gx0 < 0 ? 0 : (W - gx0 > V ? V : W - gx0);
+  constexpr bool vec = VEC;   // W % V == 0: interior groups are whole vectors
+  const Coef k = A.k;
+
+  float t[RPT][NL][V];
+  float ps[RPT][V], sumd[RPT][V], sumr[RPT][V];
+  float capt[RPT][V], caps[RPT][V];
+#pragma unroll
+  for (int j = 0; j < RPT; j++) {
+    const int gy = y0 + rr0 + RSTEP * j;
+    const int nv = gy < H ? nvx : 0;
+    const long long idx = (long long)gy * W + gx0;
+    ldg<V>(A.ps_in, idx, nv, vec, ps[j]);
+    if (TWO) {
+      ldg<V>(A.cap, idx, nv, vec, caps[j]);
+      ldg<V>(A.cap + P, idx, nv, vec, capt[j]);
+    }
+#pragma unroll
+    for (int e = 0; e < V; e++) {
+      sumd[j][e] = 0.f;
+      sumr[j][e] = 0.f;
+    }
+  }
+
+#pragma unroll
+  for (int l = 0; l < NL; l++) {
+    const TS* qx_in = A.q_in + (long long)(2 * l) * P;
+    const TS* qy_in = qx_in + P;
+    const float* u_in = A.u_in + (long long)l * P;
+    const TS* p_in = A.p_in + (long long)l * P;
+    float ul[RPT][V], pl[RPT][V];
+    // ---- stage q^k and v = (p - p_s) - u/c: interior by the owning threads
+#pragma unroll
+    for (int j = 0; j < RPT; j++) {
+      const int r = rr0 + RSTEP * j;
+      const int gy = y0 + r;
+      const int nv = gy < H ? nvx : 0;
+      const long long idx = (long long)gy * W + gx0;
+      float qxv[V], qyv[V];
+      ldg<V>(qx_in, idx, nv, vec, qxv);
+      ldg<V>(qy_in, idx, nv, vec, qyv);
+      ldg<V>(u_in, idx, nv, vec, ul[j]);
+      ldg<V>(p_in, idx, nv, vec, pl[j]);
+#pragma unroll
+      for (int e = 0; e < V; e++) {
+        sqx[r + 2][c0 + OX + e] = qxv[e];
+        sqy[r + 2][c0 + OX + e] = qyv[e];
+        sw[r + 2][c0 + OX + e] = vterm(pl[j][e], ps[j][e], ul[j][e], k.inv_c);
+        if (CHECK) su[r + 2][c0 + OX + e] = ul[j][e];
+      }
+    }
+    // q halo: rows {-2,-1,TY} x cols -2..TX, then cols {-2,-1,TX} x rows 0..TY-1
+    for (int h = tid; h < 3 * (TX + 3) + 3 * TY; h += 256) {
+      int r, c;
+      if (h < 3 * (TX + 3)) {
+        const int rr = h / (TX + 3);
+        r = rr == 0 ? -2 : (rr == 1 ? -1 : TY);
+        c = h % (TX + 3) - 2;
+      } else {
+        const int hh = h - 3 * (TX + 3);
+        r = hh / 3;
+        const int cc = hh % 3;
+        c = cc == 0 ? -2 : (cc == 1 ? -1 : TX);
+      }
+      const int hx = x0 + c, hy = y0 + r;
+      const bool in = hx >= 0 && hx < W && hy >= 0 && hy < H;
+      const long long idx = (long long)hy * W + hx;
+      sqx[r + 2][c + OX] = in ? ld(qx_in, idx) : 0.f;
+      sqy[r + 2][c + OX] = in ? ld(qy_in, idx) : 0.f;
+    }
+    // v halo: rows {-1,TY} x cols -1..TX, then cols {-1,TX} x rows 0..TY-1
+    for (int h = tid; h < 2 * (TX + 2) + 2 * TY; h += 256) {
+      int r, c;
+      if (h < 2 * (TX + 2)) {
+        r = h < TX + 2 ? -1 : TY;
+        c = h % (TX + 2) - 1;
+      } else {
+        const int hh = h - 2 * (TX + 2);
+        r = hh >> 1;
+        c = (hh & 1) ? TX : -1;
+      }
+      const int hx = x0 + c, hy = y0 + r;
+      const bool in = hx >= 0 && hx < W && hy >= 0 && hy < H;
+      const long long idx = (long long)hy * W + hx;
+      const float uu = in ? u_in[idx] : 0.f;
+      const float pp = in ? ld(p_in, idx) : 0.f;
+      const float ss = in ? ld(A.ps_in, idx) : 0.f;
+      sw[r + 2][c + OX] = vterm(pp, ss, uu, k.inv_c);
+      if (CHECK) su[r + 2][c + OX] = uu;
+    }
+    __syncthreads();
+    // ---- gap of the input iterate (two-label; q^k is still intact in LDS)
+    if (CHECK) {
+#pragma unroll
+      for (int j = 0; j < RPT; j++) {
+        const int r = rr0 + RSTEP * j;
+        const int gy = y0 + r;
+        const int nv = gy < H ? nvx : 0;
+#pragma unroll
+        for (int e = 0; e < V; e++) {
+          if (e < nv) {
+            const int gx = gx0 + e, c = c0 + OX + e;
+            const double dq =
+                (((gx + 1 < W) ? (double)sqx[r + 2][c] : 0.0) - ((gx > 0) ? (double)sqx[r + 2][c - 1] : 0.0)) +
+                (((gy + 1 < H) ? (double)sqy[r + 2][c] : 0.0) - ((gy > 0) ? (double)sqy[r + 1][c] : 0.0));
+            gap_two_px(g, su[r + 2][c], su[r + 2][c + 1], su[r + 3][c], gx + 1 < W, gy + 1 < H, dq,
+                       caps[j][e], capt[j][e], ps[j][e], pl[j][e], A.iso);
+          }
+        }
+      }
+    }
+    // ---- w = div q^k + v on rows -1..TY, cols -1..TX
+    for (int h = tid; h < (TY + 2) * (TX + 2); h += 256) {
+      const int r = h / (TX + 2) - 1, c = h % (TX + 2) - 1;
+      const int hx = x0 + c, hy = y0 + r;
+      const float d = div2(sqx[r + 2][c + OX], sqx[r + 2][c + OX - 1], sqy[r + 2][c + OX],
+                           sqy[r + 1][c + OX], hx + 1 < W, hx > 0, hy + 1 < H, hy > 0);
+      sw[r + 2][c + OX] = wterm(d, sw[r + 2][c + OX]);
+    }
+    __syncthreads();
+    // ---- q^{k+1} = P_alpha(q^k + grad(w)/a) on rows -1..TY-1, cols -1..TX-1 (in place)
+    for (int h = tid; h < (TY + 1) * (TX + 1); h += 256) {
+      const int r = h / (TX + 1) - 1, c = h % (TX + 1) - 1;
+      const int hx = x0 + c, hy = y0 + r;
+      const float w0 = sw[r + 2][c + OX];
+      float qx = qstep(sqx[r + 2][c + OX], sw[r + 2][c + OX + 1], w0, hx + 1 < W, k.inv_a);
+      float qy = qstep(sqy[r + 2][c + OX], sw[r + 3][c + OX], w0, hy + 1 < H, k.inv_a);
+      proj(qx, qy, k.alpha, A.iso);
+      sqx[r + 2][c + OX] = quant<TS>(qx);
+      sqy[r + 2][c + OX] = quant<TS>(qy);
+    }
+    __syncthreads();
+    // ---- owned groups: d = div q^{k+1}, store q^{k+1}, per-label p and u parts
+    {
+      TS* qx_out = A.q_out + (long long)(2 * l) * P;
+      TS* qy_out = qx_out + P;
+      TS* p_out = A.p_out + (long long)l * P;
+      const TS* capl = A.cap + (long long)(TWO ? 1 : l) * P;
+#pragma unroll
+      for (int j = 0; j < RPT; j++) {
+        const int r = rr0 + RSTEP * j;
+        const int gy = y0 + r;
+        const int nv = gy < H ? nvx : 0;
+        const long long idx = (long long)gy * W + gx0;
+        float C[V], qxv[V], qyv[V], pn[V];
+        if (TWO) {
+#pragma unroll
+          for (int e = 0; e < V; e++) C[e] = capt[j][e];
+        } else {
+          ldg<V>(capl, idx, nv, vec, C);
+        }
+#pragma unroll
+        for (int e = 0; e < V; e++) {
+          const int gx = gx0 + e, c = c0 + OX + e;
+          qxv[e] = sqx[r + 2][c];
+          qyv[e] = sqy[r + 2][c];
+          const float d = div2(qxv[e], sqx[r + 2][c - 1], qyv[e], sqy[r + 1][c], gx + 1 < W, gx > 0,
+                               gy + 1 < H, gy > 0);
+          label_update(k, ul[j][e], pl[j][e], ps[j][e], d, C[e], pn[e], t[j][l][e], sumd[j][e], sumr[j][e]);
+        }
+        if (A.write) {
+          stg<V>(qx_out, idx, nv, vec, qxv);
+          stg<V>(qy_out, idx, nv, vec, qyv);
+          stg<V>(p_out, idx, nv, vec, pn);
+        }
+      }
+    }
+    if (NL > 1) __syncthreads();
+  }
+  // ---- p_s and u
+#pragma unroll
+  for (int j = 0; j < RPT; j++) {
+    const int gy = y0 + rr0 + RSTEP * j;
+    const int nv = gy < H ? nvx : 0;
+    const long long idx = (long long)gy * W + gx0;
+    float psn[V];
+#pragma unroll
+    for (int e = 0; e < V; e++) psn[e] = finish_ps(k, ps[j][e], sumd[j][e], sumr[j][e], TWO, TWO ? caps[j][e] : 0.f);
+    if (A.write) {
+      stg<V>(A.ps_out, idx, nv, vec, psn);
+#pragma unroll
+      for (int l = 0; l < NL; l++) {
+        float un[V];
+#pragma unroll
+        for (int e = 0; e < V; e++) un[e] = finish_u(k, t[j][l][e], psn[e]);
+        stg<V>(A.u_out + (long long)l * P, idx, nv, vec, un);
+      }
+    }
+  }
+}
+
+}  // namespace mf

@@ -1,0 +1,276 @@
+// 3-D fused rpADMM tile (two-label model), z-marching; shared by the
+// single-solve kernel and the persistent pool kernel.
+//
+// A block owns a 64 x 8 tile of the xy plane and a slab [z0, z1) of planes.
+// It marches s = z0-2 .. z1, and at step s
+//   1. stages q^k(s) (x, y, z components) and v(s) = (p_t - p_s) - u/c on
+//      the tile plus its xy halo, into ring slot s & 1;
+//   2. forms w(s) = div q^k(s) + v(s) (needs q_z^k(s-1), still in the other
+//      slot);
+//   3. forms q^{k+1}(s-1) = P_alpha(q^k(s-1) + grad w / a) in place (needs
+//      w(s-1) in-plane and w(s) for the z difference);
+//   4. for the owned pixels of plane s-1: d = div q^{k+1}(s-1) (the q_z of
+//      plane s-2 is kept in registers), the pointwise p and u updates, and
+//      the stores.
+// Every plane is read from memory once per slab (plus two warm-up planes),
+// so z-neighbours cost no extra traffic; xy halos are shared through L2.
+// The arithmetic is the same device-function sequence as the unfused 3-D
+// baseline, so the two agree bit for bit.
+#pragma once
+#include "mf_kernels.h"
+
+namespace mf {
+
+template <typename TS>
+__device__ __forceinline__ float quant3(float v);
+template <>
+__device__ __forceinline__ float quant3<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ float quant3<bf16_t>(float v) {
+  return __uint_as_float(((uint32_t)f2bf(v)) << 16);
+}
+
+template <typename TS>
+struct K3 {
+  int W, H, D;
+  long long P, SZ;     // plane stride (fields), z stride (W*H)
+  int tiles_x, tiles_y, tz;
+  const TS* cap;
+  const float* u_in;
+  float* u_out;
+  const TS* q_in;
+  TS* q_out;
+  const TS* ps_in;
+  TS* ps_out;
+  const TS* p_in;
+  TS* p_out;
+  Coef k;
+  double* acc;
+  const int* done;
+  int write;
+  int iso;
+};
+
+__device__ __forceinline__ void proj3r(float& x, float& y, float& z, float alpha, int iso) {
+  if (iso) proj3<true>(x, y, z, alpha);
+  else proj3<false>(x, y, z, alpha);
+}
+
+template <bool SU>
+struct Smem3 {
+  static constexpr int SW = 64 + 8;   // cols -4 .. 67
+  static constexpr int SH = 8 + 3;    // rows -2 .. 8
+  __align__(16) float sqx[2][SH][SW];
+  __align__(16) float sqy[2][SH][SW];
+  __align__(16) float sqz[2][SH][SW];
+  __align__(16) float sw[2][SH][SW];
+  __align__(16) float su[SU ? 2 : 1][SU ? SH : 1][SU ? SW : 1];
+  double sred[4 * 5];
+};
+
+// One 64 x 8 tile of the xy plane over the slab [z0, z1).
+template <typename TS, bool CHECK, bool VEC, bool SU>
+__device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, int z1, Smem3<SU>& S,
+                                       double (&g)[5]) {
+  static_assert(!CHECK || SU, "the gap needs the u staging array");
+  constexpr int TX = 64, TY = 8, V = 2, TPR = TX / V, OX = 4;
+  auto& sqx = S.sqx;
+  auto& sqy = S.sqy;
+  auto& sqz = S.sqz;
+  auto& sw = S.sw;
+  auto& su = S.su;
+  const int tid = threadIdx.x;
+  const int W = A.W, H = A.H, D = A.D;
+  const long long P = A.P, SZ = A.SZ;
+  const int c0 = (tid % TPR) * V;
+  const int r0 = tid / TPR;      // owned row of the tile (0..7)
+  const int gx0 = x0 + c0, gy = y0 + r0;
+  const int nvxy = (gy < H) ? (W - gx0 < 0 ? 0 : (W - gx0 > V ? V : W - gx0)) : 0;
+  constexpr bool vec = VEC;
+  const Coef k = A.k;
+  const TS* qx_in = A.q_in;
+  const TS* qy_in = A.q_in + P;
+  const TS* qz_in = A.q_in + 2 * P;
+
+  // owner registers: values of plane s-1 (rotated each step)
+  float u_m[V], p_m[V], s_m[V];   // u, p_t, p_s at plane s-1
+  float q1z_mm[V];                // q_z^{k+1} at plane s-2
+  double dk_m[V];                 // div q^k at plane s-1 (gap, FP64)
+#pragma unroll
+  for (int e = 0; e < V; e++) {
+    u_m[e] = p_m[e] = s_m[e] = q1z_mm[e] = 0.f;
+    dk_m[e] = 0.0;
+  }
+
+#pragma unroll 1
+  for (int s = z0 - 2; s <= z1; s++) {
+    const int sl = s & 1, pl = sl ^ 1;   // slot of plane s, slot of plane s-1
+    const bool zin = s >= 0 && s < D;
+    const long long zoff = (long long)s * SZ;
+    // ---- 1. stage plane s: interior by owners, then halos
+    float u_c[V], p_c[V], s_c[V];
+    {
+      const int nv = zin ? nvxy : 0;
+      const long long idx = zoff + (long long)gy * W + gx0;
+      float qxv[V], qyv[V], qzv[V];
+      ldg<V>(qx_in, idx, nv, vec, qxv);
+      ldg<V>(qy_in, idx, nv, vec, qyv);
+      ldg<V>(qz_in, idx, nv, vec, qzv);
+      ldg<V>(A.u_in, idx, nv, vec, u_c);
+      ldg<V>(A.p_in, idx, nv, vec, p_c);
+      ldg<V>(A.ps_in, idx, nv, vec, s_c);
+#pragma unroll
+      for (int e = 0; e < V; e++) {
+        const int c = c0 + OX + e;
+        sqx[sl][r0 + 2][c] = qxv[e];
+        sqy[sl][r0 + 2][c] = qyv[e];
+        sqz[sl][r0 + 2][c] = qzv[e];
+        sw[sl][r0 + 2][c] = vterm(p_c[e], s_c[e], u_c[e], k.inv_c);
+        if (CHECK) su[sl][r0 + 2][c] = u_c[e];
+      }
+    }
+    for (int h = tid; h < 3 * (TX + 3) + 3 * TY; h += 256) {
+      int r, c;
+      if (h < 3 * (TX + 3)) {
+        const int rr = h / (TX + 3);
+        r = rr == 0 ? -2 : (rr == 1 ? -1 : TY);
+        c = h % (TX + 3) - 2;
+      } else {
+        const int hh = h - 3 * (TX + 3);
+        r = hh / 3;
+        const int cc = hh % 3;
+        c = cc == 0 ? -2 : (cc == 1 ? -1 : TX);
+      }
+      const int hx = x0 + c, hy = y0 + r;
+      const bool in = zin && hx >= 0 && hx < W && hy >= 0 && hy < H;
+      const long long idx = zoff + (long long)hy * W + hx;
+      sqx[sl][r + 2][c + OX] = in ? ld(qx_in, idx) : 0.f;
+      sqy[sl][r + 2][c + OX] = in ? ld(qy_in, idx) : 0.f;
+      sqz[sl][r + 2][c + OX] = in ? ld(qz_in, idx) : 0.f;
+    }
+    for (int h = tid; h < 2 * (TX + 2) + 2 * TY; h += 256) {
+      int r, c;
+      if (h < 2 * (TX + 2)) {
+        r = h < TX + 2 ? -1 : TY;
+        c = h % (TX + 2) - 1;
+      } else {
+        const int hh = h - 2 * (TX + 2);
+        r = hh >> 1;
+        c = (hh & 1) ? TX : -1;
+      }
+      const int hx = x0 + c, hy = y0 + r;
+      const bool in = zin && hx >= 0 && hx < W && hy >= 0 && hy < H;
+      const long long idx = zoff + (long long)hy * W + hx;
+      const float uu = in ? A.u_in[idx] : 0.f;
+      const float pp = in ? ld(A.p_in, idx) : 0.f;
+      const float ss = in ? ld(A.ps_in, idx) : 0.f;
+      sw[sl][r + 2][c + OX] = vterm(pp, ss, uu, k.inv_c);
+      if (CHECK) su[sl][r + 2][c + OX] = uu;
+    }
+    __syncthreads();
+    // ---- gap of plane s-1 of the input iterate (owned pixels)
+    if (CHECK && s - 1 >= z0 && s - 1 < z1) {
+      const int zz = s - 1;
+      const int nv = nvxy;
+      const long long idx = (long long)zz * SZ + (long long)gy * W + gx0;
+      float cs[V], ct[V];
+      ldg<V>(A.cap, idx, nv, vec, cs);
+      ldg<V>(A.cap + P, idx, nv, vec, ct);
+#pragma unroll
+      for (int e = 0; e < V; e++) {
+        if (e < nv) {
+          const int gx = gx0 + e, c = c0 + OX + e;
+          const double u0 = fmin(1.0, fmax(0.0, (double)su[pl][r0 + 2][c]));
+          const double gxx = gx + 1 < W ? fmin(1.0, fmax(0.0, (double)su[pl][r0 + 2][c + 1])) - u0 : 0.0;
+          const double gyy = gy + 1 < H ? fmin(1.0, fmax(0.0, (double)su[pl][r0 + 3][c])) - u0 : 0.0;
+          const double gzz = zz + 1 < D ? fmin(1.0, fmax(0.0, (double)su[sl][r0 + 2][c])) - u0 : 0.0;
+          const double dq = dk_m[e];
+          g[0] += (1.0 - u0) * (double)cs[e] + u0 * (double)ct[e];
+          g[1] += A.iso ? sqrt((gxx * gxx + gyy * gyy) + gzz * gzz) : (fabs(gxx) + fabs(gyy)) + fabs(gzz);
+          g[2] += fmin((double)cs[e], (double)ct[e] + dq);
+          const double r = ((double)p_m[e] - (double)s_m[e]) + dq;
+          g[3] += r * r;
+          g[4] += (double)s_m[e];
+        }
+      }
+    }
+    // ---- 2. w(s) = div q^k(s) + v(s) on rows -1..TY, cols -1..TX
+    for (int h = tid; h < (TY + 2) * (TX + 2); h += 256) {
+      const int r = h / (TX + 2) - 1, c = h % (TX + 2) - 1;
+      const int hx = x0 + c, hy = y0 + r;
+      const float d = div3(sqx[sl][r + 2][c + OX], sqx[sl][r + 2][c + OX - 1], sqy[sl][r + 2][c + OX],
+                           sqy[sl][r + 1][c + OX], sqz[sl][r + 2][c + OX], sqz[pl][r + 2][c + OX],
+                           hx + 1 < W, hx > 0, hy + 1 < H, hy > 0, s + 1 < D, s > 0);
+      sw[sl][r + 2][c + OX] = wterm(d, sw[sl][r + 2][c + OX]);
+    }
+    // FP64 div q^k at the owned pixels of plane s, for the next step's gap
+    // (q_z^k(s-1) is still intact in the other slot until step 3)
+    if (CHECK) {
+#pragma unroll
+      for (int e = 0; e < V; e++) {
+        const int gx = gx0 + e, c = c0 + OX + e;
+        dk_m[e] = (((gx + 1 < W) ? (double)sqx[sl][r0 + 2][c] : 0.0) - ((gx > 0) ? (double)sqx[sl][r0 + 2][c - 1] : 0.0)) +
+                  (((gy + 1 < H) ? (double)sqy[sl][r0 + 2][c] : 0.0) - ((gy > 0) ? (double)sqy[sl][r0 + 1][c] : 0.0)) +
+                  (((s + 1 < D) ? (double)sqz[sl][r0 + 2][c] : 0.0) - ((s > 0) ? (double)sqz[pl][r0 + 2][c] : 0.0));
+      }
+    }
+    __syncthreads();
+    // ---- 3. q^{k+1}(s-1) in place, rows -1..TY-1, cols -1..TX-1
+    if (s - 1 >= z0 - 1) {
+      for (int h = tid; h < (TY + 1) * (TX + 1); h += 256) {
+        const int r = h / (TX + 1) - 1, c = h % (TX + 1) - 1;
+        const int hx = x0 + c, hy = y0 + r;
+        const float w0 = sw[pl][r + 2][c + OX];
+        float qx = qstep(sqx[pl][r + 2][c + OX], sw[pl][r + 2][c + OX + 1], w0, hx + 1 < W, k.inv_a);
+        float qy = qstep(sqy[pl][r + 2][c + OX], sw[pl][r + 3][c + OX], w0, hy + 1 < H, k.inv_a);
+        float qz = qstep(sqz[pl][r + 2][c + OX], sw[sl][r + 2][c + OX], w0, s < D, k.inv_a);
+        proj3r(qx, qy, qz, k.alpha, A.iso);
+        sqx[pl][r + 2][c + OX] = quant3<TS>(qx);
+        sqy[pl][r + 2][c + OX] = quant3<TS>(qy);
+        sqz[pl][r + 2][c + OX] = quant3<TS>(qz);
+      }
+    }
+    __syncthreads();
+    // ---- 4. owned pixels of plane s-1: divergence, updates, stores
+    if (s - 1 >= z0 && s - 1 < z1) {
+      const int zz = s - 1;
+      const int nv = nvxy;
+      const long long idx = (long long)zz * SZ + (long long)gy * W + gx0;
+      float cs[V], ct[V], qxv[V], qyv[V], qzv[V], pn[V], psn[V], un[V];
+      ldg<V>(A.cap, idx, nv, vec, cs);
+      ldg<V>(A.cap + P, idx, nv, vec, ct);
+#pragma unroll
+      for (int e = 0; e < V; e++) {
+        const int gx = gx0 + e, c = c0 + OX + e;
+        qxv[e] = sqx[pl][r0 + 2][c];
+        qyv[e] = sqy[pl][r0 + 2][c];
+        qzv[e] = sqz[pl][r0 + 2][c];
+        const float d = div3(qxv[e], sqx[pl][r0 + 2][c - 1], qyv[e], sqy[pl][r0 + 1][c], qzv[e], q1z_mm[e],
+                             gx + 1 < W, gx > 0, gy + 1 < H, gy > 0, zz + 1 < D, zz > 0);
+        float t, sd = 0.f, sr = 0.f;
+        label_update(k, u_m[e], p_m[e], s_m[e], d, ct[e], pn[e], t, sd, sr);
+        psn[e] = finish_ps(k, s_m[e], sd, sr, true, cs[e]);
+        un[e] = finish_u(k, t, psn[e]);
+      }
+      if (A.write) {
+        stg<V>(A.q_out, idx, nv, vec, qxv);
+        stg<V>(A.q_out + P, idx, nv, vec, qyv);
+        stg<V>(A.q_out + 2 * P, idx, nv, vec, qzv);
+        stg<V>(A.p_out, idx, nv, vec, pn);
+        stg<V>(A.ps_out, idx, nv, vec, psn);
+        stg<V>(A.u_out, idx, nv, vec, un);
+      }
+    }
+    // ---- rotate owner registers
+#pragma unroll
+    for (int e = 0; e < V; e++) {
+      q1z_mm[e] = sqz[pl][r0 + 2][c0 + OX + e];
+      u_m[e] = u_c[e];
+      p_m[e] = p_c[e];
+      s_m[e] = s_c[e];
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace mf

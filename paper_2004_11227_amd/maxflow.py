@@ -39,7 +39,8 @@ class mf_params(ctypes.Structure):
                 ("sigma", ctypes.c_double), ("tau", ctypes.c_double), ("a", ctypes.c_double),
                 ("a_tilde", ctypes.c_double), ("a1", ctypes.c_double), ("a2", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("check_every", ctypes.c_int32), ("tile_rows", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("promote_gap", ctypes.c_double), ("promote_iter", ctypes.c_int32)]
 
 
 class mf_gap(ctypes.Structure):
@@ -111,7 +112,8 @@ def _check(status, allow=(MF_OK,)):
 
 def make_params(shape, model="two", method="eb", tv="iso", storage="f32", variant="fused",
                 nlabels=2, alpha=0.5, c=0.0, relax=0.0, sigma=0.0, tau=0.0, a=0.0, a_tilde=0.0,
-                a1=0.0, a2=0.0, max_iter=1000, tol=1e-4, check_every=10, tile_rows=0) -> mf_params:
+                a1=0.0, a2=0.0, max_iter=1000, tol=1e-4, check_every=10, tile_rows=0,
+                promote_gap=0.0, promote_iter=0) -> mf_params:
     shape = tuple(int(s) for s in shape)
     p = mf_params()
     p.ndim = len(shape)
@@ -126,6 +128,7 @@ def make_params(shape, model="two", method="eb", tv="iso", storage="f32", varian
     p.alpha, p.c, p.relax, p.sigma, p.tau = alpha, c, relax, sigma, tau
     p.a, p.a_tilde, p.a1, p.a2 = a, a_tilde, a1, a2
     p.max_iter, p.tol, p.check_every, p.tile_rows = int(max_iter), float(tol), int(check_every), int(tile_rows)
+    p.promote_gap, p.promote_iter = float(promote_gap), int(promote_iter)
     return p
 
 
@@ -159,6 +162,8 @@ class Solver:
             raise ValueError(f"caps must have {ncap} planes")
         self.device = caps.device
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # create() reads `caps` on the solver stream
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
         nbytes = workspace_bytes(self.params)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         h = ctypes.c_void_p()
@@ -232,3 +237,115 @@ class Solver:
 
     def import_state(self, blob: torch.Tensor, iter: int):
         _check(lib().maxflow_import_state(self._h, ctypes.c_void_p(blob.data_ptr()), int(iter)))
+
+
+# ---------------------------------------------------------------------------- pool
+
+_POOL_SIG = {
+    "mf_pool_footprint": (ctypes.c_size_t, [ctypes.POINTER(mf_params)]),
+    "mf_pool_table_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
+    "mf_pool_create": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "mf_pool_admit": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(mf_params), ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_int64)]),
+    "mf_pool_advance": (ctypes.c_int32, [ctypes.c_void_p]),
+    "mf_pool_poll": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(mf_gap),
+                                      ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "mf_pool_retire": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "mf_pool_stats": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+    "mf_pool_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
+    "mf_pool_promotions": (ctypes.c_int64, [ctypes.c_void_p]),
+}
+EXPORTS += list(_POOL_SIG)
+
+
+def _pool_lib():
+    L = lib()
+    if not getattr(L, "_pool_ready", False):
+        for name, (res, args) in _POOL_SIG.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        L._pool_ready = True
+    return L
+
+
+def pool_footprint(shape, **kw) -> int:
+    p = make_params(shape, **kw)
+    n = _pool_lib().mf_pool_footprint(ctypes.byref(p))
+    if n == 0:
+        raise MaxflowError(MF_EINVAL, last_error())
+    return int(n)
+
+
+class Pool:
+    """Continuous-batching pool over one device arena (a torch uint8 tensor
+    owned here).  admit() returns a solve id, or None when the arena, the slot
+    table or the class work list is full (MF_ENOMEM)."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 256, max_tiles: int = 1 << 16,
+                 steps_per_advance: int = 10, device=None, stream: torch.cuda.Stream | None = None):
+        L = _pool_lib()
+        self.device = torch.device(device or "cuda")
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        _check(L.mf_pool_create(ctypes.c_void_p(self.arena.data_ptr()), int(arena_bytes), int(max_slots),
+                                int(max_tiles), int(steps_per_advance), ctypes.c_void_p(self.stream.cuda_stream),
+                                ctypes.byref(h)))
+        self._h = h
+        self.max_slots = max_slots
+        self.meta = {}
+        self._ids = (ctypes.c_int64 * max_slots)()
+        self._gaps = (mf_gap * max_slots)()
+
+    def admit(self, caps: torch.Tensor, **kw):
+        shape = tuple(caps.shape[1:])
+        p = make_params(shape, **kw)
+        if caps.dtype != torch.float32 or not caps.is_cuda or not caps.is_contiguous():
+            raise ValueError("caps must be a contiguous float32 device tensor")
+        sid = ctypes.c_int64()
+        # the admission copies read `caps` on the pool stream
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        st = _pool_lib().mf_pool_admit(self._h, ctypes.byref(p), ctypes.c_void_p(caps.data_ptr()),
+                                       ctypes.byref(sid))
+        if st == MF_ENOMEM:
+            return None
+        _check(st)
+        L = 1 if kw.get("model", "two") == "two" else int(kw.get("nlabels", 2))
+        self.meta[int(sid.value)] = (shape, L)
+        return int(sid.value)
+
+    def advance(self):
+        _check(_pool_lib().mf_pool_advance(self._h))
+
+    def poll(self):
+        n = ctypes.c_int32()
+        _check(_pool_lib().mf_pool_poll(self._h, self._ids, self._gaps, self.max_slots, ctypes.byref(n)))
+        return [(int(self._ids[i]), self._gaps[i].as_dict()) for i in range(n.value)]
+
+    def retire(self, sid: int, want_u: bool = True, want_labels: bool = True):
+        shape, L = self.meta.pop(sid)
+        u = torch.empty((L,) + shape, dtype=torch.float32, device=self.device) if want_u else None
+        lab = torch.empty(shape, dtype=torch.int32, device=self.device) if want_labels else None
+        _check(_pool_lib().mf_pool_retire(self._h, int(sid), ctypes.c_void_p(u.data_ptr() if u is not None else 0),
+                                          ctypes.c_void_p(lab.data_ptr() if lab is not None else 0)))
+        return u, lab
+
+    def stats(self):
+        a, used, free = ctypes.c_int32(), ctypes.c_size_t(), ctypes.c_size_t()
+        _check(_pool_lib().mf_pool_stats(self._h, ctypes.byref(a), ctypes.byref(used), ctypes.byref(free)))
+        return dict(active=a.value, bytes_in_use=used.value, largest_free=free.value,
+                    promotions=int(_pool_lib().mf_pool_promotions(self._h)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _pool_lib().mf_pool_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

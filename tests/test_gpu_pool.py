@@ -1,0 +1,177 @@
+"""The batched pool (persistent work-list kernels, hipGraph super-steps,
+device-side convergence decisions) through the C ABI.
+
+* every solve's result is bit-identical alone and in a mix of grids of
+  different sizes and models, with the same stop iterate;
+* a pool solve equals the single-solve API with the same storage, bit for
+  bit (same tile bodies);
+* FP32 pool iterates match the FP64 oracle;
+* admission is decided by footprint and memory is reused after retirement.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2004_11227_amd import maxflow as mfx
+from paper_2004_11227_amd import serving, synth
+
+from _gpu import banner, gpu_solver, need_gpu, oracle_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _mix():
+    out = []
+    rng = np.random.default_rng(11)
+    for i, (shape, model, n) in enumerate([((64, 64), "two", 2), ((131, 77), "two", 2), ((200, 256), "two", 2),
+                                           ((90, 97), "potts", 3), ((64, 130), "potts", 4),
+                                           ((75, 75), "potts", 8), ((70, 128), "potts", 2),
+                                           ((20, 24, 37), "two", 2), ((33, 40, 64), "two", 2)]):
+        if len(shape) == 3:
+            caps = synth.two_label_caps(synth.ellipsoid_volume(*shape, 4, 0.1, 500 + i))
+        elif model == "two":
+            caps = synth.two_label_caps(synth.ellipse_image(*shape, 5, 0.12, 500 + i))
+        else:
+            img, _ = synth.voronoi_image(*shape, n, 0.12, 500 + i, ncells=12)
+            caps = synth.potts_caps(img, n)
+        kw = dict(model=model, nlabels=n, method="eb" if i % 2 else "fg", alpha=float(rng.uniform(0.2, 0.5)),
+                  storage="bf16", tol=1e-4, max_iter=600, check_every=10, promote_gap=2e-3, promote_iter=200)
+        out.append((torch.from_numpy(caps.astype(np.float32)).cuda(), kw))
+    return out
+
+
+def _run_pool(items, steps=10):
+    pool = mfx.Pool(1 << 30, max_slots=64, max_tiles=1 << 15, steps_per_advance=steps)
+    ids = [pool.admit(c, **kw) for c, kw in items]
+    assert all(i is not None for i in ids)
+    res = {}
+    while len(res) < len(ids):
+        pool.advance()
+        for sid, g in pool.poll():
+            u, lab = pool.retire(sid)
+            res[sid] = (g, u.cpu().numpy(), lab.cpu().numpy())
+    pool.close()
+    return [res[i] for i in ids]
+
+
+def test_alone_equals_mix_bitwise():
+    banner("pool alone vs mix")
+    items = _mix()
+    mixed = _run_pool(items)
+    for k, it in enumerate(items):
+        alone = _run_pool([it])[0]
+        gm, um, lm = mixed[k]
+        ga, ua, la = alone
+        assert gm["iter"] == ga["iter"] and gm["status"] == ga["status"], (k, gm, ga)
+        assert np.array_equal(um, ua) and np.array_equal(lm, la), k
+        assert gm["status"] in (0, 1)
+        if gm["status"] == 0:
+            assert gm["rel_gap"] <= 1e-4
+
+
+@pytest.mark.parametrize("model,n,storage", [("two", 2, "bf16"), ("potts", 4, "bf16"), ("two", 2, "f32"),
+                                             ("potts", 3, "f32")])
+def test_pool_equals_single_solve_api(model, n, storage):
+    banner(f"pool vs single {model} {n} {storage}")
+    shape = (150, 203)
+    if model == "two":
+        caps = synth.two_label_caps(synth.ellipse_image(*shape, 6, 0.12, 77))
+    else:
+        img, _ = synth.voronoi_image(*shape, n, 0.12, 77, ncells=16)
+        caps = synth.potts_caps(img, n)
+    kw = dict(model=model, nlabels=n, method="eb", alpha=0.35, storage=storage, tol=1e-3, max_iter=500,
+              check_every=10)
+    t = torch.from_numpy(caps.astype(np.float32)).cuda()
+    g, u, lab = _run_pool([(t, kw)])[0]
+    s = mfx.Solver(t, **kw)
+    gs = s.solve()
+    us = s.u().cpu().numpy()
+    s.close()
+    assert gs["iter"] == g["iter"] and gs["status"] == g["status"]
+    assert np.array_equal(us, u)
+    assert abs(gs["rel_gap"] - g["rel_gap"]) <= 1e-9 * max(1.0, abs(gs["rel_gap"]))
+
+
+def test_pool_fp32_matches_oracle():
+    banner("pool fp32 vs oracle")
+    shape = (97, 130)
+    caps = synth.two_label_caps(synth.ellipse_image(*shape, 5, 0.1, 91)).astype(np.float32).astype(np.float64)
+    kw = dict(model="two", method="eb", relax=1.5, alpha=0.5, storage="f32", tol=0.0, max_iter=120,
+              check_every=10)
+    g, u, _ = _run_pool([(torch.from_numpy(caps.astype(np.float32)).cuda(), kw)])[0]
+    assert g["iter"] == 120 and g["status"] == 1
+    pr = oracle_problem(shape, kw)
+    st = oracle.init_state(pr, caps)
+    oracle.step(pr, caps, st, 120)
+    assert np.max(np.abs(u - st.u)) <= 1e-4
+    e = oracle.energy(pr, caps, st)
+    assert abs(g["rel_gap"] - e["rel_gap"]) < 1e-5
+
+
+def test_bf16_promotion_reaches_tolerance():
+    """BF16 flow storage floors the Potts gap near 1e-3; with promotion the
+    solve finishes in FP32 storage and reaches 1e-4."""
+    banner("pool promotion")
+    img, _ = synth.voronoi_image(256, 256, 4, 0.15, 2004, ncells=32)
+    caps = torch.from_numpy(synth.potts_caps(img, 4).astype(np.float32)).cuda()
+    base = dict(model="potts", nlabels=4, method="eb", alpha=0.3, storage="bf16", tol=1e-4, max_iter=1000)
+    pool = mfx.Pool(1 << 30, max_slots=8, max_tiles=1 << 14, steps_per_advance=10)
+    a = pool.admit(caps, **base)
+    b = pool.admit(caps, promote_gap=2e-3, promote_iter=300, **base)
+    res = {}
+    while len(res) < 2:
+        pool.advance()
+        for sid, g in pool.poll():
+            pool.retire(sid)
+            res[sid] = g
+    assert pool.stats()["promotions"] == 1
+    pool.close()
+    assert res[a]["status"] == 1 and res[a]["rel_gap"] > 1e-4     # floored in BF16
+    assert res[b]["status"] == 0 and res[b]["rel_gap"] <= 1e-4     # finished in FP32
+
+
+def test_admission_by_footprint_and_reuse():
+    banner("pool footprint admission")
+    shape = (256, 256)
+    kw = dict(model="two", method="eb", alpha=0.5, storage="bf16", tol=1e-3, max_iter=200)
+    fp = mfx.pool_footprint(shape, **kw)
+    table = mfx._pool_lib().mf_pool_table_bytes(8, 4096)
+    pool = mfx.Pool(table + 2 * fp + 4096, max_slots=8, max_tiles=4096, steps_per_advance=10)
+    caps = torch.from_numpy(synth.two_label_caps(synth.ellipse_image(*shape, 5, 0.1, 3)).astype(np.float32)).cuda()
+    a = pool.admit(caps, **kw)
+    b = pool.admit(caps, **kw)
+    c = pool.admit(caps, **kw)
+    assert a is not None and b is not None and c is None     # third does not fit
+    done = []
+    while not done:
+        pool.advance()
+        done = pool.poll()
+    for sid, _ in done:
+        pool.retire(sid)
+    c = pool.admit(caps, **kw)
+    assert c is not None                                        # memory reused
+    pool.close()
+
+
+def test_serving_loop_end_to_end():
+    banner("serving loop")
+    reqs = synth.serving_trace(24, seed=7, rate=None, lo=48, hi=320, frac3d=0.1, side3d=32)
+    caps = {r.rid: torch.from_numpy(synth.request_caps(r).astype(np.float32)).cuda() for r in reqs}
+
+    def kw_of(r):
+        return dict(model=r.model, nlabels=r.nlabels, method="eb", alpha=r.alpha, storage="bf16", tol=1e-4,
+                    max_iter=1000, check_every=10)
+
+    pool = mfx.Pool(2 << 30, max_slots=32, max_tiles=1 << 15, steps_per_advance=10)
+    be = serving.PoolBackend(pool, lambda r: caps[r.rid], kw_of)
+    rep = serving.serve(reqs, be)
+    pool.close()
+    assert len(rep.records) == 24
+    assert all(r.status in (0, 1) for r in rep.records)
+    assert all(r.iters % 10 == 0 or r.iters == 1000 for r in rep.records)
