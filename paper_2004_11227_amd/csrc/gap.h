@@ -8,6 +8,7 @@ namespace mf {
 template <typename TS>
 struct KG {
   int W, H, D;
+  int pitch;          // row stride (>= W)
   long long P, n;
   const TS* cap;
   const float* u;
@@ -21,7 +22,7 @@ struct KG {
 
 __device__ __forceinline__ double clip01(float v) { return fmin(1.0, fmax(0.0, (double)v)); }
 
-// Adds to g the terms of pixel (x, y, z) = idx: primal data and TV at the
+// Adds to g the terms of pixel (x, y, z) at storage index idx: primal data and TV at the
 // projected u (clip to [0,1] for two labels, pointwise simplex projection for
 // Potts: relaxed min-cut eq. seg:chanvese / relaxed Potts eq. relaxed-potts),
 // the dual term (min(C_s, C_t + div q) or min_i(C_i + div q_i): the max-flow
@@ -29,7 +30,8 @@ __device__ __forceinline__ double clip01(float v) { return fmin(1.0, fmax(0.0, (
 // squared conservation residual and p_s.
 template <int NL, bool TWO, int NDIM, typename TS>
 __device__ __forceinline__ void gap_px(const KG<TS>& A, long long idx, int x, int y, int z, double (&g)[5]) {
-  const long long sz = (long long)A.W * A.H;
+  const long long sz = (long long)A.pitch * A.H;
+  const long long sy = A.pitch;
   const bool hx = x + 1 < A.W, hy = y + 1 < A.H, hz = NDIM == 3 && z + 1 < A.D;
   const double ps = (double)ld(A.ps, idx);
   double dq[NL];
@@ -37,7 +39,7 @@ __device__ __forceinline__ void gap_px(const KG<TS>& A, long long idx, int x, in
   for (int l = 0; l < NL; l++) {
     const TS* q = A.q + (long long)(NDIM * l) * A.P;
     double d = ((hx ? (double)ld(q, idx) : 0.0) - (x > 0 ? (double)ld(q, idx - 1) : 0.0)) +
-               ((hy ? (double)ld(q + A.P, idx) : 0.0) - (y > 0 ? (double)ld(q + A.P, idx - A.W) : 0.0));
+               ((hy ? (double)ld(q + A.P, idx) : 0.0) - (y > 0 ? (double)ld(q + A.P, idx - sy) : 0.0));
     if (NDIM == 3)
       d += (hz ? (double)ld(q + 2 * A.P, idx) : 0.0) - (z > 0 ? (double)ld(q + 2 * A.P, idx - sz) : 0.0);
     dq[l] = d;
@@ -46,7 +48,7 @@ __device__ __forceinline__ void gap_px(const KG<TS>& A, long long idx, int x, in
     const double Cs = (double)ld(A.cap, idx), Ct = (double)ld(A.cap + A.P, idx);
     const double u0 = clip01(A.u[idx]);
     const double gx = hx ? clip01(A.u[idx + 1]) - u0 : 0.0;
-    const double gy = hy ? clip01(A.u[idx + A.W]) - u0 : 0.0;
+    const double gy = hy ? clip01(A.u[idx + sy]) - u0 : 0.0;
     const double gz = hz ? clip01(A.u[idx + sz]) - u0 : 0.0;
     g[0] += (1.0 - u0) * Cs + u0 * Ct;
     g[1] += A.iso ? sqrt((gx * gx + gy * gy) + gz * gz) : (fabs(gx) + fabs(gy)) + fabs(gz);
@@ -62,7 +64,7 @@ __device__ __forceinline__ void gap_px(const KG<TS>& A, long long idx, int x, in
     for (int l = 0; l < NL; l++) v[l] = hx ? (double)A.u[(long long)l * A.P + idx + 1] : 0.0;
     simplex_proj<NL>(v, wx);
 #pragma unroll
-    for (int l = 0; l < NL; l++) v[l] = hy ? (double)A.u[(long long)l * A.P + idx + A.W] : 0.0;
+    for (int l = 0; l < NL; l++) v[l] = hy ? (double)A.u[(long long)l * A.P + idx + sy] : 0.0;
     simplex_proj<NL>(v, wy);
     if (NDIM == 3) {
 #pragma unroll

@@ -21,6 +21,7 @@ static K2<TS> make_k2(const SweepDesc& d) {
   K2<TS> a;
   a.W = d.g.W;
   a.H = d.g.H;
+  a.pitch = d.g.W;
   a.P = d.g.plane;
   a.tiles_x = (d.g.W + 63) / 64;
   a.cap = (const TS*)d.cap;

@@ -26,6 +26,7 @@ static hipError_t fused3d_ts(const SweepDesc& d, hipStream_t s) {
   a.W = d.g.W;
   a.H = d.g.H;
   a.D = d.g.D;
+  a.pitch = d.g.W;
   a.P = d.g.plane;
   a.SZ = (long long)d.g.W * d.g.H;
   a.tiles_x = (d.g.W + 63) / 64;

@@ -35,6 +35,7 @@ static hipError_t gap_nl(const GapDesc& d, hipStream_t s) {
   a.W = d.g.W;
   a.H = d.g.H;
   a.D = d.g.D;
+  a.pitch = d.g.W;
   a.P = d.g.plane;
   a.n = d.g.npix();
   a.cap = (const TS*)d.cap;
@@ -161,15 +162,16 @@ hipError_t launch_convert_planes(const void* src, bool sb, void* dst, bool db, l
 
 // ------------------------------------------------------------------ labels
 __global__ __launch_bounds__(256) void k_labels(int nl, int two, long long n, long long P, const float* u,
-                                                int32_t* lab) {
+                                                int32_t* lab, int W, int pitch) {
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const long long j = (i / W) * pitch + i % W;   // storage index of dense pixel i
     if (two) {
-      lab[i] = u[i] > 0.5f ? 1 : 0;
+      lab[i] = u[j] > 0.5f ? 1 : 0;
     } else {
       int best = 0;
-      float bv = u[i];
+      float bv = u[j];
       for (int l = 1; l < nl; l++) {
-        const float v = u[(long long)l * P + i];
+        const float v = u[(long long)l * P + j];
         if (v > bv) {
           bv = v;
           best = l;
@@ -180,9 +182,34 @@ __global__ __launch_bounds__(256) void k_labels(int nl, int two, long long n, lo
   }
 }
 
-hipError_t launch_labels(const Geom& g, int nl, bool two, const float* u, int32_t* lab, hipStream_t s) {
+hipError_t launch_labels(const Geom& g, int nl, bool two, const float* u, int32_t* lab, hipStream_t s, int pitch) {
   const long long n = g.npix();
-  hipLaunchKernelGGL(k_labels, dim3(blocks_for(n)), dim3(256), 0, s, nl, two ? 1 : 0, n, g.plane, u, lab);
+  hipLaunchKernelGGL(k_labels, dim3(blocks_for(n)), dim3(256), 0, s, nl, two ? 1 : 0, n, g.plane, u, lab, g.W,
+                     pitch > 0 ? pitch : g.W);
+  return hipGetLastError();
+}
+
+// Copy `np` planes of `rows` x W elements between row strides (and storage
+// types); destination pads (columns W .. dpitch-1) are set to 0.
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_pitch_copy(const TI* src, long long sp, int spitch, TO* dst, long long dp,
+                                                    int dpitch, int W, long long rows, int np) {
+  const long long n = rows * dpitch;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const long long r = i / dpitch;
+    const int x = (int)(i % dpitch);
+    for (int c = 0; c < np; c++)
+      st(dst + (long long)c * dp, i, x < W ? ld(src + (long long)c * sp, r * spitch + x) : 0.f);
+  }
+}
+
+hipError_t launch_pitch_copy(const void* src, bool sb, long long sp, int spitch, void* dst, bool db, long long dp,
+                             int dpitch, int W, long long rows, int np, hipStream_t s) {
+  const dim3 g(blocks_for(rows * dpitch)), b(256);
+  if (sb && db) hipLaunchKernelGGL((k_pitch_copy<bf16_t, bf16_t>), g, b, 0, s, (const bf16_t*)src, sp, spitch, (bf16_t*)dst, dp, dpitch, W, rows, np);
+  else if (sb) hipLaunchKernelGGL((k_pitch_copy<bf16_t, float>), g, b, 0, s, (const bf16_t*)src, sp, spitch, (float*)dst, dp, dpitch, W, rows, np);
+  else if (db) hipLaunchKernelGGL((k_pitch_copy<float, bf16_t>), g, b, 0, s, (const float*)src, sp, spitch, (bf16_t*)dst, dp, dpitch, W, rows, np);
+  else hipLaunchKernelGGL((k_pitch_copy<float, float>), g, b, 0, s, (const float*)src, sp, spitch, (float*)dst, dp, dpitch, W, rows, np);
   return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
-// Persistent pool kernels: one launch per class walks that class's work list
-// of (solve, tile) items drawn from many grids of different sizes, and
+// Pool kernels: one launch per class walks that class's work list of
+// (solve, tile) items drawn from many grids of different sizes (one item per
+// workgroup when the grid is sized to the list, grid-stride otherwise), and
 // advances every running solve by one iteration; the bookkeeping launch then
 // takes each solve's gap decision and advances its counter.  The tile bodies
 // are the same device functions as the single-solve kernels, so a solve
@@ -12,16 +13,17 @@
 
 namespace mf {
 
-// Item range of this workgroup: the list is cut into 8 contiguous chunks and
-// the workgroups dispatched to one XCD (block b runs on XCD b & 7) walk one
-// chunk, so neighbouring tiles of a grid share that XCD's L2.  The grid is a
-// multiple of 8 workgroups.
-__device__ __forceinline__ void xcd_range(int n, int& it0, int& it1, int& step) {
-  const int G = gridDim.x, b = blockIdx.x;
-  const int x = b & 7, lb = b >> 3, per = G >> 3;
-  it0 = (int)((long long)n * x / 8) + lb;
-  it1 = (int)((long long)n * (x + 1) / 8);
-  step = per;
+// Work item of this workgroup, or -1.  The list is cut into 8 contiguous
+// chunks and the workgroups dispatched to one XCD (block b runs on XCD b & 7)
+// take the items of one chunk, so neighbouring tiles of a grid share that
+// XCD's L2.  The host sizes the grid to 8 * ceil(n / 8) workgroups, one item
+// each: a loop over several items per workgroup doubles the register
+// footprint of the tile bodies (the compiler keeps the next item's state
+// live) and costs occupancy.
+__device__ __forceinline__ int xcd_item(int n) {
+  const int b = blockIdx.x, x = b & 7;
+  const int it = (int)((long long)n * x / 8) + (b >> 3);
+  return it < (int)((long long)n * (x + 1) / 8) ? it : -1;
 }
 
 template <typename TS>
@@ -30,6 +32,7 @@ __device__ __forceinline__ K2<TS> slot_k2(const PoolSlot& sl) {
   const int src = (int)(sl.iter & 1), dst = src ^ 1;
   a.W = sl.W;
   a.H = sl.H;
+  a.pitch = sl.pitch;
   a.P = sl.P;
   a.tiles_x = sl.tiles_x;
   a.cap = (const TS*)sl.cap;
@@ -56,43 +59,38 @@ __device__ __forceinline__ K2<TS> slot_k2(const PoolSlot& sl) {
 template <int NL, bool TWO, typename TS, int TY, bool CHECK, bool VEC>
 __global__ __launch_bounds__(256) void k_pool2d(PoolDev d, int cls) {
   __shared__ Smem2<TY, CHECK> S;
-  constexpr int V = TY >= 16 ? 4 : 2;
-  const int n = d.counts[cls];
-  int it0, it1, step;
-  xcd_range(n, it0, it1, step);
-  for (int it = it0; it < it1; it += step) {
-    const WorkItem w = d.items[cls][it];
-    PoolSlot* sl = d.slots + w.slot;
-    if (sl->state != SLOT_RUNNING) continue;
-    // two-label gaps are fused into the sweep; Potts gaps run in k_pool_gap2d
-    const bool check = TWO && sl->check_now != 0;
-    if (check != CHECK || ((sl->W % V) == 0) != VEC) continue;
-    const K2<TS> A = slot_k2<TS>(*sl);
-    double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    tile2d<NL, TWO, TS, CHECK, TY, VEC, CHECK>(A, w.x0, w.y0, S, g);
-    if (CHECK) block_accumulate<5, 4>(g, &sl->acc[0][0], S.sred);
-    __syncthreads();
-  }
+  const int it = xcd_item(d.counts[cls]);
+  if (it < 0) return;
+  const WorkItem w = d.items[cls][it];
+  PoolSlot* sl = d.slots + w.slot;
+  if (sl->state != SLOT_RUNNING) return;
+  // two-label gaps are fused into the sweep; Potts gaps run in k_pool_gap2d
+  const bool check = TWO && sl->check_now != 0;
+  if (check != CHECK) return;
+  const K2<TS> A = slot_k2<TS>(*sl);
+  double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  tile2d<NL, TWO, TS, CHECK, TY, VEC, CHECK>(A, w.x0, w.y0, S, g);
+  if (CHECK) block_accumulate<5, 4>(g, &sl->acc[0][0], S.sred);
 }
 
 template <typename TS, bool CHECK, bool VEC>
 __global__ __launch_bounds__(256) void k_pool3d(PoolDev d, int cls) {
   __shared__ Smem3<CHECK> S;
-  const int n = d.counts[cls];
-  int it0, it1, step;
-  xcd_range(n, it0, it1, step);
-  for (int it = it0; it < it1; it += step) {
-    const WorkItem w = d.items[cls][it];
-    PoolSlot* sl = d.slots + w.slot;
-    if (sl->state != SLOT_RUNNING) continue;
-    if ((sl->check_now != 0) != CHECK || ((sl->W % 2) == 0) != VEC) continue;
+  const int it = xcd_item(d.counts[cls]);
+  if (it < 0) return;
+  const WorkItem w = d.items[cls][it];
+  PoolSlot* sl = d.slots + w.slot;
+  if (sl->state != SLOT_RUNNING) return;
+  if ((sl->check_now != 0) != CHECK) return;
+  {
     K3<TS> A;
     const int src = (int)(sl->iter & 1), dst = src ^ 1;
     A.W = sl->W;
     A.H = sl->H;
     A.D = sl->D;
+    A.pitch = sl->pitch;
     A.P = sl->P;
-    A.SZ = (long long)sl->W * sl->H;
+    A.SZ = (long long)sl->pitch * sl->H;
     A.tiles_x = sl->tiles_x;
     A.tiles_y = sl->tiles_y;
     A.tz = sl->tz;
@@ -114,7 +112,6 @@ __global__ __launch_bounds__(256) void k_pool3d(PoolDev d, int cls) {
     double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     tile3d<TS, CHECK, VEC, CHECK>(A, w.x0, w.y0, w.z0, z1, S, g);
     if (CHECK) block_accumulate<5, 4>(g, &sl->acc[0][0], S.sred);
-    __syncthreads();
   }
 }
 
@@ -123,18 +120,18 @@ __global__ __launch_bounds__(256) void k_pool3d(PoolDev d, int cls) {
 template <int NL, typename TS, int TY>
 __global__ __launch_bounds__(256) void k_pool_gap2d(PoolDev d, int cls) {
   __shared__ double sred[4 * 5];
-  const int n = d.counts[cls];
-  int it0, it1, step;
-  xcd_range(n, it0, it1, step);
-  for (int it = it0; it < it1; it += step) {
-    const WorkItem w = d.items[cls][it];
-    PoolSlot* sl = d.slots + w.slot;
-    if (sl->state != SLOT_RUNNING || !sl->check_now) continue;
+  const int it = xcd_item(d.counts[cls]);
+  if (it < 0) return;
+  const WorkItem w = d.items[cls][it];
+  PoolSlot* sl = d.slots + w.slot;
+  if (sl->state != SLOT_RUNNING || !sl->check_now) return;
+  {
     KG<TS> A;
     const int src = (int)(sl->iter & 1);
     A.W = sl->W;
     A.H = sl->H;
     A.D = 1;
+    A.pitch = sl->pitch;
     A.P = sl->P;
     A.n = (long long)sl->W * sl->H;
     A.cap = (const TS*)sl->cap;
@@ -146,24 +143,27 @@ __global__ __launch_bounds__(256) void k_pool_gap2d(PoolDev d, int cls) {
     A.done = nullptr;
     A.iso = sl->iso;
     double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
     for (int e = threadIdx.x; e < 64 * TY; e += 256) {
       const int x = w.x0 + (e & 63), y = w.y0 + (e >> 6);
-      if (x < A.W && y < A.H) gap_px<NL, false, 2, TS>(A, (long long)y * A.W + x, x, y, 0, g);
+      if (x < A.W && y < A.H) gap_px<NL, false, 2, TS>(A, (long long)y * A.pitch + x, x, y, 0, g);
     }
     block_accumulate<5, 4>(g, &sl->acc[0][0], sred);
-    __syncthreads();
   }
 }
 
 // One workgroup (64 threads) per slot: sum the 64 accumulator rows, decide,
 // clear them, advance the iteration counter and publish the status.  Status
 // codes follow mf_status: 0 converged, 1 cap reached, -4 diverged.
-__global__ __launch_bounds__(64) void k_pool_book(PoolDev d) {
+// `check_step`: this super-step ran the gap-carrying launches.  A solve whose
+// check falls on another step (cannot happen with the admission rules) waits
+// for the next check step instead of deciding on empty accumulators.
+__global__ __launch_bounds__(64) void k_pool_book(PoolDev d, int check_step) {
   PoolSlot* sl = d.slots + blockIdx.x;
   const int t = threadIdx.x;
-
   if (sl->state != SLOT_RUNNING) return;
   const bool check = sl->check_now != 0;
+  if (check && !check_step) return;
   double v[5];
 #pragma unroll
   for (int j = 0; j < 5; j++) v[j] = check ? wave_sum(sl->acc[t][j]) : 0.0;
@@ -230,7 +230,7 @@ static const void* pool_kernel_ts(int model) {
   }
 }
 
-static const void* pool_kernel(int cls, bool check, bool vec) {
+const void* pool_kernel(int cls, bool check, bool vec) {
   const int model = cls % kPoolModels;
   const bool bf16 = cls >= kPoolModels;
   if (bf16) {
@@ -241,55 +241,25 @@ static const void* pool_kernel(int cls, bool check, bool vec) {
   return vec ? pool_kernel_ts<float, false, true>(model) : pool_kernel_ts<float, false, false>(model);
 }
 
-// Workgroups of a persistent launch: as many as can be resident at once on
-// the device (occupancy x CUs), a multiple of 8 for the XCD partition.
-int pool_grid(int cls, bool check, bool vec) {
-  const void* k = pool_kernel(cls, check, vec);
-  if (!k) return 0;
-  int per_cu = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
-  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    cus = 256;
-  int g = per_cu * cus;
-  g = g < 8 ? 8 : g - g % 8;
-  return g;
-}
-
-hipError_t launch_pool_class(const PoolDev& d, int cls, int grid, bool check, bool vec, hipStream_t s) {
-  const void* k = pool_kernel(cls, check, vec);
-  if (!k || grid <= 0) return hipSuccess;
-  PoolDev dd = d;
-  int c = cls;
-  void* args[] = {&dd, &c};
-  return hipLaunchKernel(k, dim3(grid), dim3(256), args, 0, s);
-}
-
-hipError_t launch_pool_gap(const PoolDev& d, int cls, int grid, hipStream_t s) {
+const void* pool_gap_kernel(int cls) {
   const int model = cls % kPoolModels;
-  const bool bf16 = cls >= kPoolModels;
-  const dim3 g(grid), b(256);
-  if (model == 0 || model == 5) return hipSuccess;   // two-label gaps are fused
-  if (bf16) {
+  if (model == 0 || model == 5) return nullptr;   // two-label gaps are fused
+  if (cls >= kPoolModels) {
     switch (model) {
-      case 1: hipLaunchKernelGGL((k_pool_gap2d<2, bf16_t, 8>), g, b, 0, s, d, cls); break;
-      case 2: hipLaunchKernelGGL((k_pool_gap2d<3, bf16_t, 8>), g, b, 0, s, d, cls); break;
-      case 3: hipLaunchKernelGGL((k_pool_gap2d<4, bf16_t, 8>), g, b, 0, s, d, cls); break;
-      default: hipLaunchKernelGGL((k_pool_gap2d<8, bf16_t, 8>), g, b, 0, s, d, cls); break;
-    }
-  } else {
-    switch (model) {
-      case 1: hipLaunchKernelGGL((k_pool_gap2d<2, float, 8>), g, b, 0, s, d, cls); break;
-      case 2: hipLaunchKernelGGL((k_pool_gap2d<3, float, 8>), g, b, 0, s, d, cls); break;
-      case 3: hipLaunchKernelGGL((k_pool_gap2d<4, float, 8>), g, b, 0, s, d, cls); break;
-      default: hipLaunchKernelGGL((k_pool_gap2d<8, float, 8>), g, b, 0, s, d, cls); break;
+      case 1: return (const void*)k_pool_gap2d<2, bf16_t, 8>;
+      case 2: return (const void*)k_pool_gap2d<3, bf16_t, 8>;
+      case 3: return (const void*)k_pool_gap2d<4, bf16_t, 8>;
+      default: return (const void*)k_pool_gap2d<8, bf16_t, 8>;
     }
   }
-  return hipGetLastError();
+  switch (model) {
+    case 1: return (const void*)k_pool_gap2d<2, float, 8>;
+    case 2: return (const void*)k_pool_gap2d<3, float, 8>;
+    case 3: return (const void*)k_pool_gap2d<4, float, 8>;
+    default: return (const void*)k_pool_gap2d<8, float, 8>;
+  }
 }
 
-hipError_t launch_pool_book(const PoolDev& d, int max_slots, hipStream_t s) {
-  hipLaunchKernelGGL(k_pool_book, dim3(max_slots), dim3(64), 0, s, d);
-  return hipGetLastError();
-}
+const void* pool_book_kernel() { return (const void*)k_pool_book; }
 
 }  // namespace mf

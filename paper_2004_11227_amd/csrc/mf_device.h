@@ -80,14 +80,19 @@ __device__ __forceinline__ void stv(bf16_t* p, long long i, const float (&v)[V])
     st(p, i, v[0]);
   }
 }
-// Group of V elements of one row, `nv` of them inside the grid (0..V): a
-// vector access when the whole group is inside and rows are V-aligned
-// (`vec`), element accesses otherwise; elements outside read as 0.
+// Group of V elements of one row, `nv` of them inside the grid (0..V).
+// With `vec` the row pitch is a multiple of V, so a group that starts inside
+// the row lies wholly inside the row's storage (the tail of a padded row
+// included): one vector access, elements past the grid edge read as 0 and
+// are written with don't-care values.  Without `vec`, element accesses.
 template <int V, typename T>
 __device__ __forceinline__ void ldg(const T* p, long long i, int nv, bool vec, float (&o)[V]) {
-  if (vec) {  // rows are V-aligned: a group is either fully inside or fully outside
-    if (nv == V) {
+  if (vec) {
+    if (nv > 0) {
       ldv<V>(p, i, o);
+#pragma unroll
+      for (int e = 1; e < V; e++)
+        if (e >= nv) o[e] = 0.f;
     } else {
 #pragma unroll
       for (int e = 0; e < V; e++) o[e] = 0.f;
@@ -100,7 +105,7 @@ __device__ __forceinline__ void ldg(const T* p, long long i, int nv, bool vec, f
 template <int V, typename T>
 __device__ __forceinline__ void stg(T* p, long long i, int nv, bool vec, const float (&v)[V]) {
   if (vec) {
-    if (nv == V) stv<V>(p, i, v);
+    if (nv > 0) stv<V>(p, i, v);
   } else {
 #pragma unroll
     for (int e = 0; e < V; e++)

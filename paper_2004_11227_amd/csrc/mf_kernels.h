@@ -89,7 +89,10 @@ hipError_t launch_init(const Geom& g, int nl, bool two, bool bf16, const void* c
 hipError_t launch_convert_caps(const float* src, void* dst, long long n_per_plane, int nplanes,
                                long long plane, bool bf16, hipStream_t s);
 hipError_t launch_labels(const Geom& g, int nl, bool two, const float* u, int32_t* lab,
-                         hipStream_t s);
+                         hipStream_t s, int pitch = 0);
+hipError_t launch_pitch_copy(const void* src, bool src_bf16, long long src_plane, int src_pitch, void* dst,
+                             bool dst_bf16, long long dst_plane, int dst_pitch, int W, long long rows, int nplanes,
+                             hipStream_t s);
 hipError_t launch_read_planes(const void* src, bool bf16, float* dst, long long n, int nplanes,
                               long long plane, hipStream_t s);
 hipError_t launch_write_planes(const float* src, void* dst, bool bf16, long long n, int nplanes,

@@ -26,6 +26,7 @@ struct PoolSlot {
   int cls;
   int W, H, D, ndim;
   int nl, two, bf16, iso;
+  int pitch;          // row stride (W rounded up to a multiple of 4)
   long long P;        // plane stride (elements)
   int tiles_x, tiles_y, tz, check_every;
   const void* cap;
@@ -57,10 +58,9 @@ struct PoolDev {
   int* counts;        // kPoolClasses entries
 };
 
-hipError_t launch_pool_class(const PoolDev& d, int cls, int grid, bool check, bool vec, hipStream_t s);
-int pool_grid(int cls, bool check, bool vec);
-hipError_t launch_pool_gap(const PoolDev& d, int cls, int grid, hipStream_t s);
-hipError_t launch_pool_book(const PoolDev& d, int max_slots, hipStream_t s);
+const void* pool_kernel(int cls, bool check, bool vec);
+const void* pool_gap_kernel(int cls);
+const void* pool_book_kernel();
 
 // Tile height of each pool class (2-D) and the z-slab depth of 3-D solves.
 constexpr int pool_tile_rows(int model) { return model == 0 ? 16 : 8; }

@@ -4,10 +4,11 @@
 // tables (slot table, per-slot status, per-class work lists and counts); the
 // rest is carved first-fit into one block per admitted solve (capacities and
 // two state buffers), so admission is decided exactly by footprint.  A
-// super-step launches, for every class, the persistent sweep kernel over the
-// class work list (and, for Potts classes, the per-tile gap kernel) on its own
-// branch, then the bookkeeping kernel; `steps_per_advance` super-steps are
-// captured once into a hipGraph and replayed by every mf_pool_advance.
+// super-step launches, for every class, the sweep kernel over the class work
+// list (and, for Potts classes, the per-tile gap kernel) as parallel graph
+// branches, then the bookkeeping kernel; `steps_per_advance` super-steps form
+// one hipGraph, built when the set of classes changes, whose kernel grids are
+// resized in place to the item counts, and replayed by every mf_pool_advance.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,7 +46,8 @@ size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
 struct Footprint {
   mf_params p;
-  Geom g;
+  Geom g;          // g.plane: plane stride of the padded layout
+  int pitch;       // row stride: W rounded up to a multiple of 4
   int nl, ncap, cls, model;
   size_t esz, cap_bytes, state_bytes, total;
 };
@@ -64,6 +66,10 @@ std::string plan_solve(const mf_params* in, Footprint& f) {
   }
   f.cls = f.model + (f.p.storage == MF_BF16 ? kPoolModels : 0);
   f.esz = f.p.storage == MF_BF16 ? 2 : 4;
+  // rows padded to a multiple of 4 elements: every tile group is one vector access
+  f.pitch = (f.g.W + 3) / 4 * 4;
+  f.g.plane = (long long)al((size_t)f.pitch * f.g.H * f.g.D * 4) / 4;
+  f.g.plane = (f.g.plane + 127) / 128 * 128;
   const size_t P = (size_t)f.g.plane;
   f.cap_bytes = al((size_t)f.ncap * P * f.esz);
   f.state_bytes = al((size_t)f.nl * P * 4) + al((size_t)f.nl * f.g.ndim * P * f.esz) + al(P * f.esz) +
@@ -128,11 +134,18 @@ struct mf_pool {
   std::vector<std::vector<WorkItem>> lists;
   std::vector<int> counts;
   PoolStat* stats_h = nullptr;                          // pinned
-  hipStream_t side[kPoolClasses] = {};
-  hipEvent_t fork = nullptr, join[kPoolClasses] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_mask = -1;                                  // classes the graph launches
+  struct Node {
+    hipGraphNode_t node;
+    const void* func;
+    int cls;
+    int book;    // 1: bookkeeping node (fixed grid), else sized by the class's items
+    int check;   // bookkeeping: check-step flag argument
+  };
+  std::vector<Node> nodes;
+  std::vector<int> node_counts;                         // counts the node grids were set for
   long long promotions = 0;
   int64_t next_id = 1;
   size_t in_use = 0;
@@ -186,10 +199,33 @@ int class_mask(const mf_pool* P) {
   return m;
 }
 
-// Capture `steps` super-steps for the classes in `mask`: per class, on its own
-// branch, the no-gap sweep, the gap-carrying sweep (two-label classes) and
-// the per-tile gap (Potts classes); then the bookkeeping launch.
-mf_status capture(mf_pool* P, int mask) {
+// Workgroups of a class launch: one per work item (a multiple of 8 for the
+// XCD partition of the item list), at least 8.
+unsigned grid_for(int items) {
+  const int g = (items + 7) / 8 * 8;
+  return (unsigned)(g < 8 ? 8 : g);
+}
+
+hipKernelNodeParams node_params(const void* func, unsigned grid, unsigned block, void** args) {
+  hipKernelNodeParams kp;
+  std::memset(&kp, 0, sizeof(kp));
+  kp.func = const_cast<void*>(func);
+  kp.gridDim = dim3(grid);
+  kp.blockDim = dim3(block);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  return kp;
+}
+
+// Build `steps` super-steps for the classes in `mask` as an explicit graph:
+// per class, the sweep (gap-carrying at step 0 for two-label classes) and,
+// at step 0, the per-tile Potts gap, all depending on the previous
+// bookkeeping node; then the bookkeeping node of the step.  Every pool solve
+// checks at multiples of check_every == steps, starting at a replay
+// boundary, so step 0 is the check step of every solve.  Kernel-node grids
+// follow the class item counts (set_grids).
+mf_status build_graph(mf_pool* P, int mask) {
   if (P->exec) {
     hipGraphExecDestroy(P->exec);
     P->exec = nullptr;
@@ -198,33 +234,59 @@ mf_status capture(mf_pool* P, int mask) {
     hipGraphDestroy(P->graph);
     P->graph = nullptr;
   }
-  PHIP(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+  P->nodes.clear();
+  PHIP(hipGraphCreate(&P->graph, 0));
+  hipGraphNode_t prev = nullptr;
+  PoolDev dev = P->dev;
   for (int s = 0; s < P->steps; s++) {
-    hipError_t e = hipEventRecord(P->fork, P->stream);
-    for (int c = 0; c < kPoolClasses && e == hipSuccess; c++) {
+    const bool cstep = s == 0;
+    std::vector<hipGraphNode_t> step_nodes;
+    for (int c = 0; c < kPoolClasses; c++) {
       if (!(mask & (1 << c))) continue;
       const int model = c % kPoolModels;
-      e = hipStreamWaitEvent(P->side[c], P->fork, 0);
-      for (int v = 0; v < 2 && e == hipSuccess; v++) {
-        e = launch_pool_class(P->dev, c, pool_grid(c, false, v), false, v, P->side[c]);
-        if (e == hipSuccess && (model == 0 || model == 5))
-          e = launch_pool_class(P->dev, c, pool_grid(c, true, v), true, v, P->side[c]);
+      const bool fused_gap = model == 0 || model == 5;
+      int cls = c;
+      void* args[] = {&dev, &cls};
+      const void* fs[2] = {pool_kernel(c, cstep && fused_gap, true), (cstep && !fused_gap) ? pool_gap_kernel(c) : nullptr};
+      for (const void* f : fs) {
+        if (!f) continue;
+        hipKernelNodeParams kp = node_params(f, grid_for(P->counts[c]), 256, args);
+        hipGraphNode_t n;
+        PHIP(hipGraphAddKernelNode(&n, P->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+        step_nodes.push_back(n);
+        P->nodes.push_back({n, f, c, 0, 0});
       }
-      if (e == hipSuccess) e = launch_pool_gap(P->dev, c, 512, P->side[c]);
-      if (e == hipSuccess) e = hipEventRecord(P->join[c], P->side[c]);
-      if (e == hipSuccess) e = hipStreamWaitEvent(P->stream, P->join[c], 0);
     }
-    if (e == hipSuccess) e = launch_pool_book(P->dev, P->max_slots, P->stream);
-    if (e != hipSuccess) {
-      hipGraph_t g = nullptr;
-      hipStreamEndCapture(P->stream, &g);
-      if (g) hipGraphDestroy(g);
-      return pfail(MF_EDEVICE, std::string("pool graph capture: ") + hipGetErrorString(e));
-    }
+    int chk = cstep ? 1 : 0;
+    void* bargs[] = {&dev, &chk};
+    hipKernelNodeParams kb = node_params(pool_book_kernel(), (unsigned)P->max_slots, 64, bargs);
+    hipGraphNode_t b;
+    if (step_nodes.empty())
+      PHIP(hipGraphAddKernelNode(&b, P->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kb));
+    else
+      PHIP(hipGraphAddKernelNode(&b, P->graph, step_nodes.data(), step_nodes.size(), &kb));
+    P->nodes.push_back({b, pool_book_kernel(), -1, 1, chk});
+    prev = b;
   }
-  PHIP(hipStreamEndCapture(P->stream, &P->graph));
   PHIP(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
   P->graph_mask = mask;
+  P->node_counts = P->counts;
+  return MF_OK;
+}
+
+// Resize the class kernel nodes of the instantiated graph to the current
+// item counts (no re-instantiation).
+mf_status set_grids(mf_pool* P) {
+  if (P->node_counts == P->counts) return MF_OK;
+  PoolDev dev = P->dev;
+  for (auto& nd : P->nodes) {
+    if (nd.book) continue;
+    int cls = nd.cls;
+    void* args[] = {&dev, &cls};
+    hipKernelNodeParams kp = node_params(nd.func, grid_for(P->counts[nd.cls]), 256, args);
+    PHIP(hipGraphExecKernelNodeSetParams(P->exec, nd.node, &kp));
+  }
+  P->node_counts = P->counts;
   return MF_OK;
 }
 
@@ -244,6 +306,7 @@ void fill_image(mf_pool* P, int slot, long long iter) {
   S.two = f.p.model == MF_TWO_LABEL;
   S.bf16 = f.p.storage == MF_BF16;
   S.iso = f.p.tv == MF_TV_ISO;
+  S.pitch = f.pitch;
   S.P = f.g.plane;
   S.tiles_x = (f.g.W + 63) / 64;
   S.tiles_y = f.g.ndim == 2 ? (f.g.H + pool_tile_rows(f.model) - 1) / pool_tile_rows(f.model) : (f.g.H + 7) / 8;
@@ -283,7 +346,7 @@ mf_status promote(mf_pool* P, int slot, long long k, bool& moved) {
   StateView n0 = carve(base + f2.cap_bytes, f2), n1 = carve(base + f2.cap_bytes + f2.state_bytes, f2);
   const StateView src = H.st[k & 1];
   const StateView& dst = (k & 1) ? n1 : n0;
-  const long long n = H.f.g.npix(), pl = H.f.g.plane;
+  const long long n = H.f.g.plane, pl = H.f.g.plane;   // whole planes, pads included
   PHIP(launch_convert_planes(P->arena + H.off, true, base, false, n, H.f.ncap, pl, pl, P->stream));
   PHIP(launch_convert_planes(src.u, false, dst.u, false, n, H.f.nl, pl, pl, P->stream));
   PHIP(launch_convert_planes(src.q, true, dst.q, false, n, H.f.nl * H.f.g.ndim, pl, pl, P->stream));
@@ -388,11 +451,6 @@ mf_status mf_pool_create(void* arena, size_t arena_bytes, int32_t max_slots, int
                        P->stream);
 
   if (e == hipSuccess) e = hipHostMalloc((void**)&P->stats_h, sizeof(PoolStat) * (size_t)max_slots, hipHostMallocDefault);
-  for (int c = 0; c < kPoolClasses && e == hipSuccess; c++) {
-    e = hipStreamCreateWithFlags(&P->side[c], hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->join[c], hipEventDisableTiming);
-  }
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&P->fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
   if (e != hipSuccess) {
     mf_pool_destroy(P);
@@ -407,6 +465,8 @@ mf_status mf_pool_admit(mf_pool* P, const mf_params* p, const float* cap, int64_
   Footprint f;
   const std::string e = plan_solve(p, f);
   if (!e.empty()) return pfail(MF_EINVAL, e);
+  if (f.p.check_every != P->steps || f.p.max_iter % f.p.check_every != 0)
+    return pfail(MF_EINVAL, "pool solves need check_every == steps_per_advance and max_iter a multiple of it");
   int slot = -1;
   for (int i = 0; i < P->max_slots; i++)
     if (!P->slots[i].used) {
@@ -445,8 +505,12 @@ mf_status mf_pool_admit(mf_pool* P, const mf_params* p, const float* cap, int64_
   H.st[1] = carve(base + f.cap_bytes + f.state_bytes, f);
   P->in_use += f.total;
   const bool bf16 = f.p.storage == MF_BF16;
-  PHIP(launch_convert_caps(cap, base, f.g.npix(), f.ncap, f.g.plane, bf16, P->stream));
-  PHIP(launch_init(f.g, f.nl, f.p.model == MF_TWO_LABEL, bf16, base, H.st[0], P->stream));
+  const long long rows = (long long)f.g.H * f.g.D;
+  PHIP(launch_pitch_copy(cap, false, f.g.npix(), f.g.W, base, bf16, f.g.plane, f.pitch, f.g.W, rows, f.ncap,
+                         P->stream));
+  Geom gp = f.g;   // initialise the padded planes whole (pads hold zero capacities)
+  gp.W = f.pitch;
+  PHIP(launch_init(gp, f.nl, f.p.model == MF_TWO_LABEL, bf16, base, H.st[0], P->stream));
   fill_image(P, slot, 0);
   PoolSlot& S = P->slot_img[slot];
   PHIP(hipMemcpyAsync(P->dev.slots + slot, &S, sizeof(S), hipMemcpyHostToDevice, P->stream));
@@ -466,10 +530,10 @@ mf_status mf_pool_admit(mf_pool* P, const mf_params* p, const float* cap, int64_
 mf_status mf_pool_advance(mf_pool* P) {
   if (!P) return pfail(MF_EINVAL, "null pool");
   const int mask = class_mask(P);
-  if (!P->exec || mask != P->graph_mask) {
-    mf_status s = capture(P, mask);
-    if (s != MF_OK) return s;
-  }
+  mf_status ms = MF_OK;
+  if (!P->exec || mask != P->graph_mask) ms = build_graph(P, mask);
+  else ms = set_grids(P);
+  if (ms != MF_OK) return ms;
   PHIP(hipGraphLaunch(P->exec, P->stream));
   return MF_OK;
 }
@@ -524,8 +588,12 @@ mf_status mf_pool_retire(mf_pool* P, int64_t solve_id, float* u_dst, int32_t* la
   PHIP(hipStreamSynchronize(P->stream));
   const long long it = P->stats_h[slot].iter;
   const StateView& v = H.st[it & 1];
-  if (u_dst) PHIP(launch_read_planes(v.u, false, u_dst, H.f.g.npix(), H.f.nl, H.f.g.plane, P->stream));
-  if (labels_dst) PHIP(launch_labels(H.f.g, H.f.nl, H.f.p.model == MF_TWO_LABEL, v.u, labels_dst, P->stream));
+  const long long rows = (long long)H.f.g.H * H.f.g.D;
+  if (u_dst)
+    PHIP(launch_pitch_copy(v.u, false, H.f.g.plane, H.f.pitch, u_dst, false, H.f.g.npix(), H.f.g.W, H.f.g.W, rows,
+                           H.f.nl, P->stream));
+  if (labels_dst)
+    PHIP(launch_labels(H.f.g, H.f.nl, H.f.p.model == MF_TWO_LABEL, v.u, labels_dst, P->stream, H.f.pitch));
   // free the slot on the device and drop its tiles
   int zero = SLOT_FREE;
   PHIP(hipMemcpyAsync(&P->dev.slots[slot].state, &zero, sizeof(int), hipMemcpyHostToDevice, P->stream));
@@ -563,11 +631,6 @@ mf_status mf_pool_destroy(mf_pool* P) {
   if (P->stream) hipStreamSynchronize(P->stream);
   if (P->exec) hipGraphExecDestroy(P->exec);
   if (P->graph) hipGraphDestroy(P->graph);
-  for (int c = 0; c < kPoolClasses; c++) {
-    if (P->side[c]) hipStreamDestroy(P->side[c]);
-    if (P->join[c]) hipEventDestroy(P->join[c]);
-  }
-  if (P->fork) hipEventDestroy(P->fork);
   if (P->stats_h) hipHostFree(P->stats_h);
   delete P;
   return MF_OK;

@@ -26,6 +26,7 @@ __device__ __forceinline__ float quant<bf16_t>(float v) {
 template <typename TS>
 struct K2 {
   int W, H;
+  int pitch;          // row stride in elements (>= W; multiple of 4 in padded layouts)
   long long P;        // plane stride
   int tiles_x;
   const TS* cap;
@@ -97,7 +98,7 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
   auto& sw = S.sw;
   auto& su = S.su;
   const int tid = threadIdx.x;
-  const int W = A.W, H = A.H;
+  const int W = A.W, H = A.H, pitch = A.pitch;
   const long long P = A.P;
   const int c0 = (tid % TPR) * V;
   const int rr0 = tid / TPR;
@@ -113,7 +114,7 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
   for (int j = 0; j < RPT; j++) {
     const int gy = y0 + rr0 + RSTEP * j;
     const int nv = gy < H ? nvx : 0;
-    const long long idx = (long long)gy * W + gx0;
+    const long long idx = (long long)gy * pitch + gx0;
     ldg<V>(A.ps_in, idx, nv, vec, ps[j]);
     if (TWO) {
       ldg<V>(A.cap, idx, nv, vec, caps[j]);
@@ -139,7 +140,7 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
       const int r = rr0 + RSTEP * j;
       const int gy = y0 + r;
       const int nv = gy < H ? nvx : 0;
-      const long long idx = (long long)gy * W + gx0;
+      const long long idx = (long long)gy * pitch + gx0;
       float qxv[V], qyv[V];
       ldg<V>(qx_in, idx, nv, vec, qxv);
       ldg<V>(qy_in, idx, nv, vec, qyv);
@@ -168,7 +169,7 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
       }
       const int hx = x0 + c, hy = y0 + r;
       const bool in = hx >= 0 && hx < W && hy >= 0 && hy < H;
-      const long long idx = (long long)hy * W + hx;
+      const long long idx = (long long)hy * pitch + hx;
       sqx[r + 2][c + OX] = in ? ld(qx_in, idx) : 0.f;
       sqy[r + 2][c + OX] = in ? ld(qy_in, idx) : 0.f;
     }
@@ -185,7 +186,7 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
       }
       const int hx = x0 + c, hy = y0 + r;
       const bool in = hx >= 0 && hx < W && hy >= 0 && hy < H;
-      const long long idx = (long long)hy * W + hx;
+      const long long idx = (long long)hy * pitch + hx;
       const float uu = in ? u_in[idx] : 0.f;
       const float pp = in ? ld(p_in, idx) : 0.f;
       const float ss = in ? ld(A.ps_in, idx) : 0.f;
@@ -245,7 +246,7 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
         const int r = rr0 + RSTEP * j;
         const int gy = y0 + r;
         const int nv = gy < H ? nvx : 0;
-        const long long idx = (long long)gy * W + gx0;
+        const long long idx = (long long)gy * pitch + gx0;
         float C[V], qxv[V], qyv[V], pn[V];
         if (TWO) {
 #pragma unroll
@@ -276,7 +277,7 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
   for (int j = 0; j < RPT; j++) {
     const int gy = y0 + rr0 + RSTEP * j;
     const int nv = gy < H ? nvx : 0;
-    const long long idx = (long long)gy * W + gx0;
+    const long long idx = (long long)gy * pitch + gx0;
     float psn[V];
 #pragma unroll
     for (int e = 0; e < V; e++) psn[e] = finish_ps(k, ps[j][e], sumd[j][e], sumr[j][e], TWO, TWO ? caps[j][e] : 0.f);

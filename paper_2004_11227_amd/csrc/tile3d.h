@@ -33,7 +33,8 @@ __device__ __forceinline__ float quant3<bf16_t>(float v) {
 template <typename TS>
 struct K3 {
   int W, H, D;
-  long long P, SZ;     // plane stride (fields), z stride (W*H)
+  int pitch;           // row stride in elements (>= W)
+  long long P, SZ;     // plane stride (fields), z stride (pitch*H)
   int tiles_x, tiles_y, tz;
   const TS* cap;
   const float* u_in;
@@ -80,7 +81,7 @@ __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, 
   auto& sw = S.sw;
   auto& su = S.su;
   const int tid = threadIdx.x;
-  const int W = A.W, H = A.H, D = A.D;
+  const int W = A.W, H = A.H, D = A.D, pitch = A.pitch;
   const long long P = A.P, SZ = A.SZ;
   const int c0 = (tid % TPR) * V;
   const int r0 = tid / TPR;      // owned row of the tile (0..7)
@@ -111,7 +112,7 @@ __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, 
     float u_c[V], p_c[V], s_c[V];
     {
       const int nv = zin ? nvxy : 0;
-      const long long idx = zoff + (long long)gy * W + gx0;
+      const long long idx = zoff + (long long)gy * pitch + gx0;
       float qxv[V], qyv[V], qzv[V];
       ldg<V>(qx_in, idx, nv, vec, qxv);
       ldg<V>(qy_in, idx, nv, vec, qyv);
@@ -143,7 +144,7 @@ __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, 
       }
       const int hx = x0 + c, hy = y0 + r;
       const bool in = zin && hx >= 0 && hx < W && hy >= 0 && hy < H;
-      const long long idx = zoff + (long long)hy * W + hx;
+      const long long idx = zoff + (long long)hy * pitch + hx;
       sqx[sl][r + 2][c + OX] = in ? ld(qx_in, idx) : 0.f;
       sqy[sl][r + 2][c + OX] = in ? ld(qy_in, idx) : 0.f;
       sqz[sl][r + 2][c + OX] = in ? ld(qz_in, idx) : 0.f;
@@ -160,7 +161,7 @@ __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, 
       }
       const int hx = x0 + c, hy = y0 + r;
       const bool in = zin && hx >= 0 && hx < W && hy >= 0 && hy < H;
-      const long long idx = zoff + (long long)hy * W + hx;
+      const long long idx = zoff + (long long)hy * pitch + hx;
       const float uu = in ? A.u_in[idx] : 0.f;
       const float pp = in ? ld(A.p_in, idx) : 0.f;
       const float ss = in ? ld(A.ps_in, idx) : 0.f;
@@ -172,7 +173,7 @@ __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, 
     if (CHECK && s - 1 >= z0 && s - 1 < z1) {
       const int zz = s - 1;
       const int nv = nvxy;
-      const long long idx = (long long)zz * SZ + (long long)gy * W + gx0;
+      const long long idx = (long long)zz * SZ + (long long)gy * pitch + gx0;
       float cs[V], ct[V];
       ldg<V>(A.cap, idx, nv, vec, cs);
       ldg<V>(A.cap + P, idx, nv, vec, ct);
@@ -235,7 +236,7 @@ __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, 
     if (s - 1 >= z0 && s - 1 < z1) {
       const int zz = s - 1;
       const int nv = nvxy;
-      const long long idx = (long long)zz * SZ + (long long)gy * W + gx0;
+      const long long idx = (long long)zz * SZ + (long long)gy * pitch + gx0;
       float cs[V], ct[V], qxv[V], qyv[V], qzv[V], pn[V], psn[V], un[V];
       ldg<V>(A.cap, idx, nv, vec, cs);
       ldg<V>(A.cap + P, idx, nv, vec, ct);

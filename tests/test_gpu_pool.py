@@ -175,3 +175,16 @@ def test_serving_loop_end_to_end():
     assert len(rep.records) == 24
     assert all(r.status in (0, 1) for r in rep.records)
     assert all(r.iters % 10 == 0 or r.iters == 1000 for r in rep.records)
+
+
+def test_pool_rejects_unaligned_check_cadence():
+    pool = mfx.Pool(1 << 28, max_slots=4, max_tiles=1024, steps_per_advance=10)
+    caps = torch.ones((2, 32, 32), device="cuda")
+    with pytest.raises(mfx.MaxflowError):
+        pool.admit(caps, model="two", check_every=5, max_iter=100)
+    with pytest.raises(mfx.MaxflowError):
+        pool.admit(caps, model="two", check_every=10, max_iter=105)
+    with pytest.raises(mfx.MaxflowError):
+        pool.admit(caps, model="two", method="dr")
+    assert pool.admit(caps, model="two", check_every=10, max_iter=100) is not None
+    pool.close()
