@@ -47,13 +47,25 @@ def alg_bytes(model: str, n: int, ndim: int, storage: str) -> int:
 
 
 BYTES_PER_PX = {"f32": alg_bytes("two", 2, 2, "f32"), "bf16": alg_bytes("two", 2, 2, "bf16")}
-KERNEL_SOURCES = ["paper_2004_11227_amd/csrc/k2d.hip", "paper_2004_11227_amd/csrc/mf_device.h"]
+SRC = "paper_2004_11227_amd/csrc/"
+KERNEL_SOURCES = [SRC + "k2d.hip", SRC + "tile2d.h", SRC + "mf_device.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused2d_two_label_2048_traffic.json")
 
+# Workloads of --profile-mode NAME (plain sweeps after a copy of known size,
+# for the FETCH_SIZE / WRITE_SIZE calibration): caps generator arguments and
+# solver keywords.
+PROFILE_WORKLOADS = {
+    "two_2048": (("c1", None), dict(model="two", method="eb", relax=1.5, alpha=0.5)),
+    "two_4096": (("c1", (4096, 4096)), dict(model="two", method="eb", relax=1.5, alpha=0.5)),
+    "two_3d_256": (("c3", None), dict(model="two", method="eb", relax=1.5, alpha=0.4)),
+    "potts4_1024": (("c2n4", None), dict(model="potts", nlabels=4, method="eb", relax=1.5, alpha=0.3)),
+    "potts8_1024": (("c2n8", None), dict(model="potts", nlabels=8, method="eb", relax=1.5, alpha=0.3)),
+}
 
-def kernel_hash() -> str:
+
+def kernel_hash(files=KERNEL_SOURCES) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -66,7 +78,10 @@ def parse():
     ap.add_argument("--kernel-sweeps", type=int, default=400)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
-    ap.add_argument("--profile-mode", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=128,
+                    help="requests of the serving mix in the secondary measurements (0: skip)")
+    ap.add_argument("--profile-mode", nargs="?", const="two_2048", default=None,
+                    choices=sorted(PROFILE_WORKLOADS))
     return ap.parse_args()
 
 
@@ -141,10 +156,14 @@ def main():
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
-        s = make_solver(torch, maxflow, caps_t, stream, **kw)
+        (cfg, size), pkw = PROFILE_WORKLOADS[args.profile_mode]
+        pc = synth.config_inputs(cfg, size=size)["caps"] if size else synth.config_inputs(cfg)["caps"]
+        pt = torch.from_numpy(pc.astype(np.float32)).to(dev)
+        s = make_solver(torch, maxflow, pt, stream, **pkw)
         s.step(30)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_mode": True, "copy_bytes": src.numel() * 4, "sweeps": 30}))
+        print(json.dumps({"profile_mode": args.profile_mode, "copy_bytes": src.numel() * 4, "sweeps": 30,
+                          "shape": list(pc.shape[1:])}))
         return
 
     s = make_solver(torch, maxflow, caps_t, stream, **kw)
@@ -179,6 +198,8 @@ def main():
     extra = {}
     if not args.no_extra:
         extra = secondary(torch, maxflow, synth, np, dev, stream)
+        if args.serving_requests > 0:
+            extra["serving"] = serving_summary(args.serving_requests)
 
     out = {"metric": "pixel*label ADMM iterations/s (two-label 2048^2, rpADMMII, FP32)",
            "value": value, "unit": "pixel*label*iterations/s", "n_gpus": 1, "steps": args.steps,
@@ -225,10 +246,31 @@ def secondary(torch, maxflow, synth, np, dev, stream):
         for stg in ("f32", "bf16"):
             sweep_rate(f"potts{n}_1024_fused_{stg}", caps, alg_bytes("potts", n, 2, stg),
                        model="potts", nlabels=n, method="eb", alpha=0.3, storage=stg)
-    vol = synth.config_inputs("c3", size=(128, 128, 128))["caps"]
-    sweep_rate("two_3d_128_unfused_f32", vol, alg_bytes("two", 2, 3, "f32"), model="two", method="eb",
-               relax=1.5, alpha=0.4, variant="unfused")
+    vol = synth.config_inputs("c3")["caps"]   # 256^3, 512 MiB FP32 working set
+    for stg in ("f32", "bf16"):
+        sweep_rate(f"two_3d_256_fused_{stg}", vol, alg_bytes("two", 2, 3, stg), iters=50, model="two",
+                   method="eb", relax=1.5, alpha=0.4, storage=stg)
+    sweep_rate("two_3d_256_unfused_f32", vol, alg_bytes("two", 2, 3, "f32"), iters=20, model="two",
+               method="eb", relax=1.5, alpha=0.4, variant="unfused")
+    del vol
     return res
+
+
+def serving_summary(nreq):
+    """Continuous batching through the pool (BF16 flows, promoted to FP32
+    near the BF16 floor) against one-at-a-time FP32 solves on the mixed
+    request trace: solves/s at saturation and p50/p99 latency under Poisson
+    arrivals at 0.7x the one-at-a-time capacity."""
+    from paper_2004_11227_amd import serving
+    r = serving.benchmark(nreq=nreq, pool_storage="bf16", tol=1e-4, max_iter=1000)
+    keep = ("solves_per_s", "p50_latency_s", "p99_latency_s", "mean_iters", "converged", "capped")
+    out = {k: r[k] for k in ("requests", "tol", "max_iter", "total_pixels", "promotions_total",
+                             "speedup_solves_per_s", "latency_rate_per_s")}
+    for k in ("sequential_fp32", "pool"):
+        out[k] = {kk: r[k][kk] for kk in keep if kk in r[k]}
+    for k in ("sequential_fp32_latency", "pool_latency"):
+        out[k] = {kk: r[k][kk] for kk in ("p50_latency_s", "p99_latency_s", "mean_latency_s", "solves_per_s")}
+    return out
 
 
 if __name__ == "__main__":
