@@ -38,18 +38,18 @@ __device__ __forceinline__ void gap_px(const KG<TS>& A, long long idx, int x, in
 #pragma unroll
   for (int l = 0; l < NL; l++) {
     const TS* q = A.q + (long long)(NDIM * l) * A.P;
-    double d = ((hx ? (double)ld(q, idx) : 0.0) - (x > 0 ? (double)ld(q, idx - 1) : 0.0)) +
-               ((hy ? (double)ld(q + A.P, idx) : 0.0) - (y > 0 ? (double)ld(q + A.P, idx - sy) : 0.0));
+    double d = ((double)ldz(q, idx, hx) - (double)ldz(q, idx - 1, x > 0)) +
+               ((double)ldz(q + A.P, idx, hy) - (double)ldz(q + A.P, idx - sy, y > 0));
     if (NDIM == 3)
-      d += (hz ? (double)ld(q + 2 * A.P, idx) : 0.0) - (z > 0 ? (double)ld(q + 2 * A.P, idx - sz) : 0.0);
+      d += (double)ldz(q + 2 * A.P, idx, hz) - (double)ldz(q + 2 * A.P, idx - sz, z > 0);
     dq[l] = d;
   }
   if (TWO) {
     const double Cs = (double)ld(A.cap, idx), Ct = (double)ld(A.cap + A.P, idx);
     const double u0 = clip01(A.u[idx]);
-    const double gx = hx ? clip01(A.u[idx + 1]) - u0 : 0.0;
-    const double gy = hy ? clip01(A.u[idx + sy]) - u0 : 0.0;
-    const double gz = hz ? clip01(A.u[idx + sz]) - u0 : 0.0;
+    const double gx = hx ? clip01(ldz(A.u, idx + 1, hx)) - u0 : 0.0;
+    const double gy = hy ? clip01(ldz(A.u, idx + sy, hy)) - u0 : 0.0;
+    const double gz = hz ? clip01(ldz(A.u, idx + sz, hz)) - u0 : 0.0;
     g[0] += (1.0 - u0) * Cs + u0 * Ct;
     g[1] += A.iso ? sqrt((gx * gx + gy * gy) + gz * gz) : (fabs(gx) + fabs(gy)) + fabs(gz);
     g[2] += fmin(Cs, Ct + dq[0]);
@@ -61,14 +61,14 @@ __device__ __forceinline__ void gap_px(const KG<TS>& A, long long idx, int x, in
     for (int l = 0; l < NL; l++) v[l] = (double)A.u[(long long)l * A.P + idx];
     simplex_proj<NL>(v, w0);
 #pragma unroll
-    for (int l = 0; l < NL; l++) v[l] = hx ? (double)A.u[(long long)l * A.P + idx + 1] : 0.0;
+    for (int l = 0; l < NL; l++) v[l] = (double)ldz(A.u, (long long)l * A.P + idx + 1, hx);
     simplex_proj<NL>(v, wx);
 #pragma unroll
-    for (int l = 0; l < NL; l++) v[l] = hy ? (double)A.u[(long long)l * A.P + idx + sy] : 0.0;
+    for (int l = 0; l < NL; l++) v[l] = (double)ldz(A.u, (long long)l * A.P + idx + sy, hy);
     simplex_proj<NL>(v, wy);
     if (NDIM == 3) {
 #pragma unroll
-      for (int l = 0; l < NL; l++) v[l] = hz ? (double)A.u[(long long)l * A.P + idx + sz] : 0.0;
+      for (int l = 0; l < NL; l++) v[l] = (double)ldz(A.u, (long long)l * A.P + idx + sz, hz);
       simplex_proj<NL>(v, wz);
     }
     double mn = 1e300;

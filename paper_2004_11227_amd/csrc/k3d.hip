@@ -20,6 +20,23 @@ __global__ __launch_bounds__(256) void k_fused3d(const K3<TS> A) {
   if (CHECK) block_accumulate<5, 4>(g, A.acc, S.sred);
 }
 
+// Workgroups of k_fused3d resident at once on the current device.
+template <typename TS, bool CHECK>
+static long long resident_blocks3(bool vec) {
+  static int cached[2] = {0, 0};
+  int& c = cached[vec ? 1 : 0];
+  if (c == 0) {
+    int per_cu = 0, dev = 0, cus = 0;
+    const void* f = vec ? (const void*)k_fused3d<TS, CHECK, true> : (const void*)k_fused3d<TS, CHECK, false>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+    c = per_cu * cus;
+  }
+  return c;
+}
+
 template <typename TS, bool CHECK>
 static hipError_t fused3d_ts(const SweepDesc& d, hipStream_t s) {
   K3<TS> a;
@@ -31,10 +48,16 @@ static hipError_t fused3d_ts(const SweepDesc& d, hipStream_t s) {
   a.SZ = (long long)d.g.W * d.g.H;
   a.tiles_x = (d.g.W + 63) / 64;
   a.tiles_y = (d.g.H + 7) / 8;
-  // slab depth: enough blocks to fill the chip, at least 8 planes per slab
+  // Slab depth: each slab re-reads 3 warm-up planes, so slabs should be
+  // deep, but the grid must fill the chip.  Cut the volume into as many
+  // slabs as make one full wave of resident workgroups (occupancy x CUs):
+  // a partial second wave would run on a fraction of the chip.
   const long long nxy = (long long)a.tiles_x * a.tiles_y;
-  int tz = d.g.D;
-  while (tz > 8 && nxy * ((d.g.D + tz - 1) / tz) < 2048) tz = (tz + 1) / 2;
+  const long long resident = resident_blocks3<TS, CHECK>(d.g.W % 2 == 0);
+  long long nslab = resident / nxy;
+  if (nslab < 1) nslab = 1;
+  int tz = (int)((d.g.D + nslab - 1) / nslab);
+  if (tz < 8) tz = d.g.D < 8 ? d.g.D : 8;
   a.tz = tz;
   a.cap = (const TS*)d.cap;
   a.u_in = d.in.u;

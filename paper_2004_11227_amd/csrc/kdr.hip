@@ -88,10 +88,10 @@ __global__ __launch_bounds__(256) void k_dr_r1(const KD<TS> A) {
 #pragma unroll
     for (int l = 0; l < NL; l++) {
       const TS* q = A.qb + (long long)(NDIM * l) * A.P;
-      float d = ((c.x + 1 < A.W ? ld(q, idx) : 0.f) - (c.x > 0 ? ld(q, idx - 1) : 0.f)) +
-                ((c.y + 1 < A.H ? ld(q + A.P, idx) : 0.f) - (c.y > 0 ? ld(q + A.P, idx - A.W) : 0.f));
+      float d = (ldz(q, idx, c.x + 1 < A.W) - ldz(q, idx - 1, c.x > 0)) +
+                (ldz(q + A.P, idx, c.y + 1 < A.H) - ldz(q + A.P, idx - A.W, c.y > 0));
       if (NDIM == 3)
-        d += (c.z + 1 < A.D ? ld(q + 2 * A.P, idx) : 0.f) - (c.z > 0 ? ld(q + 2 * A.P, idx - sz) : 0.f);
+        d += ldz(q + 2 * A.P, idx, c.z + 1 < A.D) - ldz(q + 2 * A.P, idx - sz, c.z > 0);
       float bl = -A.sigma * ((d + ld(A.pb + (long long)l * A.P, idx)) - psb);
       // Potts: + st ((n-1) u_i - sum_{j != i} u_j) = st (n u_i - sum_j u_j)
       if (!TWO) bl += (A.sigma * A.tau) * ((float)NL * uk[l] - usum);

@@ -32,11 +32,11 @@ __device__ __forceinline__ float div_at(const TS* q, long long P, long long idx,
                                         int W, int H, int D) {
   const long long sz = (long long)W * H;
   if (NDIM == 2) {
-    return div2(ld(q, idx), x > 0 ? ld(q, idx - 1) : 0.f, ld(q + P, idx),
-                y > 0 ? ld(q + P, idx - W) : 0.f, x + 1 < W, x > 0, y + 1 < H, y > 0);
+    return div2(ld(q, idx), ldz(q, idx - 1, x > 0), ld(q + P, idx),
+                ldz(q + P, idx - W, y > 0), x + 1 < W, x > 0, y + 1 < H, y > 0);
   }
-  return div3(ld(q, idx), x > 0 ? ld(q, idx - 1) : 0.f, ld(q + P, idx), y > 0 ? ld(q + P, idx - W) : 0.f,
-              ld(q + 2 * P, idx), z > 0 ? ld(q + 2 * P, idx - sz) : 0.f, x + 1 < W, x > 0, y + 1 < H,
+  return div3(ld(q, idx), ldz(q, idx - 1, x > 0), ld(q + P, idx), ldz(q + P, idx - W, y > 0),
+              ld(q + 2 * P, idx), ldz(q + 2 * P, idx - sz, z > 0), x + 1 < W, x > 0, y + 1 < H,
               y > 0, z + 1 < D, z > 0);
 }
 

@@ -80,26 +80,40 @@ __device__ __forceinline__ void stv(bf16_t* p, long long i, const float (&v)[V])
     st(p, i, v[0]);
   }
 }
+// Workgroup barrier for communication through LDS only: waits for this
+// wave's LDS operations and meets the other waves, but leaves its global
+// loads in flight.  __syncthreads() also drains outstanding global loads (its
+// release fence covers global memory), which would stall loads that were
+// issued ahead of their use.  No kernel here communicates through global
+// memory inside a workgroup.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Guarded scalar load without a branch: the load always issues (from
+// element 0 when `ok` is false, which every plane has) and the value is
+// selected afterwards.  A load inside a branch makes the compiler wait for it
+// at the end of the branch, which serialises the loads of a tile; branchless
+// loads can all be in flight before the first use.
+template <typename T>
+__device__ __forceinline__ float ldz(const T* p, long long i, bool ok) {
+  const float v = ld(p, ok ? i : 0);
+  return ok ? v : 0.f;
+}
+
 // Group of V elements of one row, `nv` of them inside the grid (0..V).
 // With `vec` the row pitch is a multiple of V, so a group that starts inside
 // the row lies wholly inside the row's storage (the tail of a padded row
 // included): one vector access, elements past the grid edge read as 0 and
 // are written with don't-care values.  Without `vec`, element accesses.
+// Loads are branchless (see ldz).
 template <int V, typename T>
 __device__ __forceinline__ void ldg(const T* p, long long i, int nv, bool vec, float (&o)[V]) {
   if (vec) {
-    if (nv > 0) {
-      ldv<V>(p, i, o);
+    ldv<V>(p, nv > 0 ? i : 0, o);
 #pragma unroll
-      for (int e = 1; e < V; e++)
-        if (e >= nv) o[e] = 0.f;
-    } else {
-#pragma unroll
-      for (int e = 0; e < V; e++) o[e] = 0.f;
-    }
+    for (int e = 0; e < V; e++) o[e] = e < nv ? o[e] : 0.f;
   } else {
 #pragma unroll
-    for (int e = 0; e < V; e++) o[e] = e < nv ? ld(p, i + e) : 0.f;
+    for (int e = 0; e < V; e++) o[e] = ldz(p, i + e, e < nv);
   }
 }
 template <int V, typename T>

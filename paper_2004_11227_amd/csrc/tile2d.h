@@ -84,6 +84,17 @@ struct Smem2 {
   double sred[4 * 5];
 };
 
+// Loads of one label ahead of its use: the owned groups of q_x, q_y, u, p
+// (and the label's capacities for Potts), and this thread's xy-halo entries.
+// Raw values: entries outside the grid load element 0 of their plane and are
+// zeroed when the label is staged, so the loads of label l+1 stay in flight
+// across the LDS phases of label l.
+template <int RPT, int V, int KQ, int KW>
+struct Lab2 {
+  float qx[RPT][V], qy[RPT][V], u[RPT][V], p[RPT][V], C[RPT][V];
+  float hqx[KQ], hqy[KQ], hu[KW], hp[KW];
+};
+
 template <int NL, bool TWO, typename TS, bool CHECK, int TY, bool VEC, bool SU>
 __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY, SU>& S, double (&g)[5]) {
   static_assert(!CHECK || SU, "the gap needs the u staging array");
@@ -93,6 +104,9 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
   constexpr int RSTEP = 256 / TPR;   // tile rows covered by one pass of the block
   constexpr int RPT = TY / RSTEP;    // rows per thread
   constexpr int OX = 4;              // LDS column offset
+  constexpr int NHQ = 3 * (TX + 3) + 3 * TY;   // q halo: rows {-2,-1,TY} x cols -2..TX, cols {-2,-1,TX} x rows 0..TY-1
+  constexpr int NHW = 2 * (TX + 2) + 2 * TY;   // v halo: rows {-1,TY} x cols -1..TX, cols {-1,TX} x rows 0..TY-1
+  constexpr int KQ = (NHQ + 255) / 256, KW = (NHW + 255) / 256;
   auto& sqx = S.sqx;
   auto& sqy = S.sqy;
   auto& sw = S.sw;
@@ -107,18 +121,106 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
   constexpr bool vec = VEC;   // W % V == 0: interior groups are whole vectors
   const Coef k = A.k;
 
-  float t[RPT][NL][V];
-  float ps[RPT][V], sumd[RPT][V], sumr[RPT][V];
-  float capt[RPT][V], caps[RPT][V];
+  // owned groups: valid element counts and storage offsets
+  int nvj[RPT];
+  long long oj[RPT];
 #pragma unroll
   for (int j = 0; j < RPT; j++) {
     const int gy = y0 + rr0 + RSTEP * j;
-    const int nv = gy < H ? nvx : 0;
-    const long long idx = (long long)gy * pitch + gx0;
-    ldg<V>(A.ps_in, idx, nv, vec, ps[j]);
+    nvj[j] = gy < H ? nvx : 0;
+    oj[j] = (long long)gy * pitch + gx0;
+  }
+  // this thread's halo entries: tile coordinates, inside flags, offsets
+  int hq_r[KQ], hq_c[KQ], hw_r[KW], hw_c[KW];
+  bool hq_in[KQ], hw_in[KW];
+  long long hq_o[KQ], hw_o[KW];
+#pragma unroll
+  for (int m = 0; m < KQ; m++) {
+    const int h = tid + 256 * m;
+    int r = 0, c = 0;
+    if (h < 3 * (TX + 3)) {
+      const int rr = h / (TX + 3);
+      r = rr == 0 ? -2 : (rr == 1 ? -1 : TY);
+      c = h % (TX + 3) - 2;
+    } else {
+      const int hh = h - 3 * (TX + 3);
+      r = hh / 3;
+      const int cc = hh % 3;
+      c = cc == 0 ? -2 : (cc == 1 ? -1 : TX);
+    }
+    hq_r[m] = r;
+    hq_c[m] = c;
+    hq_in[m] = h < NHQ && x0 + c >= 0 && x0 + c < W && y0 + r >= 0 && y0 + r < H;
+    hq_o[m] = hq_in[m] ? (long long)(y0 + r) * pitch + (x0 + c) : 0;
+  }
+#pragma unroll
+  for (int m = 0; m < KW; m++) {
+    const int h = tid + 256 * m;
+    int r = 0, c = 0;
+    if (h < 2 * (TX + 2)) {
+      r = h < TX + 2 ? -1 : TY;
+      c = h % (TX + 2) - 1;
+    } else {
+      const int hh = h - 2 * (TX + 2);
+      r = hh >> 1;
+      c = (hh & 1) ? TX : -1;
+    }
+    hw_r[m] = r;
+    hw_c[m] = c;
+    hw_in[m] = h < NHW && x0 + c >= 0 && x0 + c < W && y0 + r >= 0 && y0 + r < H;
+    hw_o[m] = hw_in[m] ? (long long)(y0 + r) * pitch + (x0 + c) : 0;
+  }
+
+  // raw group load (element 0 of the plane for groups outside the grid)
+  auto ldr = [&](auto* p, int j, float (&o)[V]) {
+    if (vec) {
+      ldv<V>(p, nvj[j] > 0 ? oj[j] : 0, o);
+    } else {
+#pragma unroll
+      for (int e = 0; e < V; e++) o[e] = ld(p, e < nvj[j] ? oj[j] + e : 0);
+    }
+  };
+  auto zmask = [&](int j, float (&o)[V]) {
+#pragma unroll
+    for (int e = 0; e < V; e++) o[e] = e < nvj[j] ? o[e] : 0.f;
+  };
+  using LabT = Lab2<RPT, V, KQ, KW>;
+  auto fetch = [&](int l, LabT& F) {
+    const TS* qx_in = A.q_in + (long long)(2 * l) * P;
+    const TS* qy_in = qx_in + P;
+    const float* u_in = A.u_in + (long long)l * P;
+    const TS* p_in = A.p_in + (long long)l * P;
+#pragma unroll
+    for (int j = 0; j < RPT; j++) {
+      ldr(qx_in, j, F.qx[j]);
+      ldr(qy_in, j, F.qy[j]);
+      ldr(u_in, j, F.u[j]);
+      ldr(p_in, j, F.p[j]);
+      if (!TWO) ldr(A.cap + (long long)l * P, j, F.C[j]);
+    }
+#pragma unroll
+    for (int m = 0; m < KQ; m++) {
+      F.hqx[m] = ld(qx_in, hq_o[m]);
+      F.hqy[m] = ld(qy_in, hq_o[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < KW; m++) {
+      F.hu[m] = ld(u_in, hw_o[m]);
+      F.hp[m] = ld(p_in, hw_o[m]);
+    }
+  };
+
+  // label-independent loads: p_s (owned and halo), two-label capacities
+  float t[RPT][NL][V];
+  float ps[RPT][V], sumd[RPT][V], sumr[RPT][V];
+  float capt[RPT][V], caps[RPT][V];
+  float hps[KW];
+#pragma unroll
+  for (int j = 0; j < RPT; j++) {
+    ldr(A.ps_in, j, ps[j]);
     if (TWO) {
-      ldg<V>(A.cap, idx, nv, vec, caps[j]);
-      ldg<V>(A.cap + P, idx, nv, vec, capt[j]);
+      ldr(A.cap, j, caps[j]);
+      ldr(A.cap + P, j, capt[j]);
     }
 #pragma unroll
     for (int e = 0; e < V; e++) {
@@ -126,81 +228,63 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
       sumr[j][e] = 0.f;
     }
   }
+#pragma unroll
+  for (int m = 0; m < KW; m++) hps[m] = ld(A.ps_in, hw_o[m]);
+  LabT F;
+  fetch(0, F);
+#pragma unroll
+  for (int j = 0; j < RPT; j++) zmask(j, ps[j]);
+#pragma unroll
+  for (int m = 0; m < KW; m++) hps[m] = hw_in[m] ? hps[m] : 0.f;
 
 #pragma unroll
   for (int l = 0; l < NL; l++) {
-    const TS* qx_in = A.q_in + (long long)(2 * l) * P;
-    const TS* qy_in = qx_in + P;
-    const float* u_in = A.u_in + (long long)l * P;
-    const TS* p_in = A.p_in + (long long)l * P;
-    float ul[RPT][V], pl[RPT][V];
-    // ---- stage q^k and v = (p - p_s) - u/c: interior by the owning threads
+    float ul[RPT][V], pl[RPT][V], Cl[RPT][V];
+    // ---- stage q^k and v = (p - p_s) - u/c of label l from the registers
 #pragma unroll
     for (int j = 0; j < RPT; j++) {
       const int r = rr0 + RSTEP * j;
-      const int gy = y0 + r;
-      const int nv = gy < H ? nvx : 0;
-      const long long idx = (long long)gy * pitch + gx0;
-      float qxv[V], qyv[V];
-      ldg<V>(qx_in, idx, nv, vec, qxv);
-      ldg<V>(qy_in, idx, nv, vec, qyv);
-      ldg<V>(u_in, idx, nv, vec, ul[j]);
-      ldg<V>(p_in, idx, nv, vec, pl[j]);
+      zmask(j, F.qx[j]);
+      zmask(j, F.qy[j]);
+      zmask(j, F.u[j]);
+      zmask(j, F.p[j]);
 #pragma unroll
       for (int e = 0; e < V; e++) {
-        sqx[r + 2][c0 + OX + e] = qxv[e];
-        sqy[r + 2][c0 + OX + e] = qyv[e];
+        ul[j][e] = F.u[j][e];
+        pl[j][e] = F.p[j][e];
+        Cl[j][e] = TWO ? capt[j][e] : F.C[j][e];
+        sqx[r + 2][c0 + OX + e] = F.qx[j][e];
+        sqy[r + 2][c0 + OX + e] = F.qy[j][e];
         sw[r + 2][c0 + OX + e] = vterm(pl[j][e], ps[j][e], ul[j][e], k.inv_c);
         if (CHECK) su[r + 2][c0 + OX + e] = ul[j][e];
       }
     }
-    // q halo: rows {-2,-1,TY} x cols -2..TX, then cols {-2,-1,TX} x rows 0..TY-1
-    for (int h = tid; h < 3 * (TX + 3) + 3 * TY; h += 256) {
-      int r, c;
-      if (h < 3 * (TX + 3)) {
-        const int rr = h / (TX + 3);
-        r = rr == 0 ? -2 : (rr == 1 ? -1 : TY);
-        c = h % (TX + 3) - 2;
-      } else {
-        const int hh = h - 3 * (TX + 3);
-        r = hh / 3;
-        const int cc = hh % 3;
-        c = cc == 0 ? -2 : (cc == 1 ? -1 : TX);
+#pragma unroll
+    for (int m = 0; m < KQ; m++) {
+      if (tid + 256 * m < NHQ) {
+        sqx[hq_r[m] + 2][hq_c[m] + OX] = hq_in[m] ? F.hqx[m] : 0.f;
+        sqy[hq_r[m] + 2][hq_c[m] + OX] = hq_in[m] ? F.hqy[m] : 0.f;
       }
-      const int hx = x0 + c, hy = y0 + r;
-      const bool in = hx >= 0 && hx < W && hy >= 0 && hy < H;
-      const long long idx = (long long)hy * pitch + hx;
-      sqx[r + 2][c + OX] = in ? ld(qx_in, idx) : 0.f;
-      sqy[r + 2][c + OX] = in ? ld(qy_in, idx) : 0.f;
     }
-    // v halo: rows {-1,TY} x cols -1..TX, then cols {-1,TX} x rows 0..TY-1
-    for (int h = tid; h < 2 * (TX + 2) + 2 * TY; h += 256) {
-      int r, c;
-      if (h < 2 * (TX + 2)) {
-        r = h < TX + 2 ? -1 : TY;
-        c = h % (TX + 2) - 1;
-      } else {
-        const int hh = h - 2 * (TX + 2);
-        r = hh >> 1;
-        c = (hh & 1) ? TX : -1;
+#pragma unroll
+    for (int m = 0; m < KW; m++) {
+      if (tid + 256 * m < NHW) {
+        const float uu = hw_in[m] ? F.hu[m] : 0.f;
+        const float pp = hw_in[m] ? F.hp[m] : 0.f;
+        sw[hw_r[m] + 2][hw_c[m] + OX] = vterm(pp, hps[m], uu, k.inv_c);
+        if (CHECK) su[hw_r[m] + 2][hw_c[m] + OX] = uu;
       }
-      const int hx = x0 + c, hy = y0 + r;
-      const bool in = hx >= 0 && hx < W && hy >= 0 && hy < H;
-      const long long idx = (long long)hy * pitch + hx;
-      const float uu = in ? u_in[idx] : 0.f;
-      const float pp = in ? ld(p_in, idx) : 0.f;
-      const float ss = in ? ld(A.ps_in, idx) : 0.f;
-      sw[r + 2][c + OX] = vterm(pp, ss, uu, k.inv_c);
-      if (CHECK) su[r + 2][c + OX] = uu;
     }
-    __syncthreads();
+    // ---- issue the loads of label l+1
+    if (l + 1 < NL) fetch(l + 1, F);
+    lds_barrier();
     // ---- gap of the input iterate (two-label; q^k is still intact in LDS)
     if (CHECK) {
 #pragma unroll
       for (int j = 0; j < RPT; j++) {
         const int r = rr0 + RSTEP * j;
         const int gy = y0 + r;
-        const int nv = gy < H ? nvx : 0;
+        const int nv = nvj[j];
 #pragma unroll
         for (int e = 0; e < V; e++) {
           if (e < nv) {
@@ -222,7 +306,7 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
                            sqy[r + 1][c + OX], hx + 1 < W, hx > 0, hy + 1 < H, hy > 0);
       sw[r + 2][c + OX] = wterm(d, sw[r + 2][c + OX]);
     }
-    __syncthreads();
+    lds_barrier();
     // ---- q^{k+1} = P_alpha(q^k + grad(w)/a) on rows -1..TY-1, cols -1..TX-1 (in place)
     for (int h = tid; h < (TY + 1) * (TX + 1); h += 256) {
       const int r = h / (TX + 1) - 1, c = h % (TX + 1) - 1;
@@ -234,26 +318,19 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
       sqx[r + 2][c + OX] = quant<TS>(qx);
       sqy[r + 2][c + OX] = quant<TS>(qy);
     }
-    __syncthreads();
+    lds_barrier();
     // ---- owned groups: d = div q^{k+1}, store q^{k+1}, per-label p and u parts
     {
       TS* qx_out = A.q_out + (long long)(2 * l) * P;
       TS* qy_out = qx_out + P;
       TS* p_out = A.p_out + (long long)l * P;
-      const TS* capl = A.cap + (long long)(TWO ? 1 : l) * P;
 #pragma unroll
       for (int j = 0; j < RPT; j++) {
         const int r = rr0 + RSTEP * j;
         const int gy = y0 + r;
-        const int nv = gy < H ? nvx : 0;
-        const long long idx = (long long)gy * pitch + gx0;
-        float C[V], qxv[V], qyv[V], pn[V];
-        if (TWO) {
-#pragma unroll
-          for (int e = 0; e < V; e++) C[e] = capt[j][e];
-        } else {
-          ldg<V>(capl, idx, nv, vec, C);
-        }
+        const int nv = nvj[j];
+        const long long idx = oj[j];
+        float qxv[V], qyv[V], pn[V];
 #pragma unroll
         for (int e = 0; e < V; e++) {
           const int gx = gx0 + e, c = c0 + OX + e;
@@ -261,7 +338,7 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
           qyv[e] = sqy[r + 2][c];
           const float d = div2(qxv[e], sqx[r + 2][c - 1], qyv[e], sqy[r + 1][c], gx + 1 < W, gx > 0,
                                gy + 1 < H, gy > 0);
-          label_update(k, ul[j][e], pl[j][e], ps[j][e], d, C[e], pn[e], t[j][l][e], sumd[j][e], sumr[j][e]);
+          label_update(k, ul[j][e], pl[j][e], ps[j][e], d, Cl[j][e], pn[e], t[j][l][e], sumd[j][e], sumr[j][e]);
         }
         if (A.write) {
           stg<V>(qx_out, idx, nv, vec, qxv);
@@ -270,14 +347,13 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
         }
       }
     }
-    if (NL > 1) __syncthreads();
+    if (NL > 1) lds_barrier();
   }
   // ---- p_s and u
 #pragma unroll
   for (int j = 0; j < RPT; j++) {
-    const int gy = y0 + rr0 + RSTEP * j;
-    const int nv = gy < H ? nvx : 0;
-    const long long idx = (long long)gy * pitch + gx0;
+    const int nv = nvj[j];
+    const long long idx = oj[j];
     float psn[V];
 #pragma unroll
     for (int e = 0; e < V; e++) psn[e] = finish_ps(k, ps[j][e], sumd[j][e], sumr[j][e], TWO, TWO ? caps[j][e] : 0.f);

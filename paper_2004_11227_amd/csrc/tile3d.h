@@ -69,12 +69,26 @@ struct Smem3 {
   double sred[4 * 5];
 };
 
-// One 64 x 8 tile of the xy plane over the slab [z0, z1).
+// Registers holding one plane's loads ahead of their use: the owned pixels
+// (q, u, p_t, p_s), at most one xy-halo entry of q and one of (u, p_t, p_s)
+// per thread, and the capacities of the owned pixels.
+template <int V>
+struct Plane3 {
+  float qx[V], qy[V], qz[V], u[V], p[V], ps[V];
+  float hqx, hqy, hqz, hu, hp, hps;
+};
+
+// One 64 x 8 tile of the xy plane over the slab [z0, z1).  The global loads
+// of plane s+1 (and the capacities of plane s) are issued at the start of
+// step s, so their latency overlaps the LDS phases of step s.
 template <typename TS, bool CHECK, bool VEC, bool SU>
 __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, int z1, Smem3<SU>& S,
                                        double (&g)[5]) {
   static_assert(!CHECK || SU, "the gap needs the u staging array");
   constexpr int TX = 64, TY = 8, V = 2, TPR = TX / V, OX = 4;
+  constexpr int NHQ = 3 * (TX + 3) + 3 * TY;   // q halo: rows -2, -1, TY; cols -2, -1, TX
+  constexpr int NHW = 2 * (TX + 2) + 2 * TY;   // w halo: rows -1, TY; cols -1, TX
+  static_assert(NHQ <= 256 && NHW <= 256, "one halo entry per thread");
   auto& sqx = S.sqx;
   auto& sqy = S.sqy;
   auto& sqz = S.sqz;
@@ -93,6 +107,111 @@ __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, 
   const TS* qy_in = A.q_in + P;
   const TS* qz_in = A.q_in + 2 * P;
 
+  // this thread's halo entries (tile coordinates), fixed over the march
+  int hq_r = 0, hq_c = 0, hw_r = 0, hw_c = 0;
+  if (tid < NHQ) {
+    if (tid < 3 * (TX + 3)) {
+      const int rr = tid / (TX + 3);
+      hq_r = rr == 0 ? -2 : (rr == 1 ? -1 : TY);
+      hq_c = tid % (TX + 3) - 2;
+    } else {
+      const int hh = tid - 3 * (TX + 3);
+      hq_r = hh / 3;
+      const int cc = hh % 3;
+      hq_c = cc == 0 ? -2 : (cc == 1 ? -1 : TX);
+    }
+  }
+  if (tid < NHW) {
+    if (tid < 2 * (TX + 2)) {
+      hw_r = tid < TX + 2 ? -1 : TY;
+      hw_c = tid % (TX + 2) - 1;
+    } else {
+      const int hh = tid - 2 * (TX + 2);
+      hw_r = hh >> 1;
+      hw_c = (hh & 1) ? TX : -1;
+    }
+  }
+  const bool hq_xy = tid < NHQ && x0 + hq_c >= 0 && x0 + hq_c < W && y0 + hq_r >= 0 && y0 + hq_r < H;
+  const bool hw_xy = tid < NHW && x0 + hw_c >= 0 && x0 + hw_c < W && y0 + hw_r >= 0 && y0 + hw_r < H;
+  const long long hq_off = (long long)(y0 + hq_r) * pitch + (x0 + hq_c);
+  const long long hw_off = (long long)(y0 + hw_r) * pitch + (x0 + hw_c);
+  const long long own_off = (long long)gy * pitch + gx0;
+
+  // Raw loads of plane s into F (no masking: entries outside the grid or
+  // the slab load element 0 of the plane, one line for the whole wave); the
+  // zeros are applied when the plane is staged, a step later, so the loads
+  // stay in flight across the LDS phases.
+  auto fetch = [&](int s, Plane3<V>& F) {
+    const bool zin = s >= 0 && s < D && s <= z1;
+    const long long zoff = (long long)s * SZ;
+    if (vec) {
+      const long long i = (zin && nvxy > 0) ? zoff + own_off : 0;
+      ldv<V>(qx_in, i, F.qx);
+      ldv<V>(qy_in, i, F.qy);
+      ldv<V>(qz_in, i, F.qz);
+      ldv<V>(A.u_in, i, F.u);
+      ldv<V>(A.p_in, i, F.p);
+      ldv<V>(A.ps_in, i, F.ps);
+    } else {
+#pragma unroll
+      for (int e = 0; e < V; e++) {
+        const long long i = (zin && e < nvxy) ? zoff + own_off + e : 0;
+        F.qx[e] = ld(qx_in, i);
+        F.qy[e] = ld(qy_in, i);
+        F.qz[e] = ld(qz_in, i);
+        F.u[e] = ld(A.u_in, i);
+        F.p[e] = ld(A.p_in, i);
+        F.ps[e] = ld(A.ps_in, i);
+      }
+    }
+    const long long iq = (zin && hq_xy) ? zoff + hq_off : 0;
+    const long long iw = (zin && hw_xy) ? zoff + hw_off : 0;
+    F.hqx = ld(qx_in, iq);
+    F.hqy = ld(qy_in, iq);
+    F.hqz = ld(qz_in, iq);
+    F.hu = ld(A.u_in, iw);
+    F.hp = ld(A.p_in, iw);
+    F.hps = ld(A.ps_in, iw);
+  };
+  // Zero the entries of plane s that lie outside the grid.
+  auto mask = [&](int s, Plane3<V>& F) {
+    const bool zin = s >= 0 && s < D;
+#pragma unroll
+    for (int e = 0; e < V; e++) {
+      const bool ok = zin && e < nvxy;
+      F.qx[e] = ok ? F.qx[e] : 0.f;
+      F.qy[e] = ok ? F.qy[e] : 0.f;
+      F.qz[e] = ok ? F.qz[e] : 0.f;
+      F.u[e] = ok ? F.u[e] : 0.f;
+      F.p[e] = ok ? F.p[e] : 0.f;
+      F.ps[e] = ok ? F.ps[e] : 0.f;
+    }
+    const bool iq = zin && hq_xy, iw = zin && hw_xy;
+    F.hqx = iq ? F.hqx : 0.f;
+    F.hqy = iq ? F.hqy : 0.f;
+    F.hqz = iq ? F.hqz : 0.f;
+    F.hu = iw ? F.hu : 0.f;
+    F.hp = iw ? F.hp : 0.f;
+    F.hps = iw ? F.hps : 0.f;
+  };
+  // Capacities of the owned pixels of plane z (raw: only pixels inside the
+  // grid and the slab are used).
+  auto fetch_caps = [&](int z, float (&cs)[V], float (&ct)[V]) {
+    const bool ok = z >= z0 && z < z1;
+    if (vec) {
+      const long long i = (ok && nvxy > 0) ? (long long)z * SZ + own_off : 0;
+      ldv<V>(A.cap, i, cs);
+      ldv<V>(A.cap + P, i, ct);
+    } else {
+#pragma unroll
+      for (int e = 0; e < V; e++) {
+        const long long i = (ok && e < nvxy) ? (long long)z * SZ + own_off + e : 0;
+        cs[e] = ld(A.cap, i);
+        ct[e] = ld(A.cap + P, i);
+      }
+    }
+  };
+
   // owner registers: values of plane s-1 (rotated each step)
   float u_m[V], p_m[V], s_m[V];   // u, p_t, p_s at plane s-1
   float q1z_mm[V];                // q_z^{k+1} at plane s-2
@@ -102,81 +221,53 @@ __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, 
     u_m[e] = p_m[e] = s_m[e] = q1z_mm[e] = 0.f;
     dk_m[e] = 0.0;
   }
+  Plane3<V> F;
+  fetch(z0 - 2, F);
+  float cs_n[V], ct_n[V];         // capacities of plane s-1 (loaded a step ahead)
+#pragma unroll
+  for (int e = 0; e < V; e++) cs_n[e] = ct_n[e] = 0.f;
 
 #pragma unroll 1
   for (int s = z0 - 2; s <= z1; s++) {
     const int sl = s & 1, pl = sl ^ 1;   // slot of plane s, slot of plane s-1
-    const bool zin = s >= 0 && s < D;
-    const long long zoff = (long long)s * SZ;
-    // ---- 1. stage plane s: interior by owners, then halos
+    // ---- 1. stage plane s from the prefetch registers
+    mask(s, F);
     float u_c[V], p_c[V], s_c[V];
-    {
-      const int nv = zin ? nvxy : 0;
-      const long long idx = zoff + (long long)gy * pitch + gx0;
-      float qxv[V], qyv[V], qzv[V];
-      ldg<V>(qx_in, idx, nv, vec, qxv);
-      ldg<V>(qy_in, idx, nv, vec, qyv);
-      ldg<V>(qz_in, idx, nv, vec, qzv);
-      ldg<V>(A.u_in, idx, nv, vec, u_c);
-      ldg<V>(A.p_in, idx, nv, vec, p_c);
-      ldg<V>(A.ps_in, idx, nv, vec, s_c);
 #pragma unroll
-      for (int e = 0; e < V; e++) {
-        const int c = c0 + OX + e;
-        sqx[sl][r0 + 2][c] = qxv[e];
-        sqy[sl][r0 + 2][c] = qyv[e];
-        sqz[sl][r0 + 2][c] = qzv[e];
-        sw[sl][r0 + 2][c] = vterm(p_c[e], s_c[e], u_c[e], k.inv_c);
-        if (CHECK) su[sl][r0 + 2][c] = u_c[e];
-      }
+    for (int e = 0; e < V; e++) {
+      const int c = c0 + OX + e;
+      u_c[e] = F.u[e];
+      p_c[e] = F.p[e];
+      s_c[e] = F.ps[e];
+      sqx[sl][r0 + 2][c] = F.qx[e];
+      sqy[sl][r0 + 2][c] = F.qy[e];
+      sqz[sl][r0 + 2][c] = F.qz[e];
+      sw[sl][r0 + 2][c] = vterm(p_c[e], s_c[e], u_c[e], k.inv_c);
+      if (CHECK) su[sl][r0 + 2][c] = u_c[e];
     }
-    for (int h = tid; h < 3 * (TX + 3) + 3 * TY; h += 256) {
-      int r, c;
-      if (h < 3 * (TX + 3)) {
-        const int rr = h / (TX + 3);
-        r = rr == 0 ? -2 : (rr == 1 ? -1 : TY);
-        c = h % (TX + 3) - 2;
-      } else {
-        const int hh = h - 3 * (TX + 3);
-        r = hh / 3;
-        const int cc = hh % 3;
-        c = cc == 0 ? -2 : (cc == 1 ? -1 : TX);
-      }
-      const int hx = x0 + c, hy = y0 + r;
-      const bool in = zin && hx >= 0 && hx < W && hy >= 0 && hy < H;
-      const long long idx = zoff + (long long)hy * pitch + hx;
-      sqx[sl][r + 2][c + OX] = in ? ld(qx_in, idx) : 0.f;
-      sqy[sl][r + 2][c + OX] = in ? ld(qy_in, idx) : 0.f;
-      sqz[sl][r + 2][c + OX] = in ? ld(qz_in, idx) : 0.f;
+    if (tid < NHQ) {
+      sqx[sl][hq_r + 2][hq_c + OX] = F.hqx;
+      sqy[sl][hq_r + 2][hq_c + OX] = F.hqy;
+      sqz[sl][hq_r + 2][hq_c + OX] = F.hqz;
     }
-    for (int h = tid; h < 2 * (TX + 2) + 2 * TY; h += 256) {
-      int r, c;
-      if (h < 2 * (TX + 2)) {
-        r = h < TX + 2 ? -1 : TY;
-        c = h % (TX + 2) - 1;
-      } else {
-        const int hh = h - 2 * (TX + 2);
-        r = hh >> 1;
-        c = (hh & 1) ? TX : -1;
-      }
-      const int hx = x0 + c, hy = y0 + r;
-      const bool in = zin && hx >= 0 && hx < W && hy >= 0 && hy < H;
-      const long long idx = zoff + (long long)hy * pitch + hx;
-      const float uu = in ? A.u_in[idx] : 0.f;
-      const float pp = in ? ld(A.p_in, idx) : 0.f;
-      const float ss = in ? ld(A.ps_in, idx) : 0.f;
-      sw[sl][r + 2][c + OX] = vterm(pp, ss, uu, k.inv_c);
-      if (CHECK) su[sl][r + 2][c + OX] = uu;
+    if (tid < NHW) {
+      sw[sl][hw_r + 2][hw_c + OX] = vterm(F.hp, F.hps, F.hu, k.inv_c);
+      if (CHECK) su[sl][hw_r + 2][hw_c + OX] = F.hu;
     }
-    __syncthreads();
+    float cs[V], ct[V];
+#pragma unroll
+    for (int e = 0; e < V; e++) {
+      cs[e] = cs_n[e];
+      ct[e] = ct_n[e];
+    }
+    // ---- issue the loads of plane s+1 and the capacities of plane s
+    fetch(s + 1, F);
+    fetch_caps(s, cs_n, ct_n);
+    lds_barrier();
     // ---- gap of plane s-1 of the input iterate (owned pixels)
     if (CHECK && s - 1 >= z0 && s - 1 < z1) {
       const int zz = s - 1;
       const int nv = nvxy;
-      const long long idx = (long long)zz * SZ + (long long)gy * pitch + gx0;
-      float cs[V], ct[V];
-      ldg<V>(A.cap, idx, nv, vec, cs);
-      ldg<V>(A.cap + P, idx, nv, vec, ct);
 #pragma unroll
       for (int e = 0; e < V; e++) {
         if (e < nv) {
@@ -215,7 +306,7 @@ __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, 
                   (((s + 1 < D) ? (double)sqz[sl][r0 + 2][c] : 0.0) - ((s > 0) ? (double)sqz[pl][r0 + 2][c] : 0.0));
       }
     }
-    __syncthreads();
+    lds_barrier();
     // ---- 3. q^{k+1}(s-1) in place, rows -1..TY-1, cols -1..TX-1
     if (s - 1 >= z0 - 1) {
       for (int h = tid; h < (TY + 1) * (TX + 1); h += 256) {
@@ -231,15 +322,13 @@ __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, 
         sqz[pl][r + 2][c + OX] = quant3<TS>(qz);
       }
     }
-    __syncthreads();
+    lds_barrier();
     // ---- 4. owned pixels of plane s-1: divergence, updates, stores
     if (s - 1 >= z0 && s - 1 < z1) {
       const int zz = s - 1;
       const int nv = nvxy;
-      const long long idx = (long long)zz * SZ + (long long)gy * pitch + gx0;
-      float cs[V], ct[V], qxv[V], qyv[V], qzv[V], pn[V], psn[V], un[V];
-      ldg<V>(A.cap, idx, nv, vec, cs);
-      ldg<V>(A.cap + P, idx, nv, vec, ct);
+      const long long idx = (long long)zz * SZ + own_off;
+      float qxv[V], qyv[V], qzv[V], pn[V], psn[V], un[V];
 #pragma unroll
       for (int e = 0; e < V; e++) {
         const int gx = gx0 + e, c = c0 + OX + e;
@@ -270,7 +359,7 @@ __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, 
       p_m[e] = p_c[e];
       s_m[e] = s_c[e];
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 

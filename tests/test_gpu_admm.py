@@ -114,6 +114,51 @@ def test_3d_fused_gap_and_solve():
     assert np.max(np.abs(g["u"] - st.u)) <= TOL_U
 
 
+def test_3d_full_size_one_step_random_state():
+    """256^3 (the 3-D workload size, launched with the slab depth the solver
+    picks for it), one iteration from a seeded random admissible state, every
+    field compared with the oracle."""
+    banner("3d one step 256^3 random state")
+    inp = synth.config_inputs("c3")
+    caps = inp["caps"].astype(np.float32).astype(np.float64)
+    shape = caps.shape[1:]
+    rs = synth.random_state(shape, 2, "two", 0.4, caps, seed=98)
+    f32 = {k: v.astype(np.float32).astype(np.float64) for k, v in rs.items()}
+    del rs
+    s = gpu_solver(caps, model="two", method="eb", relax=1.5, alpha=0.4)
+    for f in ("u", "q", "ps", "p"):
+        s.write(f, torch.from_numpy(f32[f].astype(np.float32)))
+    s.step(1)
+    g = gpu_fields(s)
+    s.close()
+    pr = oracle_problem(shape, dict(model="two", method="eb", relax=1.5, alpha=0.4))
+    st = oracle.state_from_arrays(pr, f32["u"], f32["q"], f32["ps"], f32["p"])
+    oracle.step(pr, caps, st, 1)
+    for f in ("u", "q", "ps", "p"):
+        err = np.max(np.abs(g[f] - getattr(st, f)))
+        assert err < 2e-5, (f, err)
+
+
+def test_3d_full_size_fused_equals_unfused_bitwise():
+    """256^3, 12 iterations (one gap check inside): the fused z-marching
+    sweep at its production slab depth gives the unfused passes' bits."""
+    banner("3d bitwise 256^3")
+    caps = synth.config_inputs("c3")["caps"]
+    ref = None
+    for variant in ("unfused", "fused"):
+        s = gpu_solver(caps, model="two", method="eb", relax=1.5, alpha=0.4, variant=variant,
+                       tol=0.0, max_iter=12, check_every=10)
+        s.solve()
+        torch.cuda.synchronize()
+        g = {f: s.read(f).cpu().numpy() for f in ("u", "q")}
+        s.close()
+        if ref is None:
+            ref = g
+        else:
+            for f in ref:
+                assert np.array_equal(ref[f], g[f]), f
+
+
 def test_potts_3d_fused_request_runs_unfused():
     banner("potts 3d")
     vol = synth.ellipsoid_volume(12, 14, 18, 3, 0.1, 3006)
