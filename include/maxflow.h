@@ -93,7 +93,8 @@ typedef struct {
   int32_t max_iter;      /* iteration cap for maxflow_solve (>= 0)                   */
   double tol;            /* relative primal-dual gap tolerance for maxflow_solve      */
   int32_t check_every;   /* gap cadence in iterations; 0 -> 10                        */
-  int32_t tile_rows;     /* fused 2-D tile height (8, 16 or 32); 0 -> tuned default   */
+  int32_t tile_rows;     /* fused 2-D tile height (8, 16 or 32); 0 -> 16 (8 for BF16 Potts
+                            with n >= 8); maxflow_tune chooses per problem             */
   /* Pool only, BF16 storage: a solve whose gap at a check is <= promote_gap,
    * or that reaches iteration promote_iter, is frozen at that iterate and
    * continued with FP32 flows (BF16 rounding floors the reachable gap near
@@ -170,6 +171,22 @@ mf_status maxflow_import_state(mf_solver* s, const void* src, int64_t iter);
 
 mf_status maxflow_destroy(mf_solver* s);
 
+/* Autotuner for the launch shape of the fused 2-D sweep.  Times `sweeps`
+ * sweeps (after two warm-up sweeps) for each candidate tile height (8, 16
+ * and 32 rows of 64 columns) on the solver's stream with HIP events, keeps
+ * the fastest for this solver, and returns it in *best_tile_rows.  Every
+ * candidate runs iterate k -> k+1 from the solver's current iterate k
+ * without advancing it, so the solver's state and iteration count are
+ * unchanged; the tile height never changes the iterates (bit-identical).
+ * `us_per_iter` (host, 3 entries, may be null) receives microseconds per
+ * sweep for heights 8, 16, 32.  Solvers without a tile-height choice (3-D,
+ * the unfused variant) time their one configuration, report it in the entry
+ * of their current height (others 0) and keep it; rPDRQ (in-place sweeps)
+ * runs nothing and reports zeros.  Synchronises the stream.  Errors:
+ * MF_EINVAL (null solver or best_tile_rows, sweeps < 1 or > 10000),
+ * MF_EDEVICE. */
+mf_status maxflow_tune(mf_solver* s, int32_t sweeps, int32_t* best_tile_rows, double* us_per_iter);
+
 /* Thread-local message describing the last error (solver and pool calls). */
 const char* maxflow_last_error(void);
 
@@ -178,18 +195,21 @@ const char* maxflow_last_error(void);
  *
  * The pool keeps many rpADMM solves resident in one caller-owned device arena
  * and advances all of them together.  Each solve is cut into tiles; one
- * persistent kernel per model class walks a device-resident work list of
- * (solve, tile) items drawn from grids of any size, and every running solve
- * advances one iteration per super-step with its own iteration counter, gap
- * cadence and convergence decision (all on the GPU).  `steps_per_advance`
- * super-steps are captured once into a hipGraph; admission and retirement
- * edit the device tables between replays, so the graph never changes.  A
- * solve's iterates are bit-identical alone, in any mix, and through the
- * single-solve API with the same storage (tiles of 64 x 16 two-label, 64 x 8
- * Potts).  Supported: methods FG and EB; 2-D two-label and Potts (n = 2, 3,
- * 4, 8); 3-D two-label; FP32 or BF16 storage.  Convergence follows the same
- * rule as maxflow_solve (gap at multiples of check_every, tolerance tol, cap
- * max_iter) and the state stays at the accepted iterate.
+ * kernel launch per model class walks a device-resident work list of
+ * (solve, tile) items drawn from grids of any size (one item per workgroup),
+ * and every running solve advances one iteration per super-step with its own
+ * iteration counter, gap cadence and convergence decision (all on the GPU).
+ * `steps_per_advance` super-steps form one hipGraph; admission and
+ * retirement edit the device tables between replays and resize the graph's
+ * kernel grids in place (the graph is rebuilt only when the set of classes
+ * present changes).  A solve's iterates are bit-identical alone, in any mix,
+ * and through the single-solve API with the same storage.  Supported:
+ * methods FG and EB; 2-D two-label and Potts (n = 2, 3, 4, 8); 3-D two-label;
+ * FP32 or BF16 storage (BF16 solves may be promoted to FP32 storage near the
+ * BF16 rounding floor, see promote_gap / promote_iter).  Convergence follows
+ * the same rule as maxflow_solve (gap at multiples of check_every, tolerance
+ * tol, cap max_iter) and the state stays at the accepted iterate; the pool
+ * requires check_every == steps_per_advance and max_iter a multiple of it.
  * ---------------------------------------------------------------------- */
 typedef struct mf_pool mf_pool;
 

@@ -104,7 +104,9 @@ std::string resolve(const mf_params* in, Resolved& r) {
   if (!(p.tol >= 0.0)) return "tol must be >= 0";
   if (p.check_every == 0) p.check_every = 10;
   if (p.check_every < 1) return "check_every must be >= 1";
-  if (p.tile_rows == 0) p.tile_rows = two ? 16 : 8;
+  // default tile height: 16 rows, except 8 for BF16 Potts with n >= 8 (the
+  // measured fastest on gfx950 at 1024^2; maxflow_tune picks per problem)
+  if (p.tile_rows == 0) p.tile_rows = (!two && p.storage == MF_BF16 && p.nlabels >= 8) ? 8 : 16;
   if (p.tile_rows != 8 && p.tile_rows != 16 && p.tile_rows != 32) return "tile_rows must be 8, 16 or 32";
   if (!(p.promote_gap >= 0.0) || p.promote_iter < 0) return "promote_gap and promote_iter must be >= 0";
   r.nl = two ? 1 : p.nlabels;
@@ -579,6 +581,61 @@ mf_status maxflow_import_state(mf_solver* s, const void* src, int64_t iter) {
     HIP_TRY(hipMemcpyAsync(s->ws + s->L.stz, (const char*)src + s->L.state_bytes, s->L.state_bytes,
                            hipMemcpyDeviceToDevice, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
+  return MF_OK;
+}
+
+mf_status maxflow_tune(mf_solver* s, int32_t sweeps, int32_t* best_tile_rows, double* us_per_iter) {
+  if (!s || !best_tile_rows) return fail(MF_EINVAL, "null solver or best_tile_rows");
+  if (sweeps < 1 || sweeps > 10000) return fail(MF_EINVAL, "sweeps must be in 1..10000");
+  const bool choice = s->r.p.method != MF_RPDRQ && s->r.p.variant == MF_FUSED && s->r.g.ndim == 2;
+  const int cand[3] = {8, 16, 32};
+  double us[3] = {0.0, 0.0, 0.0};
+  if (s->r.p.method == MF_RPDRQ) {   // in-place sweeps, no launch-shape choice: nothing is run
+    *best_tile_rows = s->r.p.tile_rows;
+    if (us_per_iter)
+      for (int c = 0; c < 3; c++) us_per_iter[c] = 0.0;
+    return MF_OK;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(MF_EDEVICE, "event creation failed");
+  }
+  const int keep = s->r.p.tile_rows;
+  int best = keep;
+  double best_us = 0.0;
+  hipError_t he = hipSuccess;
+  for (int c = 0; c < 3 && he == hipSuccess; c++) {
+    if (!choice && cand[c] != keep) continue;
+    s->r.p.tile_rows = cand[c];
+    float ms = 0.f;
+    // iterate k -> k+1 repeatedly: buffer k & 1 (the current iterate) is
+    // only read, buffer (k+1) & 1 is scratch until the next real sweep
+    for (int w = 0; w < 2 + sweeps && he == hipSuccess; w++) {
+      if (w == 2) he = hipEventRecord(e0, s->stream);
+      if (he == hipSuccess) he = admm_sweep(s, s->iter, false, true, nullptr);
+    }
+    if (he == hipSuccess) he = hipEventRecord(e1, s->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (he != hipSuccess) break;
+    us[c] = 1e3 * (double)ms / sweeps;
+    if (best_us == 0.0 || us[c] < best_us) {
+      best_us = us[c];
+      best = cand[c];
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  s->r.p.tile_rows = best;
+  if (he != hipSuccess) {
+    s->r.p.tile_rows = keep;
+    return fail(MF_EDEVICE, std::string("tuning sweep: ") + hipGetErrorString(he));
+  }
+  *best_tile_rows = best;
+  if (us_per_iter)
+    for (int c = 0; c < 3; c++) us_per_iter[c] = us[c];
   return MF_OK;
 }
 

@@ -6,6 +6,8 @@
 // are the same device functions as the single-solve kernels, so a solve
 // produces the same bits in the pool, alone or in any mix, and through the
 // single-solve API with the same tile shape.
+#include <type_traits>
+
 #include "mf_pool.h"
 #include "tile2d.h"
 #include "tile3d.h"
@@ -215,17 +217,18 @@ __global__ __launch_bounds__(64) void k_pool_book(PoolDev d, int check_step) {
 // Kernel of one (class, gap-carrying, vector-aligned) launch.
 template <typename TS, bool CHECK, bool VEC>
 static const void* pool_kernel_ts(int model) {
+  constexpr bool BF = std::is_same<TS, bf16_t>::value;
   if (CHECK) {
-    if (model == 0) return (const void*)k_pool2d<1, true, TS, 16, true, VEC>;
+    if (model == 0) return (const void*)k_pool2d<1, true, TS, pool_tile_rows(0, BF), true, VEC>;
     if (model == 5) return (const void*)k_pool3d<TS, true, VEC>;
     return nullptr;   // Potts sweeps never carry the gap
   }
   switch (model) {
-    case 0: return (const void*)k_pool2d<1, true, TS, 16, false, VEC>;
-    case 1: return (const void*)k_pool2d<2, false, TS, 8, false, VEC>;
-    case 2: return (const void*)k_pool2d<3, false, TS, 8, false, VEC>;
-    case 3: return (const void*)k_pool2d<4, false, TS, 8, false, VEC>;
-    case 4: return (const void*)k_pool2d<8, false, TS, 8, false, VEC>;
+    case 0: return (const void*)k_pool2d<1, true, TS, pool_tile_rows(0, BF), false, VEC>;
+    case 1: return (const void*)k_pool2d<2, false, TS, pool_tile_rows(1, BF), false, VEC>;
+    case 2: return (const void*)k_pool2d<3, false, TS, pool_tile_rows(2, BF), false, VEC>;
+    case 3: return (const void*)k_pool2d<4, false, TS, pool_tile_rows(3, BF), false, VEC>;
+    case 4: return (const void*)k_pool2d<8, false, TS, pool_tile_rows(4, BF), false, VEC>;
     default: return (const void*)k_pool3d<TS, false, VEC>;
   }
 }
@@ -241,23 +244,21 @@ const void* pool_kernel(int cls, bool check, bool vec) {
   return vec ? pool_kernel_ts<float, false, true>(model) : pool_kernel_ts<float, false, false>(model);
 }
 
+template <typename TS>
+static const void* pool_gap_kernel_ts(int model) {
+  constexpr bool BF = std::is_same<TS, bf16_t>::value;
+  switch (model) {
+    case 1: return (const void*)k_pool_gap2d<2, TS, pool_tile_rows(1, BF)>;
+    case 2: return (const void*)k_pool_gap2d<3, TS, pool_tile_rows(2, BF)>;
+    case 3: return (const void*)k_pool_gap2d<4, TS, pool_tile_rows(3, BF)>;
+    case 4: return (const void*)k_pool_gap2d<8, TS, pool_tile_rows(4, BF)>;
+    default: return nullptr;   // two-label gaps are fused into the sweep
+  }
+}
+
 const void* pool_gap_kernel(int cls) {
   const int model = cls % kPoolModels;
-  if (model == 0 || model == 5) return nullptr;   // two-label gaps are fused
-  if (cls >= kPoolModels) {
-    switch (model) {
-      case 1: return (const void*)k_pool_gap2d<2, bf16_t, 8>;
-      case 2: return (const void*)k_pool_gap2d<3, bf16_t, 8>;
-      case 3: return (const void*)k_pool_gap2d<4, bf16_t, 8>;
-      default: return (const void*)k_pool_gap2d<8, bf16_t, 8>;
-    }
-  }
-  switch (model) {
-    case 1: return (const void*)k_pool_gap2d<2, float, 8>;
-    case 2: return (const void*)k_pool_gap2d<3, float, 8>;
-    case 3: return (const void*)k_pool_gap2d<4, float, 8>;
-    default: return (const void*)k_pool_gap2d<8, float, 8>;
-  }
+  return cls >= kPoolModels ? pool_gap_kernel_ts<bf16_t>(model) : pool_gap_kernel_ts<float>(model);
 }
 
 const void* pool_book_kernel() { return (const void*)k_pool_book; }

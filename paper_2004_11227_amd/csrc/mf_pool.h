@@ -62,7 +62,8 @@ const void* pool_kernel(int cls, bool check, bool vec);
 const void* pool_gap_kernel(int cls);
 const void* pool_book_kernel();
 
-// Tile height of each pool class (2-D) and the z-slab depth of 3-D solves.
-constexpr int pool_tile_rows(int model) { return model == 0 ? 16 : 8; }
+// Tile height of a 2-D pool class (model index as in the class table; the
+// same defaults as single solves: 16 rows, 8 for BF16 Potts with n = 8).
+constexpr int pool_tile_rows(int model, bool bf16) { return (model == 4 && bf16) ? 8 : 16; }
 
 }  // namespace mf

@@ -309,7 +309,8 @@ void fill_image(mf_pool* P, int slot, long long iter) {
   S.pitch = f.pitch;
   S.P = f.g.plane;
   S.tiles_x = (f.g.W + 63) / 64;
-  S.tiles_y = f.g.ndim == 2 ? (f.g.H + pool_tile_rows(f.model) - 1) / pool_tile_rows(f.model) : (f.g.H + 7) / 8;
+  const int TY = pool_tile_rows(f.model, f.p.storage == MF_BF16);
+  S.tiles_y = f.g.ndim == 2 ? (f.g.H + TY - 1) / TY : (f.g.H + 7) / 8;
   S.tz = f.g.ndim == 3 ? std::min(f.g.D, 16) : 1;
   S.check_every = f.p.check_every;
   S.cap = P->arena + H.off;
@@ -332,6 +333,27 @@ void fill_image(mf_pool* P, int slot, long long iter) {
 // it, move its tiles to the FP32 class and release the BF16 block.  The
 // solve resumes at k with the gap re-evaluated there, so the trajectory does
 // not depend on when the host gets to it.
+// Work items (tile origins) of a solve in `slot`: 64 x TY tiles of the
+// class's tile height (2-D), 64 x 8 x 16 bricks (3-D).
+std::vector<WorkItem> make_items(int slot, const Footprint& f) {
+  std::vector<WorkItem> items;
+  const int tx = (f.g.W + 63) / 64;
+  if (f.g.ndim == 2) {
+    const int TY = pool_tile_rows(f.model, f.p.storage == MF_BF16);
+    const int ty = (f.g.H + TY - 1) / TY;
+    for (int y = 0; y < ty; y++)
+      for (int x = 0; x < tx; x++) items.push_back({slot, x * 64, y * TY, 0});
+  } else {
+    const int ty = (f.g.H + 7) / 8;
+    const int tz = std::min(f.g.D, 16);
+    const int nz = (f.g.D + tz - 1) / tz;
+    for (int z = 0; z < nz; z++)
+      for (int y = 0; y < ty; y++)
+        for (int x = 0; x < tx; x++) items.push_back({slot, x * 64, y * 8, z * tz});
+  }
+  return items;
+}
+
 mf_status promote(mf_pool* P, int slot, long long k, bool& moved) {
   moved = false;
   HostSlot& H = P->slots[slot];
@@ -340,6 +362,8 @@ mf_status promote(mf_pool* P, int slot, long long k, bool& moved) {
   Footprint f2;
   const std::string e = plan_solve(&p32, f2);
   if (!e.empty()) return pfail(MF_EINVAL, e);
+  const std::vector<WorkItem> items = make_items(slot, f2);
+  if ((long long)P->lists[f2.cls].size() + (long long)items.size() > P->max_tiles) return MF_OK;   // stays frozen
   size_t off;
   if (!alloc_block(P, f2.total, off)) return MF_OK;   // no room yet: stays frozen
   char* base = P->arena + off;
@@ -366,11 +390,11 @@ mf_status promote(mf_pool* P, int slot, long long k, bool& moved) {
   st.state = SLOT_RUNNING;
   st.iter = k;
   PHIP(hipMemcpyAsync(P->dev.stats + slot, &st, sizeof(st), hipMemcpyHostToDevice, P->stream));
+  // the FP32 class may tile differently: rebuild this solve's items there
   auto& Lo = P->lists[old_cls];
   auto& Ln = P->lists[f2.cls];
-  for (const WorkItem& w : Lo)
-    if (w.slot == slot) Ln.push_back(w);
   Lo.erase(std::remove_if(Lo.begin(), Lo.end(), [&](const WorkItem& w) { return w.slot == slot; }), Lo.end());
+  Ln.insert(Ln.end(), items.begin(), items.end());
   mf_status ms = upload_list(P, old_cls);
   if (ms == MF_OK) ms = upload_list(P, f2.cls);
   if (ms != MF_OK) return ms;
@@ -474,22 +498,7 @@ mf_status mf_pool_admit(mf_pool* P, const mf_params* p, const float* cap, int64_
       break;
     }
   if (slot < 0) return pfail(MF_ENOMEM, "no free slot");
-  // work items of this solve
-  std::vector<WorkItem> items;
-  const int tx = (f.g.W + 63) / 64;
-  if (f.g.ndim == 2) {
-    const int TY = pool_tile_rows(f.model);
-    const int ty = (f.g.H + TY - 1) / TY;
-    for (int y = 0; y < ty; y++)
-      for (int x = 0; x < tx; x++) items.push_back({slot, x * 64, y * TY, 0});
-  } else {
-    const int ty = (f.g.H + 7) / 8;
-    const int tz = std::min(f.g.D, 16);
-    const int nz = (f.g.D + tz - 1) / tz;
-    for (int z = 0; z < nz; z++)
-      for (int y = 0; y < ty; y++)
-        for (int x = 0; x < tx; x++) items.push_back({slot, x * 64, y * 8, z * tz});
-  }
+  const std::vector<WorkItem> items = make_items(slot, f);
   auto& L = P->lists[f.cls];
   if ((long long)L.size() + (long long)items.size() > P->max_tiles) return pfail(MF_ENOMEM, "work list full");
   size_t off;

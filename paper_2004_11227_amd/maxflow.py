@@ -60,7 +60,7 @@ EXPORTS = ["maxflow_workspace_bytes", "maxflow_create", "maxflow_reset", "maxflo
            "maxflow_gap", "maxflow_solve", "maxflow_iter", "maxflow_read_u", "maxflow_labels",
            "maxflow_read_field", "maxflow_write_field", "maxflow_state_bytes",
            "maxflow_export_state", "maxflow_import_state", "maxflow_destroy",
-           "maxflow_last_error"]
+           "maxflow_last_error", "maxflow_tune"]
 
 
 def lib():
@@ -91,6 +91,7 @@ def lib():
         "maxflow_import_state": (S, [V, V, ctypes.c_int64]),
         "maxflow_destroy": (S, [V]),
         "maxflow_last_error": (ctypes.c_char_p, []),
+        "maxflow_tune": (S, [V, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -150,6 +151,12 @@ class Solver:
 
     def __init__(self, caps: torch.Tensor, stream: torch.cuda.Stream | None = None, **kw):
         shape = tuple(caps.shape[1:])
+        auto = kw.get("tile_rows") == "auto"
+        if auto:   # a cached choice, else the default now and the autotuner below
+            from . import tuning
+            cached = tuning.lookup(shape, caps.device, **kw)
+            kw = {**kw, "tile_rows": cached or 0}
+            auto = cached is None
         self.params = make_params(shape, **kw)
         self.shape = shape
         self.model = kw.get("model", "two")
@@ -171,6 +178,11 @@ class Solver:
                                     ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self._h = h
+        self._kw = kw
+        if auto:
+            from . import tuning
+            best, us = self.tune()
+            tuning.store(shape, caps.device, best, us, **kw)
 
     # -- lifecycle
     def close(self):
@@ -183,6 +195,15 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+    def tune(self, sweeps: int = 20):
+        """Time the candidate tile heights on this solver (state unchanged),
+        keep the fastest.  Returns (tile_rows, {rows: us_per_sweep})."""
+        best = ctypes.c_int32()
+        us = (ctypes.c_double * 3)()
+        _check(lib().maxflow_tune(self._h, int(sweeps), ctypes.byref(best), us))
+        self.params.tile_rows = int(best.value)
+        return int(best.value), {r: float(us[i]) for i, r in enumerate((8, 16, 32)) if us[i] > 0}
 
     # -- iteration
     @property

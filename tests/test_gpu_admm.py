@@ -326,3 +326,41 @@ def test_export_import_resume_bitwise():
         assert np.array_equal(ga[f], gc[f])
     for s in (a, b, c):
         s.close()
+
+
+def test_autotune_keeps_state_and_caches(tmp_path, monkeypatch):
+    """maxflow_tune times the candidate tile heights without moving the
+    iterate; the tuned solver continues bit-identically; the choice is
+    cached and reused."""
+    banner("autotune")
+    from paper_2004_11227_amd import tuning
+    monkeypatch.setenv("MF_TUNING_CACHE", str(tmp_path / "tune.json"))
+    tuning.clear()
+    caps = synth.config_inputs("c1", size=(300, 333))["caps"]
+    kw = dict(model="two", method="eb", relax=1.5, alpha=0.5)
+    ref = gpu_solver(caps, **kw)
+    ref.step(7)
+    s = gpu_solver(caps, **kw)
+    s.step(5)
+    before = gpu_fields(s)
+    best, us = s.tune(sweeps=5)
+    assert best in (8, 16, 32) and set(us) == {8, 16, 32} and all(v > 0 for v in us.values())
+    assert s.iter == 5
+    after = gpu_fields(s)
+    for f in before:
+        assert np.array_equal(before[f], after[f]), f
+    s.step(2)
+    a, b = gpu_fields(ref), gpu_fields(s)
+    for f in a:
+        assert np.array_equal(a[f], b[f]), f
+    s.close()
+    ref.close()
+    t = gpu_solver(caps, tile_rows="auto", **kw)
+    assert t.params.tile_rows in (8, 16, 32)
+    assert tuning.lookup(caps.shape[1:], t.device, **kw) == t.params.tile_rows
+    t.close()
+    tuning.clear()
+    u = gpu_solver(caps, tile_rows="auto", **kw)   # from the file, no tuning
+    assert u.params.tile_rows == tuning.lookup(caps.shape[1:], u.device, **kw)
+    u.close()
+    tuning.clear()
