@@ -123,7 +123,12 @@ std::string resolve(const mf_params* in, Resolved& r) {
   }
   const long long n = r.g.npix();
   if (n > (1LL << 34)) return "grid too large";
-  r.g.plane = (long long)align_up((size_t)n, 128);
+  // Fused rpADMM sweeps use rows padded to a multiple of 4 elements, so every
+  // owned group of a tile is one vector access whatever the width; the
+  // element-wise kernels (unfused passes, rPDRQ) use the dense layout.
+  const bool padded = p.method != MF_RPDRQ && p.variant == MF_FUSED && !(p.ndim == 3 && p.model == MF_POTTS);
+  r.g.pitch = padded ? (r.g.W + 3) / 4 * 4 : r.g.W;
+  r.g.plane = (long long)align_up((size_t)r.g.nstore(), 128);
   r.esz = p.storage == MF_BF16 ? 2 : 4;
   r.nq = r.nl * p.ndim;
   return "";
@@ -386,8 +391,8 @@ mf_status maxflow_create(const mf_params* p, const float* cap, void* workspace, 
       return fail(MF_EDEVICE, "event creation failed");
     }
   }
-  hipError_t he = launch_convert_caps(cap, s->cap, r.g.npix(), r.ncap, r.g.plane, r.p.storage == MF_BF16,
-                                      s->stream);
+  hipError_t he = launch_pitch_copy(cap, false, r.g.npix(), r.g.W, s->cap, r.p.storage == MF_BF16, r.g.plane,
+                                    r.g.pitch, r.g.W, (long long)r.g.H * r.g.D, r.ncap, s->stream);
   if (he != hipSuccess) {
     maxflow_destroy(s);
     return fail(MF_EDEVICE, std::string("capacity copy: ") + hipGetErrorString(he));
@@ -504,7 +509,7 @@ mf_status maxflow_read_u(mf_solver* s, float* dst) { return maxflow_read_field(s
 mf_status maxflow_labels(mf_solver* s, int32_t* dst) {
   if (!s || !dst) return fail(MF_EINVAL, "null argument");
   const StateView& v = s->r.p.method == MF_RPDRQ ? s->st[0] : s->st[s->iter & 1];
-  HIP_TRY(launch_labels(s->r.g, s->r.nl, s->r.p.model == MF_TWO_LABEL, v.u, dst, s->stream));
+  HIP_TRY(launch_labels(s->r.g, s->r.nl, s->r.p.model == MF_TWO_LABEL, v.u, dst, s->stream, s->r.g.pitch));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return MF_OK;
 }
@@ -534,8 +539,9 @@ mf_status maxflow_read_field(mf_solver* s, int32_t field, float* dst) {
   bool is_u;
   mf_status e = field_ptr(s, field, &ptr, &np, &is_u);
   if (e != MF_OK) return e;
-  HIP_TRY(launch_read_planes(ptr, is_u ? false : s->r.p.storage == MF_BF16, dst, s->r.g.npix(), np,
-                             s->r.g.plane, s->stream));
+  const Geom& g = s->r.g;
+  HIP_TRY(launch_pitch_copy(ptr, is_u ? false : s->r.p.storage == MF_BF16, g.plane, g.pitch, dst, false, g.npix(),
+                            g.W, g.W, (long long)g.H * g.D, np, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return MF_OK;
 }
@@ -547,8 +553,9 @@ mf_status maxflow_write_field(mf_solver* s, int32_t field, const float* src) {
   bool is_u;
   mf_status e = field_ptr(s, field, &ptr, &np, &is_u);
   if (e != MF_OK) return e;
-  HIP_TRY(launch_write_planes(src, ptr, is_u ? false : s->r.p.storage == MF_BF16, s->r.g.npix(), np,
-                              s->r.g.plane, s->stream));
+  const Geom& g = s->r.g;
+  HIP_TRY(launch_pitch_copy(src, false, g.npix(), g.W, ptr, is_u ? false : s->r.p.storage == MF_BF16, g.plane,
+                            g.pitch, g.W, (long long)g.H * g.D, np, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return MF_OK;
 }

@@ -21,7 +21,7 @@ static K2<TS> make_k2(const SweepDesc& d) {
   K2<TS> a;
   a.W = d.g.W;
   a.H = d.g.H;
-  a.pitch = d.g.W;
+  a.pitch = d.g.pitch;
   a.P = d.g.plane;
   a.tiles_x = (d.g.W + 63) / 64;
   a.cap = (const TS*)d.cap;
@@ -46,7 +46,7 @@ template <int NL, bool TWO, typename TS, bool CHECK, int TY>
 static hipError_t fused_launch(const K2<TS>& a, int H, hipStream_t s) {
   constexpr int V = TY >= 16 ? 4 : 2;
   const int nb = a.tiles_x * ((H + TY - 1) / TY);
-  if (a.W % V == 0)
+  if (a.pitch % V == 0)
     hipLaunchKernelGGL((k_fused2d<NL, TWO, TS, CHECK, TY, true>), dim3(nb), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((k_fused2d<NL, TWO, TS, CHECK, TY, false>), dim3(nb), dim3(256), 0, s, a);

@@ -43,9 +43,9 @@ static hipError_t fused3d_ts(const SweepDesc& d, hipStream_t s) {
   a.W = d.g.W;
   a.H = d.g.H;
   a.D = d.g.D;
-  a.pitch = d.g.W;
+  a.pitch = d.g.pitch;
   a.P = d.g.plane;
-  a.SZ = (long long)d.g.W * d.g.H;
+  a.SZ = (long long)d.g.pitch * d.g.H;
   a.tiles_x = (d.g.W + 63) / 64;
   a.tiles_y = (d.g.H + 7) / 8;
   // Slab depth: each slab re-reads 3 warm-up planes, so slabs should be
@@ -53,7 +53,7 @@ static hipError_t fused3d_ts(const SweepDesc& d, hipStream_t s) {
   // slabs as make one full wave of resident workgroups (occupancy x CUs):
   // a partial second wave would run on a fraction of the chip.
   const long long nxy = (long long)a.tiles_x * a.tiles_y;
-  const long long resident = resident_blocks3<TS, CHECK>(d.g.W % 2 == 0);
+  const long long resident = resident_blocks3<TS, CHECK>(d.g.pitch % 2 == 0);
   long long nslab = resident / nxy;
   if (nslab < 1) nslab = 1;
   int tz = (int)((d.g.D + nslab - 1) / nslab);
@@ -74,7 +74,7 @@ static hipError_t fused3d_ts(const SweepDesc& d, hipStream_t s) {
   a.write = d.write ? 1 : 0;
   a.iso = d.iso ? 1 : 0;
   const long long nb = nxy * ((d.g.D + tz - 1) / tz);
-  if (d.g.W % 2 == 0)
+  if (d.g.pitch % 2 == 0)
     hipLaunchKernelGGL((k_fused3d<TS, CHECK, true>), dim3((unsigned)nb), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((k_fused3d<TS, CHECK, false>), dim3((unsigned)nb), dim3(256), 0, s, a);

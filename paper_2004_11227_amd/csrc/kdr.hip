@@ -251,6 +251,7 @@ static hipError_t dr_ts(const PdrqDesc& d, hipStream_t s) {
 }
 
 hipError_t launch_pdrq_iter(const PdrqDesc& d, hipStream_t s) {
+  if (d.g.pitch != d.g.W) return hipErrorInvalidValue;   // element-wise sweeps use the dense layout
   if (d.g.ndim == 2) return d.bf16 ? dr_ts<2, bf16_t>(d, s) : dr_ts<2, float>(d, s);
   return d.bf16 ? dr_ts<3, bf16_t>(d, s) : dr_ts<3, float>(d, s);
 }

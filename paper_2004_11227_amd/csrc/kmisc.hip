@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void k_gap(const KG<TS> A) {
     const int x = (int)(idx % A.W);
     const int y = (int)((idx / A.W) % A.H);
     const int z = (int)(idx / sz);
-    gap_px<NL, TWO, NDIM, TS>(A, idx, x, y, z, g);
+    gap_px<NL, TWO, NDIM, TS>(A, ((long long)z * A.H + y) * A.pitch + x, x, y, z, g);
   }
   block_accumulate<5, 4>(g, A.acc, sred);
 }
@@ -35,7 +35,7 @@ static hipError_t gap_nl(const GapDesc& d, hipStream_t s) {
   a.W = d.g.W;
   a.H = d.g.H;
   a.D = d.g.D;
-  a.pitch = d.g.W;
+  a.pitch = d.g.pitch;
   a.P = d.g.plane;
   a.n = d.g.npix();
   a.cap = (const TS*)d.cap;
@@ -94,7 +94,7 @@ static int blocks_for(long long n) {
 hipError_t launch_init(const Geom& g, int nl, bool two, bool bf16, const void* cap, StateView st,
                        hipStream_t s) {
   const int ncap = two ? 2 : nl;
-  const long long n = g.npix();
+  const long long n = g.nstore();   // pads included (their capacities are 0)
   if (bf16)
     hipLaunchKernelGGL(k_init<bf16_t>, dim3(blocks_for(n)), dim3(256), 0, s, nl, ncap, g.ndim, n, g.plane,
                        (const bf16_t*)cap, st.u, (bf16_t*)st.q, (bf16_t*)st.ps, (bf16_t*)st.p);

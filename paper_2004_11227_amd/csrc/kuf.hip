@@ -158,6 +158,7 @@ static hipError_t unfused_ts(const SweepDesc& d, hipStream_t s) {
 }
 
 hipError_t launch_unfused(const SweepDesc& d, hipStream_t s) {
+  if (d.g.pitch != d.g.W) return hipErrorInvalidValue;   // element-wise passes use the dense layout
   if (d.g.ndim == 2) return d.bf16 ? unfused_ts<2, bf16_t>(d, s) : unfused_ts<2, float>(d, s);
   return d.bf16 ? unfused_ts<3, bf16_t>(d, s) : unfused_ts<3, float>(d, s);
 }

@@ -26,8 +26,10 @@ struct Ctrl {
 struct Geom {
   int ndim;
   int W, H, D;       // D = 1 in 2-D
-  long long plane;   // element stride between planes
+  int pitch;         // row stride in elements (>= W; padded layouts round W up to 4)
+  long long plane;   // element stride between planes (>= pitch * H * D)
   long long npix() const { return (long long)W * H * D; }
+  long long nstore() const { return (long long)pitch * H * D; }
 };
 
 // One state buffer (all planes of one iterate).

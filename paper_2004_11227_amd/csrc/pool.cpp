@@ -68,6 +68,7 @@ std::string plan_solve(const mf_params* in, Footprint& f) {
   f.esz = f.p.storage == MF_BF16 ? 2 : 4;
   // rows padded to a multiple of 4 elements: every tile group is one vector access
   f.pitch = (f.g.W + 3) / 4 * 4;
+  f.g.pitch = f.pitch;
   f.g.plane = (long long)al((size_t)f.pitch * f.g.H * f.g.D * 4) / 4;
   f.g.plane = (f.g.plane + 127) / 128 * 128;
   const size_t P = (size_t)f.g.plane;
@@ -517,9 +518,8 @@ mf_status mf_pool_admit(mf_pool* P, const mf_params* p, const float* cap, int64_
   const long long rows = (long long)f.g.H * f.g.D;
   PHIP(launch_pitch_copy(cap, false, f.g.npix(), f.g.W, base, bf16, f.g.plane, f.pitch, f.g.W, rows, f.ncap,
                          P->stream));
-  Geom gp = f.g;   // initialise the padded planes whole (pads hold zero capacities)
-  gp.W = f.pitch;
-  PHIP(launch_init(gp, f.nl, f.p.model == MF_TWO_LABEL, bf16, base, H.st[0], P->stream));
+  // initialise the padded planes whole (pads hold zero capacities)
+  PHIP(launch_init(f.g, f.nl, f.p.model == MF_TWO_LABEL, bf16, base, H.st[0], P->stream));
   fill_image(P, slot, 0);
   PoolSlot& S = P->slot_img[slot];
   PHIP(hipMemcpyAsync(P->dev.slots + slot, &S, sizeof(S), hipMemcpyHostToDevice, P->stream));
