@@ -101,6 +101,12 @@ typedef struct {
    * 1e-3 for Potts problems).  0 disables either trigger. */
   double promote_gap;
   int32_t promote_iter;
+  /* Iterations per fused pass (temporal blocking) of the single-solve API:
+   * 1, or 2 for the two-label 2-D rpADMM sweep (FG/EB, fused variant),
+   * which reads and writes the state once per two iterations with iterates
+   * bit-identical to depth 1.  0 -> 2 where it applies, else 1.  Odd
+   * iteration counts finish with one depth-1 sweep. */
+  int32_t depth;
 } mf_params;
 
 /* Gap at an iterate.  primal = P(u) at clip(u,0,1) (two-label) or the pointwise
@@ -179,7 +185,8 @@ mf_status maxflow_destroy(mf_solver* s);
  * without advancing it, so the solver's state and iteration count are
  * unchanged; the tile height never changes the iterates (bit-identical).
  * `us_per_iter` (host, 3 entries, may be null) receives microseconds per
- * sweep for heights 8, 16, 32.  Solvers without a tile-height choice (3-D,
+ * iteration for heights 8, 16, 32.  Depth-2 solvers time their two-iteration
+ * pass at heights 16 and 32 (8 reports 0).  Solvers without a tile-height choice (3-D,
  * the unfused variant) time their one configuration, report it in the entry
  * of their current height (others 0) and keep it; rPDRQ (in-place sweeps)
  * runs nothing and reports zeros.  Synchronises the stream.  Errors:

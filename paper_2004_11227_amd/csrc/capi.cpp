@@ -18,6 +18,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/maxflow.h"
 #include "mf_kernels.h"
@@ -109,6 +111,12 @@ std::string resolve(const mf_params* in, Resolved& r) {
   if (p.tile_rows == 0) p.tile_rows = (!two && p.storage == MF_BF16 && p.nlabels >= 8) ? 8 : 16;
   if (p.tile_rows != 8 && p.tile_rows != 16 && p.tile_rows != 32) return "tile_rows must be 8, 16 or 32";
   if (!(p.promote_gap >= 0.0) || p.promote_iter < 0) return "promote_gap and promote_iter must be >= 0";
+  {
+    const bool d2ok = two && p.ndim == 2 && p.method != MF_RPDRQ && p.variant == MF_FUSED;
+    if (p.depth == 0) p.depth = d2ok ? 2 : 1;
+    if (p.depth != 1 && p.depth != 2) return "depth must be 1 or 2";
+    if (p.depth == 2 && !d2ok) return "depth 2 applies to the fused two-label 2-D rpADMM sweep";
+  }
   r.nl = two ? 1 : p.nlabels;
   r.ncap = two ? 2 : p.nlabels;
   r.g.ndim = p.ndim;
@@ -211,6 +219,7 @@ struct mf_solver {
   StateView z;
   float* wbuf;
   int64_t iter;
+  int off;          // iterate k lives in state buffer (k + off) & 1
   int* host_done;   // pinned polling slots
   hipEvent_t ev[8];
   int dev;
@@ -239,6 +248,11 @@ Coef coef_of(const Resolved& r) {
   return k;
 }
 
+// State buffer of iterate k (rpADMM ping-pong).  A depth-1 sweep writes
+// iterate k+1 into the other buffer; a depth-2 pass writes iterate k+2 into
+// the other buffer and flips `off`.
+int buf_of(const mf_solver* s, int64_t k) { return (int)((k + s->off) & 1); }
+
 bool fused_gap(const mf_solver* s) {
   return s->r.p.variant == MF_FUSED && s->r.p.model == MF_TWO_LABEL;
 }
@@ -255,8 +269,8 @@ hipError_t admm_sweep(mf_solver* s, int64_t k, bool check, bool write, const int
   d.write = write;
   d.tile_rows = s->r.p.tile_rows;
   d.cap = s->cap;
-  d.in = s->st[k & 1];
-  d.out = s->st[(k + 1) & 1];
+  d.in = s->st[buf_of(s, k)];
+  d.out = s->st[buf_of(s, k) ^ 1];
   d.wbuf = s->wbuf;
   d.k = coef_of(s->r);
   d.acc = &s->ctrl->acc[0][0];
@@ -265,6 +279,30 @@ hipError_t admm_sweep(mf_solver* s, int64_t k, bool check, bool write, const int
   if (s->r.p.variant == MF_UNFUSED || (s->r.g.ndim == 3 && s->r.p.model == MF_POTTS))
     return launch_unfused(d, s->stream);
   return launch_fused(d, s->stream);
+}
+
+// Depth-2 pass from iterate k to k+2 (two-label 2-D fused sweep); `flip`
+// records that iterate k+2 now lives in the other buffer.
+hipError_t admm_pass2(mf_solver* s, int64_t k, bool check, const int* done, bool flip = true) {
+  SweepDesc d;
+  d.g = s->r.g;
+  d.nl = s->r.nl;
+  d.two = true;
+  d.bf16 = s->r.p.storage == MF_BF16;
+  d.iso = s->r.p.tv == MF_TV_ISO;
+  d.check = check;
+  d.write = true;
+  d.tile_rows = s->r.p.tile_rows;
+  d.cap = s->cap;
+  d.in = s->st[buf_of(s, k)];
+  d.out = s->st[buf_of(s, k) ^ 1];
+  d.wbuf = s->wbuf;
+  d.k = coef_of(s->r);
+  d.acc = &s->ctrl->acc[0][0];
+  d.done = done;
+  const hipError_t e = launch_fused2d_d2(d, s->stream);
+  if (e == hipSuccess && flip) s->off ^= 1;
+  return e;
 }
 
 hipError_t dr_iter(mf_solver* s, bool keep_z, const int* done) {
@@ -301,7 +339,7 @@ hipError_t gap_of(mf_solver* s, int64_t k, const int* done) {
     d.st = s->z;
     d.st.u = s->st[0].u;
   } else {
-    d.st = s->st[k & 1];
+    d.st = s->st[buf_of(s, k)];
   }
   d.acc = &s->ctrl->acc[0][0];
   d.done = done;
@@ -321,6 +359,7 @@ mf_status init_state(mf_solver* s) {
   }
   HIP_TRY(launch_ctrl_reset(s->ctrl, s->stream));
   s->iter = 0;
+  s->off = 0;
   return MF_OK;
 }
 
@@ -421,13 +460,19 @@ int64_t maxflow_iter(const mf_solver* s) { return s ? s->iter : -1; }
 mf_status maxflow_step(mf_solver* s, int32_t iters) {
   if (!s) return fail(MF_EINVAL, "null solver");
   if (iters < 0) return fail(MF_EINVAL, "iters must be >= 0");
-  for (int32_t i = 0; i < iters; i++) {
+  const bool d2 = s->r.p.depth == 2;
+  for (int32_t i = 0; i < iters;) {
     if (s->r.p.method == MF_RPDRQ) {
       HIP_TRY(dr_iter(s, i == iters - 1, nullptr));
+    } else if (d2 && iters - i >= 2) {
+      HIP_TRY(admm_pass2(s, s->iter, false, nullptr));
+      s->iter += 1;
+      i += 1;
     } else {
       HIP_TRY(admm_sweep(s, s->iter, false, true, nullptr));
     }
     s->iter += 1;
+    i += 1;
   }
   return MF_OK;
 }
@@ -454,6 +499,10 @@ mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
   const int* done = &s->ctrl->done;
   HIP_TRY(launch_ctrl_reset(s->ctrl, s->stream));
   int64_t k = s->iter;
+  const bool d2 = p.depth == 2;
+  // buffer offset in effect at each checked iterate: the accepted iterate's
+  // buffer once later passes (which flip the offset) have been skipped
+  std::vector<std::pair<int64_t, int>> off_at;
   // polling ring: after each check, copy `done` to pinned memory + event
   int issued = 0, observed = 0;
   const int lookahead = 3;
@@ -461,10 +510,18 @@ mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
   while (!stop) {
     // ---- gap of iterate k and the decision
     const bool final_check = k >= max_iter;
+    const int64_t n = final_check ? 0 : std::min<int64_t>(ce, max_iter - k);
+    off_at.emplace_back(k, s->off);
+    int64_t j = 1;   // iterations of the chunk issued with the check
     if (dr) {
       HIP_TRY(gap_of(s, k, done));
     } else if (fused_gap(s)) {
-      HIP_TRY(admm_sweep(s, k, true, !final_check, done));
+      if (d2 && n >= 2) {
+        HIP_TRY(admm_pass2(s, k, true, done));
+        j = 2;
+      } else {
+        HIP_TRY(admm_sweep(s, k, true, !final_check, done));
+      }
     } else {
       HIP_TRY(gap_of(s, k, done));
       if (!final_check) HIP_TRY(admm_sweep(s, k, false, true, done));
@@ -472,11 +529,18 @@ mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
     HIP_TRY(launch_bookkeep(s->ctrl, k, p.alpha, p.tol, nres(s), final_check ? 1 : 0, 1, s->stream));
     if (final_check) break;
     // ---- the rest of the chunk
-    const int64_t n = std::min<int64_t>(ce, max_iter - k);
     if (dr) {
-      for (int64_t j = 0; j < n; j++) HIP_TRY(dr_iter(s, j == n - 1, done));
+      for (int64_t i = 0; i < n; i++) HIP_TRY(dr_iter(s, i == n - 1, done));
     } else {
-      for (int64_t j = 1; j < n; j++) HIP_TRY(admm_sweep(s, k + j, false, true, done));
+      while (j < n) {
+        if (d2 && n - j >= 2) {
+          HIP_TRY(admm_pass2(s, k + j, false, done));
+          j += 2;
+        } else {
+          HIP_TRY(admm_sweep(s, k + j, false, true, done));
+          j += 1;
+        }
+      }
     }
     k += n;
     // ---- poll the decision without stalling the queue
@@ -498,6 +562,8 @@ mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
   HIP_TRY(hipStreamSynchronize(s->stream));
   if (!c.done) return fail(MF_EDEVICE, "solve ended without a decision");
   s->iter = c.iter;
+  for (const auto& e : off_at)
+    if (e.first == c.iter) s->off = e.second;
   const mf_status st = (mf_status)c.status;
   fill_gap(c, s->iter, out, st);
   if (st == MF_EDIVERGED) return fail(MF_EDIVERGED, "non-finite gap");
@@ -508,7 +574,7 @@ mf_status maxflow_read_u(mf_solver* s, float* dst) { return maxflow_read_field(s
 
 mf_status maxflow_labels(mf_solver* s, int32_t* dst) {
   if (!s || !dst) return fail(MF_EINVAL, "null argument");
-  const StateView& v = s->r.p.method == MF_RPDRQ ? s->st[0] : s->st[s->iter & 1];
+  const StateView& v = s->r.p.method == MF_RPDRQ ? s->st[0] : s->st[buf_of(s, s->iter)];
   HIP_TRY(launch_labels(s->r.g, s->r.nl, s->r.p.model == MF_TWO_LABEL, v.u, dst, s->stream, s->r.g.pitch));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return MF_OK;
@@ -516,7 +582,7 @@ mf_status maxflow_labels(mf_solver* s, int32_t* dst) {
 
 static mf_status field_ptr(mf_solver* s, int32_t field, void** ptr, int* np, bool* is_u) {
   const bool dr = s->r.p.method == MF_RPDRQ;
-  const StateView& v = dr ? s->st[0] : s->st[s->iter & 1];
+  const StateView& v = dr ? s->st[0] : s->st[buf_of(s, s->iter)];
   *is_u = false;
   switch (field) {
     case 0: *ptr = v.u; *np = s->r.nl; *is_u = true; return MF_OK;
@@ -568,7 +634,7 @@ size_t maxflow_state_bytes(const mf_solver* s) {
 mf_status maxflow_export_state(mf_solver* s, void* dst) {
   if (!s || !dst) return fail(MF_EINVAL, "null argument");
   const bool dr = s->r.p.method == MF_RPDRQ;
-  const size_t off = dr ? s->L.state[0] : s->L.state[s->iter & 1];
+  const size_t off = dr ? s->L.state[0] : s->L.state[buf_of(s, s->iter)];
   HIP_TRY(hipMemcpyAsync(dst, s->ws + off, s->L.state_bytes, hipMemcpyDeviceToDevice, s->stream));
   if (dr)
     HIP_TRY(hipMemcpyAsync((char*)dst + s->L.state_bytes, s->ws + s->L.stz, s->L.state_bytes,
@@ -582,7 +648,7 @@ mf_status maxflow_import_state(mf_solver* s, const void* src, int64_t iter) {
   if (iter < 0) return fail(MF_EINVAL, "iter must be >= 0");
   const bool dr = s->r.p.method == MF_RPDRQ;
   s->iter = iter;
-  const size_t off = dr ? s->L.state[0] : s->L.state[iter & 1];
+  const size_t off = dr ? s->L.state[0] : s->L.state[buf_of(s, iter)];
   HIP_TRY(hipMemcpyAsync(s->ws + off, src, s->L.state_bytes, hipMemcpyDeviceToDevice, s->stream));
   if (dr)
     HIP_TRY(hipMemcpyAsync(s->ws + s->L.stz, (const char*)src + s->L.state_bytes, s->L.state_bytes,
@@ -613,21 +679,24 @@ mf_status maxflow_tune(mf_solver* s, int32_t sweeps, int32_t* best_tile_rows, do
   int best = keep;
   double best_us = 0.0;
   hipError_t he = hipSuccess;
+  const bool d2 = s->r.p.depth == 2;   // depth-2 passes tile 16 or 32 rows
   for (int c = 0; c < 3 && he == hipSuccess; c++) {
     if (!choice && cand[c] != keep) continue;
+    if (d2 && cand[c] == 8) continue;
     s->r.p.tile_rows = cand[c];
     float ms = 0.f;
     // iterate k -> k+1 repeatedly: buffer k & 1 (the current iterate) is
     // only read, buffer (k+1) & 1 is scratch until the next real sweep
     for (int w = 0; w < 2 + sweeps && he == hipSuccess; w++) {
       if (w == 2) he = hipEventRecord(e0, s->stream);
-      if (he == hipSuccess) he = admm_sweep(s, s->iter, false, true, nullptr);
+      if (he == hipSuccess)
+        he = d2 ? admm_pass2(s, s->iter, false, nullptr, false) : admm_sweep(s, s->iter, false, true, nullptr);
     }
     if (he == hipSuccess) he = hipEventRecord(e1, s->stream);
     if (he == hipSuccess) he = hipEventSynchronize(e1);
     if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
     if (he != hipSuccess) break;
-    us[c] = 1e3 * (double)ms / sweeps;
+    us[c] = 1e3 * (double)ms / sweeps / (d2 ? 2 : 1);   // per iteration
     if (best_us == 0.0 || us[c] < best_us) {
       best_us = us[c];
       best = cand[c];

@@ -1,5 +1,7 @@
-// 2-D rpADMM sweep: the fused LDS-tiled pass (one tile per workgroup).
+// 2-D rpADMM sweep: the fused LDS-tiled pass (one tile per workgroup), and
+// the depth-2 pass of the two-label model (two iterations per launch).
 #include "tile2d.h"
+#include "tile2d_d2.h"
 
 namespace mf {
 
@@ -12,6 +14,18 @@ __global__ __launch_bounds__(256) void k_fused2d(const K2<TS> A) {
   const int y0 = (tile / A.tiles_x) * TY;
   double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   tile2d<NL, TWO, TS, CHECK, TY, VEC, CHECK>(A, x0, y0, S, g);
+  if (CHECK) block_accumulate<5, 4>(g, A.acc, S.sred);
+}
+
+template <typename TS, bool CHECK, int TY>
+__global__ __launch_bounds__(256) void k_fused2d_d2(const K2<TS> A) {
+  __shared__ Smem2d2<TY> S;
+  if (A.done && *A.done) return;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (tile % A.tiles_x) * 64;
+  const int y0 = (tile / A.tiles_x) * TY;
+  double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  tile2d_d2<TS, CHECK, TY>(A, x0, y0, S, g);
   if (CHECK) block_accumulate<5, 4>(g, A.acc, S.sred);
 }
 
@@ -85,6 +99,27 @@ static hipError_t fused_ts(const SweepDesc& d, hipStream_t s) {
 
 hipError_t launch_fused2d(const SweepDesc& d, hipStream_t s) {
   return d.bf16 ? fused_ts<bf16_t>(d, s) : fused_ts<float>(d, s);
+}
+
+template <typename TS, bool CHECK>
+static hipError_t fused_d2_ts(const SweepDesc& d, hipStream_t s) {
+  const K2<TS> a = make_k2<TS>(d);
+  if (d.tile_rows == 32) {
+    const int nb = a.tiles_x * ((d.g.H + 31) / 32);
+    hipLaunchKernelGGL((k_fused2d_d2<TS, CHECK, 32>), dim3(nb), dim3(256), 0, s, a);
+  } else {
+    const int nb = a.tiles_x * ((d.g.H + 15) / 16);
+    hipLaunchKernelGGL((k_fused2d_d2<TS, CHECK, 16>), dim3(nb), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+// Two iterations (d.in = iterate k, d.out = iterate k+2) of the two-label 2-D
+// model; rows padded to a multiple of 4; tile height 16 (8 is taken as 16) or 32.
+hipError_t launch_fused2d_d2(const SweepDesc& d, hipStream_t s) {
+  if (!d.two || d.g.ndim != 2 || d.g.pitch % 4 != 0 || !d.write) return hipErrorInvalidValue;
+  if (d.bf16) return d.check ? fused_d2_ts<bf16_t, true>(d, s) : fused_d2_ts<bf16_t, false>(d, s);
+  return d.check ? fused_d2_ts<float, true>(d, s) : fused_d2_ts<float, false>(d, s);
 }
 
 }  // namespace mf

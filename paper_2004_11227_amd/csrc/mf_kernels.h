@@ -81,6 +81,7 @@ struct PdrqDesc {
 };
 
 hipError_t launch_fused(const SweepDesc& d, hipStream_t s);
+hipError_t launch_fused2d_d2(const SweepDesc& d, hipStream_t s);
 hipError_t launch_unfused(const SweepDesc& d, hipStream_t s);
 hipError_t launch_gap(const GapDesc& d, hipStream_t s);
 hipError_t launch_pdrq_iter(const PdrqDesc& d, hipStream_t s);

@@ -303,7 +303,8 @@ def test_invalid_parameters_rejected():
     caps = torch.ones((2, 8, 8), device="cuda")
     from paper_2004_11227_amd import maxflow as mfx
     for kw in [dict(alpha=-1.0), dict(relax=2.5), dict(a=3.0), dict(method="fg", relax=1.7),
-               dict(model="potts", nlabels=5), dict(tile_rows=12)]:
+               dict(model="potts", nlabels=5), dict(tile_rows=12), dict(depth=3),
+               dict(depth=2, variant="unfused"), dict(depth=2, method="dr")]:
         with pytest.raises(mfx.MaxflowError):
             mfx.Solver(caps if kw.get("model") != "potts" else torch.ones((5, 8, 8), device="cuda"), **kw)
 
@@ -337,7 +338,7 @@ def test_autotune_keeps_state_and_caches(tmp_path, monkeypatch):
     monkeypatch.setenv("MF_TUNING_CACHE", str(tmp_path / "tune.json"))
     tuning.clear()
     caps = synth.config_inputs("c1", size=(300, 333))["caps"]
-    kw = dict(model="two", method="eb", relax=1.5, alpha=0.5)
+    kw = dict(model="two", method="eb", relax=1.5, alpha=0.5, depth=1)
     ref = gpu_solver(caps, **kw)
     ref.step(7)
     s = gpu_solver(caps, **kw)
@@ -364,3 +365,77 @@ def test_autotune_keeps_state_and_caches(tmp_path, monkeypatch):
     assert u.params.tile_rows == tuning.lookup(caps.shape[1:], u.device, **kw)
     u.close()
     tuning.clear()
+    # depth-2 solvers time their two-iteration pass at 16 and 32 rows
+    kw2 = {**kw, "depth": 2}
+    d = gpu_solver(caps, **kw2)
+    d.step(4)
+    before = gpu_fields(d)
+    best, us = d.tune(sweeps=3)
+    assert best in (16, 32) and set(us) == {16, 32} and d.iter == 4
+    after = gpu_fields(d)
+    for f in before:
+        assert np.array_equal(before[f], after[f]), f
+    d.close()
+    assert tuning.key(caps.shape[1:], None, **kw) != tuning.key(caps.shape[1:], None, **kw2)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("shape", [(1, 1), (1, 70), (70, 1), (17, 130), (65, 64), (200, 333)])
+def test_depth2_equals_depth1_bitwise(storage, shape):
+    """Two iterations per pass (iterate k+1 kept in LDS) give the depth-1
+    iterates bit for bit, for odd and even step counts and both tile
+    heights."""
+    banner(f"depth2 {shape} {storage}")
+    caps = synth.two_label_caps(synth.ellipse_image(*shape, 3, 0.15, 3100))
+    kw = dict(model="two", method="eb", relax=1.5, alpha=0.5, storage=storage)
+    ref = gpu_solver(caps, depth=1, **kw)
+    runs = [gpu_solver(caps, depth=2, tile_rows=tr, **kw) for tr in (16, 32)]
+    for n in (2, 1, 4, 3):
+        ref.step(n)
+        a = gpu_fields(ref)
+        for s in runs:
+            s.step(n)
+            b = gpu_fields(s)
+            for f in a:
+                assert np.array_equal(a[f], b[f]), (n, s.params.tile_rows, f)
+    for s in runs + [ref]:
+        s.close()
+
+
+@pytest.mark.parametrize("method", ["fg", "eb"])
+def test_depth2_solve_stops_like_depth1(method):
+    """solve(): the gap is fused into the two-iteration pass at the checked
+    iterate; the stop iterate, the gap and the accepted state (rolled back
+    past passes already queued) equal the depth-1 solve."""
+    banner(f"depth2 solve {method}")
+    caps = synth.config_inputs("c1", size=(257, 300))["caps"]
+    kw = dict(model="two", method=method, relax=1.5, alpha=0.5, tol=2e-3, max_iter=997, check_every=10)
+    out = []
+    for depth in (1, 2):
+        s = gpu_solver(caps, depth=depth, **kw)
+        res = s.solve()
+        out.append((res, gpu_fields(s)))
+        s.step(3)   # continue from the accepted iterate
+        out.append((None, gpu_fields(s)))
+        s.close()
+    (r1, f1), (_, g1), (r2, f2), (_, g2) = out
+    assert r1["iter"] == r2["iter"] and r1["status"] == r2["status"] and r1["iter"] < 997
+    assert r1["rel_gap"] == r2["rel_gap"]
+    for f in f1:
+        assert np.array_equal(f1[f], f2[f]), f
+        assert np.array_equal(g1[f], g2[f]), f
+
+
+def test_depth2_cap_reached_odd_max_iter():
+    banner("depth2 odd cap")
+    caps = synth.config_inputs("c1", size=(130, 190))["caps"]
+    kw = dict(model="two", method="eb", relax=1.5, alpha=0.5, tol=0.0, max_iter=33, check_every=10)
+    res = []
+    for depth in (1, 2):
+        s = gpu_solver(caps, depth=depth, **kw)
+        r = s.solve()
+        res.append((r, gpu_fields(s)))
+        s.close()
+    assert res[0][0]["iter"] == res[1][0]["iter"] == 33
+    for f in res[0][1]:
+        assert np.array_equal(res[0][1][f], res[1][1][f]), f
