@@ -2,16 +2,18 @@
 
 One step = one complete solve of the two-label 2048x2048 workload (seeded
 ellipse image, 40 ellipses, noise 0.15, alpha 0.5, relaxation 1.5): initial
-point, 500 iterations of the fused sweep with the FP64 primal-dual gap every
-10 iterations (tolerance 0, so all 500 iterations run) and label extraction.
+point, 500 iterations of the fused sweep (two iterations per pass, iterates
+bit-identical to one per pass) with the FP64 primal-dual gap every 10
+iterations (tolerance 0, so all 500 iterations run) and label extraction.
 Inputs are resident in HBM before the timed region starts.
 
 Prints one JSON line.  value = pixels * labels * iterations / second with
 labels = 2 for the two-label model.  `roofline` reports the dominant kernel
-(the fused sweep without the gap reduction): algorithmic bytes per launch
-(48 B per pixel: read u, q_x, q_y, p_s, p_t, C_s, C_t; write u, q_x, q_y,
-p_s, p_t; FP32) divided by its average duration measured with HIP events on
-the solver's stream over a run of back-to-back sweeps.  `cpu_baseline` times
+(the two-iteration fused pass without the gap reduction): algorithmic bytes
+per launch (48 B per pixel: read u, q_x, q_y, p_s, p_t, C_s, C_t once; write
+u, q_x, q_y, p_s, p_t once; FP32; the intermediate iterate never leaves LDS)
+divided by its average duration measured with HIP events on the solver's
+stream over a run of back-to-back passes.  `cpu_baseline` times
 the FP64 oracle on a bounded sample of the same workload on the host cores.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
@@ -31,7 +33,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM = 8.0e12          # MI355X HBM3E, bytes/s
 WORKLOAD = dict(name="two_label_2d_2048", shape=(2048, 2048), iters=500, method="eb", relax=1.5,
-                alpha=0.5, check_every=10)
+                alpha=0.5, check_every=10, depth=2, tile_rows=16)
 
 
 def alg_bytes(model: str, n: int, ndim: int, storage: str) -> int:
@@ -48,15 +50,19 @@ def alg_bytes(model: str, n: int, ndim: int, storage: str) -> int:
 
 BYTES_PER_PX = {"f32": alg_bytes("two", 2, 2, "f32"), "bf16": alg_bytes("two", 2, 2, "bf16")}
 SRC = "paper_2004_11227_amd/csrc/"
-KERNEL_SOURCES = [SRC + "k2d.hip", SRC + "tile2d.h", SRC + "mf_device.h"]
+KERNEL_SOURCES = [SRC + "k2d.hip", SRC + "tile2d.h", SRC + "tile2d_d2.h", SRC + "mf_device.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused2d_two_label_2048_traffic.json")
 
 # Workloads of --profile-mode NAME (plain sweeps after a copy of known size,
 # for the FETCH_SIZE / WRITE_SIZE calibration): caps generator arguments and
 # solver keywords.
 PROFILE_WORKLOADS = {
-    "two_2048": (("c1", None), dict(model="two", method="eb", relax=1.5, alpha=0.5)),
-    "two_4096": (("c1", (4096, 4096)), dict(model="two", method="eb", relax=1.5, alpha=0.5)),
+    "two_2048": (("c1", None), dict(model="two", method="eb", relax=1.5, alpha=0.5, depth=2, tile_rows=16)),
+    "two_2048_d1": (("c1", None), dict(model="two", method="eb", relax=1.5, alpha=0.5, depth=1, tile_rows=16)),
+    "two_4096": (("c1", (4096, 4096)), dict(model="two", method="eb", relax=1.5, alpha=0.5, depth=2,
+                                           tile_rows=16)),
+    "two_4096_d1": (("c1", (4096, 4096)), dict(model="two", method="eb", relax=1.5, alpha=0.5, depth=1,
+                                              tile_rows=16)),
     "two_3d_256": (("c3", None), dict(model="two", method="eb", relax=1.5, alpha=0.4)),
     "potts4_1024": (("c2n4", None), dict(model="potts", nlabels=4, method="eb", relax=1.5, alpha=0.3)),
     "potts8_1024": (("c2n8", None), dict(model="potts", nlabels=8, method="eb", relax=1.5, alpha=0.3)),
@@ -90,7 +96,8 @@ def make_solver(torch, maxflow, caps_t, stream, **kw):
 
 
 def time_sweeps(torch, solver, stream, n):
-    """Average duration of one plain sweep, HIP events on the solver's stream."""
+    """Average time per iteration of plain sweeps (no gap), HIP events on the
+    solver's stream."""
     solver.step(20)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -148,7 +155,7 @@ def main():
     H, W = wl["shape"]
     npx = H * W
     kw = dict(model="two", method=wl["method"], relax=wl["relax"], alpha=wl["alpha"], tol=0.0,
-              max_iter=wl["iters"], check_every=wl["check_every"])
+              max_iter=wl["iters"], check_every=wl["check_every"], depth=wl["depth"], tile_rows=wl["tile_rows"])
 
     if args.profile_mode:
         # known-size copy for counter calibration, then plain sweeps
@@ -185,14 +192,17 @@ def main():
     assert res["iter"] == wl["iters"], res
     value = npx * 2 * wl["iters"] / dt
 
-    # dominant kernel: fused sweep, average duration over back-to-back launches
-    t_sweep = time_sweeps(torch, s, stream, args.kernel_sweeps)
+    # dominant kernel: the two-iteration pass, average duration over
+    # back-to-back launches (step(n) issues n / 2 passes)
+    t_iter = time_sweeps(torch, s, stream, args.kernel_sweeps)
+    t_launch = t_iter * wl["depth"]
     launch_bytes = BYTES_PER_PX["f32"] * npx
-    achieved = launch_bytes / t_sweep
+    achieved = launch_bytes / t_launch
     roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
             "frac": achieved / PEAK_HBM, "traffic": traffic_for(launch_bytes),
-            "kernel": "k_fused2d<two-label,f32,16 rows>", "bytes_per_launch": launch_bytes,
-            "avg_launch_us": t_sweep * 1e6}
+            "kernel": f"k_fused2d_d2<float, false, {wl['tile_rows']}> (two iterations per launch)",
+            "bytes_per_launch": launch_bytes, "avg_launch_us": t_launch * 1e6,
+            "iterations_per_launch": wl["depth"]}
     s.close()
 
     extra = {}
@@ -207,7 +217,8 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": wl["name"], "shape": list(wl["shape"]), "iterations": wl["iters"],
                       "method": "rpADMMII", "relax": wl["relax"], "alpha": wl["alpha"],
-                      "gap_every": wl["check_every"], "labels": 2, "parallelism": "single GPU"},
+                      "gap_every": wl["check_every"], "labels": 2, "iterations_per_pass": wl["depth"],
+                      "tile_rows": wl["tile_rows"], "parallelism": "single GPU"},
            "roofline": roof}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(caps64, wl)
@@ -221,6 +232,9 @@ def secondary(torch, maxflow, synth, np, dev, stream):
     res = {}
 
     def sweep_rate(name, caps, nbytes_px, iters=200, **kw):
+        # per-iteration time; alg_GBps = algorithmic bytes of one depth-1
+        # sweep / time per iteration (a depth-2 pass moves them once per two
+        # iterations, so its figure can exceed the HBM peak)
         t = torch.from_numpy(caps.astype(np.float32)).to(dev)
         s = maxflow.Solver(t, stream=stream, **kw)
         dt = time_sweeps(torch, s, stream, iters)
@@ -233,12 +247,14 @@ def secondary(torch, maxflow, synth, np, dev, stream):
 
     c1 = synth.config_inputs("c1")["caps"]
     b2 = alg_bytes("two", 2, 2, "f32")
+    sweep_rate("two_2048_fused_f32_depth1", c1, b2, model="two", method="eb", relax=1.5, depth=1)
     sweep_rate("two_2048_unfused_f32", c1, b2, model="two", method="eb", relax=1.5, variant="unfused")
-    sweep_rate("two_2048_fused_bf16", c1, alg_bytes("two", 2, 2, "bf16"), model="two", method="eb",
-               relax=1.5, storage="bf16")
+    sweep_rate("two_2048_fused_bf16_depth2", c1, alg_bytes("two", 2, 2, "bf16"), model="two", method="eb",
+               relax=1.5, storage="bf16", depth=2)
     sweep_rate("two_2048_pdrq_f32", c1, b2, model="two", method="dr")
     big = synth.config_inputs("c1", size=(4096, 4096))["caps"]
-    sweep_rate("two_4096_fused_f32", big, b2, iters=100, model="two", method="eb", relax=1.5)
+    sweep_rate("two_4096_fused_f32_depth1", big, b2, iters=100, model="two", method="eb", relax=1.5, depth=1)
+    sweep_rate("two_4096_fused_f32_depth2", big, b2, iters=100, model="two", method="eb", relax=1.5, depth=2)
     del big
     for n in (4, 8):
         img, _ = synth.voronoi_image(1024, 1024, n, 0.15, 2000)
