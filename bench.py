@@ -251,7 +251,8 @@ def secondary(torch, maxflow, synth, np, dev, stream):
     sweep_rate("two_2048_unfused_f32", c1, b2, model="two", method="eb", relax=1.5, variant="unfused")
     sweep_rate("two_2048_fused_bf16_depth2", c1, alg_bytes("two", 2, 2, "bf16"), model="two", method="eb",
                relax=1.5, storage="bf16", depth=2)
-    sweep_rate("two_2048_pdrq_f32", c1, b2, model="two", method="dr")
+    sweep_rate("two_2048_pdrq_f32_fused", c1, b2, model="two", method="dr")
+    sweep_rate("two_2048_pdrq_f32_inplace", c1, b2, model="two", method="dr", variant="unfused")
     big = synth.config_inputs("c1", size=(4096, 4096))["caps"]
     sweep_rate("two_4096_fused_f32_depth1", big, b2, iters=100, model="two", method="eb", relax=1.5, depth=1)
     sweep_rate("two_4096_fused_f32_depth2", big, b2, iters=100, model="two", method="eb", relax=1.5, depth=2)

@@ -134,7 +134,8 @@ std::string resolve(const mf_params* in, Resolved& r) {
   // Fused rpADMM sweeps use rows padded to a multiple of 4 elements, so every
   // owned group of a tile is one vector access whatever the width; the
   // element-wise kernels (unfused passes, rPDRQ) use the dense layout.
-  const bool padded = p.method != MF_RPDRQ && p.variant == MF_FUSED && !(p.ndim == 3 && p.model == MF_POTTS);
+  const bool padded = p.variant == MF_FUSED && !(p.ndim == 3 && p.model == MF_POTTS) &&
+                      (p.method != MF_RPDRQ || (two && p.ndim == 2));
   r.g.pitch = padded ? (r.g.W + 3) / 4 * 4 : r.g.W;
   r.g.plane = (long long)align_up((size_t)r.g.nstore(), 128);
   r.esz = p.storage == MF_BF16 ? 2 : 4;
@@ -143,9 +144,15 @@ std::string resolve(const mf_params* in, Resolved& r) {
 }
 
 struct Layout {
-  size_t ctrl, cap, state[2], stz, wbuf, total;
+  size_t ctrl, cap, state[2], stz, wbuf, wbuf_bytes, total;
   size_t state_bytes;
 };
+
+// rPDRQ as one tiled pass per iteration (two-label 2-D, fused variant);
+// otherwise three in-place element-wise launches.
+bool dr_fused(const Resolved& r) {
+  return r.p.method == MF_RPDRQ && r.p.variant == MF_FUSED && r.p.model == MF_TWO_LABEL && r.p.ndim == 2;
+}
 
 Layout plan(const Resolved& r) {
   Layout L{};
@@ -161,19 +168,21 @@ Layout plan(const Resolved& r) {
   L.state[0] = off;
   off += L.state_bytes;
   const bool dr = r.p.method == MF_RPDRQ;
-  if (!dr) {
+  if (!dr || dr_fused(r)) {   // ping-pong buffers
     L.state[1] = off;
     off += L.state_bytes;
-  } else {
+  } else {                    // the in-place rPDRQ launches
     L.state[1] = L.state[0];
   }
   // rPDRQ resolvent outputs (same shape as q, ps, p)
   L.stz = off;
   if (dr) off += L.state_bytes;
-  // scratch planes: unfused w, or rPDRQ b
+  // scratch planes: unfused w, or rPDRQ b (the fused rPDRQ pass keeps b in
+  // LDS, but initialisation writes the resolvent outputs' u slot here)
   L.wbuf = off;
   const bool unfused = r.p.variant == MF_UNFUSED || (r.p.ndim == 3 && r.p.model == MF_POTTS);
   if (dr || unfused) off = align_up(off + (size_t)r.nl * P * 4, 256);
+  L.wbuf_bytes = off - L.wbuf;
   L.total = off;
   return L;
 }
@@ -305,7 +314,7 @@ hipError_t admm_pass2(mf_solver* s, int64_t k, bool check, const int* done, bool
   return e;
 }
 
-hipError_t dr_iter(mf_solver* s, bool keep_z, const int* done) {
+hipError_t dr_iter(mf_solver* s, int64_t k, bool keep_z, const int* done) {
   PdrqDesc d;
   d.g = s->r.g;
   d.nl = s->r.nl;
@@ -313,9 +322,12 @@ hipError_t dr_iter(mf_solver* s, bool keep_z, const int* done) {
   d.bf16 = s->r.p.storage == MF_BF16;
   d.iso = s->r.p.tv == MF_TV_ISO;
   d.cap = s->cap;
-  d.st = s->st[0];
+  d.st = s->st[buf_of(s, k)];
+  d.out = s->st[buf_of(s, k) ^ 1];   // the same buffer for the in-place launches
   d.z = s->z;
   d.b = s->wbuf;
+  d.fused = dr_fused(s->r);
+  d.tile_rows = s->r.p.tile_rows;
   d.sigma = (float)s->r.p.sigma;
   d.tau = (float)s->r.p.tau;
   d.rho = (float)s->r.p.relax;
@@ -337,7 +349,7 @@ hipError_t gap_of(mf_solver* s, int64_t k, const int* done) {
   d.cap = s->cap;
   if (s->r.p.method == MF_RPDRQ) {
     d.st = s->z;
-    d.st.u = s->st[0].u;
+    d.st.u = s->st[buf_of(s, k)].u;
   } else {
     d.st = s->st[buf_of(s, k)];
   }
@@ -352,6 +364,8 @@ mf_status init_state(mf_solver* s) {
   HIP_TRY(launch_init(s->r.g, s->r.nl, s->r.p.model == MF_TWO_LABEL, s->r.p.storage == MF_BF16, s->cap,
                       s->st[0], s->stream));
   if (s->r.p.method == MF_RPDRQ) {
+    if (s->L.wbuf_bytes < (size_t)s->r.nl * (size_t)s->r.g.plane * 4)
+      return fail(MF_EDEVICE, "internal: rPDRQ layout without its scratch planes");
     StateView z = s->z;
     // resolvent outputs of "iteration 0" := the initial flows
     HIP_TRY(launch_init(s->r.g, s->r.nl, s->r.p.model == MF_TWO_LABEL, s->r.p.storage == MF_BF16, s->cap,
@@ -463,7 +477,7 @@ mf_status maxflow_step(mf_solver* s, int32_t iters) {
   const bool d2 = s->r.p.depth == 2;
   for (int32_t i = 0; i < iters;) {
     if (s->r.p.method == MF_RPDRQ) {
-      HIP_TRY(dr_iter(s, i == iters - 1, nullptr));
+      HIP_TRY(dr_iter(s, s->iter, i == iters - 1, nullptr));
     } else if (d2 && iters - i >= 2) {
       HIP_TRY(admm_pass2(s, s->iter, false, nullptr));
       s->iter += 1;
@@ -530,7 +544,7 @@ mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
     if (final_check) break;
     // ---- the rest of the chunk
     if (dr) {
-      for (int64_t i = 0; i < n; i++) HIP_TRY(dr_iter(s, i == n - 1, done));
+      for (int64_t i = 0; i < n; i++) HIP_TRY(dr_iter(s, k + i, i == n - 1, done));
     } else {
       while (j < n) {
         if (d2 && n - j >= 2) {
@@ -574,7 +588,7 @@ mf_status maxflow_read_u(mf_solver* s, float* dst) { return maxflow_read_field(s
 
 mf_status maxflow_labels(mf_solver* s, int32_t* dst) {
   if (!s || !dst) return fail(MF_EINVAL, "null argument");
-  const StateView& v = s->r.p.method == MF_RPDRQ ? s->st[0] : s->st[buf_of(s, s->iter)];
+  const StateView& v = s->st[buf_of(s, s->iter)];
   HIP_TRY(launch_labels(s->r.g, s->r.nl, s->r.p.model == MF_TWO_LABEL, v.u, dst, s->stream, s->r.g.pitch));
   HIP_TRY(hipStreamSynchronize(s->stream));
   return MF_OK;
@@ -582,7 +596,7 @@ mf_status maxflow_labels(mf_solver* s, int32_t* dst) {
 
 static mf_status field_ptr(mf_solver* s, int32_t field, void** ptr, int* np, bool* is_u) {
   const bool dr = s->r.p.method == MF_RPDRQ;
-  const StateView& v = dr ? s->st[0] : s->st[buf_of(s, s->iter)];
+  const StateView& v = s->st[buf_of(s, s->iter)];
   *is_u = false;
   switch (field) {
     case 0: *ptr = v.u; *np = s->r.nl; *is_u = true; return MF_OK;
@@ -634,7 +648,7 @@ size_t maxflow_state_bytes(const mf_solver* s) {
 mf_status maxflow_export_state(mf_solver* s, void* dst) {
   if (!s || !dst) return fail(MF_EINVAL, "null argument");
   const bool dr = s->r.p.method == MF_RPDRQ;
-  const size_t off = dr ? s->L.state[0] : s->L.state[buf_of(s, s->iter)];
+  const size_t off = s->L.state[buf_of(s, s->iter)];
   HIP_TRY(hipMemcpyAsync(dst, s->ws + off, s->L.state_bytes, hipMemcpyDeviceToDevice, s->stream));
   if (dr)
     HIP_TRY(hipMemcpyAsync((char*)dst + s->L.state_bytes, s->ws + s->L.stz, s->L.state_bytes,
@@ -648,7 +662,7 @@ mf_status maxflow_import_state(mf_solver* s, const void* src, int64_t iter) {
   if (iter < 0) return fail(MF_EINVAL, "iter must be >= 0");
   const bool dr = s->r.p.method == MF_RPDRQ;
   s->iter = iter;
-  const size_t off = dr ? s->L.state[0] : s->L.state[buf_of(s, iter)];
+  const size_t off = s->L.state[buf_of(s, iter)];
   HIP_TRY(hipMemcpyAsync(s->ws + off, src, s->L.state_bytes, hipMemcpyDeviceToDevice, s->stream));
   if (dr)
     HIP_TRY(hipMemcpyAsync(s->ws + s->L.stz, (const char*)src + s->L.state_bytes, s->L.state_bytes,

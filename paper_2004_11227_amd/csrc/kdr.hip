@@ -16,9 +16,60 @@
 //        y = y-bar + tau K u and the relaxed reflection
 //        y-bar += rho (prox(2y - y-bar) - y) in place (each cell touches only
 //        its own flows; b is read from its plane, not recomputed).
+// The two-label 2-D model also has a fused tiled pass (tiledr.h) that runs
+// the same per-cell arithmetic with the state read once and written once
+// into the other ping-pong buffer.
 #include "mf_kernels.h"
+#include "tiledr.h"
 
 namespace mf {
+
+template <typename TS, int TY>
+__global__ __launch_bounds__(256) void k_dr_fused2d(const KDF<TS> A) {
+  __shared__ SmemDR<TY> S;
+  if (A.done && *A.done) return;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (tile % A.tiles_x) * 64;
+  const int y0 = (tile / A.tiles_x) * TY;
+  tile_dr2d<TS, TY>(A, x0, y0, S);
+}
+
+template <typename TS>
+static hipError_t dr_fused_ts(const PdrqDesc& d, hipStream_t s) {
+  KDF<TS> a;
+  a.W = d.g.W;
+  a.H = d.g.H;
+  a.pitch = d.g.pitch;
+  a.P = d.g.plane;
+  a.tiles_x = (d.g.W + 63) / 64;
+  a.cap = (const TS*)d.cap;
+  a.u_in = d.st.u;
+  a.u_out = d.out.u;
+  a.qb_in = (const TS*)d.st.q;
+  a.qb_out = (TS*)d.out.q;
+  a.psb_in = (const TS*)d.st.ps;
+  a.psb_out = (TS*)d.out.ps;
+  a.pb_in = (const TS*)d.st.p;
+  a.pb_out = (TS*)d.out.p;
+  a.zq = (TS*)d.z.q;
+  a.zs = (TS*)d.z.ps;
+  a.zp = (TS*)d.z.p;
+  a.sigma = d.sigma;
+  a.tau = d.tau;
+  a.rho = d.rho;
+  a.inv_st = d.inv_st;
+  a.alpha = d.alpha;
+  a.m = 2.f;
+  a.iso = d.iso ? 1 : 0;
+  a.keep_z = d.keep_z ? 1 : 0;
+  a.done = d.done;
+  if (d.tile_rows == 32) {
+    hipLaunchKernelGGL((k_dr_fused2d<TS, 32>), dim3(a.tiles_x * ((d.g.H + 31) / 32)), dim3(256), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_dr_fused2d<TS, 16>), dim3(a.tiles_x * ((d.g.H + 15) / 16)), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
 
 template <typename TS>
 struct KD {
@@ -251,6 +302,10 @@ static hipError_t dr_ts(const PdrqDesc& d, hipStream_t s) {
 }
 
 hipError_t launch_pdrq_iter(const PdrqDesc& d, hipStream_t s) {
+  if (d.fused) {
+    if (!d.two || d.g.ndim != 2 || d.g.pitch % 4 != 0) return hipErrorInvalidValue;
+    return d.bf16 ? dr_fused_ts<bf16_t>(d, s) : dr_fused_ts<float>(d, s);
+  }
   if (d.g.pitch != d.g.W) return hipErrorInvalidValue;   // element-wise sweeps use the dense layout
   if (d.g.ndim == 2) return d.bf16 ? dr_ts<2, bf16_t>(d, s) : dr_ts<2, float>(d, s);
   return d.bf16 ? dr_ts<3, bf16_t>(d, s) : dr_ts<3, float>(d, s);

@@ -72,11 +72,14 @@ struct PdrqDesc {
   int nl;
   bool two, bf16, iso;
   const void* cap;
-  StateView st;        // u and the reflected variables (q-bar, p_s-bar, p-bar), in place
+  StateView st;        // u and the reflected variables (q-bar, p_s-bar, p-bar) of iterate k
+  StateView out;       // iterate k+1: = st for the in-place launches, the other buffer when fused
   StateView z;         // resolvent outputs (written when `keep_z`)
   float* b;            // NL planes of the right-hand side b^k
   float sigma, tau, rho, inv_st, alpha;
   bool keep_z;
+  bool fused;          // one tiled pass (two-label 2-D, padded rows, tile_rows 16 or 32)
+  int tile_rows;
   const int* done;
 };
 

@@ -48,3 +48,35 @@ def test_workspace_bytes_and_validation_without_gpu():
         mfx.workspace_bytes(mfx.make_params((16, 16), model="potts", nlabels=6))
     with pytest.raises(mfx.MaxflowError):
         mfx.workspace_bytes(mfx.make_params((16, 16), method="eb", relax=2.0))
+
+
+@pytest.mark.parametrize("shape", [(2048, 2048), (77, 131), (1, 5)])
+def test_workspace_layout_reserves_every_region(shape):
+    """The workspace covers every region a solver writes: ping-pong state
+    buffers for the fused passes, the resolvent outputs and the scratch
+    planes of rPDRQ (initialisation writes the resolvent outputs' u slot
+    into the scratch planes, also for the fused pass that keeps b in LDS)."""
+    if not os.path.exists(LIB):
+        pytest.skip("libmaxflow.so not built")
+    from paper_2004_11227_amd import maxflow as mfx
+
+    def ws(**kw):
+        return mfx.workspace_bytes(mfx.make_params(shape, model="two", **kw))
+
+    H, W = shape
+    pitch = (W + 3) // 4 * 4
+    P = (pitch * H + 127) // 128 * 128          # plane of the padded layout (elements)
+    Pd = (W * H + 127) // 128 * 128              # plane of the dense layout
+
+    def al(b):
+        return (b + 255) // 256 * 256
+
+    state_pad = al(4 * P) + al(8 * P) + al(4 * P) + al(4 * P)
+    state_dense = al(4 * Pd) + al(8 * Pd) + al(4 * Pd) + al(4 * Pd)
+    # fused rPDRQ: two state buffers + resolvent outputs + one FP32 scratch plane
+    assert ws(method="dr", variant="fused") - ws(method="eb", variant="fused") == state_pad + al(4 * P)
+    # in-place rPDRQ: one state buffer + resolvent outputs + scratch = the unfused rpADMM layout
+    assert ws(method="dr", variant="unfused") == ws(method="eb", variant="unfused")
+    # unfused rpADMM: dense planes, two state buffers and one FP32 scratch plane
+    assert ws(method="eb", variant="unfused") - ws(method="eb", variant="fused") == \
+        (al(8 * Pd) - al(8 * P)) + 2 * (state_dense - state_pad) + al(4 * Pd)

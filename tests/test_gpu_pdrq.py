@@ -1,4 +1,6 @@
-"""GPU parity of rPDRQ (in-place red-black half-sweeps) against the FP64 oracle."""
+"""GPU parity of rPDRQ against the FP64 oracle: the fused tiled pass
+(two-label 2-D) and the in-place red-black launches (the unfused variant,
+Potts and 3-D)."""
 import numpy as np
 import pytest
 import torch
@@ -16,11 +18,12 @@ def _gpu():
     need_gpu()
 
 
+@pytest.mark.parametrize("variant", ["fused", "unfused"])
 @pytest.mark.parametrize("shape", [(128, 128), (77, 131), (1, 64), (64, 1), (2, 2)])
-def test_two_label_2d(shape):
-    banner(f"pdrq two-label {shape}")
+def test_two_label_2d(shape, variant):
+    banner(f"pdrq two-label {shape} {variant}")
     caps = synth.config_inputs("c0", size=shape)["caps"]
-    du, dis, g, st = compare_run(caps, 150, model="two", method="dr", alpha=0.5)
+    du, dis, g, st = compare_run(caps, 150, model="two", method="dr", alpha=0.5, variant=variant)
     print(f"max|du|={du:.3e} dis={dis:.2e}")
     assert du <= 1e-4 and dis <= 1e-3
     for f in ("zq", "zs", "zp"):
@@ -61,3 +64,45 @@ def test_solve_gap_on_resolvent_outputs():
     e = oracle.energy(pr, caps, st)
     assert abs(res["rel_gap"] - e["rel_gap"]) < 1e-5
     assert e["rel_gap"] <= 1.5e-3
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("shape", [(1, 1), (3, 70), (70, 3), (33, 130), (200, 333)])
+def test_fused_equals_inplace_bitwise(storage, shape):
+    """The tiled pass (ping-pong buffers) and the three in-place launches give
+    the same bits: state and resolvent outputs, odd and even step counts,
+    both tile heights."""
+    banner(f"pdrq fused bitwise {shape} {storage}")
+    caps = synth.two_label_caps(synth.ellipse_image(*shape, 3, 0.15, 3200))
+    kw = dict(model="two", method="dr", alpha=0.5, storage=storage)
+    ref = gpu_solver(caps, variant="unfused", **kw)
+    runs = [gpu_solver(caps, variant="fused", tile_rows=tr, **kw) for tr in (16, 32)]
+    for n in (1, 2, 5):
+        ref.step(n)
+        a = gpu_fields(ref)
+        for s in runs:
+            s.step(n)
+            b = gpu_fields(s)
+            for f in a:
+                assert np.array_equal(a[f], b[f]), (n, s.params.tile_rows, f)
+    for s in runs + [ref]:
+        s.close()
+
+
+def test_fused_solve_equals_inplace():
+    banner("pdrq fused solve")
+    caps = synth.config_inputs("c0", size=(200, 170))["caps"]
+    kw = dict(model="two", method="dr", alpha=0.5, tol=1e-3, max_iter=2000, check_every=10)
+    out = []
+    for variant in ("unfused", "fused"):
+        s = gpu_solver(caps, variant=variant, **kw)
+        r = s.solve()
+        f = gpu_fields(s)
+        s.step(3)
+        out.append((r, f, gpu_fields(s)))
+        s.close()
+    (r1, f1, g1), (r2, f2, g2) = out
+    assert r1["iter"] == r2["iter"] and r1["rel_gap"] == r2["rel_gap"] and r1["status"] == 0
+    for k in f1:
+        assert np.array_equal(f1[k], f2[k]), k
+        assert np.array_equal(g1[k], g2[k]), k
