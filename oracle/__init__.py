@@ -30,7 +30,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 MODELS = {"two": 0, "potts": 1}
-METHODS = {"fg": 0, "eb": 1, "dr": 2}
+METHODS = {"fg": 0, "eb": 1, "dr": 2, "ty": 3, "cp": 4}
 TVS = {"iso": 0, "aniso": 1}
 
 
@@ -74,7 +74,7 @@ def _L():
         _lib.or_init.argtypes = [G, PR, P, P, P, P, P]
         _lib.or_admm_iter.argtypes = [G, PR, P, P, P, P, P]
         _lib.or_pdrq_iter.argtypes = [G, PR, P, P, P, P, P, P, P, P]
-        _lib.or_run.argtypes = [G, PR, P, ctypes.c_long, P, P, P, P, P, P, P]
+        _lib.or_run.argtypes = [G, PR, P, ctypes.c_long, P, P, P, P, P, P, P, P]
         _lib.or_energy.argtypes = [G, PR, P, P, P, P, P, P]
         _lib.or_labels.argtypes = [G, PR, P, ctypes.POINTER(ctypes.c_int)]
         _lib.or_num_threads.restype = ctypes.c_int
@@ -103,7 +103,10 @@ class Problem:
     """Model + method + parameters.  Zero parameters take the paper's values:
     c = 0.3; relax = 1.618 (FG r), 1.9 (EB rho, DR rho); a = 4*ndim,
     a_tilde = 2, a1 = 2, a2 = 2n; rPDRQ (sigma, tau) = (0.2, 1.0) two-label,
-    (5, 0.4) Potts."""
+    (5, 0.4) Potts; ALG1 sigma = 0.4, tau = 1 / (L^2 sigma) with the bound
+    L^2 = 4 ndim + 2 (two labels) or 4 ndim + n + 1 (n labels) on |K^* K|.
+    Methods: fg (rpADMMI), eb (rpADMMII), dr (rPDRQ), ty (pADMM-TY), cp
+    (ALG1)."""
     shape: tuple
     model: str = "two"
     method: str = "eb"
@@ -125,8 +128,12 @@ class Problem:
         if self.model == "two":
             self.nlabels = 2
         self.c = self.c or 0.3
-        self.relax = self.relax or {"fg": 1.618, "eb": 1.9, "dr": 1.9}[self.method]
-        if self.model == "two":
+        self.relax = self.relax or {"fg": 1.618, "eb": 1.9, "dr": 1.9, "ty": 1.0, "cp": 1.0}[self.method]
+        if self.method == "cp":
+            self.sigma = self.sigma or 0.4
+            l2 = 4.0 * nd + (2.0 if self.model == "two" else self.nlabels + 1.0)
+            self.tau = self.tau or 1.0 / (l2 * self.sigma)
+        elif self.model == "two":
             self.sigma = self.sigma or 0.2
             self.tau = self.tau or 1.0
         else:
@@ -162,11 +169,13 @@ class State:
     zs: np.ndarray = None
     zp: np.ndarray = None
     iters: int = 0
+    # ALG1 extrapolated primal variable u-bar
+    ub: np.ndarray = None
 
     def copy(self) -> "State":
         c = lambda a: None if a is None else a.copy()
         return State(c(self.u), c(self.q), c(self.ps), c(self.p), c(self.zq), c(self.zs),
-                     c(self.zp), self.iters)
+                     c(self.zp), self.iters, c(self.ub))
 
 
 def _caps(prob: Problem, caps) -> np.ndarray:
@@ -189,6 +198,8 @@ def init_state(prob: Problem, caps) -> State:
     st = State(u, q, ps, p)
     if prob.method == "dr":
         st.zq, st.zs, st.zp = q.copy(), ps.copy(), p.copy()
+    if prob.method == "cp":
+        st.ub = u.copy()
     return st
 
 
@@ -197,6 +208,8 @@ def state_from_arrays(prob: Problem, u, q, ps, p) -> State:
     st = State(f(u), f(q), f(ps), f(p))
     if prob.method == "dr":
         st.zq, st.zs, st.zp = st.q.copy(), st.ps.copy(), st.p.copy()
+    if prob.method == "cp":
+        st.ub = st.u.copy()
     return st
 
 
@@ -208,9 +221,12 @@ def step(prob: Problem, caps, st: State, iters: int = 1) -> State:
     z = st.zq if st.zq is not None else np.zeros(1)
     zs = st.zs if st.zs is not None else np.zeros(1)
     zp = st.zp if st.zp is not None else np.zeros(1)
+    if prob.method == "cp" and st.ub is None:
+        st.ub = st.u.copy()
+    ub = st.ub if st.ub is not None else np.zeros(1)
     _L().or_run(ctypes.byref(_grid(prob.shape)), ctypes.byref(prob._params()), _ptr(caps),
                 int(iters), _ptr(st.u), _ptr(st.q), _ptr(st.ps), _ptr(st.p),
-                _ptr(z), _ptr(zs), _ptr(zp))
+                _ptr(z), _ptr(zs), _ptr(zp), _ptr(ub))
     st.iters += iters
     return st
 

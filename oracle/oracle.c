@@ -348,11 +348,118 @@ void or_pdrq_iter(const or_grid* g, const or_params* p, const double* caps,
   free(b); free(dq); free(gu); free(qn);
 }
 
+/* pADMM-TY, the classical ADMM the paper compares against: the same q-step
+ * as above, then the flows block by block.
+ * Two labels (eq. ADMM:Tai_yuan): p_s, then p_t with the new p_s, then u:
+ *   p_s' = min(C_s, p_t + div q' - u/c + 1/c),
+ *   p_t' = min(C_t, p_s' - div q' + u/c),
+ *   u'   = u - c (p_t' - p_s' + div q').
+ * n labels (eq. mADMM:Tai_yuan):
+ *   p_i' = min(C_i, p_s - div q_i' + u_i/c),
+ *   p_s' = (sum_i (p_i + div q_i' - u_i/c) + 1/c) / n   (with the printed p_i,
+ *          the old flows),
+ *   u_i' = u_i - c (p_i' - p_s' + div q_i').
+ * The printed "u^k = u^k - ..." is the multiplier update u^{k+1}. */
+void or_ty_iter(const or_grid* g, const or_params* p, const double* caps,
+                double* u, double* q, double* ps, double* pp) {
+  const size_t N = npix(g);
+  const int d = g->ndim;
+  const double c = p->c;
+  double* f = dalloc(N);
+  if (p->model == OR_TWO) {
+    const double* Cs = caps;
+    const double* Ct = caps + N;
+    double* dq = dalloc(N);
+    for (size_t i = 0; i < N; i++) f[i] = pp[i] - ps[i] - u[i] / c;
+    admm_q_step(g, p, q, f);
+    or_div(g, q, dq);
+    for (size_t i = 0; i < N; i++) {
+      const double psn = fmin(Cs[i], pp[i] + dq[i] - u[i] / c + 1.0 / c);
+      const double ptn = fmin(Ct[i], psn - dq[i] + u[i] / c);
+      u[i] = u[i] - c * (ptn - psn + dq[i]);
+      ps[i] = psn;
+      pp[i] = ptn;
+    }
+    free(dq);
+  } else {
+    const int n = p->nlabels;
+    double* dqa = dalloc((size_t)n * N);
+    for (int l = 0; l < n; l++) {
+      for (size_t i = 0; i < N; i++) f[i] = pp[l * N + i] - ps[i] - u[l * N + i] / c;
+      admm_q_step(g, p, q + (size_t)l * d * N, f);
+      or_div(g, q + (size_t)l * d * N, dqa + (size_t)l * N);
+    }
+    for (size_t i = 0; i < N; i++) {
+      double pn[64], s = 0.0;
+      for (int l = 0; l < n; l++) {
+        const double di = dqa[l * N + i], ui = u[l * N + i];
+        pn[l] = fmin(caps[l * N + i], ps[i] - di + ui / c);
+        s += pp[l * N + i] + di - ui / c;
+      }
+      const double psn = s / n + 1.0 / (n * c);
+      for (int l = 0; l < n; l++) {
+        u[l * N + i] = u[l * N + i] - c * (pn[l] - psn + dqa[l * N + i]);
+        pp[l * N + i] = pn[l];
+      }
+      ps[i] = psn;
+    }
+    free(dqa);
+  }
+  free(f);
+}
+
+/* ALG1: the Chambolle-Pock primal-dual algorithm applied to the primal-dual
+ * forms of the appendix (eqs. iteration:pd:seg and alg1:4labels), dual step
+ * first with the extrapolated u-bar, then the primal step, then the
+ * extrapolation u-bar' = 2 u' - u.
+ * Two labels: q' = P_alpha(q - sigma grad u-bar), p_t' = min(C_t, p_t +
+ *   sigma u-bar), p_s' = min(C_s, p_s - sigma u-bar + sigma) (the +sigma of
+ *   the source term, as in the n-label p_s step; the printed p-bar on p_t is
+ *   p_t), u' = u - tau (div q' + p_t' - p_s').
+ * n labels: q_i' = P_alpha(q_i - sigma grad u-bar_i) (u-bar as in the
+ *   general dual step), p_i' = min(C_i, p_i + sigma u-bar_i), p_s' = p_s -
+ *   sigma sum_i u-bar_i + sigma, u_i' = u_i - tau (div q_i' + p_i' - p_s'). */
+void or_cp_iter(const or_grid* g, const or_params* p, const double* caps,
+                double* u, double* ub, double* q, double* ps, double* pp) {
+  const size_t N = npix(g);
+  const int d = g->ndim;
+  const int two = p->model == OR_TWO;
+  const int L = two ? 1 : p->nlabels;
+  const double sg = p->sigma, tau = p->tau;
+  double* gu = dalloc((size_t)d * N);
+  double* dq = dalloc((size_t)L * N);
+  for (int l = 0; l < L; l++) {
+    double* ql = q + (size_t)l * d * N;
+    or_grad(g, ub + (size_t)l * N, gu);
+    for (size_t j = 0; j < (size_t)d * N; j++) ql[j] = ql[j] - sg * gu[j];
+    or_project_alpha(g, p->tv, p->alpha, ql);
+    or_div(g, ql, dq + (size_t)l * N);
+  }
+  for (size_t i = 0; i < N; i++) {
+    double sum_ub = 0.0;
+    for (int l = 0; l < L; l++) {
+      pp[l * N + i] = fmin(caps[(two ? 1 : l) * N + i], pp[l * N + i] + sg * ub[l * N + i]);
+      sum_ub += ub[l * N + i];
+    }
+    double psn = ps[i] - sg * sum_ub + sg;
+    if (two) psn = fmin(caps[i], psn);
+    ps[i] = psn;
+    for (int l = 0; l < L; l++) {
+      const double un = u[l * N + i] - tau * (dq[l * N + i] + pp[l * N + i] - psn);
+      ub[l * N + i] = 2.0 * un - u[l * N + i];
+      u[l * N + i] = un;
+    }
+  }
+  free(gu); free(dq);
+}
+
 void or_run(const or_grid* g, const or_params* p, const double* caps, long iters,
             double* u, double* q, double* ps, double* pp,
-            double* zq, double* zs, double* zp) {
+            double* zq, double* zs, double* zp, double* ub) {
   for (long k = 0; k < iters; k++) {
     if (p->method == OR_DR) or_pdrq_iter(g, p, caps, u, q, ps, pp, zq, zs, zp);
+    else if (p->method == OR_TY) or_ty_iter(g, p, caps, u, q, ps, pp);
+    else if (p->method == OR_CP) or_cp_iter(g, p, caps, u, ub, q, ps, pp);
     else or_admm_iter(g, p, caps, u, q, ps, pp);
   }
 }

@@ -17,6 +17,9 @@
  *   caps               two-label: [C_s, C_t]; Potts: [C_1..C_n]
  * For rPDRQ, (q, ps, p) hold the reflected variables (q-bar, p-bar) and the
  * resolvent outputs of the last iteration are written to (zq, zs, zp).
+ * The comparison methods of the experiments section are here too: the
+ * classical sequential ADMM (pADMM-TY) and the Chambolle-Pock primal-dual
+ * algorithm (ALG1, which also keeps the extrapolated u-bar [L][N]).
  */
 #ifndef MAXFLOW_ORACLE_H
 #define MAXFLOW_ORACLE_H
@@ -29,7 +32,7 @@ extern "C" {
 typedef struct { int ndim; long nx, ny, nz; } or_grid;
 
 enum { OR_TWO = 0, OR_POTTS = 1 };
-enum { OR_FG = 0, OR_EB = 1, OR_DR = 2 };
+enum { OR_FG = 0, OR_EB = 1, OR_DR = 2, OR_TY = 3, OR_CP = 4 };
 enum { OR_ISO = 0, OR_ANISO = 1 };
 
 typedef struct {
@@ -37,7 +40,7 @@ typedef struct {
   double alpha;          /* TV weight                                        */
   double c;              /* ADMM step                                        */
   double relax;          /* FG: r; EB: rho_k (constant); DR: rho             */
-  double sigma, tau;     /* rPDRQ step sizes                                 */
+  double sigma, tau;     /* rPDRQ / ALG1 step sizes                          */
   double a;              /* q preconditioner N = a c I                       */
   double a_tilde;        /* two-label p preconditioner M = a~ c I_2          */
   double a1, a2;         /* Potts block preconditioner diag(a1 I.., a2 I)    */
@@ -56,9 +59,13 @@ void or_admm_iter(const or_grid* g, const or_params* p, const double* caps,
 void or_pdrq_iter(const or_grid* g, const or_params* p, const double* caps,
                   double* u, double* qb, double* psb, double* pb,
                   double* zq, double* zs, double* zp);
+void or_ty_iter(const or_grid* g, const or_params* p, const double* caps,
+                double* u, double* q, double* ps, double* pp);
+void or_cp_iter(const or_grid* g, const or_params* p, const double* caps,
+                double* u, double* ub, double* q, double* ps, double* pp);
 void or_run(const or_grid* g, const or_params* p, const double* caps, long iters,
             double* u, double* q, double* ps, double* pp,
-            double* zq, double* zs, double* zp);
+            double* zq, double* zs, double* zp, double* ub);
 void or_energy(const or_grid* g, const or_params* p, const double* caps,
                const double* u, const double* q, const double* ps, const double* pp,
                double out[5]);
