@@ -23,6 +23,20 @@
  *   MF_RPDRQ      rPDRQ, relaxed Douglas-Rachford with a symmetric red-black
  *                 Gauss-Seidel preconditioner (eq. iteration:quadratic:seg;
  *                 multi-label eq. pdrq:4labels for general n, T_0 of Lemma 1).
+ * The comparison methods of the experiments section (element-wise kernels;
+ * the unfused variant is implied):
+ *   MF_PADMM_TY   pADMM-TY, the classical sequential ADMM (eq. ADMM:Tai_yuan;
+ *                 multi-label eq. mADMM:Tai_yuan, blocks q, p_i, p_s, u in
+ *                 sequence, so the p_s step takes the new p_i).  Uses c and
+ *                 a; no convergence guarantee.
+ *   MF_CP_ALG1    ALG1, the Chambolle-Pock primal-dual algorithm of the
+ *                 appendix (eqs. iteration:pd:seg, alg1:4labels; the
+ *                 two-label p_s step with +sigma as in the n-label one).
+ *                 sigma 0 -> 0.4, tau 0 -> 1 / (L^2 sigma) with L^2 = 4 ndim
+ *                 + 2 (two labels) or 4 ndim + n + 1 (n labels); sigma tau
+ *                 L^2 > 1 is rejected.  Keeps the extrapolated u-bar in the
+ *                 state (exported with it).
+ * pADMMI (FG without relaxation) is MF_RPADMM_FG with relax = 1.
  *
  * Discretisation: forward-difference gradient with Neumann boundary,
  * div = -grad^*, unit spacing; 2-D or 3-D grids (3-D uses a = 12).
@@ -61,7 +75,13 @@ typedef enum {
 } mf_status;
 
 typedef enum { MF_TWO_LABEL = 0, MF_POTTS = 1 } mf_model;
-typedef enum { MF_RPADMM_FG = 0, MF_RPADMM_EB = 1, MF_RPDRQ = 2 } mf_method;
+typedef enum {
+  MF_RPADMM_FG = 0,
+  MF_RPADMM_EB = 1,
+  MF_RPDRQ = 2,
+  MF_PADMM_TY = 3,
+  MF_CP_ALG1 = 4
+} mf_method;
 /* MF_TV_ISO: pointwise Euclidean |q(x)| <= alpha, the P_alpha of eq.
  * (projections).  MF_TV_ANISO: per-component |q_k(x)| <= alpha (l1 TV). */
 typedef enum { MF_TV_ISO = 0, MF_TV_ANISO = 1 } mf_tv;

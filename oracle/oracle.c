@@ -354,10 +354,12 @@ void or_pdrq_iter(const or_grid* g, const or_params* p, const double* caps,
  *   p_s' = min(C_s, p_t + div q' - u/c + 1/c),
  *   p_t' = min(C_t, p_s' - div q' + u/c),
  *   u'   = u - c (p_t' - p_s' + div q').
- * n labels (eq. mADMM:Tai_yuan):
+ * n labels (eq. mADMM:Tai_yuan), blocks in the order q, p_i, p_s, u:
  *   p_i' = min(C_i, p_s - div q_i' + u_i/c),
- *   p_s' = (sum_i (p_i + div q_i' - u_i/c) + 1/c) / n   (with the printed p_i,
- *          the old flows),
+ *   p_s' = (sum_i (p_i' + div q_i' - u_i/c) + 1/c) / n   (the new p_i', as a
+ *          sequential block update takes them; with the old p_i, as the
+ *          printed superscript reads, the scheme diverges on every input
+ *          tried, unlike the convergence the experiments report),
  *   u_i' = u_i - c (p_i' - p_s' + div q_i').
  * The printed "u^k = u^k - ..." is the multiplier update u^{k+1}. */
 void or_ty_iter(const or_grid* g, const or_params* p, const double* caps,
@@ -394,7 +396,7 @@ void or_ty_iter(const or_grid* g, const or_params* p, const double* caps,
       for (int l = 0; l < n; l++) {
         const double di = dqa[l * N + i], ui = u[l * N + i];
         pn[l] = fmin(caps[l * N + i], ps[i] - di + ui / c);
-        s += pp[l * N + i] + di - ui / c;
+        s += pn[l] + di - ui / c;
       }
       const double psn = s / n + 1.0 / (n * c);
       for (int l = 0; l < n; l++) {

@@ -70,7 +70,9 @@ std::string resolve(const mf_params* in, Resolved& r) {
   for (int i = 0; i < p.ndim; i++)
     if (p.shape[i] < 1 || p.shape[i] > (1LL << 30)) return "shape entries must be >= 1";
   if (p.model != MF_TWO_LABEL && p.model != MF_POTTS) return "unknown model";
-  if (p.method < MF_RPADMM_FG || p.method > MF_RPDRQ) return "unknown method";
+  if (p.method < MF_RPADMM_FG || p.method > MF_CP_ALG1) return "unknown method";
+  const bool cmp = p.method == MF_PADMM_TY || p.method == MF_CP_ALG1;
+  if (cmp) p.variant = MF_UNFUSED;   // the comparison methods run element-wise kernels
   if (p.tv != MF_TV_ISO && p.tv != MF_TV_ANISO) return "unknown tv";
   if (p.storage != MF_F32 && p.storage != MF_BF16) return "unknown storage";
   if (p.variant != MF_FUSED && p.variant != MF_UNFUSED) return "unknown variant";
@@ -83,13 +85,23 @@ std::string resolve(const mf_params* in, Resolved& r) {
   if (!(p.alpha >= 0.0) || !std::isfinite(p.alpha)) return "alpha must be finite and >= 0";
   if (p.c == 0.0) p.c = 0.3;
   if (!(p.c > 0.0) || !std::isfinite(p.c)) return "c must be > 0";
-  if (p.relax == 0.0) p.relax = p.method == MF_RPADMM_FG ? 1.618 : 1.9;
-  if (p.method == MF_RPADMM_FG) {
+  if (p.relax == 0.0) p.relax = p.method == MF_RPADMM_FG ? 1.618 : (cmp ? 1.0 : 1.9);
+  if (cmp) {
+    if (p.relax != 1.0) return "pADMM-TY and ALG1 take no relaxation (relax 0 or 1)";
+  } else if (p.method == MF_RPADMM_FG) {
     if (!(p.relax > 0.0 && p.relax < 0.5 * (1.0 + std::sqrt(5.0)))) return "FG relaxation r must be in (0, 1.618..)";
   } else if (!(p.relax > 0.0 && p.relax < 2.0)) {
     return "relaxation rho must be in (0, 2)";
   }
   const bool two = p.model == MF_TWO_LABEL;
+  if (p.method == MF_CP_ALG1) {
+    // |K^* K| <= |div^* div| + 2 (two labels) or + n + 1 (n labels)
+    const double l2 = 4.0 * p.ndim + (two ? 2.0 : p.nlabels + 1.0);
+    if (p.sigma == 0.0) p.sigma = 0.4;
+    if (p.tau == 0.0) p.tau = 1.0 / (l2 * p.sigma);
+    if (!(p.sigma > 0.0) || !(p.tau > 0.0)) return "sigma and tau must be > 0";
+    if (p.sigma * p.tau * l2 > 1.0 + 1e-12) return "ALG1 needs sigma tau |K^*K| <= 1";
+  }
   if (p.sigma == 0.0) p.sigma = two ? 0.2 : 5.0;
   if (p.tau == 0.0) p.tau = two ? 1.0 : 0.4;
   if (!(p.sigma > 0.0) || !(p.tau > 0.0)) return "sigma and tau must be > 0";
@@ -165,6 +177,7 @@ Layout plan(const Resolved& r) {
   // state: u (nl f32) + q (nq) + ps (1) + p (nl) in storage type
   L.state_bytes = align_up((size_t)r.nl * P * 4, 256) + align_up((size_t)r.nq * P * r.esz, 256) +
                   align_up(P * r.esz, 256) + align_up((size_t)r.nl * P * r.esz, 256);
+  if (r.p.method == MF_CP_ALG1) L.state_bytes += align_up((size_t)r.nl * P * 4, 256);   // u-bar
   L.state[0] = off;
   off += L.state_bytes;
   const bool dr = r.p.method == MF_RPDRQ;
@@ -198,6 +211,10 @@ StateView view(char* base, size_t off, const Resolved& r) {
   v.ps = b;
   b += align_up(P * r.esz, 256);
   v.p = b;
+  if (r.p.method == MF_CP_ALG1) {
+    b += align_up((size_t)r.nl * P * r.esz, 256);
+    v.ub = (float*)b;
+  }
   return v;
 }
 
@@ -284,6 +301,9 @@ hipError_t admm_sweep(mf_solver* s, int64_t k, bool check, bool write, const int
   d.k = coef_of(s->r);
   d.acc = &s->ctrl->acc[0][0];
   d.done = done;
+  d.scheme = s->r.p.method == MF_PADMM_TY ? 1 : (s->r.p.method == MF_CP_ALG1 ? 2 : 0);
+  d.sigma = (float)s->r.p.sigma;
+  d.tau = (float)s->r.p.tau;
   // Potts 3-D has no fused pass: it always runs the per-operator kernels
   if (s->r.p.variant == MF_UNFUSED || (s->r.g.ndim == 3 && s->r.p.model == MF_POTTS))
     return launch_unfused(d, s->stream);
@@ -371,6 +391,8 @@ mf_status init_state(mf_solver* s) {
     HIP_TRY(launch_init(s->r.g, s->r.nl, s->r.p.model == MF_TWO_LABEL, s->r.p.storage == MF_BF16, s->cap,
                         StateView{s->wbuf, z.q, z.ps, z.p}, s->stream));
   }
+  if (s->r.p.method == MF_CP_ALG1)   // u-bar^0 = u^0 = 0
+    HIP_TRY(hipMemsetAsync(s->st[0].ub, 0, (size_t)s->r.nl * (size_t)s->r.g.plane * 4, s->stream));
   HIP_TRY(launch_ctrl_reset(s->ctrl, s->stream));
   s->iter = 0;
   s->off = 0;

@@ -4,6 +4,14 @@
 //   K_pu: d_i = div q_i', then the pointwise p, p_s, u updates
 // The arithmetic is the same sequence of device functions as the fused
 // passes, so both produce the same bits.
+//
+// The same element-wise machinery runs the paper's comparison methods:
+//   pADMM-TY (eqs. ADMM:Tai_yuan, mADMM:Tai_yuan): K_w and K_q as above,
+//     then block-sequential flow updates (K_ty);
+//   ALG1 (Chambolle-Pock, eqs. iteration:pd:seg, alg1:4labels): K_cpd, the
+//     dual step q' = P_alpha(q - sigma grad u-bar), p' = min(C, p + sigma
+//     u-bar), p_s' = (min(C_s,) p_s - sigma sum u-bar + sigma); then K_cpp,
+//     the primal step u' = u - tau (div q' + p' - p_s') and u-bar' = 2u' - u.
 #include "mf_kernels.h"
 
 namespace mf {
@@ -25,6 +33,9 @@ struct KU {
   Coef k;
   const int* done;
   int iso;
+  const float* ub_in;   // ALG1
+  float* ub_out;
+  float sigma, tau;
 };
 
 template <int NDIM, typename TS>
@@ -72,13 +83,13 @@ __global__ __launch_bounds__(256) void k_uf_q(const KU<TS> A) {
       const float w0 = w[idx];
       const TS* qi = A.q_in + (long long)(NDIM * l) * A.P;
       TS* qo = A.q_out + (long long)(NDIM * l) * A.P;
-      float qx = qstep(ld(qi, idx), x + 1 < A.W ? w[idx + 1] : 0.f, w0, x + 1 < A.W, A.k.inv_a);
-      float qy = qstep(ld(qi + A.P, idx), y + 1 < A.H ? w[idx + A.W] : 0.f, w0, y + 1 < A.H, A.k.inv_a);
+      float qx = qstep(ld(qi, idx), ldz(w, idx + 1, x + 1 < A.W), w0, x + 1 < A.W, A.k.inv_a);
+      float qy = qstep(ld(qi + A.P, idx), ldz(w, idx + A.W, y + 1 < A.H), w0, y + 1 < A.H, A.k.inv_a);
       if (NDIM == 2) {
         if (A.iso) proj2<true>(qx, qy, A.k.alpha);
         else proj2<false>(qx, qy, A.k.alpha);
       } else {
-        float qz = qstep(ld(qi + 2 * A.P, idx), z + 1 < A.D ? w[idx + sz] : 0.f, w0, z + 1 < A.D, A.k.inv_a);
+        float qz = qstep(ld(qi + 2 * A.P, idx), ldz(w, idx + sz, z + 1 < A.D), w0, z + 1 < A.D, A.k.inv_a);
         if (A.iso) proj3<true>(qx, qy, qz, A.k.alpha);
         else proj3<false>(qx, qy, qz, A.k.alpha);
         st(qo + 2 * A.P, idx, qz);
@@ -116,6 +127,112 @@ __global__ __launch_bounds__(256) void k_uf_pu(const KU<TS> A) {
   }
 }
 
+// pADMM-TY flows and multiplier from d_i = div q_i' (blocks in sequence).
+// Two labels: p_s' with p_t^k, then p_t' with p_s'; n labels: p_i' with
+// p_s^k, then p_s' with the new p_i', then u_i' = u_i - c (p_i' - p_s' + d_i).
+template <int NL, bool TWO, int NDIM, typename TS>
+__global__ __launch_bounds__(256) void k_ty(const KU<TS> A) {
+  if (A.done && *A.done) return;
+  const float c = A.k.c, inv_c = A.k.inv_c;
+  for (long long idx = blockIdx.x * 256LL + threadIdx.x; idx < A.n; idx += (long long)gridDim.x * 256) {
+    const int x = (int)(idx % A.W);
+    const int y = (int)((idx / A.W) % A.H);
+    const int z = (int)(idx / ((long long)A.W * A.H));
+    const float ps = ld(A.ps_in, idx);
+    if (TWO) {
+      const float d = div_at<NDIM>(A.q_out, A.P, idx, x, y, z, A.W, A.H, A.D);
+      const float u = A.u_in[idx];
+      const float psn = fminf(ld(A.cap, idx), ((ld(A.p_in, idx) + d) - u * inv_c) + inv_c);
+      const float ptn = fminf(ld(A.cap + A.P, idx), (psn - d) + u * inv_c);
+      st(A.ps_out, idx, psn);
+      st(A.p_out, idx, ptn);
+      A.u_out[idx] = u - c * ((ptn - psn) + d);
+    } else {
+      float d[NL], pn[NL];
+      float s = 0.f;
+#pragma unroll
+      for (int l = 0; l < NL; l++) {
+        d[l] = div_at<NDIM>(A.q_out + (long long)(NDIM * l) * A.P, A.P, idx, x, y, z, A.W, A.H, A.D);
+        const float u = A.u_in[(long long)l * A.P + idx];
+        pn[l] = fminf(ld(A.cap + (long long)l * A.P, idx), (ps - d[l]) + u * inv_c);
+        s += (pn[l] + d[l]) - u * inv_c;
+      }
+      const float psn = s / (float)NL + inv_c / (float)NL;
+      st(A.ps_out, idx, psn);
+#pragma unroll
+      for (int l = 0; l < NL; l++) {
+        st(A.p_out + (long long)l * A.P, idx, pn[l]);
+        const float u = A.u_in[(long long)l * A.P + idx];
+        A.u_out[(long long)l * A.P + idx] = u - c * ((pn[l] - psn) + d[l]);
+      }
+    }
+  }
+}
+
+// ALG1 dual step at every cell: q_i' from the forward differences of u-bar_i,
+// then the flows.
+template <int NL, bool TWO, int NDIM, typename TS>
+__global__ __launch_bounds__(256) void k_cpd(const KU<TS> A) {
+  if (A.done && *A.done) return;
+  const long long sz = (long long)A.W * A.H;
+  const float sg = A.sigma;
+  for (long long idx = blockIdx.x * 256LL + threadIdx.x; idx < A.n; idx += (long long)gridDim.x * 256) {
+    const int x = (int)(idx % A.W);
+    const int y = (int)((idx / A.W) % A.H);
+    const int z = (int)(idx / sz);
+    float sub = 0.f;
+#pragma unroll
+    for (int l = 0; l < NL; l++) {
+      const float* ub = A.ub_in + (long long)l * A.P;
+      const float b0 = ub[idx];
+      const TS* qi = A.q_in + (long long)(NDIM * l) * A.P;
+      TS* qo = A.q_out + (long long)(NDIM * l) * A.P;
+      // neighbour loads guarded by their own conditions (ldz loads element 0 otherwise)
+      const bool hx = x + 1 < A.W, hy = y + 1 < A.H;
+      float qx = ld(qi, idx) - sg * (hx ? ldz(ub, idx + 1, hx) - b0 : 0.f);
+      float qy = ld(qi + A.P, idx) - sg * (hy ? ldz(ub, idx + A.W, hy) - b0 : 0.f);
+      if (NDIM == 2) {
+        if (A.iso) proj2<true>(qx, qy, A.k.alpha);
+        else proj2<false>(qx, qy, A.k.alpha);
+      } else {
+        const bool hz = z + 1 < A.D;
+        float qz = ld(qi + 2 * A.P, idx) - sg * (hz ? ldz(ub, idx + sz, hz) - b0 : 0.f);
+        if (A.iso) proj3<true>(qx, qy, qz, A.k.alpha);
+        else proj3<false>(qx, qy, qz, A.k.alpha);
+        st(qo + 2 * A.P, idx, qz);
+      }
+      st(qo, idx, qx);
+      st(qo + A.P, idx, qy);
+      const float C = ld(A.cap + (long long)(TWO ? 1 : l) * A.P, idx);
+      st(A.p_out + (long long)l * A.P, idx, fminf(C, ld(A.p_in + (long long)l * A.P, idx) + sg * b0));
+      sub += b0;
+    }
+    float psn = (ld(A.ps_in, idx) - sg * sub) + sg;
+    if (TWO) psn = fminf(ld(A.cap, idx), psn);
+    st(A.ps_out, idx, psn);
+  }
+}
+
+// ALG1 primal step and extrapolation (after K_cpd has finished everywhere).
+template <int NL, bool TWO, int NDIM, typename TS>
+__global__ __launch_bounds__(256) void k_cpp(const KU<TS> A) {
+  if (A.done && *A.done) return;
+  for (long long idx = blockIdx.x * 256LL + threadIdx.x; idx < A.n; idx += (long long)gridDim.x * 256) {
+    const int x = (int)(idx % A.W);
+    const int y = (int)((idx / A.W) % A.H);
+    const int z = (int)(idx / ((long long)A.W * A.H));
+    const float psn = ld(A.ps_out, idx);
+#pragma unroll
+    for (int l = 0; l < NL; l++) {
+      const float d = div_at<NDIM>(A.q_out + (long long)(NDIM * l) * A.P, A.P, idx, x, y, z, A.W, A.H, A.D);
+      const float u = A.u_in[(long long)l * A.P + idx];
+      const float un = u - A.tau * ((d + ld(A.p_out + (long long)l * A.P, idx)) - psn);
+      A.u_out[(long long)l * A.P + idx] = un;
+      A.ub_out[(long long)l * A.P + idx] = 2.f * un - u;
+    }
+  }
+}
+
 template <int NL, bool TWO, int NDIM, typename TS>
 static hipError_t unfused_nl(const SweepDesc& d, hipStream_t s) {
   KU<TS> a;
@@ -137,11 +254,24 @@ static hipError_t unfused_nl(const SweepDesc& d, hipStream_t s) {
   a.k = d.k;
   a.done = d.done;
   a.iso = d.iso ? 1 : 0;
+  a.ub_in = d.in.ub;
+  a.ub_out = d.out.ub;
+  a.sigma = d.sigma;
+  a.tau = d.tau;
   long long nb = (a.n + 255) / 256;
   if (nb > 16384) nb = 16384;
+  if (d.scheme == 2) {
+    if (!a.ub_in || !a.ub_out) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_cpd<NL, TWO, NDIM, TS>), dim3((int)nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_cpp<NL, TWO, NDIM, TS>), dim3((int)nb), dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((k_uf_w<NL, NDIM, TS>), dim3((int)nb), dim3(256), 0, s, a);
   hipLaunchKernelGGL((k_uf_q<NL, NDIM, TS>), dim3((int)nb), dim3(256), 0, s, a);
-  hipLaunchKernelGGL((k_uf_pu<NL, TWO, NDIM, TS>), dim3((int)nb), dim3(256), 0, s, a);
+  if (d.scheme == 1)
+    hipLaunchKernelGGL((k_ty<NL, TWO, NDIM, TS>), dim3((int)nb), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_uf_pu<NL, TWO, NDIM, TS>), dim3((int)nb), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ struct StateView {
   void* q;     // NL * ndim planes (storage type)
   void* ps;    // 1 plane
   void* p;     // NL planes
+  float* ub = nullptr;   // ALG1 only: extrapolated u-bar, NL planes FP32
 };
 
 struct SweepDesc {
@@ -55,6 +56,8 @@ struct SweepDesc {
   Coef k;
   double* acc;     // Ctrl::acc of this solve
   const int* done; // Ctrl::done of this solve, or nullptr
+  int scheme = 0;  // element-wise passes: 0 rpADMM, 1 pADMM-TY, 2 ALG1
+  float sigma = 0.f, tau = 0.f;   // ALG1 step sizes
 };
 
 struct GapDesc {

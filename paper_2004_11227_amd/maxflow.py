@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libmaxflow.so")
 
 MF_OK, MF_ENOTCONV, MF_EINVAL, MF_ENOMEM, MF_EDEVICE, MF_EDIVERGED = 0, 1, -1, -2, -3, -4
 MODELS = {"two": 0, "potts": 1}
-METHODS = {"fg": 0, "eb": 1, "dr": 2}
+METHODS = {"fg": 0, "eb": 1, "dr": 2, "ty": 3, "cp": 4}
 TVS = {"iso": 0, "aniso": 1}
 STORAGES = {"f32": 0, "bf16": 1}
 VARIANTS = {"fused": 0, "unfused": 1}

@@ -108,6 +108,19 @@ def test_alg1_step_sizes_satisfy_the_bound(model, n):
     assert pr.sigma * pr.tau * (8.0 + m) == pytest.approx(1.0)
 
 
+def test_ty_potts_converges_on_a_voronoi_image():
+    """The sequential pADMM-TY converges on the 4-label synthetic stand-in
+    (the experiments report convergence for 4 labels; with the old p_i in
+    the p_s step the iterates grow without bound)."""
+    img, _ = synth.voronoi_image(40, 50, 4, 0.15, 2204, ncells=16)
+    caps = synth.potts_caps(img, 4)
+    pr = oracle.Problem((40, 50), model="potts", nlabels=4, method="ty", alpha=0.3)
+    st = oracle.init_state(pr, caps)
+    oracle.step(pr, caps, st, 600)
+    e = oracle.energy(pr, caps, st)
+    assert e["rel_gap"] < 1e-3 and np.abs(st.u).max() < 2.0
+
+
 def test_alg1_iterates_feasible_and_gap_nonnegative():
     shape = (9, 11)
     caps = _rand_caps(shape, 4)
@@ -153,10 +166,10 @@ def test_ty_two_label_blocks_maximise_the_augmented_lagrangian():
 
 
 def test_ty_potts_blocks_maximise_the_augmented_lagrangian():
-    """n labels (eq. mADMM:Tai_yuan, with the printed p_i^k in the p_s step):
+    """n labels (eq. mADMM:Tai_yuan, blocks q, p_i, p_s, u in sequence):
     p_i' maximises L = <1, p_s> + sum_i <u_i, div q_i + p_i - p_s> - c/2 sum_i
     |div q_i + p_i - p_s|^2 over p_i <= C_i with p_s at p_s^k, and p_s'
-    maximises it over p_s with every p_i at p_i^k."""
+    maximises it over p_s with every p_i at its new value p_i'."""
     shape, n = (3, 4), 3
     caps = _rand_caps(shape, 9, "potts", n)
     pr = oracle.Problem(shape, model="potts", nlabels=n, method="ty", alpha=0.3)
@@ -182,5 +195,6 @@ def test_ty_potts_blocks_maximise_the_augmented_lagrangian():
                 return lag(p, ps0)
             pi = _argmax_1d(f, caps[(i,) + idx] - 50.0, caps[(i,) + idx])
             assert abs(pi - s1.p[(i,) + idx]) < 1e-6, (idx, i)
-        ps1 = _argmax_1d(lambda x: lag(p0, x), ps0 - 50.0, ps0 + 50.0)
+        p1 = s1.p[(slice(None),) + idx]
+        ps1 = _argmax_1d(lambda x: lag(p1, x), ps0 - 50.0, ps0 + 50.0)
         assert abs(ps1 - s1.ps[idx]) < 1e-6, idx
