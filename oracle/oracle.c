@@ -358,8 +358,8 @@ void or_pdrq_iter(const or_grid* g, const or_params* p, const double* caps,
  *   p_i' = min(C_i, p_s - div q_i' + u_i/c),
  *   p_s' = (sum_i (p_i' + div q_i' - u_i/c) + 1/c) / n   (the new p_i', as a
  *          sequential block update takes them; with the old p_i, as the
- *          printed superscript reads, the scheme diverges on every input
- *          tried, unlike the convergence the experiments report),
+ *          printed superscript reads, the scheme diverges on every
+ *          synthetic input tried),
  *   u_i' = u_i - c (p_i' - p_s' + div q_i').
  * The printed "u^k = u^k - ..." is the multiplier update u^{k+1}. */
 void or_ty_iter(const or_grid* g, const or_params* p, const double* caps,

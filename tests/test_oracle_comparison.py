@@ -109,9 +109,8 @@ def test_alg1_step_sizes_satisfy_the_bound(model, n):
 
 
 def test_ty_potts_converges_on_a_voronoi_image():
-    """The sequential pADMM-TY converges on the 4-label synthetic stand-in
-    (the experiments report convergence for 4 labels; with the old p_i in
-    the p_s step the iterates grow without bound)."""
+    """The sequential pADMM-TY converges on a 4-label synthetic stand-in
+    (with the old p_i in the p_s step the iterates grow without bound)."""
     img, _ = synth.voronoi_image(40, 50, 4, 0.15, 2204, ncells=16)
     caps = synth.potts_caps(img, 4)
     pr = oracle.Problem((40, 50), model="potts", nlabels=4, method="ty", alpha=0.3)
