@@ -109,20 +109,31 @@ def time_sweeps(torch, solver, stream, n):
 
 
 def cpu_baseline(caps64, wl):
+    """The FP64 oracle on the host cores (all of them, then one thread) on a
+    bounded sample of the workload's iterations."""
     import oracle
     shape = wl["shape"]
     pr = oracle.Problem(shape, model="two", method=wl["method"], relax=wl["relax"], alpha=wl["alpha"])
     st = oracle.init_state(pr, caps64)
     oracle.step(pr, caps64, st, 1)
+    n = shape[0] * shape[1]
+    threads = oracle.num_threads()
     iters = 40
     t0 = time.perf_counter()
     oracle.step(pr, caps64, st, iters)
     dt = time.perf_counter() - t0
-    n = shape[0] * shape[1]
-    return {"value": n * 2 * iters / dt, "unit": "pixel*label*iterations/s", "cores": oracle.num_threads(),
+    iters1 = 10
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.step(pr, caps64, st, iters1)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    return {"value": n * 2 * iters / dt, "unit": "pixel*label*iterations/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{iters} of the {wl['iters']} iterations of the {shape[0]}x{shape[1]} two-label "
-                      f"rpADMMII workload, FP64, OpenMP threads={oracle.num_threads()}, {dt:.1f} s"}
+                      f"rpADMMII workload, FP64, OpenMP threads={threads}, {dt:.1f} s",
+            "single_thread": {"value": n * 2 * iters1 / dt1, "cores": 1,
+                              "sample": f"{iters1} further iterations on one thread, {dt1:.1f} s"}}
 
 
 def traffic_for(launch_bytes):

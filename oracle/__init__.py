@@ -78,11 +78,17 @@ def _L():
         _lib.or_energy.argtypes = [G, PR, P, P, P, P, P, P]
         _lib.or_labels.argtypes = [G, PR, P, ctypes.POINTER(ctypes.c_int)]
         _lib.or_num_threads.restype = ctypes.c_int
+        _lib.or_set_threads.argtypes = [ctypes.c_int]
     return _lib
 
 
 def num_threads() -> int:
     return int(_L().or_num_threads())
+
+
+def set_threads(n: int):
+    """Threads of the oracle's parallel loops (results do not depend on it)."""
+    _L().or_set_threads(int(n))
 
 
 def _ptr(a: np.ndarray):

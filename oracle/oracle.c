@@ -33,6 +33,16 @@ int or_num_threads(void) {
 #endif
 }
 
+/* Threads of the later parallel loops (reductions stay in row order, so the
+ * results do not depend on it). */
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* Forward differences with Neumann boundary (the discretisation the paper
  * takes from Chambolle-Pock for its bound ||div^* div|| <= 8, Theorem 1):
  * (grad f)_k(x) = f(x + e_k) - f(x) if x + e_k lies in the grid, else 0. */

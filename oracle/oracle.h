@@ -71,6 +71,7 @@ void or_energy(const or_grid* g, const or_params* p, const double* caps,
                double out[5]);
 void or_labels(const or_grid* g, const or_params* p, const double* u, int* lab);
 int  or_num_threads(void);
+void or_set_threads(int n);
 
 #ifdef __cplusplus
 }
