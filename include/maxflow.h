@@ -113,8 +113,10 @@ typedef struct {
   int32_t max_iter;      /* iteration cap for maxflow_solve (>= 0)                   */
   double tol;            /* relative primal-dual gap tolerance for maxflow_solve      */
   int32_t check_every;   /* gap cadence in iterations; 0 -> 10                        */
-  int32_t tile_rows;     /* fused 2-D tile height (8, 16 or 32); 0 -> 16 (8 for BF16 Potts
-                            with n >= 8); maxflow_tune chooses per problem             */
+  int32_t tile_rows;     /* fused tile height (8, 16 or 32 rows of 64 columns; the fused
+                            3-D sweep tiles 8 rows for 8 and 16 rows for 16 or 32);
+                            0 -> 16, except 8 for BF16 Potts with n >= 8 and for the
+                            BF16 3-D sweep; maxflow_tune chooses per problem          */
   /* Pool only, BF16 storage: a solve whose gap at a check is <= promote_gap,
    * or that reaches iteration promote_iter, is frozen at that iterate and
    * continued with FP32 flows (BF16 rounding floors the reachable gap near
@@ -127,6 +129,10 @@ typedef struct {
    * bit-identical to depth 1.  0 -> 2 where it applies, else 1.  Odd
    * iteration counts finish with one depth-1 sweep. */
   int32_t depth;
+  /* Fused 3-D sweep: planes per z-slab of a workgroup (each slab re-reads
+   * 3 warm-up planes).  0 -> 16 (capped at D); otherwise >= 4.  Never
+   * changes the iterates. */
+  int32_t slab_depth;
 } mf_params;
 
 /* Gap at an iterate.  primal = P(u) at clip(u,0,1) (two-label) or the pointwise
@@ -197,17 +203,18 @@ mf_status maxflow_import_state(mf_solver* s, const void* src, int64_t iter);
 
 mf_status maxflow_destroy(mf_solver* s);
 
-/* Autotuner for the launch shape of the fused 2-D sweep.  Times `sweeps`
+/* Autotuner for the launch shape of the fused sweeps.  Times `sweeps`
  * sweeps (after two warm-up sweeps) for each candidate tile height (8, 16
- * and 32 rows of 64 columns) on the solver's stream with HIP events, keeps
+ * and 32 rows of 64 columns; 8 and 16 for the fused 3-D sweep, whose
+ * entry for 32 reports 0) on the solver's stream with HIP events, keeps
  * the fastest for this solver, and returns it in *best_tile_rows.  Every
  * candidate runs iterate k -> k+1 from the solver's current iterate k
  * without advancing it, so the solver's state and iteration count are
  * unchanged; the tile height never changes the iterates (bit-identical).
  * `us_per_iter` (host, 3 entries, may be null) receives microseconds per
  * iteration for heights 8, 16, 32.  Depth-2 solvers time their two-iteration
- * pass at heights 16 and 32 (8 reports 0).  Solvers without a tile-height choice (3-D,
- * the unfused variant) time their one configuration, report it in the entry
+ * pass at heights 16 and 32 (8 reports 0).  Solvers without a tile-height choice (3-D
+ * Potts, the unfused variant) time their one configuration, report it in the entry
  * of their current height (others 0) and keep it; rPDRQ (in-place sweeps)
  * runs nothing and reports zeros.  Synchronises the stream.  Errors:
  * MF_EINVAL (null solver or best_tile_rows, sweeps < 1 or > 10000),

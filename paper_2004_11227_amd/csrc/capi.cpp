@@ -118,11 +118,14 @@ std::string resolve(const mf_params* in, Resolved& r) {
   if (!(p.tol >= 0.0)) return "tol must be >= 0";
   if (p.check_every == 0) p.check_every = 10;
   if (p.check_every < 1) return "check_every must be >= 1";
-  // default tile height: 16 rows, except 8 for BF16 Potts with n >= 8 (the
-  // measured fastest on gfx950 at 1024^2; maxflow_tune picks per problem)
-  if (p.tile_rows == 0) p.tile_rows = (!two && p.storage == MF_BF16 && p.nlabels >= 8) ? 8 : 16;
+  // default tile height: 16 rows, except 8 for BF16 Potts with n >= 8 and
+  // for the BF16 3-D sweep (the measured fastest on gfx950 at 1024^2 and
+  // 256^3; maxflow_tune picks per problem)
+  if (p.tile_rows == 0)
+    p.tile_rows = (p.storage == MF_BF16 && ((!two && p.nlabels >= 8) || (two && p.ndim == 3))) ? 8 : 16;
   if (p.tile_rows != 8 && p.tile_rows != 16 && p.tile_rows != 32) return "tile_rows must be 8, 16 or 32";
   if (!(p.promote_gap >= 0.0) || p.promote_iter < 0) return "promote_gap and promote_iter must be >= 0";
+  if (p.slab_depth != 0 && p.slab_depth < 4) return "slab_depth must be 0 or >= 4";
   {
     const bool d2ok = two && p.ndim == 2 && p.method != MF_RPDRQ && p.variant == MF_FUSED;
     if (p.depth == 0) p.depth = d2ok ? 2 : 1;
@@ -294,6 +297,7 @@ hipError_t admm_sweep(mf_solver* s, int64_t k, bool check, bool write, const int
   d.check = check;
   d.write = write;
   d.tile_rows = s->r.p.tile_rows;
+  d.slab_depth = s->r.p.slab_depth;
   d.cap = s->cap;
   d.in = s->st[buf_of(s, k)];
   d.out = s->st[buf_of(s, k) ^ 1];
@@ -696,7 +700,9 @@ mf_status maxflow_import_state(mf_solver* s, const void* src, int64_t iter) {
 mf_status maxflow_tune(mf_solver* s, int32_t sweeps, int32_t* best_tile_rows, double* us_per_iter) {
   if (!s || !best_tile_rows) return fail(MF_EINVAL, "null solver or best_tile_rows");
   if (sweeps < 1 || sweeps > 10000) return fail(MF_EINVAL, "sweeps must be in 1..10000");
-  const bool choice = s->r.p.method != MF_RPDRQ && s->r.p.variant == MF_FUSED && s->r.g.ndim == 2;
+  const bool fused = s->r.p.method != MF_RPDRQ && s->r.p.variant == MF_FUSED;
+  const bool d3 = s->r.g.ndim == 3;
+  const bool choice = fused && (!d3 || s->r.p.model == MF_TWO_LABEL);
   const int cand[3] = {8, 16, 32};
   double us[3] = {0.0, 0.0, 0.0};
   if (s->r.p.method == MF_RPDRQ) {   // in-place sweeps, no launch-shape choice: nothing is run
@@ -719,6 +725,7 @@ mf_status maxflow_tune(mf_solver* s, int32_t sweeps, int32_t* best_tile_rows, do
   for (int c = 0; c < 3 && he == hipSuccess; c++) {
     if (!choice && cand[c] != keep) continue;
     if (d2 && cand[c] == 8) continue;
+    if (d3 && choice && cand[c] == 32) continue;   // 3-D tiles are 8 or 16 rows
     s->r.p.tile_rows = cand[c];
     float ms = 0.f;
     // iterate k -> k+1 repeatedly: buffer k & 1 (the current iterate) is

@@ -3,42 +3,26 @@
 
 namespace mf {
 
-template <typename TS, bool CHECK, bool VEC>
+template <typename TS, bool CHECK, bool VEC, int TY>
 __global__ __launch_bounds__(256) void k_fused3d(const K3<TS> A) {
-  __shared__ Smem3<CHECK> S;
+  __shared__ Smem3<CHECK, TY> S;
   if (A.done && *A.done) return;
   const int nxy = A.tiles_x * A.tiles_y;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int slab = tile / nxy;
   const int txy = tile % nxy;
   const int x0 = (txy % A.tiles_x) * 64;
-  const int y0 = (txy / A.tiles_x) * 8;
+  const int y0 = (txy / A.tiles_x) * TY;
   const int z0 = slab * A.tz;
   const int z1 = min(z0 + A.tz, A.D);
   double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  tile3d<TS, CHECK, VEC, CHECK>(A, x0, y0, z0, z1, S, g);
+  tile3d<TS, CHECK, VEC, CHECK, TY>(A, x0, y0, z0, z1, S, g);
   if (CHECK) block_accumulate<5, 4>(g, A.acc, S.sred);
 }
 
-// Workgroups of k_fused3d resident at once on the current device.
-template <typename TS, bool CHECK>
-static long long resident_blocks3(bool vec) {
-  static int cached[2] = {0, 0};
-  int& c = cached[vec ? 1 : 0];
-  if (c == 0) {
-    int per_cu = 0, dev = 0, cus = 0;
-    const void* f = vec ? (const void*)k_fused3d<TS, CHECK, true> : (const void*)k_fused3d<TS, CHECK, false>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-      cus = 256;
-    c = per_cu * cus;
-  }
-  return c;
-}
-
-template <typename TS, bool CHECK>
-static hipError_t fused3d_ts(const SweepDesc& d, hipStream_t s) {
+template <typename TS, bool CHECK, int TY>
+static hipError_t fused3d_ty(const SweepDesc& d, hipStream_t s) {
+  constexpr int V = TY / 4;
   K3<TS> a;
   a.W = d.g.W;
   a.H = d.g.H;
@@ -47,17 +31,14 @@ static hipError_t fused3d_ts(const SweepDesc& d, hipStream_t s) {
   a.P = d.g.plane;
   a.SZ = (long long)d.g.pitch * d.g.H;
   a.tiles_x = (d.g.W + 63) / 64;
-  a.tiles_y = (d.g.H + 7) / 8;
-  // Slab depth: each slab re-reads 3 warm-up planes, so slabs should be
-  // deep, but the grid must fill the chip.  Cut the volume into as many
-  // slabs as make one full wave of resident workgroups (occupancy x CUs):
-  // a partial second wave would run on a fraction of the chip.
+  a.tiles_y = (d.g.H + TY - 1) / TY;
+  // Slab depth: each slab re-reads 3 warm-up planes; 16 planes measured
+  // fastest at 256^3, 128 x 512^2 and 512 x 128 x 256 (slab counts that are
+  // multiples of the 8 XCDs keep each XCD's run of workgroups on whole
+  // slabs, so xy neighbours share its L2).  slab_depth overrides it.
   const long long nxy = (long long)a.tiles_x * a.tiles_y;
-  const long long resident = resident_blocks3<TS, CHECK>(d.g.pitch % 2 == 0);
-  long long nslab = resident / nxy;
-  if (nslab < 1) nslab = 1;
-  int tz = (int)((d.g.D + nslab - 1) / nslab);
-  if (tz < 8) tz = d.g.D < 8 ? d.g.D : 8;
+  int tz = d.slab_depth > 0 ? d.slab_depth : 16;
+  if (tz > d.g.D) tz = d.g.D;
   a.tz = tz;
   a.cap = (const TS*)d.cap;
   a.u_in = d.in.u;
@@ -74,11 +55,17 @@ static hipError_t fused3d_ts(const SweepDesc& d, hipStream_t s) {
   a.write = d.write ? 1 : 0;
   a.iso = d.iso ? 1 : 0;
   const long long nb = nxy * ((d.g.D + tz - 1) / tz);
-  if (d.g.pitch % 2 == 0)
-    hipLaunchKernelGGL((k_fused3d<TS, CHECK, true>), dim3((unsigned)nb), dim3(256), 0, s, a);
+  if (d.g.pitch % V == 0)
+    hipLaunchKernelGGL((k_fused3d<TS, CHECK, true, TY>), dim3((unsigned)nb), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((k_fused3d<TS, CHECK, false>), dim3((unsigned)nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_fused3d<TS, CHECK, false, TY>), dim3((unsigned)nb), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+// xy tile height: 16 rows when tile_rows asks for 16 or more, else 8.
+template <typename TS, bool CHECK>
+static hipError_t fused3d_ts(const SweepDesc& d, hipStream_t s) {
+  return d.tile_rows >= 16 ? fused3d_ty<TS, CHECK, 16>(d, s) : fused3d_ty<TS, CHECK, 8>(d, s);
 }
 
 hipError_t launch_fused3d(const SweepDesc& d, hipStream_t s) {

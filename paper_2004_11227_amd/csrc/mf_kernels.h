@@ -50,6 +50,7 @@ struct SweepDesc {
   bool check;      // accumulate the gap of the input iterate (fused only)
   bool write;      // write the output iterate
   int tile_rows;   // fused 2-D tile height
+  int slab_depth = 0;   // fused 3-D: planes per z-slab (0: one wave of workgroups)
   const void* cap;
   StateView in, out;
   float* wbuf;     // unfused: NL planes of w

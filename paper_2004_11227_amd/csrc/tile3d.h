@@ -57,10 +57,10 @@ __device__ __forceinline__ void proj3r(float& x, float& y, float& z, float alpha
   else proj3<false>(x, y, z, alpha);
 }
 
-template <bool SU>
+template <bool SU, int TY = 8>
 struct Smem3 {
   static constexpr int SW = 64 + 8;   // cols -4 .. 67
-  static constexpr int SH = 8 + 3;    // rows -2 .. 8
+  static constexpr int SH = TY + 3;   // rows -2 .. TY
   __align__(16) float sqx[2][SH][SW];
   __align__(16) float sqy[2][SH][SW];
   __align__(16) float sqz[2][SH][SW];
@@ -78,14 +78,16 @@ struct Plane3 {
   float hqx, hqy, hqz, hu, hp, hps;
 };
 
-// One 64 x 8 tile of the xy plane over the slab [z0, z1).  The global loads
-// of plane s+1 (and the capacities of plane s) are issued at the start of
-// step s, so their latency overlaps the LDS phases of step s.
-template <typename TS, bool CHECK, bool VEC, bool SU>
-__device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, int z1, Smem3<SU>& S,
+// One 64 x TY tile (TY = 8 or 16; V = TY / 4 columns per thread) of the xy
+// plane over the slab [z0, z1).  The global loads of plane s+1 (and the
+// capacities of plane s) are issued at the start of step s, so their latency
+// overlaps the LDS phases of step s.
+template <typename TS, bool CHECK, bool VEC, bool SU, int TY = 8>
+__device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, int z1, Smem3<SU, TY>& S,
                                        double (&g)[5]) {
   static_assert(!CHECK || SU, "the gap needs the u staging array");
-  constexpr int TX = 64, TY = 8, V = 2, TPR = TX / V, OX = 4;
+  static_assert(TY == 8 || TY == 16, "3-D tiles are 64 x 8 or 64 x 16");
+  constexpr int TX = 64, V = TY / 4, TPR = TX / V, OX = 4;
   constexpr int NHQ = 3 * (TX + 3) + 3 * TY;   // q halo: rows -2, -1, TY; cols -2, -1, TX
   constexpr int NHW = 2 * (TX + 2) + 2 * TY;   // w halo: rows -1, TY; cols -1, TX
   static_assert(NHQ <= 256 && NHW <= 256, "one halo entry per thread");

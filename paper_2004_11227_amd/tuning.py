@@ -1,7 +1,7 @@
 """Cache of autotuned launch shapes.
 
 The autotuner itself is native (``maxflow_tune``: it times the candidate
-tile heights of the fused 2-D sweep with HIP events on the solver's stream).
+tile heights of the fused 2-D and 3-D sweeps with HIP events on the solver's stream).
 This module keeps its choices in a JSON file so that a shape class is timed
 once per device: the key is (device name, model, labels, dimensions,
 storage, method, variant, requested depth, log2 of the pixel count), the value the chosen

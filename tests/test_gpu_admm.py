@@ -97,6 +97,31 @@ def test_3d_fused_equals_unfused_bitwise(storage, shape):
                 assert np.array_equal(ref[f], g[f]), f
 
 
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_3d_tile_height_and_slab_depth_bitwise(storage):
+    """The 3-D sweep's launch shape (64 x 8 or 64 x 16 xy tiles, slab depths
+    4 .. more than D) never changes the iterates: every combination gives the
+    unfused passes' bits, on a volume ragged in every axis, across a gap
+    check."""
+    shape = (37, 45, 70)
+    caps = synth.two_label_caps(synth.ellipsoid_volume(*shape, 5, 0.1, 3007))
+    kw = dict(model="two", method="eb", relax=1.5, alpha=0.4, storage=storage, tol=0.0, max_iter=13,
+              check_every=5)
+    s = gpu_solver(caps, variant="unfused", **kw)
+    s.solve()
+    ref = gpu_fields(s)
+    s.close()
+    for rows in (8, 16):
+        for sd in (0, 4, 5, 16, 64):
+            banner(f"3d {storage} tile_rows={rows} slab_depth={sd}")
+            s = gpu_solver(caps, tile_rows=rows, slab_depth=sd, **kw)
+            s.solve()
+            g = gpu_fields(s)
+            s.close()
+            for f in ref:
+                assert np.array_equal(ref[f], g[f]), (rows, sd, f)
+
+
 def test_3d_fused_gap_and_solve():
     banner("3d fused solve")
     caps = synth.two_label_caps(synth.ellipsoid_volume(24, 26, 30, 4, 0.1, 3005)).astype(np.float32).astype(np.float64)
@@ -377,6 +402,17 @@ def test_autotune_keeps_state_and_caches(tmp_path, monkeypatch):
         assert np.array_equal(before[f], after[f]), f
     d.close()
     assert tuning.key(caps.shape[1:], None, **kw) != tuning.key(caps.shape[1:], None, **kw2)
+    # the fused 3-D sweep chooses between 64 x 8 and 64 x 16 xy tiles
+    caps3 = synth.two_label_caps(synth.ellipsoid_volume(40, 48, 70, 4, 0.1, 3008))
+    v = gpu_solver(caps3, model="two", method="eb", relax=1.5, alpha=0.4)
+    v.step(3)
+    before = gpu_fields(v)
+    best, us = v.tune(sweeps=3)
+    assert best in (8, 16) and set(us) == {8, 16} and v.iter == 3
+    after = gpu_fields(v)
+    for f in before:
+        assert np.array_equal(before[f], after[f]), f
+    v.close()
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
