@@ -54,7 +54,8 @@ class _Params(ctypes.Structure):
                 ("nlabels", ctypes.c_int), ("alpha", ctypes.c_double), ("c", ctypes.c_double),
                 ("relax", ctypes.c_double), ("sigma", ctypes.c_double), ("tau", ctypes.c_double),
                 ("a", ctypes.c_double), ("a_tilde", ctypes.c_double), ("a1", ctypes.c_double),
-                ("a2", ctypes.c_double)]
+                ("a2", ctypes.c_double), ("gs_sweeps", ctypes.c_int), ("relax0", ctypes.c_double),
+                ("relax_ramp", ctypes.c_long)]
 
 
 _lib = None
@@ -74,7 +75,9 @@ def _L():
         _lib.or_init.argtypes = [G, PR, P, P, P, P, P]
         _lib.or_admm_iter.argtypes = [G, PR, P, P, P, P, P]
         _lib.or_pdrq_iter.argtypes = [G, PR, P, P, P, P, P, P, P, P]
-        _lib.or_run.argtypes = [G, PR, P, ctypes.c_long, P, P, P, P, P, P, P, P]
+        _lib.or_run.argtypes = [G, PR, P, ctypes.c_long, ctypes.c_long, P, P, P, P, P, P, P, P]
+        _lib.or_rho_at.argtypes = [PR, ctypes.c_long]
+        _lib.or_rho_at.restype = ctypes.c_double
         _lib.or_energy.argtypes = [G, PR, P, P, P, P, P, P]
         _lib.or_labels.argtypes = [G, PR, P, ctypes.POINTER(ctypes.c_int)]
         _lib.or_num_threads.restype = ctypes.c_int
@@ -112,7 +115,10 @@ class Problem:
     (5, 0.4) Potts; ALG1 sigma = 0.4, tau = 1 / (L^2 sigma) with the bound
     L^2 = 4 ndim + 2 (two labels) or 4 ndim + n + 1 (n labels) on |K^* K|.
     Methods: fg (rpADMMI), eb (rpADMMII), dr (rPDRQ), ty (pADMM-TY), cp
-    (ALG1)."""
+    (ALG1).  Preconditioner variants: gs_sweeps symmetric red-black
+    Gauss-Seidel sweeps per rPDRQ iteration (M_n; 0 -> 1); for rpADMMII a
+    non-decreasing relaxation rising linearly from relax0 to relax over
+    relax_ramp iterations (relax0 = 0: constant)."""
     shape: tuple
     model: str = "two"
     method: str = "eb"
@@ -127,6 +133,9 @@ class Problem:
     a_tilde: float = 0.0
     a1: float = 0.0
     a2: float = 0.0
+    gs_sweeps: int = 0
+    relax0: float = 0.0
+    relax_ramp: int = 0
 
     def __post_init__(self):
         self.shape = tuple(int(s) for s in self.shape)
@@ -161,7 +170,12 @@ class Problem:
     def _params(self) -> _Params:
         return _Params(MODELS[self.model], METHODS[self.method], TVS[self.tv], self.nlabels,
                        self.alpha, self.c, self.relax, self.sigma, self.tau, self.a,
-                       self.a_tilde, self.a1, self.a2)
+                       self.a_tilde, self.a1, self.a2, int(self.gs_sweeps), float(self.relax0),
+                       int(self.relax_ramp))
+
+    def rho_at(self, k: int) -> float:
+        """rpADMMII relaxation of the step from iterate k to k+1."""
+        return float(_L().or_rho_at(ctypes.byref(self._params()), int(k)))
 
 
 @dataclass
@@ -231,7 +245,7 @@ def step(prob: Problem, caps, st: State, iters: int = 1) -> State:
         st.ub = st.u.copy()
     ub = st.ub if st.ub is not None else np.zeros(1)
     _L().or_run(ctypes.byref(_grid(prob.shape)), ctypes.byref(prob._params()), _ptr(caps),
-                int(iters), _ptr(st.u), _ptr(st.q), _ptr(st.ps), _ptr(st.p),
+                int(st.iters), int(iters), _ptr(st.u), _ptr(st.q), _ptr(st.ps), _ptr(st.p),
                 _ptr(z), _ptr(zs), _ptr(zp), _ptr(ub))
     st.iters += iters
     return st

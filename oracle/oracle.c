@@ -325,9 +325,13 @@ void or_pdrq_iter(const or_grid* g, const or_params* p, const double* caps,
       b[l * N + i] = bi;
     }
   }
-  /* u^{k+1}: one symmetric red-black GS sweep per label */
+  /* u^{k+1}: gs_sweeps symmetric red-black GS sweeps per label (one sweep is
+   * the sRBGS preconditioner; n sweeps are the preconditioner M_n, n steps of
+   * the preconditioned iteration for T u = b from u^k) */
   const double m = two ? 2.0 : (double)(L + 1);
-  for (int l = 0; l < L; l++) or_rbgs_sweep(g, m, st, b + (size_t)l * N, u + (size_t)l * N);
+  const int nsw = p->gs_sweeps > 1 ? p->gs_sweeps : 1;
+  for (int l = 0; l < L; l++)
+    for (int sw = 0; sw < nsw; sw++) or_rbgs_sweep(g, m, st, b + (size_t)l * N, u + (size_t)l * N);
   /* y^{k+1} = y-bar + tau K u^{k+1}, then the relaxed reflection */
   for (int l = 0; l < L; l++) {
     double* qbl = qb + (size_t)l * d * N;
@@ -465,14 +469,29 @@ void or_cp_iter(const or_grid* g, const or_params* p, const double* caps,
   free(gu); free(dq);
 }
 
-void or_run(const or_grid* g, const or_params* p, const double* caps, long iters,
+/* rho_k of rpADMMII at iteration k (the step from iterate k to k+1): the
+ * relaxation may be any non-decreasing sequence in (0, 2); here either the
+ * constant relax, or a linear rise from relax0 at k = 0 to relax at
+ * k = relax_ramp, constant afterwards. */
+double or_rho_at(const or_params* p, long k) {
+  if (!(p->relax0 > 0.0) || p->relax_ramp <= 0 || k >= p->relax_ramp) return p->relax;
+  return p->relax0 + (p->relax - p->relax0) * ((double)k / (double)p->relax_ramp);
+}
+
+/* Iterations k0 .. k0+iters-1 (k0 = index of the incoming iterate, which
+ * only the rpADMMII relaxation schedule depends on). */
+void or_run(const or_grid* g, const or_params* p, const double* caps, long k0, long iters,
             double* u, double* q, double* ps, double* pp,
             double* zq, double* zs, double* zp, double* ub) {
+  or_params pk = *p;
   for (long k = 0; k < iters; k++) {
     if (p->method == OR_DR) or_pdrq_iter(g, p, caps, u, q, ps, pp, zq, zs, zp);
     else if (p->method == OR_TY) or_ty_iter(g, p, caps, u, q, ps, pp);
     else if (p->method == OR_CP) or_cp_iter(g, p, caps, u, ub, q, ps, pp);
-    else or_admm_iter(g, p, caps, u, q, ps, pp);
+    else {
+      if (p->method == OR_EB) pk.relax = or_rho_at(p, k0 + k);
+      or_admm_iter(g, &pk, caps, u, q, ps, pp);
+    }
   }
 }
 

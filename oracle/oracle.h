@@ -39,11 +39,17 @@ typedef struct {
   int model, method, tv, nlabels;
   double alpha;          /* TV weight                                        */
   double c;              /* ADMM step                                        */
-  double relax;          /* FG: r; EB: rho_k (constant); DR: rho             */
+  double relax;          /* FG: r; EB: rho (constant, or the schedule's end); DR: rho */
   double sigma, tau;     /* rPDRQ / ALG1 step sizes                          */
   double a;              /* q preconditioner N = a c I                       */
   double a_tilde;        /* two-label p preconditioner M = a~ c I_2          */
   double a1, a2;         /* Potts block preconditioner diag(a1 I.., a2 I)    */
+  int gs_sweeps;         /* DR: symmetric red-black GS sweeps per iteration
+                            (the preconditioner M_n; 0 or 1 -> one sweep)   */
+  double relax0;         /* EB: rho_0 of a non-decreasing schedule; 0 -> the
+                            constant rho = relax                             */
+  long relax_ramp;       /* EB: rho_k rises linearly from relax0 to relax over
+                            relax_ramp iterations, then stays at relax      */
 } or_params;
 
 void or_grad(const or_grid* g, const double* f, double* out);
@@ -63,7 +69,8 @@ void or_ty_iter(const or_grid* g, const or_params* p, const double* caps,
                 double* u, double* q, double* ps, double* pp);
 void or_cp_iter(const or_grid* g, const or_params* p, const double* caps,
                 double* u, double* ub, double* q, double* ps, double* pp);
-void or_run(const or_grid* g, const or_params* p, const double* caps, long iters,
+double or_rho_at(const or_params* p, long k);
+void or_run(const or_grid* g, const or_params* p, const double* caps, long k0, long iters,
             double* u, double* q, double* ps, double* pp,
             double* zq, double* zs, double* zp, double* ub);
 void or_energy(const or_grid* g, const or_params* p, const double* caps,
