@@ -133,6 +133,19 @@ typedef struct {
    * 3 warm-up planes).  0 -> 16 (capped at D); otherwise >= 4.  Never
    * changes the iterates. */
   int32_t slab_depth;
+  /* Preconditioner variants (section on rPDRQ; EB scheme's relaxation).
+   * gs_sweeps: symmetric red-black Gauss-Seidel sweeps per rPDRQ iteration,
+   *   i.e. the preconditioner M_n (n steps of the preconditioned iteration
+   *   for T u = b from u^k); 0 -> 1; 1..64; > 1 runs the in-place launches
+   *   and only applies to rPDRQ.
+   * relax0, relax_ramp: rpADMMII only.  relax0 = 0: constant rho = relax.
+   *   Otherwise the non-decreasing sequence rho_k = relax0 + (relax -
+   *   relax0) min(k, relax_ramp) / relax_ramp for the step from iterate k,
+   *   with 0 < relax0 <= relax < 2 and relax_ramp >= 1; depth-2 passes
+   *   start once rho_k is constant (k >= relax_ramp).  Not in the pool. */
+  int32_t gs_sweeps;
+  double relax0;
+  int32_t relax_ramp;
 } mf_params;
 
 /* Gap at an iterate.  primal = P(u) at clip(u,0,1) (two-label) or the pointwise

@@ -126,6 +126,16 @@ std::string resolve(const mf_params* in, Resolved& r) {
   if (p.tile_rows != 8 && p.tile_rows != 16 && p.tile_rows != 32) return "tile_rows must be 8, 16 or 32";
   if (!(p.promote_gap >= 0.0) || p.promote_iter < 0) return "promote_gap and promote_iter must be >= 0";
   if (p.slab_depth != 0 && p.slab_depth < 4) return "slab_depth must be 0 or >= 4";
+  if (p.gs_sweeps == 0) p.gs_sweeps = 1;
+  if (p.gs_sweeps < 1 || p.gs_sweeps > 64) return "gs_sweeps must be in 1..64";
+  if (p.gs_sweeps > 1 && p.method != MF_RPDRQ) return "gs_sweeps applies to rPDRQ";
+  if (p.relax0 != 0.0) {
+    if (p.method != MF_RPADMM_EB) return "a relaxation schedule applies to rpADMMII (eb)";
+    if (!(p.relax0 > 0.0) || !(p.relax0 <= p.relax)) return "relax0 must be in (0, relax]";
+    if (p.relax_ramp < 1) return "relax_ramp must be >= 1";
+  } else if (p.relax_ramp < 0) {
+    return "relax_ramp must be >= 0";
+  }
   {
     const bool d2ok = two && p.ndim == 2 && p.method != MF_RPDRQ && p.variant == MF_FUSED;
     if (p.depth == 0) p.depth = d2ok ? 2 : 1;
@@ -148,9 +158,9 @@ std::string resolve(const mf_params* in, Resolved& r) {
   if (n > (1LL << 34)) return "grid too large";
   // Fused rpADMM sweeps use rows padded to a multiple of 4 elements, so every
   // owned group of a tile is one vector access whatever the width; the
-  // element-wise kernels (unfused passes, rPDRQ) use the dense layout.
+  // element-wise kernels (unfused passes, in-place rPDRQ) use the dense layout.
   const bool padded = p.variant == MF_FUSED && !(p.ndim == 3 && p.model == MF_POTTS) &&
-                      (p.method != MF_RPDRQ || (two && p.ndim == 2));
+                      (p.method != MF_RPDRQ || (two && p.ndim == 2 && p.gs_sweeps == 1));
   r.g.pitch = padded ? (r.g.W + 3) / 4 * 4 : r.g.W;
   r.g.plane = (long long)align_up((size_t)r.g.nstore(), 128);
   r.esz = p.storage == MF_BF16 ? 2 : 4;
@@ -166,7 +176,8 @@ struct Layout {
 // rPDRQ as one tiled pass per iteration (two-label 2-D, fused variant);
 // otherwise three in-place element-wise launches.
 bool dr_fused(const Resolved& r) {
-  return r.p.method == MF_RPDRQ && r.p.variant == MF_FUSED && r.p.model == MF_TWO_LABEL && r.p.ndim == 2;
+  return r.p.method == MF_RPDRQ && r.p.variant == MF_FUSED && r.p.model == MF_TWO_LABEL && r.p.ndim == 2 &&
+         r.p.gs_sweeps == 1;
 }
 
 Layout plan(const Resolved& r) {
@@ -256,15 +267,26 @@ struct mf_solver {
 
 namespace {
 
-Coef coef_of(const Resolved& r) {
+// rpADMMII relaxation of the step from iterate k: the constant relax, or
+// the linear rise from relax0 (k = 0) to relax (k >= relax_ramp).
+double rho_at(const mf_params& p, int64_t k) {
+  if (p.relax0 == 0.0 || k >= p.relax_ramp) return p.relax;
+  return p.relax0 + (p.relax - p.relax0) * ((double)k / (double)p.relax_ramp);
+}
+
+// Iterations k and k+1 share their coefficients (a depth-2 pass applies).
+bool same_coef(const mf_params& p, int64_t k) { return p.relax0 == 0.0 || k >= p.relax_ramp; }
+
+Coef coef_of(const Resolved& r, int64_t it) {
   const mf_params& p = r.p;
   Coef k;
   k.alpha = (float)p.alpha;
   k.inv_c = (float)(1.0 / p.c);
   k.c = (float)p.c;
   const bool eb = p.method == MF_RPADMM_EB;
-  k.rho = eb ? (float)p.relax : 1.f;
-  k.omr = eb ? (float)(1.0 - p.relax) : 0.f;
+  const double rho = eb ? rho_at(p, it) : 1.0;
+  k.rho = (float)rho;
+  k.omr = (float)(1.0 - rho);
   k.ku = eb ? (float)p.c : (float)(p.relax * p.c);
   k.inv_a = (float)(1.0 / p.a);
   if (p.model == MF_TWO_LABEL) {
@@ -302,7 +324,7 @@ hipError_t admm_sweep(mf_solver* s, int64_t k, bool check, bool write, const int
   d.in = s->st[buf_of(s, k)];
   d.out = s->st[buf_of(s, k) ^ 1];
   d.wbuf = s->wbuf;
-  d.k = coef_of(s->r);
+  d.k = coef_of(s->r, k);
   d.acc = &s->ctrl->acc[0][0];
   d.done = done;
   d.scheme = s->r.p.method == MF_PADMM_TY ? 1 : (s->r.p.method == MF_CP_ALG1 ? 2 : 0);
@@ -330,7 +352,7 @@ hipError_t admm_pass2(mf_solver* s, int64_t k, bool check, const int* done, bool
   d.in = s->st[buf_of(s, k)];
   d.out = s->st[buf_of(s, k) ^ 1];
   d.wbuf = s->wbuf;
-  d.k = coef_of(s->r);
+  d.k = coef_of(s->r, k);
   d.acc = &s->ctrl->acc[0][0];
   d.done = done;
   const hipError_t e = launch_fused2d_d2(d, s->stream);
@@ -358,6 +380,7 @@ hipError_t dr_iter(mf_solver* s, int64_t k, bool keep_z, const int* done) {
   d.inv_st = (float)(1.0 / (s->r.p.sigma * s->r.p.tau));
   d.alpha = (float)s->r.p.alpha;
   d.keep_z = keep_z;
+  d.sweeps = s->r.p.gs_sweeps;
   d.done = done;
   return launch_pdrq_iter(d, s->stream);
 }
@@ -504,7 +527,7 @@ mf_status maxflow_step(mf_solver* s, int32_t iters) {
   for (int32_t i = 0; i < iters;) {
     if (s->r.p.method == MF_RPDRQ) {
       HIP_TRY(dr_iter(s, s->iter, i == iters - 1, nullptr));
-    } else if (d2 && iters - i >= 2) {
+    } else if (d2 && iters - i >= 2 && same_coef(s->r.p, s->iter)) {
       HIP_TRY(admm_pass2(s, s->iter, false, nullptr));
       s->iter += 1;
       i += 1;
@@ -556,7 +579,7 @@ mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
     if (dr) {
       HIP_TRY(gap_of(s, k, done));
     } else if (fused_gap(s)) {
-      if (d2 && n >= 2) {
+      if (d2 && n >= 2 && same_coef(p, k)) {
         HIP_TRY(admm_pass2(s, k, true, done));
         j = 2;
       } else {
@@ -573,7 +596,7 @@ mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
       for (int64_t i = 0; i < n; i++) HIP_TRY(dr_iter(s, k + i, i == n - 1, done));
     } else {
       while (j < n) {
-        if (d2 && n - j >= 2) {
+        if (d2 && n - j >= 2 && same_coef(p, k + j)) {
           HIP_TRY(admm_pass2(s, k + j, false, done));
           j += 2;
         } else {

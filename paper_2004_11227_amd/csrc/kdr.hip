@@ -1,6 +1,7 @@
 // rPDRQ: relaxed, preconditioned Douglas-Rachford with one symmetric
 // red-black Gauss-Seidel sweep as preconditioner (eq. iteration:quadratic:seg
-// for two labels, eq. pdrq:4labels for n labels with T_0 of Lemma 1).
+// for two labels, eq. pdrq:4labels for n labels with T_0 of Lemma 1), or n
+// sweeps (the preconditioner M_n: n preconditioned steps for T u = b).
 //
 // The u-step u^{k+1} = u^k + M^{-1}(b^k - st T u^k), M the symmetric GS
 // matrix of st T = st(-Delta + m I) in red-black order, is one in-place
@@ -10,6 +11,7 @@
 // update of the other colour, so an iteration is three launches:
 //   R1 : b^k at every cell (-> b planes), red cells updated in place
 //   B  : black cells updated in place
+//   (n sweeps: then n - 1 more red, black pairs of half-sweep launches)
 //   R2F: red cells recomputed from the final black cells (every thread that
 //        needs a red value computes it, so red values are never read from
 //        memory in this launch), red u written in place, then the flows
@@ -159,12 +161,14 @@ __global__ __launch_bounds__(256) void k_dr_r1(const KD<TS> A) {
   }
 }
 
-template <int NL, int NDIM, typename TS>
-__global__ __launch_bounds__(256) void k_dr_b(const KD<TS> A) {
+// Half-sweep over the cells of one colour (RED: the red cells, else the
+// black ones), in place.
+template <int NL, int NDIM, typename TS, bool RED>
+__global__ __launch_bounds__(256) void k_dr_half(const KD<TS> A) {
   if (A.done && *A.done) return;
   for (long long idx = blockIdx.x * 256LL + threadIdx.x; idx < A.n; idx += (long long)gridDim.x * 256) {
     const Cell c = cell_of<NDIM>(idx, A.W, A.H);
-    if (is_red(c)) continue;
+    if (is_red(c) != RED) continue;
 #pragma unroll
     for (int l = 0; l < NL; l++) {
       float* ul = A.u + (long long)l * A.P;
@@ -283,8 +287,14 @@ static hipError_t dr_nl(const PdrqDesc& d, hipStream_t s) {
   a.done = d.done;
   long long nb = (a.n + 255) / 256;
   if (nb > 16384) nb = 16384;
+  // sweeps symmetric sweeps = red, black, (red, black) x (sweeps - 1), red:
+  // a red half-sweep right after a red one would repeat it exactly
   hipLaunchKernelGGL((k_dr_r1<NL, TWO, NDIM, TS>), dim3((int)nb), dim3(256), 0, s, a);
-  hipLaunchKernelGGL((k_dr_b<NL, NDIM, TS>), dim3((int)nb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_dr_half<NL, NDIM, TS, false>), dim3((int)nb), dim3(256), 0, s, a);
+  for (int sw = 1; sw < d.sweeps; sw++) {
+    hipLaunchKernelGGL((k_dr_half<NL, NDIM, TS, true>), dim3((int)nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_dr_half<NL, NDIM, TS, false>), dim3((int)nb), dim3(256), 0, s, a);
+  }
   hipLaunchKernelGGL((k_dr_r2f<NL, TWO, NDIM, TS>), dim3((int)nb), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -302,8 +312,9 @@ static hipError_t dr_ts(const PdrqDesc& d, hipStream_t s) {
 }
 
 hipError_t launch_pdrq_iter(const PdrqDesc& d, hipStream_t s) {
+  if (d.sweeps < 1) return hipErrorInvalidValue;
   if (d.fused) {
-    if (!d.two || d.g.ndim != 2 || d.g.pitch % 4 != 0) return hipErrorInvalidValue;
+    if (!d.two || d.g.ndim != 2 || d.g.pitch % 4 != 0 || d.sweeps != 1) return hipErrorInvalidValue;
     return d.bf16 ? dr_fused_ts<bf16_t>(d, s) : dr_fused_ts<float>(d, s);
   }
   if (d.g.pitch != d.g.W) return hipErrorInvalidValue;   // element-wise sweeps use the dense layout

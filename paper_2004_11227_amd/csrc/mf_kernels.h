@@ -84,6 +84,7 @@ struct PdrqDesc {
   bool keep_z;
   bool fused;          // one tiled pass (two-label 2-D, padded rows, tile_rows 16 or 32)
   int tile_rows;
+  int sweeps = 1;      // symmetric red-black GS sweeps (in-place launches; the fused pass runs 1)
   const int* done;
 };
 

@@ -56,6 +56,7 @@ std::string plan_solve(const mf_params* in, Footprint& f) {
   std::string e = resolve_params(in, f.p, f.g, f.nl, f.ncap);
   if (!e.empty()) return e;
   if (f.p.method != MF_RPADMM_FG && f.p.method != MF_RPADMM_EB) return "the pool runs the rpADMM methods (fg, eb)";
+  if (f.p.relax0 != 0.0) return "the pool runs a constant relaxation (relax0 = 0)";
   if (f.g.ndim == 3 && f.p.model != MF_TWO_LABEL) return "the pool runs 3-D solves of the two-label model only";
   if (f.g.ndim == 3) {
     f.model = 5;

@@ -41,7 +41,8 @@ class mf_params(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("check_every", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("promote_gap", ctypes.c_double), ("promote_iter", ctypes.c_int32), ("depth", ctypes.c_int32),
-                ("slab_depth", ctypes.c_int32)]
+                ("slab_depth", ctypes.c_int32), ("gs_sweeps", ctypes.c_int32), ("relax0", ctypes.c_double),
+                ("relax_ramp", ctypes.c_int32)]
 
 
 class mf_gap(ctypes.Structure):
@@ -115,7 +116,8 @@ def _check(status, allow=(MF_OK,)):
 def make_params(shape, model="two", method="eb", tv="iso", storage="f32", variant="fused",
                 nlabels=2, alpha=0.5, c=0.0, relax=0.0, sigma=0.0, tau=0.0, a=0.0, a_tilde=0.0,
                 a1=0.0, a2=0.0, max_iter=1000, tol=1e-4, check_every=10, tile_rows=0,
-                promote_gap=0.0, promote_iter=0, depth=0, slab_depth=0) -> mf_params:
+                promote_gap=0.0, promote_iter=0, depth=0, slab_depth=0, gs_sweeps=0, relax0=0.0,
+                relax_ramp=0) -> mf_params:
     shape = tuple(int(s) for s in shape)
     p = mf_params()
     p.ndim = len(shape)
@@ -133,6 +135,7 @@ def make_params(shape, model="two", method="eb", tv="iso", storage="f32", varian
     p.promote_gap, p.promote_iter = float(promote_gap), int(promote_iter)
     p.depth = int(depth)
     p.slab_depth = int(slab_depth)
+    p.gs_sweeps, p.relax0, p.relax_ramp = int(gs_sweeps), float(relax0), int(relax_ramp)
     return p
 
 

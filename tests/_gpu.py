@@ -33,7 +33,10 @@ def oracle_problem(shape, kw) -> oracle.Problem:
     return oracle.Problem(shape, model=kw.get("model", "two"), method=kw.get("method", "eb"),
                           tv=kw.get("tv", "iso"), nlabels=kw.get("nlabels", 2),
                           alpha=kw.get("alpha", 0.5), c=kw.get("c", 0.0), relax=kw.get("relax", 0.0),
-                          sigma=kw.get("sigma", 0.0), tau=kw.get("tau", 0.0))
+                          sigma=kw.get("sigma", 0.0), tau=kw.get("tau", 0.0), a=kw.get("a", 0.0),
+                          a_tilde=kw.get("a_tilde", 0.0), a1=kw.get("a1", 0.0), a2=kw.get("a2", 0.0),
+                          gs_sweeps=kw.get("gs_sweeps", 0), relax0=kw.get("relax0", 0.0),
+                          relax_ramp=kw.get("relax_ramp", 0))
 
 
 def gpu_fields(s) -> dict:

@@ -80,3 +80,30 @@ def test_workspace_layout_reserves_every_region(shape):
     # unfused rpADMM: dense planes, two state buffers and one FP32 scratch plane
     assert ws(method="eb", variant="unfused") - ws(method="eb", variant="fused") == \
         (al(8 * Pd) - al(8 * P)) + 2 * (state_dense - state_pad) + al(4 * Pd)
+
+
+@pytest.mark.parametrize("bad", [dict(method="eb", gs_sweeps=2), dict(method="dr", gs_sweeps=65),
+                                 dict(method="fg", relax0=0.5, relax_ramp=5),
+                                 dict(method="eb", relax=1.5, relax0=1.6, relax_ramp=5),
+                                 dict(method="eb", relax0=0.5, relax_ramp=0)])
+def test_invalid_preconditioner_variants_rejected(bad):
+    from paper_2004_11227_amd import maxflow as mfx
+    with pytest.raises(mfx.MaxflowError):
+        mfx.workspace_bytes(mfx.make_params((16, 16), **bad))
+
+
+def test_valid_preconditioner_variants_accepted():
+    from paper_2004_11227_amd import maxflow as mfx
+    for kw in (dict(method="dr", gs_sweeps=4), dict(method="eb", relax=1.9, relax0=0.5, relax_ramp=10),
+               dict(method="eb", relax0=1.9, relax_ramp=1)):
+        assert mfx.workspace_bytes(mfx.make_params((16, 16), **kw)) > 0
+
+
+def test_pdrq_layout_follows_the_sweep_count():
+    """The fused rPDRQ pass (one sweep) keeps two state buffers with rows
+    padded to a multiple of 4; the in-place launches of M_n (n > 1) keep one
+    dense state, so their workspace is smaller."""
+    from paper_2004_11227_amd import maxflow as mfx
+    one = mfx.workspace_bytes(mfx.make_params((64, 1001), method="dr", gs_sweeps=1))
+    two = mfx.workspace_bytes(mfx.make_params((64, 1001), method="dr", gs_sweeps=2))
+    assert two < one
