@@ -92,6 +92,9 @@ typedef enum { MF_F32 = 0, MF_BF16 = 1 } mf_storage;
 /* MF_FUSED: one kernel per iteration (LDS tile with halo).  MF_UNFUSED: the
  * baseline, one kernel per operator; bitwise identical results. */
 typedef enum { MF_FUSED = 0, MF_UNFUSED = 1 } mf_variant;
+/* Where the capacities come from: stored planes, or one image plane and a
+ * level per label (see cap_source below). */
+typedef enum { MF_CAPS_PLANES = 0, MF_CAPS_IMAGE = 1 } mf_cap_source;
 
 typedef struct {
   int32_t ndim;          /* 2 or 3                                                    */
@@ -146,6 +149,18 @@ typedef struct {
   int32_t gs_sweeps;
   double relax0;
   int32_t relax_ramp;
+  /* Capacity source (the data costs C_s, C_t or rho(l_i, x) = C_i of the
+   * problem statement, eqs. seg:chanvese and potts-model).
+   * MF_CAPS_PLANES: `cap` of maxflow_create holds the capacity planes.
+   * MF_CAPS_IMAGE: `cap` holds one image plane I on the same grid, and the
+   *   capacities are C_k(x) = |I(x) - levels[k]|^cap_power, evaluated in FP32
+   *   wherever they are used (two-label: C_s from levels[0], C_t from
+   *   levels[1]; Potts: C_1..C_n from levels[0..n-1]).  The workspace holds
+   *   the one image plane (BF16 with BF16 storage) instead of 2 or n planes,
+   *   and every sweep reads it once per pixel.  Not in the pool. */
+  int32_t cap_source;    /* mf_cap_source                                            */
+  int32_t cap_power;     /* 1 or 2; 0 -> 2                                           */
+  double levels[8];      /* finite                                                    */
 } mf_params;
 
 /* Gap at an iterate.  primal = P(u) at clip(u,0,1) (two-label) or the pointwise
@@ -166,8 +181,8 @@ typedef struct mf_solver mf_solver;
 size_t maxflow_workspace_bytes(const mf_params* p);
 
 /* Validate p, lay out the workspace, copy the capacities (device, FP32,
- * TWO_LABEL: planes [C_s, C_t]; POTTS: planes [C_1..C_n]) into it, converting
- * to BF16 if requested, and set the initial point (q = 0, u = 0, source and
+ * TWO_LABEL: planes [C_s, C_t]; POTTS: planes [C_1..C_n]; with
+ * MF_CAPS_IMAGE the one image plane) into it, converting to BF16 if requested, and set the initial point (q = 0, u = 0, source and
  * sink flows at the pointwise minimum capacity).  The caller may free `cap`
  * once this returns.  `workspace` (device, >= maxflow_workspace_bytes(p)
  * bytes, 256-byte aligned) must outlive the solver.  `hip_stream` is a

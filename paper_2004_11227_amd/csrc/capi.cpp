@@ -55,7 +55,9 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Resolved {
   mf_params p;
   int nl;         // labels carried (1 two-label, n Potts)
-  int ncap;       // capacity planes
+  int ncap;       // capacities per pixel (2 two-label, n Potts)
+  int ncp;        // capacity planes stored: ncap, or 1 (the image)
+  CapGen cg;      // image-generated capacities
   Geom g;
   size_t esz;     // bytes per flow / capacity element
   int nq;         // q planes per state
@@ -144,6 +146,18 @@ std::string resolve(const mf_params* in, Resolved& r) {
   }
   r.nl = two ? 1 : p.nlabels;
   r.ncap = two ? 2 : p.nlabels;
+  if (p.cap_source != MF_CAPS_PLANES && p.cap_source != MF_CAPS_IMAGE) return "unknown cap_source";
+  if (p.cap_power == 0) p.cap_power = 2;
+  if (p.cap_power != 1 && p.cap_power != 2) return "cap_power must be 1 or 2";
+  r.cg = CapGen{};
+  if (p.cap_source == MF_CAPS_IMAGE) {
+    for (int i = 0; i < r.ncap; i++)
+      if (!std::isfinite(p.levels[i])) return "levels must be finite";
+    r.cg.img = 1;
+    r.cg.pw = p.cap_power;
+    for (int i = 0; i < 8; i++) r.cg.lv[i] = i < r.ncap ? (float)p.levels[i] : 0.f;
+  }
+  r.ncp = r.cg.img ? 1 : r.ncap;
   r.g.ndim = p.ndim;
   if (p.ndim == 2) {
     r.g.H = (int)p.shape[0];
@@ -187,7 +201,7 @@ Layout plan(const Resolved& r) {
   L.ctrl = off;
   off = align_up(off + sizeof(Ctrl), 256);
   L.cap = off;
-  off = align_up(off + (size_t)r.ncap * P * r.esz, 256);
+  off = align_up(off + (size_t)r.ncp * P * r.esz, 256);
   // state: u (nl f32) + q (nq) + ps (1) + p (nl) in storage type
   L.state_bytes = align_up((size_t)r.nl * P * 4, 256) + align_up((size_t)r.nq * P * r.esz, 256) +
                   align_up(P * r.esz, 256) + align_up((size_t)r.nl * P * r.esz, 256);
@@ -330,6 +344,7 @@ hipError_t admm_sweep(mf_solver* s, int64_t k, bool check, bool write, const int
   d.scheme = s->r.p.method == MF_PADMM_TY ? 1 : (s->r.p.method == MF_CP_ALG1 ? 2 : 0);
   d.sigma = (float)s->r.p.sigma;
   d.tau = (float)s->r.p.tau;
+  d.cg = s->r.cg;
   // Potts 3-D has no fused pass: it always runs the per-operator kernels
   if (s->r.p.variant == MF_UNFUSED || (s->r.g.ndim == 3 && s->r.p.model == MF_POTTS))
     return launch_unfused(d, s->stream);
@@ -353,6 +368,7 @@ hipError_t admm_pass2(mf_solver* s, int64_t k, bool check, const int* done, bool
   d.out = s->st[buf_of(s, k) ^ 1];
   d.wbuf = s->wbuf;
   d.k = coef_of(s->r, k);
+  d.cg = s->r.cg;
   d.acc = &s->ctrl->acc[0][0];
   d.done = done;
   const hipError_t e = launch_fused2d_d2(d, s->stream);
@@ -382,6 +398,7 @@ hipError_t dr_iter(mf_solver* s, int64_t k, bool keep_z, const int* done) {
   d.keep_z = keep_z;
   d.sweeps = s->r.p.gs_sweeps;
   d.done = done;
+  d.cg = s->r.cg;
   return launch_pdrq_iter(d, s->stream);
 }
 
@@ -402,6 +419,7 @@ hipError_t gap_of(mf_solver* s, int64_t k, const int* done) {
   }
   d.acc = &s->ctrl->acc[0][0];
   d.done = done;
+  d.cg = s->r.cg;
   return launch_gap(d, s->stream);
 }
 
@@ -409,14 +427,14 @@ long long nres(const mf_solver* s) { return s->r.g.npix() * s->r.nl; }
 
 mf_status init_state(mf_solver* s) {
   HIP_TRY(launch_init(s->r.g, s->r.nl, s->r.p.model == MF_TWO_LABEL, s->r.p.storage == MF_BF16, s->cap,
-                      s->st[0], s->stream));
+                      s->r.cg, s->st[0], s->stream));
   if (s->r.p.method == MF_RPDRQ) {
     if (s->L.wbuf_bytes < (size_t)s->r.nl * (size_t)s->r.g.plane * 4)
       return fail(MF_EDEVICE, "internal: rPDRQ layout without its scratch planes");
     StateView z = s->z;
     // resolvent outputs of "iteration 0" := the initial flows
     HIP_TRY(launch_init(s->r.g, s->r.nl, s->r.p.model == MF_TWO_LABEL, s->r.p.storage == MF_BF16, s->cap,
-                        StateView{s->wbuf, z.q, z.ps, z.p}, s->stream));
+                        s->r.cg, StateView{s->wbuf, z.q, z.ps, z.p}, s->stream));
   }
   if (s->r.p.method == MF_CP_ALG1)   // u-bar^0 = u^0 = 0
     HIP_TRY(hipMemsetAsync(s->st[0].ub, 0, (size_t)s->r.nl * (size_t)s->r.g.plane * 4, s->stream));
@@ -494,7 +512,7 @@ mf_status maxflow_create(const mf_params* p, const float* cap, void* workspace, 
     }
   }
   hipError_t he = launch_pitch_copy(cap, false, r.g.npix(), r.g.W, s->cap, r.p.storage == MF_BF16, r.g.plane,
-                                    r.g.pitch, r.g.W, (long long)r.g.H * r.g.D, r.ncap, s->stream);
+                                    r.g.pitch, r.g.W, (long long)r.g.H * r.g.D, r.ncp, s->stream);
   if (he != hipSuccess) {
     maxflow_destroy(s);
     return fail(MF_EDEVICE, std::string("capacity copy: ") + hipGetErrorString(he));

@@ -18,6 +18,7 @@ struct KG {
   double* acc;
   const int* done;
   int iso;
+  CapGen cg;          // cg.img: `cap` is one image plane
 };
 
 __device__ __forceinline__ double clip01(float v) { return fmin(1.0, fmax(0.0, (double)v)); }
@@ -45,7 +46,7 @@ __device__ __forceinline__ void gap_px(const KG<TS>& A, long long idx, int x, in
     dq[l] = d;
   }
   if (TWO) {
-    const double Cs = (double)ld(A.cap, idx), Ct = (double)ld(A.cap + A.P, idx);
+    const double Cs = (double)cap_ld(A.cap, A.P, 0, idx, A.cg), Ct = (double)cap_ld(A.cap, A.P, 1, idx, A.cg);
     const double u0 = clip01(A.u[idx]);
     const double gx = hx ? clip01(ldz(A.u, idx + 1, hx)) - u0 : 0.0;
     const double gy = hy ? clip01(ldz(A.u, idx + sy, hy)) - u0 : 0.0;
@@ -74,7 +75,7 @@ __device__ __forceinline__ void gap_px(const KG<TS>& A, long long idx, int x, in
     double mn = 1e300;
 #pragma unroll
     for (int l = 0; l < NL; l++) {
-      const double C = (double)ld(A.cap + (long long)l * A.P, idx);
+      const double C = (double)cap_ld(A.cap, A.P, l, idx, A.cg);
       g[0] += w0[l] * C;
       const double gx = hx ? wx[l] - w0[l] : 0.0;
       const double gy = hy ? wy[l] - w0[l] : 0.0;

@@ -5,7 +5,7 @@
 
 namespace mf {
 
-template <int NL, bool TWO, typename TS, bool CHECK, int TY, bool VEC>
+template <int NL, bool TWO, typename TS, bool CHECK, int TY, bool IMG>
 __global__ __launch_bounds__(256) void k_fused2d(const K2<TS> A) {
   __shared__ Smem2<TY, CHECK> S;
   if (A.done && *A.done) return;
@@ -13,11 +13,11 @@ __global__ __launch_bounds__(256) void k_fused2d(const K2<TS> A) {
   const int x0 = (tile % A.tiles_x) * 64;
   const int y0 = (tile / A.tiles_x) * TY;
   double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  tile2d<NL, TWO, TS, CHECK, TY, VEC, CHECK>(A, x0, y0, S, g);
+  tile2d<NL, TWO, TS, CHECK, TY, true, CHECK, IMG>(A, x0, y0, S, g);
   if (CHECK) block_accumulate<5, 4>(g, A.acc, S.sred);
 }
 
-template <typename TS, bool CHECK, int TY>
+template <typename TS, bool CHECK, int TY, bool IMG>
 __global__ __launch_bounds__(256) void k_fused2d_d2(const K2<TS> A) {
   __shared__ Smem2d2<TY> S;
   if (A.done && *A.done) return;
@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void k_fused2d_d2(const K2<TS> A) {
   const int x0 = (tile % A.tiles_x) * 64;
   const int y0 = (tile / A.tiles_x) * TY;
   double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  tile2d_d2<TS, CHECK, TY>(A, x0, y0, S, g);
+  tile2d_d2<TS, CHECK, TY, IMG>(A, x0, y0, S, g);
   if (CHECK) block_accumulate<5, 4>(g, A.acc, S.sred);
 }
 
@@ -49,6 +49,7 @@ static K2<TS> make_k2(const SweepDesc& d) {
   a.p_out = (TS*)d.out.p;
   a.wbuf = d.wbuf;
   a.k = d.k;
+  a.cg = d.cg;
   a.acc = d.acc;
   a.done = d.done;
   a.write = d.write ? 1 : 0;
@@ -56,11 +57,13 @@ static K2<TS> make_k2(const SweepDesc& d) {
   return a;
 }
 
+// Rows are padded to a multiple of 4 elements, so every owned group is one
+// vector access.
 template <int NL, bool TWO, typename TS, bool CHECK, int TY>
 static hipError_t fused_launch(const K2<TS>& a, int H, hipStream_t s) {
-  constexpr int V = TY >= 16 ? 4 : 2;
   const int nb = a.tiles_x * ((H + TY - 1) / TY);
-  if (a.pitch % V == 0)
+  if (a.pitch % 4 != 0) return hipErrorInvalidValue;
+  if (a.cg.img)
     hipLaunchKernelGGL((k_fused2d<NL, TWO, TS, CHECK, TY, true>), dim3(nb), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((k_fused2d<NL, TWO, TS, CHECK, TY, false>), dim3(nb), dim3(256), 0, s, a);
@@ -101,17 +104,22 @@ hipError_t launch_fused2d(const SweepDesc& d, hipStream_t s) {
   return d.bf16 ? fused_ts<bf16_t>(d, s) : fused_ts<float>(d, s);
 }
 
+template <typename TS, bool CHECK, bool IMG>
+static hipError_t fused_d2_img(const K2<TS>& a, const SweepDesc& d, hipStream_t s) {
+  if (d.tile_rows == 32) {
+    const int nb = a.tiles_x * ((d.g.H + 31) / 32);
+    hipLaunchKernelGGL((k_fused2d_d2<TS, CHECK, 32, IMG>), dim3(nb), dim3(256), 0, s, a);
+  } else {
+    const int nb = a.tiles_x * ((d.g.H + 15) / 16);
+    hipLaunchKernelGGL((k_fused2d_d2<TS, CHECK, 16, IMG>), dim3(nb), dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
 template <typename TS, bool CHECK>
 static hipError_t fused_d2_ts(const SweepDesc& d, hipStream_t s) {
   const K2<TS> a = make_k2<TS>(d);
-  if (d.tile_rows == 32) {
-    const int nb = a.tiles_x * ((d.g.H + 31) / 32);
-    hipLaunchKernelGGL((k_fused2d_d2<TS, CHECK, 32>), dim3(nb), dim3(256), 0, s, a);
-  } else {
-    const int nb = a.tiles_x * ((d.g.H + 15) / 16);
-    hipLaunchKernelGGL((k_fused2d_d2<TS, CHECK, 16>), dim3(nb), dim3(256), 0, s, a);
-  }
-  return hipGetLastError();
+  return d.cg.img ? fused_d2_img<TS, CHECK, true>(a, d, s) : fused_d2_img<TS, CHECK, false>(a, d, s);
 }
 
 // Two iterations (d.in = iterate k, d.out = iterate k+2) of the two-label 2-D

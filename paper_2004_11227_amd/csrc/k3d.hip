@@ -3,7 +3,7 @@
 
 namespace mf {
 
-template <typename TS, bool CHECK, bool VEC, int TY>
+template <typename TS, bool CHECK, int TY, bool IMG>
 __global__ __launch_bounds__(256) void k_fused3d(const K3<TS> A) {
   __shared__ Smem3<CHECK, TY> S;
   if (A.done && *A.done) return;
@@ -16,13 +16,15 @@ __global__ __launch_bounds__(256) void k_fused3d(const K3<TS> A) {
   const int z0 = slab * A.tz;
   const int z1 = min(z0 + A.tz, A.D);
   double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  tile3d<TS, CHECK, VEC, CHECK, TY>(A, x0, y0, z0, z1, S, g);
+  tile3d<TS, CHECK, true, CHECK, TY, IMG>(A, x0, y0, z0, z1, S, g);
   if (CHECK) block_accumulate<5, 4>(g, A.acc, S.sred);
 }
 
+// Rows are padded to a multiple of 4 elements, so every owned group is one
+// vector access.
 template <typename TS, bool CHECK, int TY>
 static hipError_t fused3d_ty(const SweepDesc& d, hipStream_t s) {
-  constexpr int V = TY / 4;
+  if (d.g.pitch % 4 != 0) return hipErrorInvalidValue;
   K3<TS> a;
   a.W = d.g.W;
   a.H = d.g.H;
@@ -50,15 +52,16 @@ static hipError_t fused3d_ty(const SweepDesc& d, hipStream_t s) {
   a.p_in = (const TS*)d.in.p;
   a.p_out = (TS*)d.out.p;
   a.k = d.k;
+  a.cg = d.cg;
   a.acc = d.acc;
   a.done = d.done;
   a.write = d.write ? 1 : 0;
   a.iso = d.iso ? 1 : 0;
   const long long nb = nxy * ((d.g.D + tz - 1) / tz);
-  if (d.g.pitch % V == 0)
-    hipLaunchKernelGGL((k_fused3d<TS, CHECK, true, TY>), dim3((unsigned)nb), dim3(256), 0, s, a);
+  if (d.cg.img)
+    hipLaunchKernelGGL((k_fused3d<TS, CHECK, TY, true>), dim3((unsigned)nb), dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((k_fused3d<TS, CHECK, false, TY>), dim3((unsigned)nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_fused3d<TS, CHECK, TY, false>), dim3((unsigned)nb), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

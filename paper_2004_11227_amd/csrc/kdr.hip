@@ -65,6 +65,7 @@ static hipError_t dr_fused_ts(const PdrqDesc& d, hipStream_t s) {
   a.iso = d.iso ? 1 : 0;
   a.keep_z = d.keep_z ? 1 : 0;
   a.done = d.done;
+  a.cg = d.cg;
   if (d.tile_rows == 32) {
     hipLaunchKernelGGL((k_dr_fused2d<TS, 32>), dim3(a.tiles_x * ((d.g.H + 31) / 32)), dim3(256), 0, s, a);
   } else {
@@ -89,6 +90,7 @@ struct KD {
   float sigma, tau, rho, inv_st, alpha, m;
   int iso, keep_z;
   const int* done;
+  CapGen cg;            // cg.img: `cap` is one image plane
 };
 
 struct Cell {
@@ -241,7 +243,7 @@ __global__ __launch_bounds__(256) void k_dr_r2f(const KD<TS> A) {
       TS* pbl = A.pb + (long long)l * A.P;
       const float pbv = ld(pbl, idx);
       const float pv = pbv + tau * u0;
-      const float zpv = fminf(ld(A.cap + (long long)(TWO ? 1 : l) * A.P, idx), 2.f * pv - pbv);
+      const float zpv = fminf(cap_ld(A.cap, A.P, TWO ? 1 : l, idx, A.cg), 2.f * pv - pbv);
       st(pbl, idx, pbv + rho * (zpv - pv));
       if (A.keep_z) st(A.zp + (long long)l * A.P, idx, zpv);
     }
@@ -249,7 +251,7 @@ __global__ __launch_bounds__(256) void k_dr_r2f(const KD<TS> A) {
     const float psbv = ld(A.psb, idx);
     const float psv = psbv - tau * usum;
     float zsv = (2.f * psv - psbv) + tau;
-    if (TWO) zsv = fminf(ld(A.cap, idx), zsv);
+    if (TWO) zsv = fminf(cap_ld(A.cap, A.P, 0, idx, A.cg), zsv);
     st(A.psb, idx, psbv + rho * (zsv - psv));
     if (A.keep_z) st(A.zs, idx, zsv);
     if (is_red(c)) {
@@ -285,6 +287,7 @@ static hipError_t dr_nl(const PdrqDesc& d, hipStream_t s) {
   a.iso = d.iso ? 1 : 0;
   a.keep_z = d.keep_z ? 1 : 0;
   a.done = d.done;
+  a.cg = d.cg;
   long long nb = (a.n + 255) / 256;
   if (nb > 16384) nb = 16384;
   // sweeps symmetric sweeps = red, black, (red, black) x (sweeps - 1), red:

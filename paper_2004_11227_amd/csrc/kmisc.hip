@@ -46,6 +46,7 @@ static hipError_t gap_nl(const GapDesc& d, hipStream_t s) {
   a.acc = d.acc;
   a.done = d.done;
   a.iso = d.iso ? 1 : 0;
+  a.cg = d.cg;
   long long nb = (a.n + 255) / 256;
   if (nb > 4096) nb = 4096;
   hipLaunchKernelGGL((k_gap<NL, TWO, NDIM, TS>), dim3((int)nb), dim3(256), 0, s, a);
@@ -70,13 +71,18 @@ hipError_t launch_gap(const GapDesc& d, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ init
-// q = 0, u = 0, p_s and every p_i (p_t) at the pointwise minimum capacity.
+// q = 0, u = 0, p_s and every p_i (p_t) at the pointwise minimum capacity
+// (0 in the padding of the rows, pitch > W).
 template <typename TS>
-__global__ __launch_bounds__(256) void k_init(int nl, int ncap, int ndim, long long n, long long P,
-                                              const TS* cap, float* u, TS* q, TS* ps, TS* p) {
+__global__ __launch_bounds__(256) void k_init(int nl, int ncap, int ndim, long long n, long long P, int pitch,
+                                              int W, const TS* cap, const CapGen cg, float* u, TS* q, TS* ps,
+                                              TS* p) {
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
-    float m = ld(cap, i);
-    for (int c = 1; c < ncap; c++) m = fminf(m, ld(cap + (long long)c * P, i));
+    float m = cap_ld(cap, P, 0, i, cg);
+#pragma unroll
+    for (int c = 1; c < 8; c++)
+      if (c < ncap) m = fminf(m, cap_ld(cap, P, c, i, cg));
+    m = (int)(i % pitch) < W ? m : 0.f;
     st(ps, i, m);
     for (int l = 0; l < nl; l++) {
       u[(long long)l * P + i] = 0.f;
@@ -91,16 +97,17 @@ static int blocks_for(long long n) {
   return (int)(nb > 8192 ? 8192 : (nb < 1 ? 1 : nb));
 }
 
-hipError_t launch_init(const Geom& g, int nl, bool two, bool bf16, const void* cap, StateView st,
-                       hipStream_t s) {
+hipError_t launch_init(const Geom& g, int nl, bool two, bool bf16, const void* cap, const CapGen& cg,
+                       StateView st, hipStream_t s) {
   const int ncap = two ? 2 : nl;
-  const long long n = g.nstore();   // pads included (their capacities are 0)
+  if (ncap > 8) return hipErrorInvalidValue;
+  const long long n = g.nstore();   // pads included
   if (bf16)
-    hipLaunchKernelGGL(k_init<bf16_t>, dim3(blocks_for(n)), dim3(256), 0, s, nl, ncap, g.ndim, n, g.plane,
-                       (const bf16_t*)cap, st.u, (bf16_t*)st.q, (bf16_t*)st.ps, (bf16_t*)st.p);
+    hipLaunchKernelGGL(k_init<bf16_t>, dim3(blocks_for(n)), dim3(256), 0, s, nl, ncap, g.ndim, n, g.plane, g.pitch,
+                       g.W, (const bf16_t*)cap, cg, st.u, (bf16_t*)st.q, (bf16_t*)st.ps, (bf16_t*)st.p);
   else
-    hipLaunchKernelGGL(k_init<float>, dim3(blocks_for(n)), dim3(256), 0, s, nl, ncap, g.ndim, n, g.plane,
-                       (const float*)cap, st.u, (float*)st.q, (float*)st.ps, (float*)st.p);
+    hipLaunchKernelGGL(k_init<float>, dim3(blocks_for(n)), dim3(256), 0, s, nl, ncap, g.ndim, n, g.plane, g.pitch,
+                       g.W, (const float*)cap, cg, st.u, (float*)st.q, (float*)st.ps, (float*)st.p);
   return hipGetLastError();
 }
 

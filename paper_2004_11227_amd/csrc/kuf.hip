@@ -36,6 +36,7 @@ struct KU {
   const float* ub_in;   // ALG1
   float* ub_out;
   float sigma, tau;
+  CapGen cg;            // cg.img: `cap` is one image plane
 };
 
 template <int NDIM, typename TS>
@@ -114,13 +115,13 @@ __global__ __launch_bounds__(256) void k_uf_pu(const KU<TS> A) {
 #pragma unroll
     for (int l = 0; l < NL; l++) {
       const float d = div_at<NDIM>(A.q_out + (long long)(NDIM * l) * A.P, A.P, idx, x, y, z, A.W, A.H, A.D);
-      const float C = ld(A.cap + (long long)(TWO ? 1 : l) * A.P, idx);
+      const float C = cap_ld(A.cap, A.P, TWO ? 1 : l, idx, A.cg);
       float pn;
       label_update(k, A.u_in[(long long)l * A.P + idx], ld(A.p_in + (long long)l * A.P, idx), ps, d, C, pn,
                    t[l], sumd, sumr);
       st(A.p_out + (long long)l * A.P, idx, pn);
     }
-    const float psn = finish_ps(k, ps, sumd, sumr, TWO, TWO ? ld(A.cap, idx) : 0.f);
+    const float psn = finish_ps(k, ps, sumd, sumr, TWO, TWO ? cap_ld(A.cap, A.P, 0, idx, A.cg) : 0.f);
     st(A.ps_out, idx, psn);
 #pragma unroll
     for (int l = 0; l < NL; l++) A.u_out[(long long)l * A.P + idx] = finish_u(k, t[l], psn);
@@ -142,8 +143,8 @@ __global__ __launch_bounds__(256) void k_ty(const KU<TS> A) {
     if (TWO) {
       const float d = div_at<NDIM>(A.q_out, A.P, idx, x, y, z, A.W, A.H, A.D);
       const float u = A.u_in[idx];
-      const float psn = fminf(ld(A.cap, idx), ((ld(A.p_in, idx) + d) - u * inv_c) + inv_c);
-      const float ptn = fminf(ld(A.cap + A.P, idx), (psn - d) + u * inv_c);
+      const float psn = fminf(cap_ld(A.cap, A.P, 0, idx, A.cg), ((ld(A.p_in, idx) + d) - u * inv_c) + inv_c);
+      const float ptn = fminf(cap_ld(A.cap, A.P, 1, idx, A.cg), (psn - d) + u * inv_c);
       st(A.ps_out, idx, psn);
       st(A.p_out, idx, ptn);
       A.u_out[idx] = u - c * ((ptn - psn) + d);
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(256) void k_ty(const KU<TS> A) {
       for (int l = 0; l < NL; l++) {
         d[l] = div_at<NDIM>(A.q_out + (long long)(NDIM * l) * A.P, A.P, idx, x, y, z, A.W, A.H, A.D);
         const float u = A.u_in[(long long)l * A.P + idx];
-        pn[l] = fminf(ld(A.cap + (long long)l * A.P, idx), (ps - d[l]) + u * inv_c);
+        pn[l] = fminf(cap_ld(A.cap, A.P, l, idx, A.cg), (ps - d[l]) + u * inv_c);
         s += (pn[l] + d[l]) - u * inv_c;
       }
       const float psn = s / (float)NL + inv_c / (float)NL;
@@ -203,12 +204,12 @@ __global__ __launch_bounds__(256) void k_cpd(const KU<TS> A) {
       }
       st(qo, idx, qx);
       st(qo + A.P, idx, qy);
-      const float C = ld(A.cap + (long long)(TWO ? 1 : l) * A.P, idx);
+      const float C = cap_ld(A.cap, A.P, TWO ? 1 : l, idx, A.cg);
       st(A.p_out + (long long)l * A.P, idx, fminf(C, ld(A.p_in + (long long)l * A.P, idx) + sg * b0));
       sub += b0;
     }
     float psn = (ld(A.ps_in, idx) - sg * sub) + sg;
-    if (TWO) psn = fminf(ld(A.cap, idx), psn);
+    if (TWO) psn = fminf(cap_ld(A.cap, A.P, 0, idx, A.cg), psn);
     st(A.ps_out, idx, psn);
   }
 }
@@ -258,6 +259,7 @@ static hipError_t unfused_nl(const SweepDesc& d, hipStream_t s) {
   a.ub_out = d.out.ub;
   a.sigma = d.sigma;
   a.tau = d.tau;
+  a.cg = d.cg;
   long long nb = (a.n + 255) / 256;
   if (nb > 16384) nb = 16384;
   if (d.scheme == 2) {

@@ -127,6 +127,27 @@ __device__ __forceinline__ void stg(T* p, long long i, int nv, bool vec, const f
   }
 }
 
+// ---------------------------------------------------------------- capacities
+// Capacities generated from one image plane I instead of stored planes: the
+// data cost of label l at x as a function of the image value and a per-label
+// level, C_l(x) = |I(x) - lv[l]|^pw with pw 1 or 2, evaluated in FP32 where
+// it is used (two-label: C_s from lv[0], C_t from lv[1]).
+struct CapGen {
+  int img = 0;        // 0: capacity planes; 1: one image plane
+  int pw = 2;         // 1 or 2
+  float lv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+};
+__device__ __forceinline__ float cap_from(float I, float lv, int pw) {
+  const float d = I - lv;
+  return pw == 1 ? fabsf(d) : d * d;
+}
+// Capacity l at storage index i: plane l of `cap`, or computed from the
+// image plane `cap` (element-wise kernels; l is a compile-time index there).
+template <typename T>
+__device__ __forceinline__ float cap_ld(const T* cap, long long P, int l, long long i, const CapGen& cg) {
+  return cg.img ? cap_from(ld(cap, i), cg.lv[l], cg.pw) : ld(cap + (long long)l * P, i);
+}
+
 // ---------------------------------------------------------------- scalars
 struct Coef {
   float alpha;      // TV weight

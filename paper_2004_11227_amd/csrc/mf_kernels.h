@@ -59,6 +59,7 @@ struct SweepDesc {
   const int* done; // Ctrl::done of this solve, or nullptr
   int scheme = 0;  // element-wise passes: 0 rpADMM, 1 pADMM-TY, 2 ALG1
   float sigma = 0.f, tau = 0.f;   // ALG1 step sizes
+  CapGen cg;       // cg.img: `cap` is one image plane
 };
 
 struct GapDesc {
@@ -69,6 +70,7 @@ struct GapDesc {
   StateView st;    // iterate (for rPDRQ: u plus the resolvent outputs)
   double* acc;
   const int* done;
+  CapGen cg;
 };
 
 struct PdrqDesc {
@@ -86,6 +88,7 @@ struct PdrqDesc {
   int tile_rows;
   int sweeps = 1;      // symmetric red-black GS sweeps (in-place launches; the fused pass runs 1)
   const int* done;
+  CapGen cg;
 };
 
 hipError_t launch_fused(const SweepDesc& d, hipStream_t s);
@@ -95,7 +98,7 @@ hipError_t launch_gap(const GapDesc& d, hipStream_t s);
 hipError_t launch_pdrq_iter(const PdrqDesc& d, hipStream_t s);
 
 // misc kernels
-hipError_t launch_init(const Geom& g, int nl, bool two, bool bf16, const void* cap,
+hipError_t launch_init(const Geom& g, int nl, bool two, bool bf16, const void* cap, const CapGen& cg,
                        StateView st, hipStream_t s);
 hipError_t launch_convert_caps(const float* src, void* dst, long long n_per_plane, int nplanes,
                                long long plane, bool bf16, hipStream_t s);

@@ -57,6 +57,7 @@ std::string plan_solve(const mf_params* in, Footprint& f) {
   if (!e.empty()) return e;
   if (f.p.method != MF_RPADMM_FG && f.p.method != MF_RPADMM_EB) return "the pool runs the rpADMM methods (fg, eb)";
   if (f.p.relax0 != 0.0) return "the pool runs a constant relaxation (relax0 = 0)";
+  if (f.p.cap_source != MF_CAPS_PLANES) return "the pool takes capacity planes (cap_source MF_CAPS_PLANES)";
   if (f.g.ndim == 3 && f.p.model != MF_TWO_LABEL) return "the pool runs 3-D solves of the two-label model only";
   if (f.g.ndim == 3) {
     f.model = 5;
@@ -520,7 +521,7 @@ mf_status mf_pool_admit(mf_pool* P, const mf_params* p, const float* cap, int64_
   PHIP(launch_pitch_copy(cap, false, f.g.npix(), f.g.W, base, bf16, f.g.plane, f.pitch, f.g.W, rows, f.ncap,
                          P->stream));
   // initialise the padded planes whole (pads hold zero capacities)
-  PHIP(launch_init(f.g, f.nl, f.p.model == MF_TWO_LABEL, bf16, base, H.st[0], P->stream));
+  PHIP(launch_init(f.g, f.nl, f.p.model == MF_TWO_LABEL, bf16, base, CapGen{}, H.st[0], P->stream));
   fill_image(P, slot, 0);
   PoolSlot& S = P->slot_img[slot];
   PHIP(hipMemcpyAsync(P->dev.slots + slot, &S, sizeof(S), hipMemcpyHostToDevice, P->stream));

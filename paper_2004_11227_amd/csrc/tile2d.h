@@ -40,6 +40,7 @@ struct K2 {
   TS* p_out;
   float* wbuf;
   Coef k;
+  CapGen cg;          // with IMG: `cap` is one image plane
   double* acc;
   const int* done;
   int write;
@@ -95,7 +96,9 @@ struct Lab2 {
   float hqx[KQ], hqy[KQ], hu[KW], hp[KW];
 };
 
-template <int NL, bool TWO, typename TS, bool CHECK, int TY, bool VEC, bool SU>
+// IMG: the capacities are computed from one image plane (A.cg), which is
+// read once per pixel instead of 2 (two-label) or NL capacity planes.
+template <int NL, bool TWO, typename TS, bool CHECK, int TY, bool VEC, bool SU, bool IMG = false>
 __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY, SU>& S, double (&g)[5]) {
   static_assert(!CHECK || SU, "the gap needs the u staging array");
   constexpr int TX = 64;
@@ -196,7 +199,7 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
       ldr(qy_in, j, F.qy[j]);
       ldr(u_in, j, F.u[j]);
       ldr(p_in, j, F.p[j]);
-      if (!TWO) ldr(A.cap + (long long)l * P, j, F.C[j]);
+      if (!TWO && !IMG) ldr(A.cap + (long long)l * P, j, F.C[j]);
     }
 #pragma unroll
     for (int m = 0; m < KQ; m++) {
@@ -210,15 +213,18 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
     }
   };
 
-  // label-independent loads: p_s (owned and halo), two-label capacities
+  // label-independent loads: p_s (owned and halo), two-label capacities or
+  // the image
   float t[RPT][NL][V];
   float ps[RPT][V], sumd[RPT][V], sumr[RPT][V];
-  float capt[RPT][V], caps[RPT][V];
+  float capt[RPT][V], caps[RPT][V], im[RPT][V];
   float hps[KW];
 #pragma unroll
   for (int j = 0; j < RPT; j++) {
     ldr(A.ps_in, j, ps[j]);
-    if (TWO) {
+    if (IMG) {
+      ldr(A.cap, j, im[j]);
+    } else if (TWO) {
       ldr(A.cap, j, caps[j]);
       ldr(A.cap + P, j, capt[j]);
     }
@@ -230,6 +236,12 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
   }
 #pragma unroll
   for (int m = 0; m < KW; m++) hps[m] = ld(A.ps_in, hw_o[m]);
+  // C_s (two-label) and the capacity of label l at owned element (j, e)
+  auto cap_s = [&](int j, int e) { return IMG ? cap_from(im[j][e], A.cg.lv[0], A.cg.pw) : caps[j][e]; };
+  auto cap_l = [&](int j, int e, int l, const LabT& F) {
+    if (IMG) return cap_from(im[j][e], A.cg.lv[TWO ? 1 : l], A.cg.pw);
+    return TWO ? capt[j][e] : F.C[j][e];
+  };
   LabT F;
   fetch(0, F);
 #pragma unroll
@@ -252,7 +264,7 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
       for (int e = 0; e < V; e++) {
         ul[j][e] = F.u[j][e];
         pl[j][e] = F.p[j][e];
-        Cl[j][e] = TWO ? capt[j][e] : F.C[j][e];
+        Cl[j][e] = cap_l(j, e, l, F);
         sqx[r + 2][c0 + OX + e] = F.qx[j][e];
         sqy[r + 2][c0 + OX + e] = F.qy[j][e];
         sw[r + 2][c0 + OX + e] = vterm(pl[j][e], ps[j][e], ul[j][e], k.inv_c);
@@ -293,7 +305,7 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
                 (((gx + 1 < W) ? (double)sqx[r + 2][c] : 0.0) - ((gx > 0) ? (double)sqx[r + 2][c - 1] : 0.0)) +
                 (((gy + 1 < H) ? (double)sqy[r + 2][c] : 0.0) - ((gy > 0) ? (double)sqy[r + 1][c] : 0.0));
             gap_two_px(g, su[r + 2][c], su[r + 2][c + 1], su[r + 3][c], gx + 1 < W, gy + 1 < H, dq,
-                       caps[j][e], capt[j][e], ps[j][e], pl[j][e], A.iso);
+                       cap_s(j, e), Cl[j][e], ps[j][e], pl[j][e], A.iso);
           }
         }
       }
@@ -356,7 +368,7 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
     const long long idx = oj[j];
     float psn[V];
 #pragma unroll
-    for (int e = 0; e < V; e++) psn[e] = finish_ps(k, ps[j][e], sumd[j][e], sumr[j][e], TWO, TWO ? caps[j][e] : 0.f);
+    for (int e = 0; e < V; e++) psn[e] = finish_ps(k, ps[j][e], sumd[j][e], sumr[j][e], TWO, TWO ? cap_s(j, e) : 0.f);
     if (A.write) {
       stg<V>(A.ps_out, idx, nv, vec, psn);
 #pragma unroll

@@ -37,7 +37,8 @@ struct Smem2d2 {
   double sred[4 * 5];
 };
 
-template <typename TS, bool CHECK, int TY>
+// IMG: capacities computed from one image plane (A.cg), read once per cell.
+template <typename TS, bool CHECK, int TY, bool IMG = false>
 __device__ __forceinline__ void tile2d_d2(const K2<TS>& A, int x0, int y0, Smem2d2<TY>& S, double (&g)[5]) {
   constexpr int TX = 64, V = 4, TPR = TX / V, RSTEP = 256 / TPR, RPT = TY / RSTEP;
   constexpr int OX = 4, OY = 3;                    // LDS offsets of tile column / row 0
@@ -78,7 +79,9 @@ __device__ __forceinline__ void tile2d_d2(const K2<TS>& A, int x0, int y0, Smem2
     ldv<V>(A.p_in, i, lpt[m]);
   }
   // capacities of the k+1 update cells (T+[-1,+1]) and of the owned groups
-  float c1s[KC], c1t[KC];
+  // (with IMG the image values, turned into capacities where they are used)
+  float c1s[KC], c1t[KC], c1i[KC];
+  bool c1in[KC];
 #pragma unroll
   for (int m = 0; m < KC; m++) {
     const int h = tid + 256 * m;
@@ -86,26 +89,41 @@ __device__ __forceinline__ void tile2d_d2(const K2<TS>& A, int x0, int y0, Smem2
     const int gy = y0 + r, gx = x0 + c;
     const bool in = h < N1C && gx >= 0 && gx < W && gy >= 0 && gy < H;
     const long long i = in ? (long long)gy * pitch + gx : 0;
-    c1s[m] = ld(A.cap, i);
-    c1t[m] = ld(A.cap + P, i);
-    c1s[m] = in ? c1s[m] : 0.f;
-    c1t[m] = in ? c1t[m] : 0.f;
+    c1in[m] = in;
+    if (IMG) {
+      c1i[m] = ld(A.cap, i);
+    } else {
+      c1s[m] = ld(A.cap, i);
+      c1t[m] = ld(A.cap + P, i);
+      c1s[m] = in ? c1s[m] : 0.f;
+      c1t[m] = in ? c1t[m] : 0.f;
+    }
   }
+  const float lv0 = A.cg.lv[0], lv1 = A.cg.lv[1];
+  const int pw = A.cg.pw;
+  auto c1_s = [&](int m) { return IMG ? (c1in[m] ? cap_from(c1i[m], lv0, pw) : 0.f) : c1s[m]; };
+  auto c1_t = [&](int m) { return IMG ? (c1in[m] ? cap_from(c1i[m], lv1, pw) : 0.f) : c1t[m]; };
   const int c0 = (tid % TPR) * V;
   const int rr0 = tid / TPR;
   const int gx0 = x0 + c0;
   const int nvx = W - gx0 < 0 ? 0 : (W - gx0 > V ? V : W - gx0);
   int nvj[RPT];
   long long oj[RPT];
-  float ocs[RPT][V], oct[RPT][V];
+  float ocs[RPT][V], oct[RPT][V], oim[RPT][V];
 #pragma unroll
   for (int j = 0; j < RPT; j++) {
     const int gy = y0 + rr0 + RSTEP * j;
     nvj[j] = gy < H ? nvx : 0;
     oj[j] = (long long)gy * pitch + gx0;
-    ldv<V>(A.cap, nvj[j] > 0 ? oj[j] : 0, ocs[j]);
-    ldv<V>(A.cap + P, nvj[j] > 0 ? oj[j] : 0, oct[j]);
+    if (IMG) {
+      ldv<V>(A.cap, nvj[j] > 0 ? oj[j] : 0, oim[j]);
+    } else {
+      ldv<V>(A.cap, nvj[j] > 0 ? oj[j] : 0, ocs[j]);
+      ldv<V>(A.cap + P, nvj[j] > 0 ? oj[j] : 0, oct[j]);
+    }
   }
+  auto o_s = [&](int j, int e) { return IMG ? cap_from(oim[j][e], lv0, pw) : ocs[j][e]; };
+  auto o_t = [&](int j, int e) { return IMG ? cap_from(oim[j][e], lv1, pw) : oct[j][e]; };
 #pragma unroll
   for (int m = 0; m < KG; m++) {
     const int h = tid + 256 * m;
@@ -137,7 +155,7 @@ __device__ __forceinline__ void tile2d_d2(const K2<TS>& A, int x0, int y0, Smem2
           const double dq =
               (((gx + 1 < W) ? (double)sqx[R][C] : 0.0) - ((gx > 0) ? (double)sqx[R][C - 1] : 0.0)) +
               (((gy + 1 < H) ? (double)sqy[R][C] : 0.0) - ((gy > 0) ? (double)sqy[R - 1][C] : 0.0));
-          gap_two_px(g, su[R][C], su[R][C + 1], su[R + 1][C], gx + 1 < W, gy + 1 < H, dq, ocs[j][e], oct[j][e],
+          gap_two_px(g, su[R][C], su[R][C + 1], su[R + 1][C], gx + 1 < W, gy + 1 < H, dq, o_s(j, e), o_t(j, e),
                      sps[R][C], spt[R][C], A.iso);
         }
       }
@@ -176,8 +194,8 @@ __device__ __forceinline__ void tile2d_d2(const K2<TS>& A, int x0, int y0, Smem2
       const float d = div2(sqx[R][C], sqx[R][C - 1], sqy[R][C], sqy[R - 1][C], hx + 1 < W, hx > 0, hy + 1 < H, hy > 0);
       float pn, t, sd = 0.f, sr = 0.f;
       const float ps = sps[R][C];
-      label_update(k, su[R][C], spt[R][C], ps, d, c1t[m], pn, t, sd, sr);
-      const float psn = finish_ps(k, ps, sd, sr, true, c1s[m]);
+      label_update(k, su[R][C], spt[R][C], ps, d, c1_t(m), pn, t, sd, sr);
+      const float psn = finish_ps(k, ps, sd, sr, true, c1_s(m));
       su[R][C] = finish_u(k, t, psn);
       spt[R][C] = quant<TS>(pn);
       sps[R][C] = quant<TS>(psn);
@@ -221,8 +239,8 @@ __device__ __forceinline__ void tile2d_d2(const K2<TS>& A, int x0, int y0, Smem2
       const float d = div2(qxv[e], sqx[R][C - 1], qyv[e], sqy[R - 1][C], gx + 1 < W, gx > 0, gy + 1 < H, gy > 0);
       float t, sd = 0.f, sr = 0.f;
       const float ps = sps[R][C];
-      label_update(k, su[R][C], spt[R][C], ps, d, oct[j][e], pn[e], t, sd, sr);
-      psn[e] = finish_ps(k, ps, sd, sr, true, ocs[j][e]);
+      label_update(k, su[R][C], spt[R][C], ps, d, o_t(j, e), pn[e], t, sd, sr);
+      psn[e] = finish_ps(k, ps, sd, sr, true, o_s(j, e));
       un[e] = finish_u(k, t, psn[e]);
     }
     if (A.write) {

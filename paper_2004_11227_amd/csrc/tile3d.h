@@ -46,6 +46,7 @@ struct K3 {
   const TS* p_in;
   TS* p_out;
   Coef k;
+  CapGen cg;           // with IMG: `cap` is one image plane
   double* acc;
   const int* done;
   int write;
@@ -81,8 +82,9 @@ struct Plane3 {
 // One 64 x TY tile (TY = 8 or 16; V = TY / 4 columns per thread) of the xy
 // plane over the slab [z0, z1).  The global loads of plane s+1 (and the
 // capacities of plane s) are issued at the start of step s, so their latency
-// overlaps the LDS phases of step s.
-template <typename TS, bool CHECK, bool VEC, bool SU, int TY = 8>
+// overlaps the LDS phases of step s.  IMG: the capacities are computed from
+// one image plane (A.cg), read once per pixel instead of the two planes.
+template <typename TS, bool CHECK, bool VEC, bool SU, int TY = 8, bool IMG = false>
 __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, int z1, Smem3<SU, TY>& S,
                                        double (&g)[5]) {
   static_assert(!CHECK || SU, "the gap needs the u staging array");
@@ -197,19 +199,19 @@ __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, 
     F.hps = iw ? F.hps : 0.f;
   };
   // Capacities of the owned pixels of plane z (raw: only pixels inside the
-  // grid and the slab are used).
+  // grid and the slab are used; with IMG the image values, in cs).
   auto fetch_caps = [&](int z, float (&cs)[V], float (&ct)[V]) {
     const bool ok = z >= z0 && z < z1;
     if (vec) {
       const long long i = (ok && nvxy > 0) ? (long long)z * SZ + own_off : 0;
       ldv<V>(A.cap, i, cs);
-      ldv<V>(A.cap + P, i, ct);
+      if (!IMG) ldv<V>(A.cap + P, i, ct);
     } else {
 #pragma unroll
       for (int e = 0; e < V; e++) {
         const long long i = (ok && e < nvxy) ? (long long)z * SZ + own_off + e : 0;
         cs[e] = ld(A.cap, i);
-        ct[e] = ld(A.cap + P, i);
+        if (!IMG) ct[e] = ld(A.cap + P, i);
       }
     }
   };
@@ -259,8 +261,8 @@ __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, 
     float cs[V], ct[V];
 #pragma unroll
     for (int e = 0; e < V; e++) {
-      cs[e] = cs_n[e];
-      ct[e] = ct_n[e];
+      cs[e] = IMG ? cap_from(cs_n[e], A.cg.lv[0], A.cg.pw) : cs_n[e];
+      ct[e] = IMG ? cap_from(cs_n[e], A.cg.lv[1], A.cg.pw) : ct_n[e];
     }
     // ---- issue the loads of plane s+1 and the capacities of plane s
     fetch(s + 1, F);

@@ -38,6 +38,7 @@ struct KDF {
   float sigma, tau, rho, inv_st, alpha, m;
   int iso, keep_z;
   const int* done;
+  CapGen cg;            // cg.img: `cap` is one image plane (read into ocs)
 };
 
 template <int TY>
@@ -100,7 +101,7 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
     nvj[j] = gy < H ? nvx : 0;
     oj[j] = (long long)gy * pitch + gx0;
     ldv<V>(A.cap, nvj[j] > 0 ? oj[j] : 0, ocs[j]);
-    ldv<V>(A.cap + P, nvj[j] > 0 ? oj[j] : 0, oct[j]);
+    if (!A.cg.img) ldv<V>(A.cap + P, nvj[j] > 0 ? oj[j] : 0, oct[j]);
   }
 #pragma unroll
   for (int m = 0; m < KG; m++) {
@@ -187,13 +188,15 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
       // p_t = p-bar_t + tau u;  z = min(C_t, 2 p_t - p-bar_t);  p-bar_t += rho (z - p_t)
       const float pbv = spt[R][C];
       const float pv = pbv + tau * u0;
-      const float zpv = fminf(oct[j][e], 2.f * pv - pbv);
+      const float Ct = A.cg.img ? cap_from(ocs[j][e], A.cg.lv[1], A.cg.pw) : oct[j][e];
+      const float zpv = fminf(Ct, 2.f * pv - pbv);
       pto[e] = pbv + rho * (zpv - pv);
       zpt[e] = zpv;
       // p_s = p-bar_s - tau u;  z_s = min(C_s, 2 p_s - p-bar_s + tau)
       const float psbv = sps[R][C];
       const float psv = psbv - tau * u0;
-      const float zsv = fminf(ocs[j][e], (2.f * psv - psbv) + tau);
+      const float Cs = A.cg.img ? cap_from(ocs[j][e], A.cg.lv[0], A.cg.pw) : ocs[j][e];
+      const float zsv = fminf(Cs, (2.f * psv - psbv) + tau);
       pso[e] = psbv + rho * (zsv - psv);
       zps[e] = zsv;
     }

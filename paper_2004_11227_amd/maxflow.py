@@ -21,6 +21,7 @@ METHODS = {"fg": 0, "eb": 1, "dr": 2, "ty": 3, "cp": 4}
 TVS = {"iso": 0, "aniso": 1}
 STORAGES = {"f32": 0, "bf16": 1}
 VARIANTS = {"fused": 0, "unfused": 1}
+CAP_SOURCES = {"planes": 0, "image": 1}
 FIELDS = {"u": 0, "q": 1, "ps": 2, "p": 3, "zq": 4, "zs": 5, "zp": 6}
 STATUS = {0: "converged", 1: "cap", -4: "diverged"}
 
@@ -42,7 +43,8 @@ class mf_params(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("promote_gap", ctypes.c_double), ("promote_iter", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("slab_depth", ctypes.c_int32), ("gs_sweeps", ctypes.c_int32), ("relax0", ctypes.c_double),
-                ("relax_ramp", ctypes.c_int32)]
+                ("relax_ramp", ctypes.c_int32), ("cap_source", ctypes.c_int32), ("cap_power", ctypes.c_int32),
+                ("levels", ctypes.c_double * 8)]
 
 
 class mf_gap(ctypes.Structure):
@@ -117,7 +119,7 @@ def make_params(shape, model="two", method="eb", tv="iso", storage="f32", varian
                 nlabels=2, alpha=0.5, c=0.0, relax=0.0, sigma=0.0, tau=0.0, a=0.0, a_tilde=0.0,
                 a1=0.0, a2=0.0, max_iter=1000, tol=1e-4, check_every=10, tile_rows=0,
                 promote_gap=0.0, promote_iter=0, depth=0, slab_depth=0, gs_sweeps=0, relax0=0.0,
-                relax_ramp=0) -> mf_params:
+                relax_ramp=0, cap_source="planes", cap_power=0, levels=()) -> mf_params:
     shape = tuple(int(s) for s in shape)
     p = mf_params()
     p.ndim = len(shape)
@@ -136,6 +138,12 @@ def make_params(shape, model="two", method="eb", tv="iso", storage="f32", varian
     p.depth = int(depth)
     p.slab_depth = int(slab_depth)
     p.gs_sweeps, p.relax0, p.relax_ramp = int(gs_sweeps), float(relax0), int(relax_ramp)
+    p.cap_source = CAP_SOURCES[cap_source]
+    p.cap_power = int(cap_power)
+    if len(levels) > 8:
+        raise ValueError("at most 8 levels")
+    for i, v in enumerate(levels):
+        p.levels[i] = float(v)
     return p
 
 
@@ -150,7 +158,9 @@ class Solver:
     """One solve on the current CUDA/HIP device.
 
     ``caps`` is a float32 device tensor of shape (2, *shape) = [C_s, C_t] for
-    the two-label model or (n, *shape) = [C_1..C_n] for Potts.  Keyword
+    the two-label model or (n, *shape) = [C_1..C_n] for Potts; with
+    ``cap_source="image"`` it is the image, shape (1, *shape), and the
+    capacities are |I - levels[k]|^cap_power.  Keyword
     arguments follow ``make_params``.  ``stream`` is a torch stream (default:
     the current stream).  The workspace is a torch uint8 tensor owned here.
     """
@@ -171,6 +181,8 @@ class Solver:
         if caps.dtype != torch.float32 or not caps.is_cuda or not caps.is_contiguous():
             raise ValueError("caps must be a contiguous float32 device tensor")
         ncap = 2 if self.model == "two" else self.L
+        if kw.get("cap_source", "planes") == "image":
+            ncap = 1
         if caps.shape[0] != ncap:
             raise ValueError(f"caps must have {ncap} planes")
         self.device = caps.device

@@ -4,7 +4,7 @@ The autotuner itself is native (``maxflow_tune``: it times the candidate
 tile heights of the fused 2-D and 3-D sweeps with HIP events on the solver's stream).
 This module keeps its choices in a JSON file so that a shape class is timed
 once per device: the key is (device name, model, labels, dimensions,
-storage, method, variant, requested depth, log2 of the pixel count), the value the chosen
+storage, method, variant, requested depth, capacity source, log2 of the pixel count), the value the chosen
 tile height and the measured microseconds per sweep of every candidate.
 ``Solver(..., tile_rows="auto")`` looks the class up and tunes on a miss.
 
@@ -30,7 +30,8 @@ def cache_path() -> str:
     return os.path.join(os.path.expanduser("~"), ".cache", "paper_2004_11227_amd", "tuning.json")
 
 
-def key(shape, device, model="two", nlabels=2, storage="f32", method="eb", variant="fused", depth=0, **_) -> str:
+def key(shape, device, model="two", nlabels=2, storage="f32", method="eb", variant="fused", depth=0,
+        cap_source="planes", **_) -> str:
     import torch
     name = torch.cuda.get_device_name(device) if device is not None else "cpu"
     npx = 1
@@ -38,6 +39,7 @@ def key(shape, device, model="two", nlabels=2, storage="f32", method="eb", varia
         npx *= int(s)
     L = 2 if model == "two" else int(nlabels)
     return "|".join([name, model, str(L), f"{len(shape)}d", storage, method, variant, f"depth{int(depth)}",
+                     f"caps-{cap_source}",
                      f"px2^{int(round(math.log2(max(npx, 1))))}"])
 
 

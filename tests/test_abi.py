@@ -107,3 +107,27 @@ def test_pdrq_layout_follows_the_sweep_count():
     one = mfx.workspace_bytes(mfx.make_params((64, 1001), method="dr", gs_sweeps=1))
     two = mfx.workspace_bytes(mfx.make_params((64, 1001), method="dr", gs_sweeps=2))
     assert two < one
+
+
+def test_image_capacities_validation_and_workspace():
+    """cap_source="image" keeps one image plane instead of 2 or n capacity
+    planes; bad powers, sources and non-finite levels are rejected, and the
+    pool takes capacity planes only."""
+    from paper_2004_11227_amd import maxflow as mfx
+    for model, n in (("two", 2), ("potts", 8)):
+        planes = mfx.workspace_bytes(mfx.make_params((256, 256), model=model, nlabels=n))
+        image = mfx.workspace_bytes(mfx.make_params((256, 256), model=model, nlabels=n, cap_source="image",
+                                                    levels=[0.1 * i for i in range(n)]))
+        assert planes - image == (n - 1) * 256 * 256 * 4
+    with pytest.raises(mfx.MaxflowError):
+        mfx.workspace_bytes(mfx.make_params((16, 16), cap_source="image", cap_power=3, levels=[0.2, 0.8]))
+    with pytest.raises(mfx.MaxflowError):
+        mfx.workspace_bytes(mfx.make_params((16, 16), cap_source="image", levels=[float("nan"), 0.8]))
+    p = mfx.make_params((16, 16))
+    p.cap_source = 2
+    with pytest.raises(mfx.MaxflowError):
+        mfx.workspace_bytes(p)
+    with pytest.raises(ValueError):
+        mfx.make_params((16, 16), cap_source="image", levels=[0.0] * 9)
+    assert mfx.lib().mf_pool_footprint(ctypes.byref(mfx.make_params((64, 64), cap_source="image",
+                                                                     levels=[0.2, 0.8]))) == 0
