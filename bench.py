@@ -36,12 +36,13 @@ WORKLOAD = dict(name="two_label_2d_2048", shape=(2048, 2048), iters=500, method=
                 alpha=0.5, check_every=10, depth=2, tile_rows=16)
 
 
-def alg_bytes(model: str, n: int, ndim: int, storage: str) -> int:
+def alg_bytes(model: str, n: int, ndim: int, storage: str, image: bool = False) -> int:
     """Minimum HBM bytes per pixel and iteration of one fused sweep: read the
     state (u, q, p_s, p / p_t) and the capacities once, write the state once.
-    u is always FP32; flows and capacities take the storage type."""
+    u is always FP32; flows and capacities take the storage type.  With
+    image-generated capacities one image plane replaces the capacity planes."""
     L = 1 if model == "two" else n
-    ncap = 2 if model == "two" else n
+    ncap = 1 if image else (2 if model == "two" else n)
     e = 4 if storage == "f32" else 2
     u = 2 * L * 4
     flows = (L * ndim + 1 + L) * 2 * e
@@ -97,8 +98,8 @@ def make_solver(torch, maxflow, caps_t, stream, **kw):
 
 def time_sweeps(torch, solver, stream, n):
     """Average time per iteration of plain sweeps (no gap), HIP events on the
-    solver's stream."""
-    solver.step(20)
+    solver's stream, after as many untimed sweeps (the clocks settle)."""
+    solver.step(max(20, n))
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -274,6 +275,19 @@ def secondary(torch, maxflow, synth, np, dev, stream):
         for stg in ("f32", "bf16"):
             sweep_rate(f"potts{n}_1024_fused_{stg}", caps, alg_bytes("potts", n, 2, stg),
                        model="potts", nlabels=n, method="eb", alpha=0.3, storage=stg)
+    # capacities generated from the image plane (the same workloads' data
+    # costs |I - l|^p): one plane read instead of 2 or n
+    img1 = synth.config_inputs("c1")["image"][None]
+    sweep_rate("two_2048_fused_f32_depth2_image", img1, alg_bytes("two", 2, 2, "f32", image=True), model="two",
+               method="eb", relax=1.5, depth=2, cap_source="image", cap_power=1, levels=(0.2, 0.8))
+    sweep_rate("two_2048_fused_f32_depth1_image", img1, alg_bytes("two", 2, 2, "f32", image=True), model="two",
+               method="eb", relax=1.5, depth=1, cap_source="image", cap_power=1, levels=(0.2, 0.8))
+    del img1
+    inp8 = synth.config_inputs("c2n8")
+    sweep_rate("potts8_1024_fused_f32_image", inp8["image"][None], alg_bytes("potts", 8, 2, "f32", image=True),
+               model="potts", nlabels=8, method="eb", alpha=0.3, cap_source="image", cap_power=2,
+               levels=tuple(k / 7 for k in range(8)))
+    del inp8
     vol = synth.config_inputs("c3")["caps"]   # 256^3, 512 MiB FP32 working set
     for stg in ("f32", "bf16"):
         sweep_rate(f"two_3d_256_fused_{stg}", vol, alg_bytes("two", 2, 3, stg), iters=50, model="two",
@@ -281,6 +295,10 @@ def secondary(torch, maxflow, synth, np, dev, stream):
     sweep_rate("two_3d_256_unfused_f32", vol, alg_bytes("two", 2, 3, "f32"), iters=20, model="two",
                method="eb", relax=1.5, alpha=0.4, variant="unfused")
     del vol
+    vimg = synth.config_inputs("c3")["image"][None]
+    sweep_rate("two_3d_256_fused_f32_image", vimg, alg_bytes("two", 2, 3, "f32", image=True), iters=50,
+               model="two", method="eb", relax=1.5, alpha=0.4, cap_source="image", cap_power=1, levels=(0.2, 0.8))
+    del vimg
     return res
 
 

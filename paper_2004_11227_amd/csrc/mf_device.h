@@ -12,26 +12,24 @@ namespace mf {
 
 // ---------------------------------------------------------------- storage
 // bfloat16 is kept as raw 16-bit words.  Widening is exact (shift into the
-// high half of an FP32 word); narrowing rounds to nearest, ties to even, and
-// keeps NaNs quiet.
+// high half of an FP32 word); narrowing is gfx950's conversion instruction
+// (v_cvt_pk_bf16_f32: round to nearest, ties to even; NaNs stay NaN).
 typedef uint16_t bf16_t;
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ float ld(const float* p, long long i) { return p[i]; }
 __device__ __forceinline__ float ld(const bf16_t* p, long long i) {
   return __uint_as_float(((uint32_t)p[i]) << 16);
 }
-__device__ __forceinline__ bf16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (bf16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (bf16_t)(u >> 16);
-}
+__device__ __forceinline__ bf16_t f2bf(float f) { return __builtin_bit_cast(bf16_t, (__bf16)f); }
 __device__ __forceinline__ void st(float* p, long long i, float v) { p[i] = v; }
 __device__ __forceinline__ void st(bf16_t* p, long long i, float v) { p[i] = f2bf(v); }
 __device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 __device__ __forceinline__ uint32_t bf_pack(float a, float b) {
-  return (uint32_t)f2bf(a) | ((uint32_t)f2bf(b) << 16);
+  typedef float f32x2_t __attribute__((ext_vector_type(2)));
+  const f32x2_t v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));   // element 0 in the low half
 }
 
 // V consecutive elements starting at p[i] (i a multiple of V, 4*V-byte
