@@ -159,15 +159,21 @@ struct Coef {
   float inv_a2;     // 1/a2  (two-label: 1/a~)
 };
 
+// 1/sqrt(v) by the hardware reciprocal square root (v_rsq_f32, about 1 ulp),
+// its argument kept at least the smallest normal so that a zero or subnormal
+// squared norm (possible only with alpha = 0) still gives a finite factor.
+__device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(fmaxf(v, 1.17549435e-38f)); }
+
 // P_alpha: isotropic (pointwise Euclidean ball, eq. projections) or
 // anisotropic (per-component clamp).  A vector inside the ball is returned
-// unchanged; outside it is scaled by alpha/|q|.
+// unchanged; outside it is scaled by alpha/|q|, formed as alpha times the
+// reciprocal square root of |q|^2 (the result's norm is alpha to a few ulp).
 template <bool ISO>
 __device__ __forceinline__ void proj2(float& x, float& y, float alpha) {
   if (ISO) {
-    const float n = sqrtf(x * x + y * y);
-    if (n > alpha) {
-      const float s = alpha / n;
+    const float n2 = x * x + y * y;
+    if (n2 > alpha * alpha) {
+      const float s = alpha * rsq(n2);
       x = x * s;
       y = y * s;
     }
@@ -179,9 +185,9 @@ __device__ __forceinline__ void proj2(float& x, float& y, float alpha) {
 template <bool ISO>
 __device__ __forceinline__ void proj3(float& x, float& y, float& z, float alpha) {
   if (ISO) {
-    const float n = sqrtf((x * x + y * y) + z * z);
-    if (n > alpha) {
-      const float s = alpha / n;
+    const float n2 = (x * x + y * y) + z * z;
+    if (n2 > alpha * alpha) {
+      const float s = alpha * rsq(n2);
       x = x * s;
       y = y * s;
       z = z * s;
