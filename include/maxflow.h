@@ -231,23 +231,37 @@ mf_status maxflow_import_state(mf_solver* s, const void* src, int64_t iter);
 
 mf_status maxflow_destroy(mf_solver* s);
 
-/* Autotuner for the launch shape of the fused sweeps.  Times `sweeps`
- * sweeps (after two warm-up sweeps) for each candidate tile height (8, 16
- * and 32 rows of 64 columns; 8 and 16 for the fused 3-D sweep, whose
- * entry for 32 reports 0) on the solver's stream with HIP events, keeps
- * the fastest for this solver, and returns it in *best_tile_rows.  Every
- * candidate runs iterate k -> k+1 from the solver's current iterate k
- * without advancing it, so the solver's state and iteration count are
- * unchanged; the tile height never changes the iterates (bit-identical).
- * `us_per_iter` (host, 3 entries, may be null) receives microseconds per
- * iteration for heights 8, 16, 32.  Depth-2 solvers time their two-iteration
- * pass at heights 16 and 32 (8 reports 0).  Solvers without a tile-height choice (3-D
- * Potts, the unfused variant) time their one configuration, report it in the entry
- * of their current height (others 0) and keep it; rPDRQ (in-place sweeps)
- * runs nothing and reports zeros.  Synchronises the stream.  Errors:
- * MF_EINVAL (null solver or best_tile_rows, sweeps < 1 or > 10000),
- * MF_EDEVICE. */
-mf_status maxflow_tune(mf_solver* s, int32_t sweeps, int32_t* best_tile_rows, double* us_per_iter);
+/* Autotuner for the launch shape: the tile height, the fusion depth
+ * (iterations per pass) and the 3-D slab depth, the knobs in `what`
+ * (MF_TUNE_* bits; the others keep the solver's values).  Candidates:
+ *   fused two-label 2-D rpADMM: depth 1 with 8, 16, 32 rows; depth 2 with
+ *     16, 32 rows;
+ *   fused 2-D Potts: 8, 16, 32 rows (8, 16 for n = 8);
+ *   fused 3-D two-label: 8 or 16 rows x slab depths 8, 16, 32;
+ *   fused two-label 2-D rPDRQ: 16, 32 rows;
+ *   any other solver: its one configuration, timed.
+ * Each candidate is timed over `sweeps` passes (after two warm-up passes) on
+ * the solver's stream with HIP events, from the solver's current iterate k
+ * into the other state buffer, so the state and the iteration count are
+ * unchanged; no launch shape changes the iterates (bit-identical).  The
+ * in-place rPDRQ launches would overwrite the state: that solver times
+ * nothing (ncand = 0).  The fastest candidate (per iteration) is kept for
+ * this solver and returned in `out` with every candidate's time.
+ * Synchronises the stream.  Errors: MF_EINVAL (null solver or out, sweeps
+ * < 1 or > 10000), MF_EDEVICE. */
+#define MF_TUNE_TILE 1
+#define MF_TUNE_DEPTH 2
+#define MF_TUNE_SLAB 4
+typedef struct {
+  int32_t tile_rows, depth, slab_depth;
+  double us_per_iter;
+} mf_tune_cand;
+typedef struct {
+  int32_t tile_rows, depth, slab_depth;   /* the choice, now in effect */
+  int32_t ncand;
+  mf_tune_cand cand[16];
+} mf_tuning;
+mf_status maxflow_tune(mf_solver* s, int32_t sweeps, int32_t what, mf_tuning* out);
 
 /* Thread-local message describing the last error (solver and pool calls). */
 const char* maxflow_last_error(void);

@@ -738,64 +738,86 @@ mf_status maxflow_import_state(mf_solver* s, const void* src, int64_t iter) {
   return MF_OK;
 }
 
-mf_status maxflow_tune(mf_solver* s, int32_t sweeps, int32_t* best_tile_rows, double* us_per_iter) {
-  if (!s || !best_tile_rows) return fail(MF_EINVAL, "null solver or best_tile_rows");
+mf_status maxflow_tune(mf_solver* s, int32_t sweeps, int32_t what, mf_tuning* out) {
+  if (!s || !out) return fail(MF_EINVAL, "null solver or out");
   if (sweeps < 1 || sweeps > 10000) return fail(MF_EINVAL, "sweeps must be in 1..10000");
-  const bool fused = s->r.p.method != MF_RPDRQ && s->r.p.variant == MF_FUSED;
+  mf_params& p = s->r.p;
+  *out = mf_tuning{};
+  const bool dr = p.method == MF_RPDRQ;
+  const bool fused = p.variant == MF_FUSED;
+  const bool two = p.model == MF_TWO_LABEL;
   const bool d3 = s->r.g.ndim == 3;
-  const bool choice = fused && (!d3 || s->r.p.model == MF_TWO_LABEL);
-  const int cand[3] = {8, 16, 32};
-  double us[3] = {0.0, 0.0, 0.0};
-  if (s->r.p.method == MF_RPDRQ) {   // in-place sweeps, no launch-shape choice: nothing is run
-    *best_tile_rows = s->r.p.tile_rows;
-    if (us_per_iter)
-      for (int c = 0; c < 3; c++) us_per_iter[c] = 0.0;
-    return MF_OK;
+  // the candidate list
+  std::vector<mf_tune_cand> cand;
+  auto add = [&](int rows, int depth, int slab) {
+    if (!(what & MF_TUNE_TILE) && rows != p.tile_rows) return;
+    if (!(what & MF_TUNE_DEPTH) && depth != p.depth) return;
+    if (!(what & MF_TUNE_SLAB) && slab != p.slab_depth) return;
+    cand.push_back(mf_tune_cand{rows, depth, slab, 0.0});
+  };
+  if (dr) {
+    if (dr_fused(s->r))
+      for (int rows : {16, 32}) add(rows, 1, p.slab_depth);
+  } else if (fused && !d3 && two) {
+    for (int rows : {8, 16, 32}) add(rows, 1, p.slab_depth);
+    for (int rows : {16, 32}) add(rows, 2, p.slab_depth);
+  } else if (fused && !d3) {
+    for (int rows : {8, 16, 32})
+      if (!(rows == 32 && p.nlabels > 4)) add(rows, 1, p.slab_depth);
+  } else if (fused && d3 && two) {
+    for (int rows : {8, 16})
+      for (int slab : {8, 16, 32}) add(rows, 1, slab);
   }
+  if (cand.empty() && !(dr && !dr_fused(s->r)))   // the one configuration
+    cand.push_back(mf_tune_cand{p.tile_rows, p.depth, p.slab_depth, 0.0});
+  if ((int)cand.size() > 16) cand.resize(16);
+  out->tile_rows = p.tile_rows;
+  out->depth = p.depth;
+  out->slab_depth = p.slab_depth;
+  if (cand.empty()) return MF_OK;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
     hipEventDestroy(e0);
     return fail(MF_EDEVICE, "event creation failed");
   }
-  const int keep = s->r.p.tile_rows;
-  int best = keep;
-  double best_us = 0.0;
+  const mf_params keep = p;
+  int best = -1;
   hipError_t he = hipSuccess;
-  const bool d2 = s->r.p.depth == 2;   // depth-2 passes tile 16 or 32 rows
-  for (int c = 0; c < 3 && he == hipSuccess; c++) {
-    if (!choice && cand[c] != keep) continue;
-    if (d2 && cand[c] == 8) continue;
-    if (d3 && choice && cand[c] == 32) continue;   // 3-D tiles are 8 or 16 rows
-    s->r.p.tile_rows = cand[c];
+  for (size_t c = 0; c < cand.size() && he == hipSuccess; c++) {
+    p.tile_rows = cand[c].tile_rows;
+    p.depth = cand[c].depth;
+    p.slab_depth = cand[c].slab_depth;
+    const bool d2 = p.depth == 2;
     float ms = 0.f;
-    // iterate k -> k+1 repeatedly: buffer k & 1 (the current iterate) is
-    // only read, buffer (k+1) & 1 is scratch until the next real sweep
+    // iterate k -> k+1 (or k+2) repeatedly: the buffer of iterate k is only
+    // read, the other one is scratch until the next real pass
     for (int w = 0; w < 2 + sweeps && he == hipSuccess; w++) {
       if (w == 2) he = hipEventRecord(e0, s->stream);
-      if (he == hipSuccess)
-        he = d2 ? admm_pass2(s, s->iter, false, nullptr, false) : admm_sweep(s, s->iter, false, true, nullptr);
+      if (he != hipSuccess) break;
+      if (dr) he = dr_iter(s, s->iter, false, nullptr);
+      else if (d2) he = admm_pass2(s, s->iter, false, nullptr, false);
+      else he = admm_sweep(s, s->iter, false, true, nullptr);
     }
     if (he == hipSuccess) he = hipEventRecord(e1, s->stream);
     if (he == hipSuccess) he = hipEventSynchronize(e1);
     if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
     if (he != hipSuccess) break;
-    us[c] = 1e3 * (double)ms / sweeps / (d2 ? 2 : 1);   // per iteration
-    if (best_us == 0.0 || us[c] < best_us) {
-      best_us = us[c];
-      best = cand[c];
-    }
+    cand[c].us_per_iter = 1e3 * (double)ms / sweeps / (d2 ? 2 : 1);
+    if (best < 0 || cand[c].us_per_iter < cand[best].us_per_iter) best = (int)c;
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
-  s->r.p.tile_rows = best;
-  if (he != hipSuccess) {
-    s->r.p.tile_rows = keep;
-    return fail(MF_EDEVICE, std::string("tuning sweep: ") + hipGetErrorString(he));
-  }
-  *best_tile_rows = best;
-  if (us_per_iter)
-    for (int c = 0; c < 3; c++) us_per_iter[c] = us[c];
+  p = keep;
+  if (he != hipSuccess) return fail(MF_EDEVICE, std::string("tuning pass: ") + hipGetErrorString(he));
+  p.tile_rows = cand[best].tile_rows;
+  p.depth = cand[best].depth;
+  p.slab_depth = cand[best].slab_depth;
+  out->tile_rows = p.tile_rows;
+  out->depth = p.depth;
+  out->slab_depth = p.slab_depth;
+  out->ncand = (int32_t)cand.size();
+  for (size_t c = 0; c < cand.size(); c++) out->cand[c] = cand[c];
   return MF_OK;
 }
 

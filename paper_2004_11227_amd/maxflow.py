@@ -47,6 +47,19 @@ class mf_params(ctypes.Structure):
                 ("levels", ctypes.c_double * 8)]
 
 
+class mf_tune_cand(ctypes.Structure):
+    _fields_ = [("tile_rows", ctypes.c_int32), ("depth", ctypes.c_int32), ("slab_depth", ctypes.c_int32),
+                ("us_per_iter", ctypes.c_double)]
+
+
+class mf_tuning(ctypes.Structure):
+    _fields_ = [("tile_rows", ctypes.c_int32), ("depth", ctypes.c_int32), ("slab_depth", ctypes.c_int32),
+                ("ncand", ctypes.c_int32), ("cand", mf_tune_cand * 16)]
+
+
+MF_TUNE_TILE, MF_TUNE_DEPTH, MF_TUNE_SLAB = 1, 2, 4
+
+
 class mf_gap(ctypes.Structure):
     _fields_ = [("iter", ctypes.c_int64), ("primal", ctypes.c_double), ("dual", ctypes.c_double),
                 ("rel_gap", ctypes.c_double), ("resid_rms", ctypes.c_double),
@@ -95,7 +108,7 @@ def lib():
         "maxflow_import_state": (S, [V, V, ctypes.c_int64]),
         "maxflow_destroy": (S, [V]),
         "maxflow_last_error": (ctypes.c_char_p, []),
-        "maxflow_tune": (S, [V, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+        "maxflow_tune": (S, [V, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(mf_tuning)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -168,10 +181,23 @@ class Solver:
     def __init__(self, caps: torch.Tensor, stream: torch.cuda.Stream | None = None, **kw):
         shape = tuple(caps.shape[1:])
         auto = kw.get("tile_rows") == "auto"
-        if auto:   # a cached choice, else the default now and the autotuner below
+        what = 0
+        if auto:
+            # tile_rows="auto": the launch shape is autotuned (the tile height,
+            # and the fusion depth and 3-D slab depth unless given); a cached
+            # choice for this shape class, else the defaults now and the
+            # autotuner below
             from . import tuning
+            what = MF_TUNE_TILE | (MF_TUNE_DEPTH if not kw.get("depth") else 0) | \
+                (MF_TUNE_SLAB if not kw.get("slab_depth") else 0)
             cached = tuning.lookup(shape, caps.device, **kw)
-            kw = {**kw, "tile_rows": cached or 0}
+            kw = {**kw, "tile_rows": 0}
+            if cached:
+                kw["tile_rows"] = cached["tile_rows"]
+                if what & MF_TUNE_DEPTH:
+                    kw["depth"] = cached["depth"]
+                if what & MF_TUNE_SLAB:
+                    kw["slab_depth"] = cached["slab_depth"]
             auto = cached is None
         self.params = make_params(shape, **kw)
         self.shape = shape
@@ -199,8 +225,8 @@ class Solver:
         self._kw = kw
         if auto:
             from . import tuning
-            best, us = self.tune()
-            tuning.store(shape, caps.device, best, us, **kw)
+            best, cands = self.tune(what=what)
+            tuning.store(shape, caps.device, best, cands, **kw)
 
     # -- lifecycle
     def close(self):
@@ -214,14 +240,18 @@ class Solver:
         except Exception:
             pass
 
-    def tune(self, sweeps: int = 20):
-        """Time the candidate tile heights on this solver (state unchanged),
-        keep the fastest.  Returns (tile_rows, {rows: us_per_sweep})."""
-        best = ctypes.c_int32()
-        us = (ctypes.c_double * 3)()
-        _check(lib().maxflow_tune(self._h, int(sweeps), ctypes.byref(best), us))
-        self.params.tile_rows = int(best.value)
-        return int(best.value), {r: float(us[i]) for i, r in enumerate((8, 16, 32)) if us[i] > 0}
+    def tune(self, sweeps: int = 20, what: int = MF_TUNE_TILE | MF_TUNE_DEPTH | MF_TUNE_SLAB):
+        """Time the candidate launch shapes on this solver (state unchanged)
+        and keep the fastest.  Returns (choice, candidates): the chosen
+        dict(tile_rows, depth, slab_depth) and a list of
+        dict(tile_rows, depth, slab_depth, us_per_iter)."""
+        t = mf_tuning()
+        _check(lib().maxflow_tune(self._h, int(sweeps), int(what), ctypes.byref(t)))
+        self.params.tile_rows, self.params.depth, self.params.slab_depth = t.tile_rows, t.depth, t.slab_depth
+        best = dict(tile_rows=int(t.tile_rows), depth=int(t.depth), slab_depth=int(t.slab_depth))
+        cands = [dict(tile_rows=int(c.tile_rows), depth=int(c.depth), slab_depth=int(c.slab_depth),
+                      us_per_iter=float(c.us_per_iter)) for c in t.cand[:t.ncand]]
+        return best, cands
 
     # -- iteration
     @property

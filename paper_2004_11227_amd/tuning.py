@@ -1,11 +1,12 @@
 """Cache of autotuned launch shapes.
 
 The autotuner itself is native (``maxflow_tune``: it times the candidate
-tile heights of the fused 2-D and 3-D sweeps with HIP events on the solver's stream).
-This module keeps its choices in a JSON file so that a shape class is timed
-once per device: the key is (device name, model, labels, dimensions,
-storage, method, variant, requested depth, capacity source, log2 of the pixel count), the value the chosen
-tile height and the measured microseconds per sweep of every candidate.
+launch shapes, tile height x fusion depth x 3-D slab depth, with HIP events on
+the solver's stream).  This module keeps its choices in a JSON file so that a
+shape class is timed once per device: the key is (device name, model,
+labels, dimensions, storage, method, variant, requested depth and slab depth
+(0: tuned), capacity source, log2 of the pixel count), the value the chosen
+shape and the measured microseconds per iteration of every candidate.
 ``Solver(..., tile_rows="auto")`` looks the class up and tunes on a miss.
 
 The file is ``$MF_TUNING_CACHE`` if set, else
@@ -31,7 +32,7 @@ def cache_path() -> str:
 
 
 def key(shape, device, model="two", nlabels=2, storage="f32", method="eb", variant="fused", depth=0,
-        cap_source="planes", **_) -> str:
+        cap_source="planes", slab_depth=0, **_) -> str:
     import torch
     name = torch.cuda.get_device_name(device) if device is not None else "cpu"
     npx = 1
@@ -39,7 +40,7 @@ def key(shape, device, model="two", nlabels=2, storage="f32", method="eb", varia
         npx *= int(s)
     L = 2 if model == "two" else int(nlabels)
     return "|".join([name, model, str(L), f"{len(shape)}d", storage, method, variant, f"depth{int(depth)}",
-                     f"caps-{cap_source}",
+                     f"slab{int(slab_depth)}", f"caps-{cap_source}",
                      f"px2^{int(round(math.log2(max(npx, 1))))}"])
 
 
@@ -55,19 +56,23 @@ def _load() -> dict:
 
 
 def lookup(shape, device, **kw):
-    """Cached tile height for this shape class, or None."""
+    """Cached launch shape dict(tile_rows, depth, slab_depth) for this shape
+    class, or None."""
     with _lock:
         e = _load().get(key(shape, device, **kw))
-    return int(e["tile_rows"]) if e else None
+    if not e or "choice" not in e:
+        return None
+    return {k: int(v) for k, v in e["choice"].items()}
 
 
-def store(shape, device, best: int, us: dict, **kw):
-    """Record a tuning result (`best` tile height, microseconds per sweep of
-    each candidate) and write the cache file (best effort)."""
+def store(shape, device, best: dict, cands: list, **kw):
+    """Record a tuning result (the chosen dict(tile_rows, depth, slab_depth)
+    and every candidate with its microseconds per iteration) and write the
+    cache file (best effort)."""
     k = key(shape, device, **kw)
     with _lock:
         d = _load()
-        d[k] = {"tile_rows": int(best), "us_per_sweep": {str(r): v for r, v in us.items()}}
+        d[k] = {"choice": {kk: int(v) for kk, v in best.items()}, "candidates": list(cands)}
         path = cache_path()
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)

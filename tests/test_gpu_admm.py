@@ -355,23 +355,26 @@ def test_export_import_resume_bitwise():
 
 
 def test_autotune_keeps_state_and_caches(tmp_path, monkeypatch):
-    """maxflow_tune times the candidate tile heights without moving the
-    iterate; the tuned solver continues bit-identically; the choice is
-    cached and reused."""
+    """maxflow_tune times the candidate launch shapes (tile height, fusion
+    depth, 3-D slab depth) without moving the iterate; the tuned solver
+    continues bit-identically; the choice is cached and reused."""
     banner("autotune")
+    from paper_2004_11227_amd import maxflow as mfx
     from paper_2004_11227_amd import tuning
     monkeypatch.setenv("MF_TUNING_CACHE", str(tmp_path / "tune.json"))
     tuning.clear()
     caps = synth.config_inputs("c1", size=(300, 333))["caps"]
-    kw = dict(model="two", method="eb", relax=1.5, alpha=0.5, depth=1)
-    ref = gpu_solver(caps, **kw)
+    kw = dict(model="two", method="eb", relax=1.5, alpha=0.5)
+    ref = gpu_solver(caps, depth=1, **kw)
     ref.step(7)
     s = gpu_solver(caps, **kw)
     s.step(5)
     before = gpu_fields(s)
-    best, us = s.tune(sweeps=5)
-    assert best in (8, 16, 32) and set(us) == {8, 16, 32} and all(v > 0 for v in us.values())
-    assert s.iter == 5
+    best, cands = s.tune(sweeps=5)
+    shapes = {(c["tile_rows"], c["depth"]) for c in cands}
+    assert shapes == {(8, 1), (16, 1), (32, 1), (16, 2), (32, 2)} and all(c["us_per_iter"] > 0 for c in cands)
+    assert (best["tile_rows"], best["depth"]) in shapes and s.iter == 5
+    assert best["tile_rows"] == s.params.tile_rows and best["depth"] == s.params.depth
     after = gpu_fields(s)
     for f in before:
         assert np.array_equal(before[f], after[f]), f
@@ -381,38 +384,54 @@ def test_autotune_keeps_state_and_caches(tmp_path, monkeypatch):
         assert np.array_equal(a[f], b[f]), f
     s.close()
     ref.close()
+    # only the tile height when the depth is fixed
+    d = gpu_solver(caps, depth=2, **kw)
+    best, cands = d.tune(sweeps=3, what=mfx.MF_TUNE_TILE)
+    assert {(c["tile_rows"], c["depth"]) for c in cands} == {(16, 2), (32, 2)} and best["depth"] == 2
+    d.close()
+    # the cache: tuned on a miss, read back on a hit
     t = gpu_solver(caps, tile_rows="auto", **kw)
-    assert t.params.tile_rows in (8, 16, 32)
-    assert tuning.lookup(caps.shape[1:], t.device, **kw) == t.params.tile_rows
+    got = tuning.lookup(caps.shape[1:], t.device, **kw)
+    assert got == dict(tile_rows=t.params.tile_rows, depth=t.params.depth, slab_depth=t.params.slab_depth)
     t.close()
     tuning.clear()
     u = gpu_solver(caps, tile_rows="auto", **kw)   # from the file, no tuning
-    assert u.params.tile_rows == tuning.lookup(caps.shape[1:], u.device, **kw)
+    assert (u.params.tile_rows, u.params.depth) == (got["tile_rows"], got["depth"])
     u.close()
     tuning.clear()
-    # depth-2 solvers time their two-iteration pass at 16 and 32 rows
-    kw2 = {**kw, "depth": 2}
-    d = gpu_solver(caps, **kw2)
-    d.step(4)
-    before = gpu_fields(d)
-    best, us = d.tune(sweeps=3)
-    assert best in (16, 32) and set(us) == {16, 32} and d.iter == 4
-    after = gpu_fields(d)
-    for f in before:
-        assert np.array_equal(before[f], after[f]), f
-    d.close()
-    assert tuning.key(caps.shape[1:], None, **kw) != tuning.key(caps.shape[1:], None, **kw2)
-    # the fused 3-D sweep chooses between 64 x 8 and 64 x 16 xy tiles
+    # 3-D: tile height x slab depth
     caps3 = synth.two_label_caps(synth.ellipsoid_volume(40, 48, 70, 4, 0.1, 3008))
     v = gpu_solver(caps3, model="two", method="eb", relax=1.5, alpha=0.4)
     v.step(3)
     before = gpu_fields(v)
-    best, us = v.tune(sweeps=3)
-    assert best in (8, 16) and set(us) == {8, 16} and v.iter == 3
+    best, cands = v.tune(sweeps=3)
+    assert {(c["tile_rows"], c["slab_depth"]) for c in cands} == {(r, z) for r in (8, 16) for z in (8, 16, 32)}
+    assert v.iter == 3 and best["slab_depth"] == v.params.slab_depth
     after = gpu_fields(v)
     for f in before:
         assert np.array_equal(before[f], after[f]), f
+    v.step(2)
+    w = gpu_solver(caps3, model="two", method="eb", relax=1.5, alpha=0.4, variant="unfused")
+    w.step(5)
+    a, b = gpu_fields(v), gpu_fields(w)
+    for f in a:
+        assert np.array_equal(a[f], b[f]), f
     v.close()
+    w.close()
+    # fused rPDRQ: 16 or 32 rows; in-place rPDRQ times nothing
+    r = gpu_solver(caps, model="two", method="dr", alpha=0.5)
+    r.step(2)
+    before = gpu_fields(r)
+    best, cands = r.tune(sweeps=3)
+    assert {c["tile_rows"] for c in cands} == {16, 32} and r.iter == 2
+    after = gpu_fields(r)
+    for f in before:
+        assert np.array_equal(before[f], after[f]), f
+    r.close()
+    r = gpu_solver(caps, model="two", method="dr", alpha=0.5, variant="unfused")
+    best, cands = r.tune(sweeps=3)
+    assert cands == []
+    r.close()
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
