@@ -298,9 +298,15 @@ size_t mf_pool_table_bytes(int32_t max_slots, int32_t max_tiles);
 
 /* `arena`: device, 256-byte aligned, caller-owned, outlives the pool;
  * `max_slots`: resident solves at most; `max_tiles`: work-list capacity per
- * class; `hip_stream`: a created (non-default) hipStream_t. */
+ * class; `steps_per_advance`: iterations per mf_pool_advance; `depth`:
+ * iterations per super-step, 1 or 2 (0 -> 2 when steps_per_advance is even,
+ * else 1; steps_per_advance must be a multiple of it).  With depth 2 the
+ * two-label 2-D classes run the two-iteration pass (iterate k+1 kept in
+ * LDS, one state read and write per two iterations) and the other classes
+ * two one-iteration sweeps per super-step; the iterates are the same bits
+ * as with depth 1.  `hip_stream`: a created (non-default) hipStream_t. */
 mf_status mf_pool_create(void* arena, size_t arena_bytes, int32_t max_slots, int32_t max_tiles,
-                         int32_t steps_per_advance, void* hip_stream, mf_pool** out);
+                         int32_t steps_per_advance, int32_t depth, void* hip_stream, mf_pool** out);
 
 /* Admit one solve: copies `cap` (device, FP32, layout as maxflow_create) into
  * the arena (converting to BF16 if asked) and sets the initial point.

@@ -10,6 +10,7 @@
 
 #include "mf_pool.h"
 #include "tile2d.h"
+#include "tile2d_d2.h"
 #include "tile3d.h"
 #include "gap.h"
 
@@ -28,10 +29,13 @@ __device__ __forceinline__ int xcd_item(int n) {
   return it < (int)((long long)n * (x + 1) / 8) ? it : -1;
 }
 
+// State buffer of the slot's current iterate.
+__device__ __forceinline__ int slot_buf(const PoolSlot& sl) { return (int)((sl.iter / sl.bufdiv) & 1); }
+
 template <typename TS>
 __device__ __forceinline__ K2<TS> slot_k2(const PoolSlot& sl) {
   K2<TS> a;
-  const int src = (int)(sl.iter & 1), dst = src ^ 1;
+  const int src = slot_buf(sl), dst = src ^ 1;
   a.W = sl.W;
   a.H = sl.H;
   a.pitch = sl.pitch;
@@ -75,6 +79,24 @@ __global__ __launch_bounds__(256) void k_pool2d(PoolDev d, int cls) {
   if (CHECK) block_accumulate<5, 4>(g, &sl->acc[0][0], S.sred);
 }
 
+// Two iterations (k -> k+2) of a two-label 2-D solve per launch, iterate
+// k+1 kept in LDS (the depth-2 tile body); iterate k is in buffer
+// (k / 2) & 1 and k+2 goes to the other one.
+template <typename TS, int TY, bool CHECK>
+__global__ __launch_bounds__(256) void k_pool2d_d2(PoolDev d, int cls) {
+  __shared__ Smem2d2<TY> S;
+  const int it = xcd_item(d.counts[cls]);
+  if (it < 0) return;
+  const WorkItem w = d.items[cls][it];
+  PoolSlot* sl = d.slots + w.slot;
+  if (sl->state != SLOT_RUNNING) return;
+  if ((sl->check_now != 0) != CHECK) return;
+  const K2<TS> A = slot_k2<TS>(*sl);
+  double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  tile2d_d2<TS, CHECK, TY>(A, w.x0, w.y0, S, g);
+  if (CHECK) block_accumulate<5, 4>(g, &sl->acc[0][0], S.sred);
+}
+
 template <typename TS, bool CHECK, bool VEC>
 __global__ __launch_bounds__(256) void k_pool3d(PoolDev d, int cls) {
   __shared__ Smem3<CHECK> S;
@@ -86,7 +108,7 @@ __global__ __launch_bounds__(256) void k_pool3d(PoolDev d, int cls) {
   if ((sl->check_now != 0) != CHECK) return;
   {
     K3<TS> A;
-    const int src = (int)(sl->iter & 1), dst = src ^ 1;
+    const int src = slot_buf(*sl), dst = src ^ 1;
     A.W = sl->W;
     A.H = sl->H;
     A.D = sl->D;
@@ -129,7 +151,7 @@ __global__ __launch_bounds__(256) void k_pool_gap2d(PoolDev d, int cls) {
   if (sl->state != SLOT_RUNNING || !sl->check_now) return;
   {
     KG<TS> A;
-    const int src = (int)(sl->iter & 1);
+    const int src = slot_buf(*sl);
     A.W = sl->W;
     A.H = sl->H;
     A.D = 1;
@@ -155,15 +177,19 @@ __global__ __launch_bounds__(256) void k_pool_gap2d(PoolDev d, int cls) {
 }
 
 // One workgroup (64 threads) per slot: sum the 64 accumulator rows, decide,
-// clear them, advance the iteration counter and publish the status.  Status
+// clear them, advance the iteration counter by the slot's pass length (2 for
+// two-iteration passes, else 1) and publish the status.  `only1`: this
+// bookkeeping follows the second half of a depth-2 super-step, in which only
+// the one-iteration classes ran; the others are left alone.  Status
 // codes follow mf_status: 0 converged, 1 cap reached, -4 diverged.
 // `check_step`: this super-step ran the gap-carrying launches.  A solve whose
 // check falls on another step (cannot happen with the admission rules) waits
 // for the next check step instead of deciding on empty accumulators.
-__global__ __launch_bounds__(64) void k_pool_book(PoolDev d, int check_step) {
+__global__ __launch_bounds__(64) void k_pool_book(PoolDev d, int check_step, int only1) {
   PoolSlot* sl = d.slots + blockIdx.x;
   const int t = threadIdx.x;
   if (sl->state != SLOT_RUNNING) return;
+  if (only1 && sl->bufdiv != 1) return;
   const bool check = sl->check_now != 0;
   if (check && !check_step) return;
   double v[5];
@@ -204,7 +230,7 @@ __global__ __launch_bounds__(64) void k_pool_book(PoolDev d, int check_step) {
     }
   }
   if (state == SLOT_RUNNING) {
-    const long long kn = k + 1;
+    const long long kn = k + sl->bufdiv;
     sl->iter = kn;
     sl->check_now = (kn % sl->check_every == 0 || kn >= sl->max_iter) ? 1 : 0;
   }
@@ -259,6 +285,16 @@ static const void* pool_gap_kernel_ts(int model) {
 const void* pool_gap_kernel(int cls) {
   const int model = cls % kPoolModels;
   return cls >= kPoolModels ? pool_gap_kernel_ts<bf16_t>(model) : pool_gap_kernel_ts<float>(model);
+}
+
+const void* pool_kernel_d2(int cls, bool check) {
+  const int model = cls % kPoolModels;
+  if (model != 0) return nullptr;
+  constexpr int TY = pool_tile_rows(0, false);
+  static_assert(pool_tile_rows(0, false) == pool_tile_rows(0, true), "one tile height for both storages");
+  if (cls >= kPoolModels)
+    return check ? (const void*)k_pool2d_d2<bf16_t, TY, true> : (const void*)k_pool2d_d2<bf16_t, TY, false>;
+  return check ? (const void*)k_pool2d_d2<float, TY, true> : (const void*)k_pool2d_d2<float, TY, false>;
 }
 
 const void* pool_book_kernel() { return (const void*)k_pool_book; }

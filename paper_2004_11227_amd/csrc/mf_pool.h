@@ -3,11 +3,14 @@
 // The pool keeps many solves resident at once.  Each solve owns a slot in a
 // device table (geometry, state buffers, iteration counter, gap
 // accumulators, decision) and its tiles are items of a per-class device work
-// list.  A super-step is one launch of a persistent kernel per class -- each
-// walks its work list and advances every running solve by one iteration,
-// reading the solve's own iteration parity and gap cadence from its slot --
-// followed by one bookkeeping launch that takes every solve's convergence
-// decision and advances its counter.  Because all of this state lives in
+// list.  A super-step advances every running solve by the pool's depth d (1
+// or 2 iterations): per class, one launch of the one-iteration kernel, or
+// with d = 2 one launch of the two-iteration kernel for the two-label 2-D
+// classes -- each walks its work list, reading the solve's own buffer parity
+// and gap cadence from its slot -- then one bookkeeping launch that takes
+// every solve's convergence decision and advances its counter by its pass
+// length; with d = 2 a second half then runs the one-iteration classes
+// again, followed by a bookkeeping launch for them alone.  Because all of this state lives in
 // device memory, one captured hipGraph of the super-step sequence serves any
 // mix; admission and retirement only edit the tables between replays.
 #pragma once
@@ -29,6 +32,7 @@ struct PoolSlot {
   int pitch;          // row stride (W rounded up to a multiple of 4)
   long long P;        // plane stride (elements)
   int tiles_x, tiles_y, tz, check_every;
+  int bufdiv;         // iterate k lives in state buffer (k / bufdiv) & 1 (2: two-iteration passes)
   const void* cap;
   StateView st[2];
   Coef k;
@@ -59,6 +63,7 @@ struct PoolDev {
 };
 
 const void* pool_kernel(int cls, bool check, bool vec);
+const void* pool_kernel_d2(int cls, bool check);   // two-label 2-D classes
 const void* pool_gap_kernel(int cls);
 const void* pool_book_kernel();
 

@@ -4,11 +4,14 @@
 // tables (slot table, per-slot status, per-class work lists and counts); the
 // rest is carved first-fit into one block per admitted solve (capacities and
 // two state buffers), so admission is decided exactly by footprint.  A
-// super-step launches, for every class, the sweep kernel over the class work
-// list (and, for Potts classes, the per-tile gap kernel) as parallel graph
-// branches, then the bookkeeping kernel; `steps_per_advance` super-steps form
-// one hipGraph, built when the set of classes changes, whose kernel grids are
-// resized in place to the item counts, and replayed by every mf_pool_advance.
+// half-step launches, for every class as a parallel graph branch, the sweep
+// over the class work list (and, for Potts classes, the per-tile gap
+// kernel), then the bookkeeping kernel.  With depth 2 the two-label 2-D
+// classes run a two-iteration pass in every other half-step and sit out the
+// halves between.  The half-steps of one advance (steps_per_advance
+// iterations) form one hipGraph, built when the set of classes changes,
+// whose kernel grids are resized in place to the item counts, and replayed
+// by every mf_pool_advance.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -128,7 +131,8 @@ struct mf_pool {
   char* arena = nullptr;
   size_t arena_bytes = 0;
   hipStream_t stream = nullptr;
-  int max_slots = 0, max_tiles = 0, steps = 0;
+  int max_slots = 0, max_tiles = 0, steps = 0;   // steps: iterations per advance
+  int depth = 1;                                  // iterations per super-step
   PoolDev dev;
   size_t data_off = 0;
   std::vector<std::pair<size_t, size_t>> free_list;   // (offset, size), sorted
@@ -146,6 +150,7 @@ struct mf_pool {
     int cls;
     int book;    // 1: bookkeeping node (fixed grid), else sized by the class's items
     int check;   // bookkeeping: check-step flag argument
+    int only1;   // bookkeeping: second-half flag argument
   };
   std::vector<Node> nodes;
   std::vector<int> node_counts;                         // counts the node grids were set for
@@ -221,13 +226,18 @@ hipKernelNodeParams node_params(const void* func, unsigned grid, unsigned block,
   return kp;
 }
 
-// Build `steps` super-steps for the classes in `mask` as an explicit graph:
-// per class, the sweep (gap-carrying at step 0 for two-label classes) and,
-// at step 0, the per-tile Potts gap, all depending on the previous
-// bookkeeping node; then the bookkeeping node of the step.  Every pool solve
-// checks at multiples of check_every == steps, starting at a replay
-// boundary, so step 0 is the check step of every solve.  Kernel-node grids
-// follow the class item counts (set_grids).
+// Build the super-steps of one advance for the classes in `mask` as an
+// explicit graph.  A half-step launches, per class and in parallel, the
+// sweep (the gap-carrying variant at step 0 for two-label classes) and, at
+// step 0, the per-tile Potts gap, all depending on the previous bookkeeping
+// node, then one bookkeeping node.  Depth 1: steps_per_advance half-steps.
+// Depth 2: steps_per_advance / 2 super-steps of two halves; the first runs
+// every class (the two-label 2-D classes with their two-iteration pass), the
+// second only the one-iteration classes, so a solve that stops at a check
+// keeps its iterate (no sweep past it overwrites its buffer).  Every pool
+// solve checks at multiples of check_every == steps_per_advance, starting
+// at a replay boundary, so step 0 is the check step of every solve.
+// Kernel-node grids follow the class item counts (set_grids).
 mf_status build_graph(mf_pool* P, int mask) {
   if (P->exec) {
     hipGraphExecDestroy(P->exec);
@@ -241,34 +251,39 @@ mf_status build_graph(mf_pool* P, int mask) {
   PHIP(hipGraphCreate(&P->graph, 0));
   hipGraphNode_t prev = nullptr;
   PoolDev dev = P->dev;
-  for (int s = 0; s < P->steps; s++) {
-    const bool cstep = s == 0;
+  const int nhalf = P->steps;   // half-steps: one iteration of the one-iteration classes each
+  for (int h = 0; h < nhalf; h++) {
+    const bool cstep = h == 0;
+    const bool second = P->depth == 2 && (h & 1);   // the one-iteration classes only
     std::vector<hipGraphNode_t> step_nodes;
     for (int c = 0; c < kPoolClasses; c++) {
       if (!(mask & (1 << c))) continue;
       const int model = c % kPoolModels;
+      const bool d2 = P->depth == 2 && model == 0;
+      if (second && d2) continue;
       const bool fused_gap = model == 0 || model == 5;
-      int cls = c;
-      void* args[] = {&dev, &cls};
-      const void* fs[2] = {pool_kernel(c, cstep && fused_gap, true), (cstep && !fused_gap) ? pool_gap_kernel(c) : nullptr};
+      const void* fs[2] = {d2 ? pool_kernel_d2(c, cstep) : pool_kernel(c, cstep && fused_gap, true),
+                           (cstep && !fused_gap) ? pool_gap_kernel(c) : nullptr};
       for (const void* f : fs) {
         if (!f) continue;
+        int cls = c;
+        void* args[] = {&dev, &cls};
         hipKernelNodeParams kp = node_params(f, grid_for(P->counts[c]), 256, args);
         hipGraphNode_t n;
         PHIP(hipGraphAddKernelNode(&n, P->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
         step_nodes.push_back(n);
-        P->nodes.push_back({n, f, c, 0, 0});
+        P->nodes.push_back({n, f, c, 0, 0, 0});
       }
     }
-    int chk = cstep ? 1 : 0;
-    void* bargs[] = {&dev, &chk};
+    int chk = cstep ? 1 : 0, only1 = second ? 1 : 0;
+    void* bargs[] = {&dev, &chk, &only1};
     hipKernelNodeParams kb = node_params(pool_book_kernel(), (unsigned)P->max_slots, 64, bargs);
     hipGraphNode_t b;
     if (step_nodes.empty())
       PHIP(hipGraphAddKernelNode(&b, P->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kb));
     else
       PHIP(hipGraphAddKernelNode(&b, P->graph, step_nodes.data(), step_nodes.size(), &kb));
-    P->nodes.push_back({b, pool_book_kernel(), -1, 1, chk});
+    P->nodes.push_back({b, pool_book_kernel(), -1, 1, chk, only1});
     prev = b;
   }
   PHIP(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
@@ -316,6 +331,7 @@ void fill_image(mf_pool* P, int slot, long long iter) {
   S.tiles_y = f.g.ndim == 2 ? (f.g.H + TY - 1) / TY : (f.g.H + 7) / 8;
   S.tz = f.g.ndim == 3 ? std::min(f.g.D, 16) : 1;
   S.check_every = f.p.check_every;
+  S.bufdiv = (P->depth == 2 && f.model == 0) ? 2 : 1;
   S.cap = P->arena + H.off;
   S.st[0] = H.st[0];
   S.st[1] = H.st[1];
@@ -371,8 +387,9 @@ mf_status promote(mf_pool* P, int slot, long long k, bool& moved) {
   if (!alloc_block(P, f2.total, off)) return MF_OK;   // no room yet: stays frozen
   char* base = P->arena + off;
   StateView n0 = carve(base + f2.cap_bytes, f2), n1 = carve(base + f2.cap_bytes + f2.state_bytes, f2);
-  const StateView src = H.st[k & 1];
-  const StateView& dst = (k & 1) ? n1 : n0;
+  const int b = (int)((k / P->slot_img[slot].bufdiv) & 1);   // the buffer of iterate k (same in both classes)
+  const StateView src = H.st[b];
+  const StateView& dst = b ? n1 : n0;
   const long long n = H.f.g.plane, pl = H.f.g.plane;   // whole planes, pads included
   PHIP(launch_convert_planes(P->arena + H.off, true, base, false, n, H.f.ncap, pl, pl, P->stream));
   PHIP(launch_convert_planes(src.u, false, dst.u, false, n, H.f.nl, pl, pl, P->stream));
@@ -430,13 +447,16 @@ size_t mf_pool_table_bytes(int32_t max_slots, int32_t max_tiles) {
 }
 
 mf_status mf_pool_create(void* arena, size_t arena_bytes, int32_t max_slots, int32_t max_tiles,
-                         int32_t steps_per_advance, void* hip_stream, mf_pool** out) {
+                         int32_t steps_per_advance, int32_t depth, void* hip_stream, mf_pool** out) {
   if (!out) return pfail(MF_EINVAL, "out is null");
   *out = nullptr;
   if (!arena || ((uintptr_t)arena & 255)) return pfail(MF_EINVAL, "arena must be a 256-byte aligned device pointer");
   if (!hip_stream) return pfail(MF_EINVAL, "the pool needs a created (non-default) stream for graph capture");
   if (max_slots < 1 || max_slots > 65536 || max_tiles < 1 || steps_per_advance < 1)
     return pfail(MF_EINVAL, "max_slots in [1, 65536], max_tiles >= 1, steps_per_advance >= 1");
+  if (depth == 0) depth = steps_per_advance % 2 == 0 ? 2 : 1;
+  if (depth != 1 && depth != 2) return pfail(MF_EINVAL, "depth must be 0, 1 or 2");
+  if (steps_per_advance % depth != 0) return pfail(MF_EINVAL, "steps_per_advance must be a multiple of depth");
   const size_t tb = mf_pool_table_bytes(max_slots, max_tiles);
   if (arena_bytes <= tb) return pfail(MF_ENOMEM, "arena smaller than the pool tables");
   mf_pool* P = new (std::nothrow) mf_pool();
@@ -447,6 +467,7 @@ mf_status mf_pool_create(void* arena, size_t arena_bytes, int32_t max_slots, int
   P->max_slots = max_slots;
   P->max_tiles = max_tiles;
   P->steps = steps_per_advance;
+  P->depth = depth;
   size_t off = 0;
   P->dev.slots = (PoolSlot*)(P->arena + off);
   off += al(sizeof(PoolSlot) * (size_t)max_slots);
@@ -598,7 +619,7 @@ mf_status mf_pool_retire(mf_pool* P, int64_t solve_id, float* u_dst, int32_t* la
   PHIP(hipMemcpyAsync(P->stats_h + slot, P->dev.stats + slot, sizeof(PoolStat), hipMemcpyDeviceToHost, P->stream));
   PHIP(hipStreamSynchronize(P->stream));
   const long long it = P->stats_h[slot].iter;
-  const StateView& v = H.st[it & 1];
+  const StateView& v = H.st[(it / P->slot_img[slot].bufdiv) & 1];
   const long long rows = (long long)H.f.g.H * H.f.g.D;
   if (u_dst)
     PHIP(launch_pitch_copy(v.u, false, H.f.g.plane, H.f.pitch, u_dst, false, H.f.g.npix(), H.f.g.W, H.f.g.W, rows,

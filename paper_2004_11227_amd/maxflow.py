@@ -314,7 +314,8 @@ _POOL_SIG = {
     "mf_pool_footprint": (ctypes.c_size_t, [ctypes.POINTER(mf_params)]),
     "mf_pool_table_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "mf_pool_create": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
-                                        ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
     "mf_pool_admit": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(mf_params), ctypes.c_void_p,
                                        ctypes.POINTER(ctypes.c_int64)]),
     "mf_pool_advance": (ctypes.c_int32, [ctypes.c_void_p]),
@@ -351,18 +352,20 @@ def pool_footprint(shape, **kw) -> int:
 class Pool:
     """Continuous-batching pool over one device arena (a torch uint8 tensor
     owned here).  admit() returns a solve id, or None when the arena, the slot
-    table or the class work list is full (MF_ENOMEM)."""
+    table or the class work list is full (MF_ENOMEM).  ``depth``: iterations
+    per super-step (0: 2 when steps_per_advance is even, else 1)."""
 
     def __init__(self, arena_bytes: int, max_slots: int = 256, max_tiles: int = 1 << 16,
-                 steps_per_advance: int = 10, device=None, stream: torch.cuda.Stream | None = None):
+                 steps_per_advance: int = 10, device=None, stream: torch.cuda.Stream | None = None,
+                 depth: int = 0):
         L = _pool_lib()
         self.device = torch.device(device or "cuda")
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
         h = ctypes.c_void_p()
         _check(L.mf_pool_create(ctypes.c_void_p(self.arena.data_ptr()), int(arena_bytes), int(max_slots),
-                                int(max_tiles), int(steps_per_advance), ctypes.c_void_p(self.stream.cuda_stream),
-                                ctypes.byref(h)))
+                                int(max_tiles), int(steps_per_advance), int(depth),
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self._h = h
         self.max_slots = max_slots
         self.meta = {}

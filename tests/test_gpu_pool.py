@@ -46,8 +46,8 @@ def _mix():
     return out
 
 
-def _run_pool(items, steps=10):
-    pool = mfx.Pool(1 << 30, max_slots=64, max_tiles=1 << 15, steps_per_advance=steps)
+def _run_pool(items, steps=10, depth=0):
+    pool = mfx.Pool(1 << 30, max_slots=64, max_tiles=1 << 15, steps_per_advance=steps, depth=depth)
     ids = [pool.admit(c, **kw) for c, kw in items]
     assert all(i is not None for i in ids)
     res = {}
@@ -73,6 +73,30 @@ def test_alone_equals_mix_bitwise():
         assert gm["status"] in (0, 1)
         if gm["status"] == 0:
             assert gm["rel_gap"] <= 1e-4
+
+
+def test_pool_depth2_equals_depth1_bitwise():
+    """Two iterations per super-step (the two-iteration pass for the
+    two-label 2-D solves, two sweeps for the others) give the iterates,
+    stop iterations and gaps of one-iteration super-steps, promotions
+    included."""
+    banner("pool depth 2 vs depth 1")
+    items = _mix()
+    d1 = _run_pool(items, depth=1)
+    d2 = _run_pool(items, depth=2)
+    for k, (a, b) in enumerate(zip(d1, d2)):
+        assert a[0]["iter"] == b[0]["iter"] and a[0]["status"] == b[0]["status"], (k, a[0], b[0])
+        assert a[0]["rel_gap"] == b[0]["rel_gap"], k
+        assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2]), k
+
+
+def test_pool_depth_rules():
+    with pytest.raises(mfx.MaxflowError):
+        mfx.Pool(1 << 24, max_slots=2, max_tiles=64, steps_per_advance=5, depth=2)
+    with pytest.raises(mfx.MaxflowError):
+        mfx.Pool(1 << 24, max_slots=2, max_tiles=64, steps_per_advance=10, depth=3)
+    p = mfx.Pool(1 << 24, max_slots=2, max_tiles=64, steps_per_advance=5)   # depth 1
+    p.close()
 
 
 @pytest.mark.parametrize("model,n,storage", [("two", 2, "bf16"), ("potts", 4, "bf16"), ("two", 2, "f32"),
