@@ -149,8 +149,7 @@ def traffic_for(launch_bytes):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU; multi-GPU runs are not supported "
-              "(the solver is single-device; see DESIGN.md for the sharding design)", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU; runs on several GPUs are not supported", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

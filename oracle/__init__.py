@@ -1,7 +1,7 @@
 """FP64 CPU oracle for the continuous max-flow methods (TEST INFRASTRUCTURE).
 
-Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
-``bench.py`` may import this package.  The solver never does: it shares no
+Only the test suite, the smoke check and the CPU-baseline leg of ``bench.py``
+may import this package.  The solver never does: it shares no
 code with this oracle.  The arithmetic lives in ``oracle.c`` (plain C loops in
 double precision, following the paper's equations); this module only
 marshals numpy arrays through ctypes and adds the pure-Python brute-force
