@@ -87,6 +87,7 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--serving-requests", type=int, default=128,
                     help="requests of the serving mix in the secondary measurements (0: skip)")
+    ap.add_argument("--profile-sweeps", type=int, default=200, help="iterations run in --profile-mode")
     ap.add_argument("--profile-mode", nargs="?", const="two_2048", default=None,
                     choices=sorted(PROFILE_WORKLOADS))
     return ap.parse_args()
@@ -178,10 +179,11 @@ def main():
         pc = synth.config_inputs(cfg, size=size)["caps"] if size else synth.config_inputs(cfg)["caps"]
         pt = torch.from_numpy(pc.astype(np.float32)).to(dev)
         s = make_solver(torch, maxflow, pt, stream, **pkw)
-        s.step(30)
+        # enough sweeps that the launch average is the steady state's
+        s.step(args.profile_sweeps)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_mode": args.profile_mode, "copy_bytes": src.numel() * 4, "sweeps": 30,
-                          "shape": list(pc.shape[1:])}))
+        print(json.dumps({"profile_mode": args.profile_mode, "copy_bytes": src.numel() * 4,
+                          "sweeps": args.profile_sweeps, "shape": list(pc.shape[1:])}))
         return
 
     s = make_solver(torch, maxflow, caps_t, stream, **kw)

@@ -747,27 +747,33 @@ mf_status maxflow_tune(mf_solver* s, int32_t sweeps, int32_t what, mf_tuning* ou
   const bool fused = p.variant == MF_FUSED;
   const bool two = p.model == MF_TWO_LABEL;
   const bool d3 = s->r.g.ndim == 3;
-  // the candidate list
+  // the candidate list: the free knobs range over their values, the others
+  // keep the solver's
   std::vector<mf_tune_cand> cand;
-  auto add = [&](int rows, int depth, int slab) {
-    if (!(what & MF_TUNE_TILE) && rows != p.tile_rows) return;
-    if (!(what & MF_TUNE_DEPTH) && depth != p.depth) return;
-    if (!(what & MF_TUNE_SLAB) && slab != p.slab_depth) return;
-    cand.push_back(mf_tune_cand{rows, depth, slab, 0.0});
-  };
-  if (dr) {
-    if (dr_fused(s->r))
-      for (int rows : {16, 32}) add(rows, 1, p.slab_depth);
-  } else if (fused && !d3 && two) {
-    for (int rows : {8, 16, 32}) add(rows, 1, p.slab_depth);
-    for (int rows : {16, 32}) add(rows, 2, p.slab_depth);
-  } else if (fused && !d3) {
-    for (int rows : {8, 16, 32})
-      if (!(rows == 32 && p.nlabels > 4)) add(rows, 1, p.slab_depth);
-  } else if (fused && d3 && two) {
-    for (int rows : {8, 16})
-      for (int slab : {8, 16, 32}) add(rows, 1, slab);
-  }
+  const std::vector<int> rows_all = {8, 16, 32}, depth_all = {1, 2}, slab_all = {8, 16, 32};
+  const std::vector<int> rows_l = (what & MF_TUNE_TILE) ? rows_all : std::vector<int>{p.tile_rows};
+  const std::vector<int> depth_l = (what & MF_TUNE_DEPTH) ? depth_all : std::vector<int>{p.depth};
+  int shape_kind = 0;   // 0: no launch-shape choice
+  if (dr && dr_fused(s->r)) shape_kind = 1;          // fused rPDRQ: 16 or 32 rows
+  else if (!dr && fused && !d3 && two) shape_kind = 2;   // depth 1: 8/16/32 rows; depth 2: 16/32
+  else if (!dr && fused && !d3) shape_kind = 3;          // Potts: 8/16/32 rows (8/16 for n > 4)
+  else if (!dr && fused && d3 && two) shape_kind = 4;    // 3-D: 8/16 rows x slab depths
+  // the slab depth only shapes the 3-D sweep
+  const std::vector<int> slab_l =
+      (shape_kind == 4 && (what & MF_TUNE_SLAB)) ? slab_all : std::vector<int>{p.slab_depth};
+  for (int rows : rows_l)
+    for (int depth : depth_l)
+      for (int slab : slab_l) {
+        bool ok = false;
+        switch (shape_kind) {
+          case 1: ok = (rows == 16 || rows == 32) && depth == 1; break;
+          case 2: ok = depth == 1 || rows != 8; break;
+          case 3: ok = depth == 1 && !(rows == 32 && p.nlabels > 4); break;
+          case 4: ok = rows != 32 && depth == 1; break;
+          default: ok = false;
+        }
+        if (ok) cand.push_back(mf_tune_cand{rows, depth, slab, 0.0});
+      }
   if (cand.empty() && !(dr && !dr_fused(s->r)))   // the one configuration
     cand.push_back(mf_tune_cand{p.tile_rows, p.depth, p.slab_depth, 0.0});
   if ((int)cand.size() > 16) cand.resize(16);
