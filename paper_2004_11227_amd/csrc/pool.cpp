@@ -275,6 +275,8 @@ mf_status build_graph(mf_pool* P, int mask) {
         P->nodes.push_back({n, f, c, 0, 0, 0});
       }
     }
+    // a second half with no one-iteration class has nothing to advance
+    if (second && step_nodes.empty()) continue;
     int chk = cstep ? 1 : 0, only1 = second ? 1 : 0;
     void* bargs[] = {&dev, &chk, &only1};
     hipKernelNodeParams kb = node_params(pool_book_kernel(), (unsigned)P->max_slots, 64, bargs);
