@@ -188,7 +188,7 @@ def run_sequential(requests, caps_of, kw_of, stream=None, clock=time.perf_counte
 def benchmark(nreq: int = 128, seed: int = 4000, pool_storage: str = "bf16", tol: float = 1e-4,
               max_iter: int = 1000, arena_bytes: int = 48 << 30, max_slots: int = 256,
               steps_per_advance: int = 10, latency_load: float = 0.7, promote_gap: float = 2e-3,
-              promote_iter: int = 200, working_set: int | None = None, log=None) -> dict:
+              promote_iter: int = 400, working_set: int | None = None, log=None) -> dict:
     """Serving workload: `nreq` requests of the mixed trace (2-D sides
     log-uniform on [64, 2048], 10 % 3-D 128^3, labels in {2,3,4,8}), each run
     to relative gap `tol` or `max_iter` iterations.
