@@ -213,7 +213,7 @@ def main():
     achieved = launch_bytes / t_launch
     roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
             "frac": achieved / PEAK_HBM, "traffic": traffic_for(launch_bytes),
-            "kernel": f"k_fused2d_d2<float, false, {wl['tile_rows']}> (two iterations per launch)",
+            "kernel": f"k_fused2d_d2<float, false, {wl['tile_rows']}, false> (two iterations per launch)",
             "bytes_per_launch": launch_bytes, "avg_launch_us": t_launch * 1e6,
             "iterations_per_launch": wl["depth"]}
     s.close()
