@@ -276,6 +276,9 @@ def secondary(torch, maxflow, synth, np, dev, stream):
         for stg in ("f32", "bf16"):
             sweep_rate(f"potts{n}_1024_fused_{stg}", caps, alg_bytes("potts", n, 2, stg),
                        model="potts", nlabels=n, method="eb", alpha=0.3, storage=stg)
+        for var, tag in (("fused", "fused"), ("unfused", "inplace")):
+            sweep_rate(f"potts{n}_1024_pdrq_f32_{tag}", caps, alg_bytes("potts", n, 2, "f32"), model="potts",
+                       nlabels=n, method="dr", alpha=0.3, variant=var)
     # capacities generated from the image plane (the same workloads' data
     # costs |I - l|^p): one plane read instead of 2 or n
     img1 = synth.config_inputs("c1")["image"][None]

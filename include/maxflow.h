@@ -238,7 +238,7 @@ mf_status maxflow_destroy(mf_solver* s);
  *     16, 32 rows;
  *   fused 2-D Potts: 8, 16, 32 rows (8, 16 for n = 8);
  *   fused 3-D two-label: 8 or 16 rows x slab depths 8, 16, 32;
- *   fused two-label 2-D rPDRQ: 16, 32 rows;
+ *   fused 2-D rPDRQ (two-label or Potts, one sweep): 16, 32 rows;
  *   any other solver: its one configuration, timed.
  * Each candidate is timed over `sweeps` passes (after two warm-up passes) on
  * the solver's stream with HIP events, from the solver's current iterate k

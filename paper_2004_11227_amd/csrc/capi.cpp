@@ -174,7 +174,7 @@ std::string resolve(const mf_params* in, Resolved& r) {
   // owned group of a tile is one vector access whatever the width; the
   // element-wise kernels (unfused passes, in-place rPDRQ) use the dense layout.
   const bool padded = p.variant == MF_FUSED && !(p.ndim == 3 && p.model == MF_POTTS) &&
-                      (p.method != MF_RPDRQ || (two && p.ndim == 2 && p.gs_sweeps == 1));
+                      (p.method != MF_RPDRQ || (p.ndim == 2 && p.gs_sweeps == 1));
   r.g.pitch = padded ? (r.g.W + 3) / 4 * 4 : r.g.W;
   r.g.plane = (long long)align_up((size_t)r.g.nstore(), 128);
   r.esz = p.storage == MF_BF16 ? 2 : 4;
@@ -187,11 +187,10 @@ struct Layout {
   size_t state_bytes;
 };
 
-// rPDRQ as one tiled pass per iteration (two-label 2-D, fused variant);
+// rPDRQ as one tiled pass per iteration (2-D, one sweep, fused variant);
 // otherwise three in-place element-wise launches.
 bool dr_fused(const Resolved& r) {
-  return r.p.method == MF_RPDRQ && r.p.variant == MF_FUSED && r.p.model == MF_TWO_LABEL && r.p.ndim == 2 &&
-         r.p.gs_sweeps == 1;
+  return r.p.method == MF_RPDRQ && r.p.variant == MF_FUSED && r.p.ndim == 2 && r.p.gs_sweeps == 1;
 }
 
 Layout plan(const Resolved& r) {

@@ -18,26 +18,26 @@
 //        y = y-bar + tau K u and the relaxed reflection
 //        y-bar += rho (prox(2y - y-bar) - y) in place (each cell touches only
 //        its own flows; b is read from its plane, not recomputed).
-// The two-label 2-D model also has a fused tiled pass (tiledr.h) that runs
-// the same per-cell arithmetic with the state read once and written once
-// into the other ping-pong buffer.
+// 2-D solves (two-label and Potts) also have a fused tiled pass (tiledr.h)
+// that runs the same per-cell arithmetic with the state read once and
+// written once into the other ping-pong buffer.
 #include "mf_kernels.h"
 #include "tiledr.h"
 
 namespace mf {
 
-template <typename TS, int TY>
+template <typename TS, int TY, int NL, bool TWO>
 __global__ __launch_bounds__(256) void k_dr_fused2d(const KDF<TS> A) {
-  __shared__ SmemDR<TY> S;
+  __shared__ SmemDR<TY, TWO> S;
   if (A.done && *A.done) return;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % A.tiles_x) * 64;
   const int y0 = (tile / A.tiles_x) * TY;
-  tile_dr2d<TS, TY>(A, x0, y0, S);
+  tile_dr2d<TS, TY, NL, TWO>(A, x0, y0, S);
 }
 
-template <typename TS>
-static hipError_t dr_fused_ts(const PdrqDesc& d, hipStream_t s) {
+template <typename TS, int NL, bool TWO>
+static hipError_t dr_fused_nl(const PdrqDesc& d, hipStream_t s) {
   KDF<TS> a;
   a.W = d.g.W;
   a.H = d.g.H;
@@ -61,17 +61,29 @@ static hipError_t dr_fused_ts(const PdrqDesc& d, hipStream_t s) {
   a.rho = d.rho;
   a.inv_st = d.inv_st;
   a.alpha = d.alpha;
-  a.m = 2.f;
+  a.m = TWO ? 2.f : (float)(NL + 1);
   a.iso = d.iso ? 1 : 0;
   a.keep_z = d.keep_z ? 1 : 0;
   a.done = d.done;
   a.cg = d.cg;
   if (d.tile_rows == 32) {
-    hipLaunchKernelGGL((k_dr_fused2d<TS, 32>), dim3(a.tiles_x * ((d.g.H + 31) / 32)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_dr_fused2d<TS, 32, NL, TWO>), dim3(a.tiles_x * ((d.g.H + 31) / 32)), dim3(256), 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_dr_fused2d<TS, 16>), dim3(a.tiles_x * ((d.g.H + 15) / 16)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_dr_fused2d<TS, 16, NL, TWO>), dim3(a.tiles_x * ((d.g.H + 15) / 16)), dim3(256), 0, s, a);
   }
   return hipGetLastError();
+}
+
+template <typename TS>
+static hipError_t dr_fused_ts(const PdrqDesc& d, hipStream_t s) {
+  if (d.two) return dr_fused_nl<TS, 1, true>(d, s);
+  switch (d.nl) {
+    case 2: return dr_fused_nl<TS, 2, false>(d, s);
+    case 3: return dr_fused_nl<TS, 3, false>(d, s);
+    case 4: return dr_fused_nl<TS, 4, false>(d, s);
+    case 8: return dr_fused_nl<TS, 8, false>(d, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename TS>
@@ -317,7 +329,7 @@ static hipError_t dr_ts(const PdrqDesc& d, hipStream_t s) {
 hipError_t launch_pdrq_iter(const PdrqDesc& d, hipStream_t s) {
   if (d.sweeps < 1) return hipErrorInvalidValue;
   if (d.fused) {
-    if (!d.two || d.g.ndim != 2 || d.g.pitch % 4 != 0 || d.sweeps != 1) return hipErrorInvalidValue;
+    if (d.g.ndim != 2 || d.g.pitch % 4 != 0 || d.sweeps != 1) return hipErrorInvalidValue;
     return d.bf16 ? dr_fused_ts<bf16_t>(d, s) : dr_fused_ts<float>(d, s);
   }
   if (d.g.pitch != d.g.W) return hipErrorInvalidValue;   // element-wise sweeps use the dense layout

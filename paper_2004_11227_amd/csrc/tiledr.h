@@ -1,18 +1,21 @@
-// Fused rPDRQ iteration for the two-label 2-D model: one 64 x TY tile per
-// workgroup, state read once and written once (ping-pong buffers).
+// Fused rPDRQ iteration for the 2-D two-label and Potts models: one 64 x TY
+// tile per workgroup, state read once and written once (ping-pong buffers).
 //
 // With T+[a,b] the tile grown by a cells on its low and b on its high sides:
 // the flows of the tile need the final u on T+[0,+1]; the final red cells
 // there need the black cells on T+[-1,+2], which need the first red cells on
 // T+[-2,+3], which need the old u on T+[-3,+4] and b on T+[-2,+3]; b needs
-// q-bar on T+[-3,+3] and p-bar on T+[-2,+3].  The pass stages u, q-bar,
-// p-bar_s, p-bar_t on T+[-3,+4] (columns widened to whole 4-element groups,
-// -4 .. 67), forms b on T+[-2,+3], runs the red, black, red half-sweeps of
-// the symmetric Gauss-Seidel step on the shrinking regions in LDS, then the
-// flows, the relaxed reflection and the stores on the tile.  Each cell's
-// arithmetic (b, the Gauss-Seidel value with its neighbours summed in the
-// order -x, +x, -y, +y, the flows and the reflection) is that of the three
-// in-place launches, so both variants give the same bits.
+// q-bar on T+[-3,+3] and p-bar on T+[-2,+3].  Per label the pass stages u,
+// q-bar and p-bar of the label on T+[-3,+4] (columns widened to whole
+// 4-element groups, -4 .. 67; p-bar_s, and for Potts the label sum of u,
+// once for all labels), forms b on T+[-2,+3], runs the red, black, red
+// half-sweeps of the symmetric Gauss-Seidel step on the shrinking regions in
+// LDS, then the label's flows, relaxed reflection and stores on the tile;
+// p-bar_s follows the last label.  Each cell's arithmetic (b with the Potts
+// coupling st (n u_i - sum_j u_j), the Gauss-Seidel value with its
+// neighbours summed in the order -x, +x, -y, +y, the flows, the reflection,
+// the label sum of the new u in label order) is that of the three in-place
+// launches, so both variants give the same bits.
 #pragma once
 #include "mf_kernels.h"
 
@@ -38,10 +41,10 @@ struct KDF {
   float sigma, tau, rho, inv_st, alpha, m;
   int iso, keep_z;
   const int* done;
-  CapGen cg;            // cg.img: `cap` is one image plane (read into ocs)
+  CapGen cg;            // cg.img: `cap` is one image plane
 };
 
-template <int TY>
+template <int TY, bool TWO>
 struct SmemDR {
   static constexpr int SW = 72;       // cols -4 .. 67
   static constexpr int SH = TY + 7;   // rows -3 .. TY+3
@@ -49,18 +52,20 @@ struct SmemDR {
   __align__(16) float sqx[SH][SW];
   __align__(16) float sqy[SH][SW];
   __align__(16) float sps[SH][SW];
-  __align__(16) float spt[SH][SW];
+  __align__(16) float spt[SH][SW];    // p-bar of the label (p-bar_t for two labels)
   __align__(16) float sb[SH][SW];
+  __align__(16) float sus[TWO ? 1 : SH][TWO ? 1 : SW];   // Potts: sum over labels of u^k
 };
 
-template <typename TS, int TY>
-__device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, SmemDR<TY>& S) {
+template <typename TS, int TY, int NL, bool TWO>
+__device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, SmemDR<TY, TWO>& S) {
   constexpr int TX = 64, V = 4, TPR = TX / V, RSTEP = 256 / TPR, RPT = TY / RSTEP;
   constexpr int OX = 4, OY = 3;
   constexpr int GPR = 18;
   constexpr int NG = (TY + 7) * GPR;
   constexpr int KG = (NG + 255) / 256;
   static_assert(RPT >= 1, "tile height must be a multiple of 16");
+  static_assert(!TWO || NL == 1, "the two-label model carries one label");
   auto& su = S.su;
   auto& sqx = S.sqx;
   auto& sqy = S.sqy;
@@ -71,8 +76,8 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
   const int W = A.W, H = A.H, pitch = A.pitch;
   const long long P = A.P;
 
-  // ---- stage u, q-bar, p-bar_s, p-bar_t on rows -3 .. TY+3, cols -4 .. 67
-  float lu[KG][V], lqx[KG][V], lqy[KG][V], lps[KG][V], lpt[KG][V];
+  // this thread's staged groups (rows -3 .. TY+3, cols -4 .. 67)
+  long long gi[KG];
   int gnv[KG];
 #pragma unroll
   for (int m = 0; m < KG; m++) {
@@ -81,55 +86,74 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
     const int gy = y0 + r, gx = x0 + c;
     const int nv = (h < NG && gy >= 0 && gy < H && gx >= 0) ? (W - gx >= V ? V : (W - gx > 0 ? W - gx : 0)) : 0;
     gnv[m] = nv;
-    const long long i = nv > 0 ? (long long)gy * pitch + gx : 0;
-    ldv<V>(A.u_in, i, lu[m]);
-    ldv<V>(A.qb_in, i, lqx[m]);
-    ldv<V>(A.qb_in + P, i, lqy[m]);
-    ldv<V>(A.psb_in, i, lps[m]);
-    ldv<V>(A.pb_in, i, lpt[m]);
+    gi[m] = nv > 0 ? (long long)gy * pitch + gx : 0;
   }
+  // write staged groups into an LDS array (entries outside the grid: 0)
+  auto put = [&](float (*dst)[SmemDR<TY, TWO>::SW], int m, const float (&v)[V]) {
+    const int h = tid + 256 * m;
+    if (h < NG) {
+      const int r = h / GPR, c = (h % GPR) * 4;
+#pragma unroll
+      for (int e = 0; e < V; e++) dst[r][c + e] = e < gnv[m] ? v[e] : 0.f;
+    }
+  };
+  // owned groups
   const int c0 = (tid % TPR) * V;
   const int rr0 = tid / TPR;
   const int gx0 = x0 + c0;
   const int nvx = W - gx0 < 0 ? 0 : (W - gx0 > V ? V : W - gx0);
   int nvj[RPT];
   long long oj[RPT];
-  float ocs[RPT][V], oct[RPT][V];
 #pragma unroll
   for (int j = 0; j < RPT; j++) {
     const int gy = y0 + rr0 + RSTEP * j;
     nvj[j] = gy < H ? nvx : 0;
     oj[j] = (long long)gy * pitch + gx0;
-    ldv<V>(A.cap, nvj[j] > 0 ? oj[j] : 0, ocs[j]);
-    if (!A.cg.img) ldv<V>(A.cap + P, nvj[j] > 0 ? oj[j] : 0, oct[j]);
   }
+  // capacities of the owned groups: plane `pl` (raw), or the image plane
+  const bool img = A.cg.img != 0;
+  auto load_cap = [&](int pl, float (&o)[RPT][V]) {
 #pragma unroll
-  for (int m = 0; m < KG; m++) {
-    const int h = tid + 256 * m;
-    if (h < NG) {
-      const int r = h / GPR, c = (h % GPR) * 4;
+    for (int j = 0; j < RPT; j++) ldv<V>(A.cap + (img ? 0 : (long long)pl * P), nvj[j] > 0 ? oj[j] : 0, o[j]);
+  };
+  auto cap_val = [&](float raw, int lv) { return img ? cap_from(raw, A.cg.lv[lv], A.cg.pw) : raw; };
+
+  // ---- label-independent staging: p-bar_s and (Potts) the label sum of u^k
+  {
+    float lps[KG][V];
 #pragma unroll
-      for (int e = 0; e < V; e++) {
-        const bool ok = e < gnv[m];
-        su[r][c + e] = ok ? lu[m][e] : 0.f;
-        sqx[r][c + e] = ok ? lqx[m][e] : 0.f;
-        sqy[r][c + e] = ok ? lqy[m][e] : 0.f;
-        sps[r][c + e] = ok ? lps[m][e] : 0.f;
-        spt[r][c + e] = ok ? lpt[m][e] : 0.f;
+    for (int m = 0; m < KG; m++) ldv<V>(A.psb_in, gi[m], lps[m]);
+    if constexpr (!TWO) {
+      float acc[KG][V];
+#pragma unroll
+      for (int m = 0; m < KG; m++)
+#pragma unroll
+        for (int e = 0; e < V; e++) acc[m][e] = 0.f;
+#pragma unroll
+      for (int l = 0; l < NL; l++) {
+        float lu[KG][V];
+#pragma unroll
+        for (int m = 0; m < KG; m++) ldv<V>(A.u_in + (long long)l * P, gi[m], lu[m]);
+#pragma unroll
+        for (int m = 0; m < KG; m++)
+#pragma unroll
+          for (int e = 0; e < V; e++) acc[m][e] += lu[m][e];
       }
+#pragma unroll
+      for (int m = 0; m < KG; m++) put(S.sus, m, acc[m]);
     }
+#pragma unroll
+    for (int m = 0; m < KG; m++) put(sps, m, lps[m]);
   }
-  lds_barrier();
-  // ---- b = -sigma (div q-bar + p-bar_t - p-bar_s) on T+[-2,+3]
-  for (int h = tid; h < (TY + 5) * (TX + 5); h += 256) {
-    const int r = h / (TX + 5) - 2, c = h % (TX + 5) - 2;
-    const int hx = x0 + c, hy = y0 + r;
-    const int R = r + OY, C = c + OX;
-    const float d = ((hx + 1 < W ? sqx[R][C] : 0.f) - (hx > 0 ? sqx[R][C - 1] : 0.f)) +
-                    ((hy + 1 < H ? sqy[R][C] : 0.f) - (hy > 0 ? sqy[R - 1][C] : 0.f));
-    sb[R][C] = -A.sigma * ((d + spt[R][C]) - sps[R][C]);
-  }
-  lds_barrier();
+  float ocs[RPT][V];   // two labels: C_s
+  if (TWO) load_cap(0, ocs);
+  float usn[RPT][V];   // sum over labels of the new u (label order)
+#pragma unroll
+  for (int j = 0; j < RPT; j++)
+#pragma unroll
+    for (int e = 0; e < V; e++) usn[j][e] = 0.f;
+  const float tau = A.tau, rho = A.rho;
+
   // Gauss-Seidel value of cell (r, c) from its neighbours in su
   auto gs = [&](int r, int c) {
     const int hx = x0 + c, hy = y0 + r;
@@ -152,67 +176,120 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
       if (c < clo + nc) su[r + OY][c + OX] = gs(r, c);
     }
   };
-  // ---- red cells of T+[-2,+3], black cells of T+[-1,+2], red cells of T+[0,+1]
-  half_sweep(-2, TY + 5, -2, TX + 5, 0);
-  lds_barrier();
-  half_sweep(-1, TY + 3, -1, TX + 3, 1);
-  lds_barrier();
-  half_sweep(0, TY + 1, 0, TX + 1, 0);
-  lds_barrier();
-  // ---- flows y = y-bar + tau K u and the relaxed reflection on the owned groups
-  const float tau = A.tau, rho = A.rho;
+
+#pragma unroll 1
+  for (int l = 0; l < NL; l++) {
+    // ---- stage u, q-bar, p-bar of label l on rows -3 .. TY+3, cols -4 .. 67
+    {
+      const float* u_in = A.u_in + (long long)l * P;
+      const TS* qx_in = A.qb_in + (long long)(2 * l) * P;
+      const TS* pb_in = A.pb_in + (long long)l * P;
+      float lu[KG][V], lqx[KG][V], lqy[KG][V], lpt[KG][V];
+#pragma unroll
+      for (int m = 0; m < KG; m++) {
+        ldv<V>(u_in, gi[m], lu[m]);
+        ldv<V>(qx_in, gi[m], lqx[m]);
+        ldv<V>(qx_in + P, gi[m], lqy[m]);
+        ldv<V>(pb_in, gi[m], lpt[m]);
+      }
+#pragma unroll
+      for (int m = 0; m < KG; m++) {
+        put(su, m, lu[m]);
+        put(sqx, m, lqx[m]);
+        put(sqy, m, lqy[m]);
+        put(spt, m, lpt[m]);
+      }
+    }
+    float ocl[RPT][V];   // C_t (two labels) or C_l, raw
+    load_cap(TWO ? 1 : l, ocl);
+    lds_barrier();
+    // ---- b on T+[-2,+3]: -sigma (div q-bar + p-bar - p-bar_s) (+ st (n u - sum u) for Potts)
+    for (int h = tid; h < (TY + 5) * (TX + 5); h += 256) {
+      const int r = h / (TX + 5) - 2, c = h % (TX + 5) - 2;
+      const int hx = x0 + c, hy = y0 + r;
+      const int R = r + OY, C = c + OX;
+      const float d = ((hx + 1 < W ? sqx[R][C] : 0.f) - (hx > 0 ? sqx[R][C - 1] : 0.f)) +
+                      ((hy + 1 < H ? sqy[R][C] : 0.f) - (hy > 0 ? sqy[R - 1][C] : 0.f));
+      float bl = -A.sigma * ((d + spt[R][C]) - sps[R][C]);
+      if constexpr (!TWO) bl += (A.sigma * A.tau) * ((float)NL * su[R][C] - S.sus[R][C]);
+      sb[R][C] = bl;
+    }
+    lds_barrier();
+    // ---- red cells of T+[-2,+3], black cells of T+[-1,+2], red cells of T+[0,+1]
+    half_sweep(-2, TY + 5, -2, TX + 5, 0);
+    lds_barrier();
+    half_sweep(-1, TY + 3, -1, TX + 3, 1);
+    lds_barrier();
+    half_sweep(0, TY + 1, 0, TX + 1, 0);
+    lds_barrier();
+    // ---- flows y = y-bar + tau K u and the relaxed reflection on the owned groups
+    TS* qx_out = A.qb_out + (long long)(2 * l) * P;
+    TS* pb_out = A.pb_out + (long long)l * P;
+    float* u_out = A.u_out + (long long)l * P;
+#pragma unroll
+    for (int j = 0; j < RPT; j++) {
+      const int r = rr0 + RSTEP * j;
+      const int gy = y0 + r;
+      float un[V], qxo[V], qyo[V], zqx[V], zqy[V], pto[V], zpt[V];
+#pragma unroll
+      for (int e = 0; e < V; e++) {
+        const int gx = gx0 + e;
+        const int R = r + OY, C = c0 + e + OX;
+        const float u0 = su[R][C];
+        un[e] = u0;
+        usn[j][e] += u0;
+        float g0 = 0.f, g1 = 0.f;
+        if (gx + 1 < W) g0 = su[R][C + 1] - u0;
+        if (gy + 1 < H) g1 = su[R + 1][C] - u0;
+        // q = q-bar - tau grad u;  z_q = P_alpha(2q - q-bar);  q-bar += rho (z_q - q)
+        const float qb0 = sqx[R][C], qb1 = sqy[R][C];
+        const float q0 = qb0 - tau * g0, q1 = qb1 - tau * g1;
+        float z0 = 2.f * q0 - qb0, z1 = 2.f * q1 - qb1;
+        if (A.iso) proj2<true>(z0, z1, A.alpha);
+        else proj2<false>(z0, z1, A.alpha);
+        qxo[e] = qb0 + rho * (z0 - q0);
+        qyo[e] = qb1 + rho * (z1 - q1);
+        zqx[e] = z0;
+        zqy[e] = z1;
+        // p = p-bar + tau u;  z = min(C, 2p - p-bar);  p-bar += rho (z - p)
+        const float pbv = spt[R][C];
+        const float pv = pbv + tau * u0;
+        const float zpv = fminf(cap_val(ocl[j][e], TWO ? 1 : l), 2.f * pv - pbv);
+        pto[e] = pbv + rho * (zpv - pv);
+        zpt[e] = zpv;
+      }
+      const int nv = nvj[j];
+      const long long idx = oj[j];
+      stg<V>(u_out, idx, nv, true, un);
+      stg<V>(qx_out, idx, nv, true, qxo);
+      stg<V>(qx_out + P, idx, nv, true, qyo);
+      stg<V>(pb_out, idx, nv, true, pto);
+      if (A.keep_z) {
+        stg<V>(A.zq + (long long)(2 * l) * P, idx, nv, true, zqx);
+        stg<V>(A.zq + (long long)(2 * l + 1) * P, idx, nv, true, zqy);
+        stg<V>(A.zp + (long long)l * P, idx, nv, true, zpt);
+      }
+    }
+    if (NL > 1) lds_barrier();   // the next label's staging overwrites the arrays
+  }
+  // ---- p_s = p-bar_s - tau sum_i u_i;  z_s = (min(C_s,) 2 p_s - p-bar_s + tau)
 #pragma unroll
   for (int j = 0; j < RPT; j++) {
     const int r = rr0 + RSTEP * j;
-    const int gy = y0 + r;
-    float un[V], qxo[V], qyo[V], zqx[V], zqy[V], pto[V], zpt[V], pso[V], zps[V];
+    float pso[V], zps[V];
 #pragma unroll
     for (int e = 0; e < V; e++) {
-      const int gx = gx0 + e;
-      const int R = r + OY, C = c0 + e + OX;
-      const float u0 = su[R][C];
-      un[e] = u0;
-      float g0 = 0.f, g1 = 0.f;
-      if (gx + 1 < W) g0 = su[R][C + 1] - u0;
-      if (gy + 1 < H) g1 = su[R + 1][C] - u0;
-      // q = q-bar - tau grad u;  z_q = P_alpha(2q - q-bar);  q-bar += rho (z_q - q)
-      const float qb0 = sqx[R][C], qb1 = sqy[R][C];
-      const float q0 = qb0 - tau * g0, q1 = qb1 - tau * g1;
-      float z0 = 2.f * q0 - qb0, z1 = 2.f * q1 - qb1;
-      if (A.iso) proj2<true>(z0, z1, A.alpha);
-      else proj2<false>(z0, z1, A.alpha);
-      qxo[e] = qb0 + rho * (z0 - q0);
-      qyo[e] = qb1 + rho * (z1 - q1);
-      zqx[e] = z0;
-      zqy[e] = z1;
-      // p_t = p-bar_t + tau u;  z = min(C_t, 2 p_t - p-bar_t);  p-bar_t += rho (z - p_t)
-      const float pbv = spt[R][C];
-      const float pv = pbv + tau * u0;
-      const float Ct = A.cg.img ? cap_from(ocs[j][e], A.cg.lv[1], A.cg.pw) : oct[j][e];
-      const float zpv = fminf(Ct, 2.f * pv - pbv);
-      pto[e] = pbv + rho * (zpv - pv);
-      zpt[e] = zpv;
-      // p_s = p-bar_s - tau u;  z_s = min(C_s, 2 p_s - p-bar_s + tau)
-      const float psbv = sps[R][C];
-      const float psv = psbv - tau * u0;
-      const float Cs = A.cg.img ? cap_from(ocs[j][e], A.cg.lv[0], A.cg.pw) : ocs[j][e];
-      const float zsv = fminf(Cs, (2.f * psv - psbv) + tau);
+      const float psbv = sps[r + OY][c0 + e + OX];
+      const float psv = psbv - tau * usn[j][e];
+      float zsv = (2.f * psv - psbv) + tau;
+      if (TWO) zsv = fminf(cap_val(ocs[j][e], 0), zsv);
       pso[e] = psbv + rho * (zsv - psv);
       zps[e] = zsv;
     }
     const int nv = nvj[j];
     const long long idx = oj[j];
-    stg<V>(A.u_out, idx, nv, true, un);
-    stg<V>(A.qb_out, idx, nv, true, qxo);
-    stg<V>(A.qb_out + P, idx, nv, true, qyo);
-    stg<V>(A.pb_out, idx, nv, true, pto);
     stg<V>(A.psb_out, idx, nv, true, pso);
-    if (A.keep_z) {
-      stg<V>(A.zq, idx, nv, true, zqx);
-      stg<V>(A.zq + P, idx, nv, true, zqy);
-      stg<V>(A.zp, idx, nv, true, zpt);
-      stg<V>(A.zs, idx, nv, true, zps);
-    }
+    if (A.keep_z) stg<V>(A.zs, idx, nv, true, zps);
   }
 }
 

@@ -102,11 +102,13 @@ def test_valid_preconditioner_variants_accepted():
 def test_pdrq_layout_follows_the_sweep_count():
     """The fused rPDRQ pass (one sweep) keeps two state buffers with rows
     padded to a multiple of 4; the in-place launches of M_n (n > 1) keep one
-    dense state, so their workspace is smaller."""
+    dense state, so their workspace is smaller (two-label and Potts)."""
     from paper_2004_11227_amd import maxflow as mfx
-    one = mfx.workspace_bytes(mfx.make_params((64, 1001), method="dr", gs_sweeps=1))
-    two = mfx.workspace_bytes(mfx.make_params((64, 1001), method="dr", gs_sweeps=2))
-    assert two < one
+    for kw in (dict(model="two"), dict(model="potts", nlabels=3), dict(model="potts", nlabels=8)):
+        one = mfx.workspace_bytes(mfx.make_params((64, 1001), method="dr", gs_sweeps=1, **kw))
+        two = mfx.workspace_bytes(mfx.make_params((64, 1001), method="dr", gs_sweeps=2, **kw))
+        unf = mfx.workspace_bytes(mfx.make_params((64, 1001), method="dr", variant="unfused", **kw))
+        assert two < one and unf == two
 
 
 def test_image_capacities_validation_and_workspace():
