@@ -273,7 +273,8 @@ struct mf_solver {
   float* wbuf;
   int64_t iter;
   int off;          // iterate k lives in state buffer (k + off) & 1
-  int* host_done;   // pinned polling slots
+  int* host_done;       // pinned, coherent polling slots (host address)
+  int* host_done_dev;   // the same slots as the device writes them
   hipEvent_t ev[8];
   int dev;
 };
@@ -498,9 +499,15 @@ mf_status maxflow_create(const mf_params* p, const float* cap, void* workspace, 
     delete s;
     return fail(MF_EDEVICE, "hipGetDevice failed");
   }
-  if (hipHostMalloc((void**)&s->host_done, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&s->host_done, 64 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent) !=
+      hipSuccess) {
     delete s;
     return fail(MF_EDEVICE, "pinned host allocation failed");
+  }
+  if (hipHostGetDevicePointer((void**)&s->host_done_dev, s->host_done, 0) != hipSuccess) {
+    hipHostFree(s->host_done);
+    delete s;
+    return fail(MF_EDEVICE, "pinned host memory is not mapped");
   }
   for (int i = 0; i < 8; i++) {
     if (hipEventCreateWithFlags(&s->ev[i], hipEventDisableTiming) != hipSuccess) {
@@ -583,7 +590,8 @@ mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
   // buffer offset in effect at each checked iterate: the accepted iterate's
   // buffer once later passes (which flip the offset) have been skipped
   std::vector<std::pair<int64_t, int>> off_at;
-  // polling ring: after each check, copy `done` to pinned memory + event
+  // polling ring: each check's bookkeeping writes `done` to a pinned slot;
+  // an event after the chunk tells the host when the slot holds it
   int issued = 0, observed = 0;
   const int lookahead = 3;
   bool stop = false;
@@ -606,7 +614,9 @@ mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
       HIP_TRY(gap_of(s, k, done));
       if (!final_check) HIP_TRY(admm_sweep(s, k, false, true, done));
     }
-    HIP_TRY(launch_bookkeep(s->ctrl, k, p.alpha, p.tol, nres(s), final_check ? 1 : 0, 1, s->stream));
+    const int slot = issued & 7;
+    HIP_TRY(launch_bookkeep(s->ctrl, k, p.alpha, p.tol, nres(s), final_check ? 1 : 0, 1, s->stream,
+                            final_check ? nullptr : s->host_done_dev + slot));
     if (final_check) break;
     // ---- the rest of the chunk
     if (dr) {
@@ -623,9 +633,8 @@ mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
       }
     }
     k += n;
-    // ---- poll the decision without stalling the queue
-    const int slot = issued & 7;
-    HIP_TRY(hipMemcpyAsync(s->host_done + slot, done, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    // ---- poll the decision without stalling the queue: the bookkeeping
+    // kernel wrote it into pinned slot `slot`; the event marks the chunk
     HIP_TRY(hipEventRecord(s->ev[slot], s->stream));
     issued++;
     while (observed < issued) {

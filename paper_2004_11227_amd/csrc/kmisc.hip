@@ -241,11 +241,19 @@ hipError_t launch_ctrl_reset(Ctrl* c, hipStream_t s) {
 // Turns the accumulated sums into the gap at iterate k, decides (when
 // `decide`) whether the solve stops there, and clears the accumulators.
 // Status codes follow mf_status: 0 converged, 1 cap reached, -4 diverged.
+// host_flag (optional): pinned host memory that receives `done`, so the host
+// polls the decision without a copy on the stream.
 __global__ void k_bookkeep(Ctrl* c, long long k, double alpha, double tol, long long nres, int final_check,
-                           int decide) {
+                           int decide, int* host_flag) {
   __shared__ double tot[8];
   const int t = threadIdx.x;
-  if (c->done) return;
+  if (c->done) {
+    if (t == 0 && host_flag) {
+      *host_flag = 1;
+      __threadfence_system();
+    }
+    return;
+  }
   if (t < 8) {
     double s = 0.0;
     for (int j = 0; j < kAccSlots; j++) s += c->acc[j][t];
@@ -281,11 +289,15 @@ __global__ void k_bookkeep(Ctrl* c, long long k, double alpha, double tol, long 
       c->iter = k;
     }
   }
+  if (host_flag) {
+    *host_flag = c->done;
+    __threadfence_system();
+  }
 }
 
 hipError_t launch_bookkeep(Ctrl* c, long long k, double alpha, double tol, long long nres, int final_check,
-                           int decide, hipStream_t s) {
-  hipLaunchKernelGGL(k_bookkeep, dim3(1), dim3(64), 0, s, c, k, alpha, tol, nres, final_check, decide);
+                           int decide, hipStream_t s, int* host_flag) {
+  hipLaunchKernelGGL(k_bookkeep, dim3(1), dim3(64), 0, s, c, k, alpha, tol, nres, final_check, decide, host_flag);
   return hipGetLastError();
 }
 

@@ -261,6 +261,34 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// One step of a wavefront sum: v plus v moved across lanes by the DPP control
+// CTRL; rows outside ROWS add 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_add(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xf, false);
+  return v + __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wavefront whose lanes are all active, by DPP
+// lane moves instead of LDS permutes: pairs and quads (quad permutations),
+// then 8 and 16 lanes (half-row and row mirrors) give every lane its row's
+// sum; row broadcasts of lanes 15 and 31 then accumulate the rows into lane
+// 63, whose value is returned to all lanes.
+__device__ __forceinline__ double wave_total(double v) {
+  v = dpp_add<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+  v = dpp_add<0x140, 0xf>(v);  // row_mirror
+  v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Block-wide sum of NQ doubles, then one hardware FP64 atomic per quantity per
 // block into slot (block id mod 64) of `dst` (rows of 8 doubles), so that
 // thousands of blocks do not serialise on one address; the slots are summed
@@ -270,7 +298,7 @@ __device__ __forceinline__ void block_accumulate(double (&v)[NQ], double* dst, d
   const int lane = threadIdx.x & 63;
   const int wave = (threadIdx.x + threadIdx.y * blockDim.x) >> 6;
 #pragma unroll
-  for (int j = 0; j < NQ; j++) v[j] = wave_sum(v[j]);
+  for (int j = 0; j < NQ; j++) v[j] = wave_total(v[j]);
   if (lane == 0) {
 #pragma unroll
     for (int j = 0; j < NQ; j++) sred[wave * NQ + j] = v[j];
