@@ -275,7 +275,6 @@ struct mf_solver {
   int off;          // iterate k lives in state buffer (k + off) & 1
   int* host_done;       // pinned, coherent polling slots (host address)
   int* host_done_dev;   // the same slots as the device writes them
-  hipEvent_t ev[8];
   int dev;
 };
 
@@ -509,14 +508,6 @@ mf_status maxflow_create(const mf_params* p, const float* cap, void* workspace, 
     delete s;
     return fail(MF_EDEVICE, "pinned host memory is not mapped");
   }
-  for (int i = 0; i < 8; i++) {
-    if (hipEventCreateWithFlags(&s->ev[i], hipEventDisableTiming) != hipSuccess) {
-      for (int j = 0; j < i; j++) hipEventDestroy(s->ev[j]);
-      hipHostFree(s->host_done);
-      delete s;
-      return fail(MF_EDEVICE, "event creation failed");
-    }
-  }
   hipError_t he = launch_pitch_copy(cap, false, r.g.npix(), r.g.W, s->cap, r.p.storage == MF_BF16, r.g.plane,
                                     r.g.pitch, r.g.W, (long long)r.g.H * r.g.D, r.ncp, s->stream);
   if (he != hipSuccess) {
@@ -590,8 +581,10 @@ mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
   // buffer offset in effect at each checked iterate: the accepted iterate's
   // buffer once later passes (which flip the offset) have been skipped
   std::vector<std::pair<int64_t, int>> off_at;
-  // polling ring: each check's bookkeeping writes `done` to a pinned slot;
-  // an event after the chunk tells the host when the slot holds it
+  // polling ring: each check's bookkeeping writes 1 (running) or 2 (stopped)
+  // into pinned slot (chunk & 7), which the host cleared before issuing the
+  // chunk; no event or copy enters the stream, so the queue has no bubbles.
+  // The host keeps at most `lookahead` unobserved chunks queued.
   int issued = 0, observed = 0;
   const int lookahead = 3;
   bool stop = false;
@@ -615,6 +608,7 @@ mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
       if (!final_check) HIP_TRY(admm_sweep(s, k, false, true, done));
     }
     const int slot = issued & 7;
+    if (!final_check) __atomic_store_n(&s->host_done[slot], 0, __ATOMIC_RELEASE);
     HIP_TRY(launch_bookkeep(s->ctrl, k, p.alpha, p.tol, nres(s), final_check ? 1 : 0, 1, s->stream,
                             final_check ? nullptr : s->host_done_dev + slot));
     if (final_check) break;
@@ -633,16 +627,24 @@ mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
       }
     }
     k += n;
-    // ---- poll the decision without stalling the queue: the bookkeeping
-    // kernel wrote it into pinned slot `slot`; the event marks the chunk
-    HIP_TRY(hipEventRecord(s->ev[slot], s->stream));
+    // ---- follow the decisions without stalling the queue
     issued++;
+    long spins = 0;
     while (observed < issued) {
       const int os = observed & 7;
-      hipError_t q = (issued - observed > lookahead) ? hipEventSynchronize(s->ev[os]) : hipEventQuery(s->ev[os]);
-      if (q == hipErrorNotReady) break;
-      if (q != hipSuccess) return fail(MF_EDEVICE, std::string("event: ") + hipGetErrorString(q));
-      if (s->host_done[os]) stop = true;
+      const int v = __atomic_load_n(&s->host_done[os], __ATOMIC_ACQUIRE);
+      if (v == 0) {
+        if (issued - observed <= lookahead) break;   // enough queued: issue the next chunk
+        if (++spins % 4096 == 0) {                   // a device error, or a flag that never comes
+          const hipError_t q = hipStreamQuery(s->stream);
+          if (q != hipSuccess && q != hipErrorNotReady)
+            return fail(MF_EDEVICE, std::string("stream: ") + hipGetErrorString(q));
+          if (q == hipSuccess && __atomic_load_n(&s->host_done[os], __ATOMIC_ACQUIRE) == 0)
+            return fail(MF_EDEVICE, "solve: decision flag not written");
+        }
+        continue;
+      }
+      if (v == 2) stop = true;
       observed++;
     }
   }
@@ -838,8 +840,6 @@ mf_status maxflow_tune(mf_solver* s, int32_t sweeps, int32_t what, mf_tuning* ou
 mf_status maxflow_destroy(mf_solver* s) {
   if (!s) return MF_OK;
   hipStreamSynchronize(s->stream);
-  for (int i = 0; i < 8; i++)
-    if (s->ev[i]) hipEventDestroy(s->ev[i]);
   if (s->host_done) hipHostFree(s->host_done);
   delete s;
   return MF_OK;

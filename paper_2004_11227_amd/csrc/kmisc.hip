@@ -241,26 +241,25 @@ hipError_t launch_ctrl_reset(Ctrl* c, hipStream_t s) {
 // Turns the accumulated sums into the gap at iterate k, decides (when
 // `decide`) whether the solve stops there, and clears the accumulators.
 // Status codes follow mf_status: 0 converged, 1 cap reached, -4 diverged.
-// host_flag (optional): pinned host memory that receives `done`, so the host
-// polls the decision without a copy on the stream.
-__global__ void k_bookkeep(Ctrl* c, long long k, double alpha, double tol, long long nres, int final_check,
-                           int decide, int* host_flag) {
-  __shared__ double tot[8];
+// One wavefront, lane t reading and clearing accumulator slot t.
+// host_flag (optional): pinned host memory that receives 1 (checked, still
+// running) or 2 (stopped), so the host follows the solve without events or
+// copies on the stream.
+static_assert(kAccSlots == 64, "one lane per accumulator slot");
+__global__ __launch_bounds__(64) void k_bookkeep(Ctrl* c, long long k, double alpha, double tol, long long nres,
+                                                 int final_check, int decide, int* host_flag) {
   const int t = threadIdx.x;
+  double tot[5];
+#pragma unroll
+  for (int j = 0; j < 5; j++) tot[j] = c->acc[t][j];   // issued together with the read of done
   if (c->done) {
-    if (t == 0 && host_flag) {
-      *host_flag = 1;
-      __threadfence_system();
-    }
+    if (t == 0 && host_flag) *host_flag = 2;
     return;
   }
-  if (t < 8) {
-    double s = 0.0;
-    for (int j = 0; j < kAccSlots; j++) s += c->acc[j][t];
-    tot[t] = s;
-  }
-  __syncthreads();
-  for (int j = t; j < kAccSlots * 8; j += blockDim.x) c->acc[j / 8][j % 8] = 0.0;
+#pragma unroll
+  for (int j = 0; j < 5; j++) tot[j] = wave_total(tot[j]);
+#pragma unroll
+  for (int j = 0; j < 8; j++) c->acc[t][j] = 0.0;
   if (t != 0) return;
   const double P = tot[0] + alpha * tot[1];
   const double D = tot[2];
@@ -289,10 +288,8 @@ __global__ void k_bookkeep(Ctrl* c, long long k, double alpha, double tol, long 
       c->iter = k;
     }
   }
-  if (host_flag) {
-    *host_flag = c->done;
-    __threadfence_system();
-  }
+  // the store reaches the coherent host page before the kernel completes
+  if (host_flag) *host_flag = c->done ? 2 : 1;
 }
 
 hipError_t launch_bookkeep(Ctrl* c, long long k, double alpha, double tol, long long nres, int final_check,

@@ -24,6 +24,13 @@
 
 namespace mf {
 
+// A tile whose cells and halo cells (rows -2 .. TY+1, cols -2 .. 65 of the
+// iterate k+1 work) all have their four neighbours inside the grid.
+template <int TY>
+__device__ __forceinline__ bool d2_interior(int x0, int y0, int W, int H) {
+  return x0 > 0 && y0 > 0 && x0 + 64 + 2 < W && y0 + TY + 2 < H;
+}
+
 template <int TY>
 struct Smem2d2 {
   static constexpr int SW = 72;       // cols -4 .. 67
@@ -38,7 +45,9 @@ struct Smem2d2 {
 };
 
 // IMG: capacities computed from one image plane (A.cg), read once per cell.
-template <typename TS, bool CHECK, int TY, bool IMG = false>
+// EDGE false: an interior tile (d2_interior), whose every boundary test is
+// true and folds away; the arithmetic is unchanged.
+template <typename TS, bool CHECK, int TY, bool IMG = false, bool EDGE = true>
 __device__ __forceinline__ void tile2d_d2(const K2<TS>& A, int x0, int y0, Smem2d2<TY>& S, double (&g)[5]) {
   constexpr int TX = 64, V = 4, TPR = TX / V, RSTEP = 256 / TPR, RPT = TY / RSTEP;
   constexpr int OX = 4, OY = 3;                    // LDS offsets of tile column / row 0
@@ -60,6 +69,11 @@ __device__ __forceinline__ void tile2d_d2(const K2<TS>& A, int x0, int y0, Smem2
   const Coef k = A.k;
   const TS* qx_in = A.q_in;
   const TS* qy_in = A.q_in + P;
+  // neighbour-inside-the-grid tests of the stencils (zero flux outside)
+  auto xp = [&](int x) { return !EDGE || x + 1 < W; };
+  auto xm = [&](int x) { return !EDGE || x > 0; };
+  auto yp = [&](int y) { return !EDGE || y + 1 < H; };
+  auto ym = [&](int y) { return !EDGE || y > 0; };
 
   // ---- 1. stage iterate k on rows -3 .. TY+1, cols -4 .. 67 (raw loads, then masks)
   float lqx[KG][V], lqy[KG][V], lu[KG][V], lps[KG][V], lpt[KG][V];
@@ -153,9 +167,9 @@ __device__ __forceinline__ void tile2d_d2(const K2<TS>& A, int x0, int y0, Smem2
           const int gx = gx0 + e, c = c0 + e;
           const int R = r + OY, C = c + OX;
           const double dq =
-              (((gx + 1 < W) ? (double)sqx[R][C] : 0.0) - ((gx > 0) ? (double)sqx[R][C - 1] : 0.0)) +
-              (((gy + 1 < H) ? (double)sqy[R][C] : 0.0) - ((gy > 0) ? (double)sqy[R - 1][C] : 0.0));
-          gap_two_px(g, su[R][C], su[R][C + 1], su[R + 1][C], gx + 1 < W, gy + 1 < H, dq, o_s(j, e), o_t(j, e),
+              ((xp(gx) ? (double)sqx[R][C] : 0.0) - (xm(gx) ? (double)sqx[R][C - 1] : 0.0)) +
+              ((yp(gy) ? (double)sqy[R][C] : 0.0) - (ym(gy) ? (double)sqy[R - 1][C] : 0.0));
+          gap_two_px(g, su[R][C], su[R][C + 1], su[R + 1][C], xp(gx), yp(gy), dq, o_s(j, e), o_t(j, e),
                      sps[R][C], spt[R][C], A.iso);
         }
       }
@@ -166,7 +180,7 @@ __device__ __forceinline__ void tile2d_d2(const K2<TS>& A, int x0, int y0, Smem2
     const int r = h / (TX + 4) - 2, c = h % (TX + 4) - 2;
     const int hx = x0 + c, hy = y0 + r;
     const int R = r + OY, C = c + OX;
-    const float d = div2(sqx[R][C], sqx[R][C - 1], sqy[R][C], sqy[R - 1][C], hx + 1 < W, hx > 0, hy + 1 < H, hy > 0);
+    const float d = div2(sqx[R][C], sqx[R][C - 1], sqy[R][C], sqy[R - 1][C], xp(hx), xm(hx), yp(hy), ym(hy));
     sw[R][C] = wterm(d, vterm(spt[R][C], sps[R][C], su[R][C], k.inv_c));
   }
   lds_barrier();
@@ -176,8 +190,8 @@ __device__ __forceinline__ void tile2d_d2(const K2<TS>& A, int x0, int y0, Smem2
     const int hx = x0 + c, hy = y0 + r;
     const int R = r + OY, C = c + OX;
     const float w0 = sw[R][C];
-    float qx = qstep(sqx[R][C], sw[R][C + 1], w0, hx + 1 < W, k.inv_a);
-    float qy = qstep(sqy[R][C], sw[R + 1][C], w0, hy + 1 < H, k.inv_a);
+    float qx = qstep(sqx[R][C], sw[R][C + 1], w0, xp(hx), k.inv_a);
+    float qy = qstep(sqy[R][C], sw[R + 1][C], w0, yp(hy), k.inv_a);
     proj(qx, qy, k.alpha, A.iso);
     sqx[R][C] = quant<TS>(qx);
     sqy[R][C] = quant<TS>(qy);
@@ -191,7 +205,7 @@ __device__ __forceinline__ void tile2d_d2(const K2<TS>& A, int x0, int y0, Smem2
       const int r = h / (TX + 2) - 1, c = h % (TX + 2) - 1;
       const int hx = x0 + c, hy = y0 + r;
       const int R = r + OY, C = c + OX;
-      const float d = div2(sqx[R][C], sqx[R][C - 1], sqy[R][C], sqy[R - 1][C], hx + 1 < W, hx > 0, hy + 1 < H, hy > 0);
+      const float d = div2(sqx[R][C], sqx[R][C - 1], sqy[R][C], sqy[R - 1][C], xp(hx), xm(hx), yp(hy), ym(hy));
       float pn, t, sd = 0.f, sr = 0.f;
       const float ps = sps[R][C];
       label_update(k, su[R][C], spt[R][C], ps, d, c1_t(m), pn, t, sd, sr);
@@ -207,7 +221,7 @@ __device__ __forceinline__ void tile2d_d2(const K2<TS>& A, int x0, int y0, Smem2
     const int r = h / (TX + 2) - 1, c = h % (TX + 2) - 1;
     const int hx = x0 + c, hy = y0 + r;
     const int R = r + OY, C = c + OX;
-    const float d = div2(sqx[R][C], sqx[R][C - 1], sqy[R][C], sqy[R - 1][C], hx + 1 < W, hx > 0, hy + 1 < H, hy > 0);
+    const float d = div2(sqx[R][C], sqx[R][C - 1], sqy[R][C], sqy[R - 1][C], xp(hx), xm(hx), yp(hy), ym(hy));
     sw[R][C] = wterm(d, vterm(spt[R][C], sps[R][C], su[R][C], k.inv_c));
   }
   lds_barrier();
@@ -217,8 +231,8 @@ __device__ __forceinline__ void tile2d_d2(const K2<TS>& A, int x0, int y0, Smem2
     const int hx = x0 + c, hy = y0 + r;
     const int R = r + OY, C = c + OX;
     const float w0 = sw[R][C];
-    float qx = qstep(sqx[R][C], sw[R][C + 1], w0, hx + 1 < W, k.inv_a);
-    float qy = qstep(sqy[R][C], sw[R + 1][C], w0, hy + 1 < H, k.inv_a);
+    float qx = qstep(sqx[R][C], sw[R][C + 1], w0, xp(hx), k.inv_a);
+    float qy = qstep(sqy[R][C], sw[R + 1][C], w0, yp(hy), k.inv_a);
     proj(qx, qy, k.alpha, A.iso);
     sqx[R][C] = quant<TS>(qx);
     sqy[R][C] = quant<TS>(qy);
@@ -236,7 +250,7 @@ __device__ __forceinline__ void tile2d_d2(const K2<TS>& A, int x0, int y0, Smem2
       const int R = r + OY, C = c0 + e + OX;
       qxv[e] = sqx[R][C];
       qyv[e] = sqy[R][C];
-      const float d = div2(qxv[e], sqx[R][C - 1], qyv[e], sqy[R - 1][C], gx + 1 < W, gx > 0, gy + 1 < H, gy > 0);
+      const float d = div2(qxv[e], sqx[R][C - 1], qyv[e], sqy[R - 1][C], xp(gx), xm(gx), yp(gy), ym(gy));
       float t, sd = 0.f, sr = 0.f;
       const float ps = sps[R][C];
       label_update(k, su[R][C], spt[R][C], ps, d, o_t(j, e), pn[e], t, sd, sr);
