@@ -13,7 +13,8 @@ __global__ __launch_bounds__(256) void k_fused2d(const K2<TS> A) {
   const int x0 = (tile % A.tiles_x) * 64;
   const int y0 = (tile / A.tiles_x) * TY;
   double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  tile2d<NL, TWO, TS, CHECK, TY, true, CHECK, IMG>(A, x0, y0, S, g);
+  if (d1_interior<TY>(x0, y0, A.W, A.H)) tile2d<NL, TWO, TS, CHECK, TY, true, CHECK, IMG, false>(A, x0, y0, S, g);
+  else tile2d<NL, TWO, TS, CHECK, TY, true, CHECK, IMG, true>(A, x0, y0, S, g);
   if (CHECK) block_accumulate<5, 4>(g, A.acc, S.sred);
 }
 

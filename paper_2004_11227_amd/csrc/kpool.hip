@@ -75,7 +75,8 @@ __global__ __launch_bounds__(256) void k_pool2d(PoolDev d, int cls) {
   if (check != CHECK) return;
   const K2<TS> A = slot_k2<TS>(*sl);
   double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  tile2d<NL, TWO, TS, CHECK, TY, VEC, CHECK>(A, w.x0, w.y0, S, g);
+  if (d1_interior<TY>(w.x0, w.y0, A.W, A.H)) tile2d<NL, TWO, TS, CHECK, TY, VEC, CHECK, false, false>(A, w.x0, w.y0, S, g);
+  else tile2d<NL, TWO, TS, CHECK, TY, VEC, CHECK, false, true>(A, w.x0, w.y0, S, g);
   if (CHECK) block_accumulate<5, 4>(g, &sl->acc[0][0], S.sred);
 }
 
@@ -93,7 +94,8 @@ __global__ __launch_bounds__(256) void k_pool2d_d2(PoolDev d, int cls) {
   if ((sl->check_now != 0) != CHECK) return;
   const K2<TS> A = slot_k2<TS>(*sl);
   double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  tile2d_d2<TS, CHECK, TY>(A, w.x0, w.y0, S, g);
+  if (d2_interior<TY>(w.x0, w.y0, A.W, A.H)) tile2d_d2<TS, CHECK, TY, false, false>(A, w.x0, w.y0, S, g);
+  else tile2d_d2<TS, CHECK, TY, false, true>(A, w.x0, w.y0, S, g);
   if (CHECK) block_accumulate<5, 4>(g, &sl->acc[0][0], S.sred);
 }
 

@@ -96,9 +96,18 @@ struct Lab2 {
   float hqx[KQ], hqy[KQ], hu[KW], hp[KW];
 };
 
+// A tile whose cells and halo cells (rows -1 .. TY, cols -1 .. 64) all have
+// their four neighbours inside the grid.
+template <int TY>
+__device__ __forceinline__ bool d1_interior(int x0, int y0, int W, int H) {
+  return x0 > 0 && y0 > 0 && x0 + 64 + 1 < W && y0 + TY + 1 < H;
+}
+
 // IMG: the capacities are computed from one image plane (A.cg), which is
 // read once per pixel instead of 2 (two-label) or NL capacity planes.
-template <int NL, bool TWO, typename TS, bool CHECK, int TY, bool VEC, bool SU, bool IMG = false>
+// EDGE false: an interior tile (d1_interior), whose every boundary test is
+// true and folds away; the arithmetic is unchanged.
+template <int NL, bool TWO, typename TS, bool CHECK, int TY, bool VEC, bool SU, bool IMG = false, bool EDGE = true>
 __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY, SU>& S, double (&g)[5]) {
   static_assert(!CHECK || SU, "the gap needs the u staging array");
   constexpr int TX = 64;
@@ -123,6 +132,11 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
   const int nvx = W - gx0 < 0 ? 0 : (W - gx0 > V ? V : W - gx0);
   constexpr bool vec = VEC;   // W % V == 0: interior groups are whole vectors
   const Coef k = A.k;
+  // neighbour-inside-the-grid tests of the stencils (zero flux outside)
+  auto xp = [&](int x) { return !EDGE || x + 1 < W; };
+  auto xm = [&](int x) { return !EDGE || x > 0; };
+  auto yp = [&](int y) { return !EDGE || y + 1 < H; };
+  auto ym = [&](int y) { return !EDGE || y > 0; };
 
   // owned groups: valid element counts and storage offsets
   int nvj[RPT];
@@ -302,9 +316,9 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
           if (e < nv) {
             const int gx = gx0 + e, c = c0 + OX + e;
             const double dq =
-                (((gx + 1 < W) ? (double)sqx[r + 2][c] : 0.0) - ((gx > 0) ? (double)sqx[r + 2][c - 1] : 0.0)) +
-                (((gy + 1 < H) ? (double)sqy[r + 2][c] : 0.0) - ((gy > 0) ? (double)sqy[r + 1][c] : 0.0));
-            gap_two_px(g, su[r + 2][c], su[r + 2][c + 1], su[r + 3][c], gx + 1 < W, gy + 1 < H, dq,
+                ((xp(gx) ? (double)sqx[r + 2][c] : 0.0) - (xm(gx) ? (double)sqx[r + 2][c - 1] : 0.0)) +
+                ((yp(gy) ? (double)sqy[r + 2][c] : 0.0) - (ym(gy) ? (double)sqy[r + 1][c] : 0.0));
+            gap_two_px(g, su[r + 2][c], su[r + 2][c + 1], su[r + 3][c], xp(gx), yp(gy), dq,
                        cap_s(j, e), Cl[j][e], ps[j][e], pl[j][e], A.iso);
           }
         }
@@ -315,7 +329,7 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
       const int r = h / (TX + 2) - 1, c = h % (TX + 2) - 1;
       const int hx = x0 + c, hy = y0 + r;
       const float d = div2(sqx[r + 2][c + OX], sqx[r + 2][c + OX - 1], sqy[r + 2][c + OX],
-                           sqy[r + 1][c + OX], hx + 1 < W, hx > 0, hy + 1 < H, hy > 0);
+                           sqy[r + 1][c + OX], xp(hx), xm(hx), yp(hy), ym(hy));
       sw[r + 2][c + OX] = wterm(d, sw[r + 2][c + OX]);
     }
     lds_barrier();
@@ -324,8 +338,8 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
       const int r = h / (TX + 1) - 1, c = h % (TX + 1) - 1;
       const int hx = x0 + c, hy = y0 + r;
       const float w0 = sw[r + 2][c + OX];
-      float qx = qstep(sqx[r + 2][c + OX], sw[r + 2][c + OX + 1], w0, hx + 1 < W, k.inv_a);
-      float qy = qstep(sqy[r + 2][c + OX], sw[r + 3][c + OX], w0, hy + 1 < H, k.inv_a);
+      float qx = qstep(sqx[r + 2][c + OX], sw[r + 2][c + OX + 1], w0, xp(hx), k.inv_a);
+      float qy = qstep(sqy[r + 2][c + OX], sw[r + 3][c + OX], w0, yp(hy), k.inv_a);
       proj(qx, qy, k.alpha, A.iso);
       sqx[r + 2][c + OX] = quant<TS>(qx);
       sqy[r + 2][c + OX] = quant<TS>(qy);
@@ -348,8 +362,8 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
           const int gx = gx0 + e, c = c0 + OX + e;
           qxv[e] = sqx[r + 2][c];
           qyv[e] = sqy[r + 2][c];
-          const float d = div2(qxv[e], sqx[r + 2][c - 1], qyv[e], sqy[r + 1][c], gx + 1 < W, gx > 0,
-                               gy + 1 < H, gy > 0);
+          const float d = div2(qxv[e], sqx[r + 2][c - 1], qyv[e], sqy[r + 1][c], xp(gx), xm(gx),
+                               yp(gy), ym(gy));
           label_update(k, ul[j][e], pl[j][e], ps[j][e], d, Cl[j][e], pn[e], t[j][l][e], sumd[j][e], sumr[j][e]);
         }
         if (A.write) {
