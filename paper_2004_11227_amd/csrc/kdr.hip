@@ -33,7 +33,8 @@ __global__ __launch_bounds__(256) void k_dr_fused2d(const KDF<TS> A) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % A.tiles_x) * 64;
   const int y0 = (tile / A.tiles_x) * TY;
-  tile_dr2d<TS, TY, NL, TWO>(A, x0, y0, S);
+  if (dr_interior<TY>(x0, y0, A.W, A.H)) tile_dr2d<TS, TY, NL, TWO, false>(A, x0, y0, S);
+  else tile_dr2d<TS, TY, NL, TWO, true>(A, x0, y0, S);
 }
 
 template <typename TS, int NL, bool TWO>
@@ -61,7 +62,7 @@ static hipError_t dr_fused_nl(const PdrqDesc& d, hipStream_t s) {
   a.rho = d.rho;
   a.inv_st = d.inv_st;
   a.alpha = d.alpha;
-  a.m = TWO ? 2.f : (float)(NL + 1);
+  set_rden(a.rden, TWO ? 2.f : (float)(NL + 1));
   a.iso = d.iso ? 1 : 0;
   a.keep_z = d.keep_z ? 1 : 0;
   a.done = d.done;
@@ -99,7 +100,8 @@ struct KD {
   TS* zs;
   TS* zp;
   float* b;
-  float sigma, tau, rho, inv_st, alpha, m;
+  float sigma, tau, rho, inv_st, alpha;
+  Rden rden;            // 1 / (|N(x)| + m) for |N(x)| = 0 .. 6, rounded once on the host
   int iso, keep_z;
   const int* done;
   CapGen cg;            // cg.img: `cap` is one image plane
@@ -121,21 +123,23 @@ __device__ __forceinline__ Cell cell_of(long long idx, int W, int H) {
 __device__ __forceinline__ bool is_red(const Cell& c) { return ((c.x + c.y + c.z) & 1) == 0; }
 
 // Gauss-Seidel value at one cell from its neighbours in `u` (one label).
+// (b / (sigma tau) + sum of the neighbours) / (|N(x)| + m), the division as a
+// product with the reciprocal of the denominator.
 template <int NDIM>
 __device__ __forceinline__ float gs_value(const float* u, const float* b, long long idx, const Cell& c, int W,
-                                          int H, int D, float inv_st, float m) {
+                                          int H, int D, float inv_st, const Rden rden) {
   const long long sz = (long long)W * H;
   float s = 0.f;
-  float nb = 0.f;
-  if (c.x > 0) { s += u[idx - 1]; nb += 1.f; }
-  if (c.x + 1 < W) { s += u[idx + 1]; nb += 1.f; }
-  if (c.y > 0) { s += u[idx - W]; nb += 1.f; }
-  if (c.y + 1 < H) { s += u[idx + W]; nb += 1.f; }
+  int nb = 0;
+  if (c.x > 0) { s += u[idx - 1]; nb++; }
+  if (c.x + 1 < W) { s += u[idx + 1]; nb++; }
+  if (c.y > 0) { s += u[idx - W]; nb++; }
+  if (c.y + 1 < H) { s += u[idx + W]; nb++; }
   if (NDIM == 3) {
-    if (c.z > 0) { s += u[idx - sz]; nb += 1.f; }
-    if (c.z + 1 < D) { s += u[idx + sz]; nb += 1.f; }
+    if (c.z > 0) { s += u[idx - sz]; nb++; }
+    if (c.z + 1 < D) { s += u[idx + sz]; nb++; }
   }
-  return (b[idx] * inv_st + s) / (nb + m);
+  return (b[idx] * inv_st + s) * rden_at(rden, nb);
 }
 
 template <int NL, bool TWO, int NDIM, typename TS>
@@ -169,7 +173,7 @@ __global__ __launch_bounds__(256) void k_dr_r1(const KD<TS> A) {
 #pragma unroll
       for (int l = 0; l < NL; l++) {
         float* ul = A.u + (long long)l * A.P;
-        ul[idx] = gs_value<NDIM>(ul, A.b + (long long)l * A.P, idx, c, A.W, A.H, A.D, A.inv_st, A.m);
+        ul[idx] = gs_value<NDIM>(ul, A.b + (long long)l * A.P, idx, c, A.W, A.H, A.D, A.inv_st, A.rden);
       }
     }
   }
@@ -186,15 +190,15 @@ __global__ __launch_bounds__(256) void k_dr_half(const KD<TS> A) {
 #pragma unroll
     for (int l = 0; l < NL; l++) {
       float* ul = A.u + (long long)l * A.P;
-      ul[idx] = gs_value<NDIM>(ul, A.b + (long long)l * A.P, idx, c, A.W, A.H, A.D, A.inv_st, A.m);
+      ul[idx] = gs_value<NDIM>(ul, A.b + (long long)l * A.P, idx, c, A.W, A.H, A.D, A.inv_st, A.rden);
     }
   }
 }
 
 template <int NDIM>
 __device__ __forceinline__ float u_final(const float* ul, const float* bl, long long idx, const Cell& c, int W,
-                                         int H, int D, float inv_st, float m) {
-  return is_red(c) ? gs_value<NDIM>(ul, bl, idx, c, W, H, D, inv_st, m) : ul[idx];
+                                         int H, int D, float inv_st, const Rden rden) {
+  return is_red(c) ? gs_value<NDIM>(ul, bl, idx, c, W, H, D, inv_st, rden) : ul[idx];
 }
 
 template <int NL, bool TWO, int NDIM, typename TS>
@@ -210,7 +214,7 @@ __global__ __launch_bounds__(256) void k_dr_r2f(const KD<TS> A) {
     for (int l = 0; l < NL; l++) {
       const float* ul = A.u + (long long)l * A.P;
       const float* bl = A.b + (long long)l * A.P;
-      const float u0 = u_final<NDIM>(ul, bl, idx, c, A.W, A.H, A.D, A.inv_st, A.m);
+      const float u0 = u_final<NDIM>(ul, bl, idx, c, A.W, A.H, A.D, A.inv_st, A.rden);
       un[l] = u0;
       usum += u0;
       // grad u^{k+1} with the forward neighbours' final values
@@ -218,17 +222,17 @@ __global__ __launch_bounds__(256) void k_dr_r2f(const KD<TS> A) {
       if (c.x + 1 < A.W) {
         Cell cn = c;
         cn.x += 1;
-        g[0] = u_final<NDIM>(ul, bl, idx + 1, cn, A.W, A.H, A.D, A.inv_st, A.m) - u0;
+        g[0] = u_final<NDIM>(ul, bl, idx + 1, cn, A.W, A.H, A.D, A.inv_st, A.rden) - u0;
       }
       if (c.y + 1 < A.H) {
         Cell cn = c;
         cn.y += 1;
-        g[1] = u_final<NDIM>(ul, bl, idx + A.W, cn, A.W, A.H, A.D, A.inv_st, A.m) - u0;
+        g[1] = u_final<NDIM>(ul, bl, idx + A.W, cn, A.W, A.H, A.D, A.inv_st, A.rden) - u0;
       }
       if (NDIM == 3 && c.z + 1 < A.D) {
         Cell cn = c;
         cn.z += 1;
-        g[2] = u_final<NDIM>(ul, bl, idx + sz, cn, A.W, A.H, A.D, A.inv_st, A.m) - u0;
+        g[2] = u_final<NDIM>(ul, bl, idx + sz, cn, A.W, A.H, A.D, A.inv_st, A.rden) - u0;
       }
       // q = q-bar - tau grad u;  z_q = P_alpha(2q - q-bar);  q-bar += rho (z_q - q)
       TS* q = A.qb + (long long)(NDIM * l) * A.P;
@@ -295,7 +299,7 @@ static hipError_t dr_nl(const PdrqDesc& d, hipStream_t s) {
   a.rho = d.rho;
   a.inv_st = d.inv_st;
   a.alpha = d.alpha;
-  a.m = TWO ? 2.f : (float)(NL + 1);
+  set_rden(a.rden, TWO ? 2.f : (float)(NL + 1));
   a.iso = d.iso ? 1 : 0;
   a.keep_z = d.keep_z ? 1 : 0;
   a.done = d.done;

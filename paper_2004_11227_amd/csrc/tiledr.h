@@ -11,7 +11,8 @@
 // once for all labels), forms b on T+[-2,+3], runs the red, black, red
 // half-sweeps of the symmetric Gauss-Seidel step on the shrinking regions in
 // LDS, then the label's flows, relaxed reflection and stores on the tile;
-// p-bar_s follows the last label.  Each cell's arithmetic (b with the Potts
+// p-bar_s follows the last label.  The loads of label l+1 are issued before
+// the LDS phases of label l.  Each cell's arithmetic (b with the Potts
 // coupling st (n u_i - sum_j u_j), the Gauss-Seidel value with its
 // neighbours summed in the order -x, +x, -y, +y, the flows, the reflection,
 // the label sum of the new u in label order) is that of the three in-place
@@ -20,6 +21,25 @@
 #include "mf_kernels.h"
 
 namespace mf {
+
+// Reciprocals 1 / (nb + m) of the Gauss-Seidel denominators, nb = 0 .. 6
+// neighbours, rounded once on the host and shared by every rPDRQ kernel.
+struct Rden {
+  float r[7];
+};
+
+inline void set_rden(Rden& d, float m) {
+  for (int i = 0; i < 7; i++) d.r[i] = 1.f / ((float)i + m);
+}
+
+// d.r[nb] by selects (a dynamic index would copy the table to scratch
+// memory); a compile-time nb folds to one entry.
+__device__ __forceinline__ float rden_at(const Rden d, int nb) {
+  float v = d.r[0];
+#pragma unroll
+  for (int i = 1; i < 7; i++) v = nb == i ? d.r[i] : v;
+  return v;
+}
 
 template <typename TS>
 struct KDF {
@@ -38,7 +58,8 @@ struct KDF {
   TS* zq;
   TS* zs;
   TS* zp;
-  float sigma, tau, rho, inv_st, alpha, m;
+  float sigma, tau, rho, inv_st, alpha;
+  Rden rden;            // 1 / (|N(x)| + m) for |N(x)| = 0 .. 6, rounded once on the host
   int iso, keep_z;
   const int* done;
   CapGen cg;            // cg.img: `cap` is one image plane
@@ -57,7 +78,16 @@ struct SmemDR {
   __align__(16) float sus[TWO ? 1 : SH][TWO ? 1 : SW];   // Potts: sum over labels of u^k
 };
 
-template <typename TS, int TY, int NL, bool TWO>
+// A tile whose b and half-sweep cells (rows -2 .. TY+2, cols -2 .. 66) all
+// have their four neighbours inside the grid.
+template <int TY>
+__device__ __forceinline__ bool dr_interior(int x0, int y0, int W, int H) {
+  return x0 > 0 && y0 > 0 && x0 + 64 + 3 < W && y0 + TY + 3 < H;
+}
+
+// EDGE false: an interior tile (dr_interior), whose every boundary test is
+// true and folds away; the arithmetic is unchanged.
+template <typename TS, int TY, int NL, bool TWO, bool EDGE = true>
 __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, SmemDR<TY, TWO>& S) {
   constexpr int TX = 64, V = 4, TPR = TX / V, RSTEP = 256 / TPR, RPT = TY / RSTEP;
   constexpr int OX = 4, OY = 3;
@@ -75,6 +105,11 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
   const int tid = threadIdx.x;
   const int W = A.W, H = A.H, pitch = A.pitch;
   const long long P = A.P;
+  // neighbour-inside-the-grid tests (zero flux outside)
+  auto xp = [&](int x) { return !EDGE || x + 1 < W; };
+  auto xm = [&](int x) { return !EDGE || x > 0; };
+  auto yp = [&](int y) { return !EDGE || y + 1 < H; };
+  auto ym = [&](int y) { return !EDGE || y > 0; };
 
   // this thread's staged groups (rows -3 .. TY+3, cols -4 .. 67)
   long long gi[KG];
@@ -117,6 +152,23 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
     for (int j = 0; j < RPT; j++) ldv<V>(A.cap + (img ? 0 : (long long)pl * P), nvj[j] > 0 ? oj[j] : 0, o[j]);
   };
   auto cap_val = [&](float raw, int lv) { return img ? cap_from(raw, A.cg.lv[lv], A.cg.pw) : raw; };
+  // u, q-bar, p-bar of one label on the staged groups and its capacities on
+  // the owned groups, fetched into registers one label ahead of their use
+  float nu[KG][V], nqx[KG][V], nqy[KG][V], npt[KG][V], ncl[RPT][V];
+  auto fetch = [&](int l) {
+    const float* u_in = A.u_in + (long long)l * P;
+    const TS* qx_in = A.qb_in + (long long)(2 * l) * P;
+    const TS* pb_in = A.pb_in + (long long)l * P;
+#pragma unroll
+    for (int m = 0; m < KG; m++) {
+      ldv<V>(u_in, gi[m], nu[m]);
+      ldv<V>(qx_in, gi[m], nqx[m]);
+      ldv<V>(qx_in + P, gi[m], nqy[m]);
+      ldv<V>(pb_in, gi[m], npt[m]);
+    }
+    load_cap(TWO ? 1 : l, ncl);
+  };
+  fetch(0);
 
   // ---- label-independent staging: p-bar_s and (Potts) the label sum of u^k
   {
@@ -158,12 +210,13 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
   auto gs = [&](int r, int c) {
     const int hx = x0 + c, hy = y0 + r;
     const int R = r + OY, C = c + OX;
-    float s = 0.f, nb = 0.f;
-    if (hx > 0) { s += su[R][C - 1]; nb += 1.f; }
-    if (hx + 1 < W) { s += su[R][C + 1]; nb += 1.f; }
-    if (hy > 0) { s += su[R - 1][C]; nb += 1.f; }
-    if (hy + 1 < H) { s += su[R + 1][C]; nb += 1.f; }
-    return (sb[R][C] * A.inv_st + s) / (nb + A.m);
+    float s = 0.f;
+    int nb = 0;
+    if (xm(hx)) { s += su[R][C - 1]; nb++; }
+    if (xp(hx)) { s += su[R][C + 1]; nb++; }
+    if (ym(hy)) { s += su[R - 1][C]; nb++; }
+    if (yp(hy)) { s += su[R + 1][C]; nb++; }
+    return (sb[R][C] * A.inv_st + s) * rden_at(A.rden, nb);
   };
   // Half-sweep over the cells of one colour (0 red, 1 black: parity of
   // x + y; x0 and y0 are even) of rows rlo .. rlo+nr-1, cols clo .. clo+nc-1:
@@ -179,37 +232,29 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
 
 #pragma unroll 1
   for (int l = 0; l < NL; l++) {
-    // ---- stage u, q-bar, p-bar of label l on rows -3 .. TY+3, cols -4 .. 67
-    {
-      const float* u_in = A.u_in + (long long)l * P;
-      const TS* qx_in = A.qb_in + (long long)(2 * l) * P;
-      const TS* pb_in = A.pb_in + (long long)l * P;
-      float lu[KG][V], lqx[KG][V], lqy[KG][V], lpt[KG][V];
+    // ---- stage u, q-bar, p-bar of label l on rows -3 .. TY+3, cols -4 .. 67,
+    // then start the loads of label l+1
 #pragma unroll
-      for (int m = 0; m < KG; m++) {
-        ldv<V>(u_in, gi[m], lu[m]);
-        ldv<V>(qx_in, gi[m], lqx[m]);
-        ldv<V>(qx_in + P, gi[m], lqy[m]);
-        ldv<V>(pb_in, gi[m], lpt[m]);
-      }
-#pragma unroll
-      for (int m = 0; m < KG; m++) {
-        put(su, m, lu[m]);
-        put(sqx, m, lqx[m]);
-        put(sqy, m, lqy[m]);
-        put(spt, m, lpt[m]);
-      }
+    for (int m = 0; m < KG; m++) {
+      put(su, m, nu[m]);
+      put(sqx, m, nqx[m]);
+      put(sqy, m, nqy[m]);
+      put(spt, m, npt[m]);
     }
     float ocl[RPT][V];   // C_t (two labels) or C_l, raw
-    load_cap(TWO ? 1 : l, ocl);
+#pragma unroll
+    for (int j = 0; j < RPT; j++)
+#pragma unroll
+      for (int e = 0; e < V; e++) ocl[j][e] = ncl[j][e];
+    if (l + 1 < NL) fetch(l + 1);
     lds_barrier();
     // ---- b on T+[-2,+3]: -sigma (div q-bar + p-bar - p-bar_s) (+ st (n u - sum u) for Potts)
     for (int h = tid; h < (TY + 5) * (TX + 5); h += 256) {
       const int r = h / (TX + 5) - 2, c = h % (TX + 5) - 2;
       const int hx = x0 + c, hy = y0 + r;
       const int R = r + OY, C = c + OX;
-      const float d = ((hx + 1 < W ? sqx[R][C] : 0.f) - (hx > 0 ? sqx[R][C - 1] : 0.f)) +
-                      ((hy + 1 < H ? sqy[R][C] : 0.f) - (hy > 0 ? sqy[R - 1][C] : 0.f));
+      const float d = ((xp(hx) ? sqx[R][C] : 0.f) - (xm(hx) ? sqx[R][C - 1] : 0.f)) +
+                      ((yp(hy) ? sqy[R][C] : 0.f) - (ym(hy) ? sqy[R - 1][C] : 0.f));
       float bl = -A.sigma * ((d + spt[R][C]) - sps[R][C]);
       if constexpr (!TWO) bl += (A.sigma * A.tau) * ((float)NL * su[R][C] - S.sus[R][C]);
       sb[R][C] = bl;
@@ -239,8 +284,8 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
         un[e] = u0;
         usn[j][e] += u0;
         float g0 = 0.f, g1 = 0.f;
-        if (gx + 1 < W) g0 = su[R][C + 1] - u0;
-        if (gy + 1 < H) g1 = su[R + 1][C] - u0;
+        if (xp(gx)) g0 = su[R][C + 1] - u0;
+        if (yp(gy)) g1 = su[R + 1][C] - u0;
         // q = q-bar - tau grad u;  z_q = P_alpha(2q - q-bar);  q-bar += rho (z_q - q)
         const float qb0 = sqx[R][C], qb1 = sqy[R][C];
         const float q0 = qb0 - tau * g0, q1 = qb1 - tau * g1;
