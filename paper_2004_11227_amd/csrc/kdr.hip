@@ -8,16 +8,14 @@
 // red, black, red sweep of
 //     u(x) <- (b(x)/st + sum_{y ~ x} u(y)) / (|N(x)| + m),
 // m = 2 (two-label) or n + 1 (Potts, per label).  Each colour needs every
-// update of the other colour, so an iteration is three launches:
+// update of the other colour, so an iteration is four launches:
 //   R1 : b^k at every cell (-> b planes), red cells updated in place
 //   B  : black cells updated in place
 //   (n sweeps: then n - 1 more red, black pairs of half-sweep launches)
-//   R2F: red cells recomputed from the final black cells (every thread that
-//        needs a red value computes it, so red values are never read from
-//        memory in this launch), red u written in place, then the flows
-//        y = y-bar + tau K u and the relaxed reflection
+//   R  : red cells updated in place from the final black cells
+//   F  : the flows y = y-bar + tau K u and the relaxed reflection
 //        y-bar += rho (prox(2y - y-bar) - y) in place (each cell touches only
-//        its own flows; b is read from its plane, not recomputed).
+//        its own flows).
 // 2-D solves (two-label and Potts) also have a fused tiled pass (tiledr.h)
 // that runs the same per-cell arithmetic with the state read once and
 // written once into the other ping-pong buffer.
@@ -111,16 +109,20 @@ struct Cell {
   int x, y, z;
 };
 
-template <int NDIM>
-__device__ __forceinline__ Cell cell_of(long long idx, int W, int H) {
-  Cell c;
-  c.x = (int)(idx % W);
-  c.y = (int)((idx / W) % H);
-  c.z = NDIM == 3 ? (int)(idx / ((long long)W * H)) : 0;
-  return c;
-}
-
 __device__ __forceinline__ bool is_red(const Cell& c) { return ((c.x + c.y + c.z) & 1) == 0; }
+
+// Row-wise visit of the cells of the dense layout: each wavefront takes one
+// row (y, z) at a time and the block's four wavefronts four rows, strided
+// over the launch's y dimension; 64-cell chunks of a row go along x.  The
+// row and its coordinates are uniform across the wavefront, so no cell
+// needs an index division.
+template <typename F>
+__device__ __forceinline__ void for_rows(int H, int D, F&& f) {
+  const long long nrows = (long long)H * D;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  for (long long row = (long long)blockIdx.y * 4 + wv; row < nrows; row += (long long)gridDim.y * 4)
+    f(row, (int)(row % H), (int)(row / H));
+}
 
 // Gauss-Seidel value at one cell from its neighbours in `u` (one label).
 // (b / (sigma tau) + sum of the neighbours) / (|N(x)| + m), the division as a
@@ -142,139 +144,130 @@ __device__ __forceinline__ float gs_value(const float* u, const float* b, long l
   return (b[idx] * inv_st + s) * rden_at(rden, nb);
 }
 
+// R1: b^k at every cell, then the red cells updated in place.
 template <int NL, bool TWO, int NDIM, typename TS>
 __global__ __launch_bounds__(256) void k_dr_r1(const KD<TS> A) {
   if (A.done && *A.done) return;
   const long long sz = (long long)A.W * A.H;
-  for (long long idx = blockIdx.x * 256LL + threadIdx.x; idx < A.n; idx += (long long)gridDim.x * 256) {
-    const Cell c = cell_of<NDIM>(idx, A.W, A.H);
-    const float psb = ld(A.psb, idx);
-    float usum = 0.f;
-    float uk[NL];
+  const int lane = threadIdx.x & 63;
+  for_rows(A.H, A.D, [&](long long row, int y, int z) {
+    for (int x = blockIdx.x * 64 + lane; x < A.W; x += gridDim.x * 64) {
+      const long long idx = row * A.W + x;
+      const Cell c{x, y, z};
+      const float psb = ld(A.psb, idx);
+      float usum = 0.f;
+      float uk[NL];
 #pragma unroll
-    for (int l = 0; l < NL; l++) {
-      uk[l] = A.u[(long long)l * A.P + idx];
-      usum += uk[l];
-    }
+      for (int l = 0; l < NL; l++) {
+        uk[l] = A.u[(long long)l * A.P + idx];
+        usum += uk[l];
+      }
 #pragma unroll
-    for (int l = 0; l < NL; l++) {
-      const TS* q = A.qb + (long long)(NDIM * l) * A.P;
-      float d = (ldz(q, idx, c.x + 1 < A.W) - ldz(q, idx - 1, c.x > 0)) +
-                (ldz(q + A.P, idx, c.y + 1 < A.H) - ldz(q + A.P, idx - A.W, c.y > 0));
-      if (NDIM == 3)
-        d += ldz(q + 2 * A.P, idx, c.z + 1 < A.D) - ldz(q + 2 * A.P, idx - sz, c.z > 0);
-      float bl = -A.sigma * ((d + ld(A.pb + (long long)l * A.P, idx)) - psb);
-      // Potts: + st ((n-1) u_i - sum_{j != i} u_j) = st (n u_i - sum_j u_j)
-      if (!TWO) bl += (A.sigma * A.tau) * ((float)NL * uk[l] - usum);
-      float* bp = A.b + (long long)l * A.P;
-      bp[idx] = bl;
+      for (int l = 0; l < NL; l++) {
+        const TS* q = A.qb + (long long)(NDIM * l) * A.P;
+        float d = (ldz(q, idx, c.x + 1 < A.W) - ldz(q, idx - 1, c.x > 0)) +
+                  (ldz(q + A.P, idx, c.y + 1 < A.H) - ldz(q + A.P, idx - A.W, c.y > 0));
+        if (NDIM == 3)
+          d += ldz(q + 2 * A.P, idx, c.z + 1 < A.D) - ldz(q + 2 * A.P, idx - sz, c.z > 0);
+        float bl = -A.sigma * ((d + ld(A.pb + (long long)l * A.P, idx)) - psb);
+        // Potts: + st ((n-1) u_i - sum_{j != i} u_j) = st (n u_i - sum_j u_j)
+        if (!TWO) bl += (A.sigma * A.tau) * ((float)NL * uk[l] - usum);
+        float* bp = A.b + (long long)l * A.P;
+        bp[idx] = bl;
+      }
+      if (is_red(c)) {
+#pragma unroll
+        for (int l = 0; l < NL; l++) {
+          float* ul = A.u + (long long)l * A.P;
+          ul[idx] = gs_value<NDIM>(ul, A.b + (long long)l * A.P, idx, c, A.W, A.H, A.D, A.inv_st, A.rden);
+        }
+      }
     }
-    if (is_red(c)) {
+  });
+}
+
+// Half-sweep over the cells of one colour (RED: the red cells, else the
+// black ones), in place; the lanes of a row take that colour's cells only
+// (every other column).
+template <int NL, int NDIM, typename TS, bool RED>
+__global__ __launch_bounds__(256) void k_dr_half(const KD<TS> A) {
+  if (A.done && *A.done) return;
+  const int lane = threadIdx.x & 63;
+  for_rows(A.H, A.D, [&](long long row, int y, int z) {
+    const int par = (y + z + (RED ? 0 : 1)) & 1;   // column parity of this colour in the row
+    for (int x = 2 * (blockIdx.x * 64 + lane) + par; x < A.W; x += 2 * gridDim.x * 64) {
+      const long long idx = row * A.W + x;
+      const Cell c{x, y, z};
 #pragma unroll
       for (int l = 0; l < NL; l++) {
         float* ul = A.u + (long long)l * A.P;
         ul[idx] = gs_value<NDIM>(ul, A.b + (long long)l * A.P, idx, c, A.W, A.H, A.D, A.inv_st, A.rden);
       }
     }
-  }
+  });
 }
 
-// Half-sweep over the cells of one colour (RED: the red cells, else the
-// black ones), in place.
-template <int NL, int NDIM, typename TS, bool RED>
-__global__ __launch_bounds__(256) void k_dr_half(const KD<TS> A) {
-  if (A.done && *A.done) return;
-  for (long long idx = blockIdx.x * 256LL + threadIdx.x; idx < A.n; idx += (long long)gridDim.x * 256) {
-    const Cell c = cell_of<NDIM>(idx, A.W, A.H);
-    if (is_red(c) != RED) continue;
-#pragma unroll
-    for (int l = 0; l < NL; l++) {
-      float* ul = A.u + (long long)l * A.P;
-      ul[idx] = gs_value<NDIM>(ul, A.b + (long long)l * A.P, idx, c, A.W, A.H, A.D, A.inv_st, A.rden);
-    }
-  }
-}
-
-template <int NDIM>
-__device__ __forceinline__ float u_final(const float* ul, const float* bl, long long idx, const Cell& c, int W,
-                                         int H, int D, float inv_st, const Rden rden) {
-  return is_red(c) ? gs_value<NDIM>(ul, bl, idx, c, W, H, D, inv_st, rden) : ul[idx];
-}
-
+// F: the flows y = y-bar + tau K u^{k+1} from the final u, and the relaxed
+// reflection y-bar += rho (prox(2y - y-bar) - y) in place (each cell
+// touches only its own flows).
 template <int NL, bool TWO, int NDIM, typename TS>
-__global__ __launch_bounds__(256) void k_dr_r2f(const KD<TS> A) {
+__global__ __launch_bounds__(256) void k_dr_flow(const KD<TS> A) {
   if (A.done && *A.done) return;
   const long long sz = (long long)A.W * A.H;
   const float tau = A.tau, rho = A.rho;
-  for (long long idx = blockIdx.x * 256LL + threadIdx.x; idx < A.n; idx += (long long)gridDim.x * 256) {
-    const Cell c = cell_of<NDIM>(idx, A.W, A.H);
-    float un[NL];
-    float usum = 0.f;
+  const int lane = threadIdx.x & 63;
+  for_rows(A.H, A.D, [&](long long row, int y, int z) {
+    for (int x = blockIdx.x * 64 + lane; x < A.W; x += gridDim.x * 64) {
+      const long long idx = row * A.W + x;
+      float usum = 0.f;
 #pragma unroll
-    for (int l = 0; l < NL; l++) {
-      const float* ul = A.u + (long long)l * A.P;
-      const float* bl = A.b + (long long)l * A.P;
-      const float u0 = u_final<NDIM>(ul, bl, idx, c, A.W, A.H, A.D, A.inv_st, A.rden);
-      un[l] = u0;
-      usum += u0;
-      // grad u^{k+1} with the forward neighbours' final values
-      float g[3] = {0.f, 0.f, 0.f};
-      if (c.x + 1 < A.W) {
-        Cell cn = c;
-        cn.x += 1;
-        g[0] = u_final<NDIM>(ul, bl, idx + 1, cn, A.W, A.H, A.D, A.inv_st, A.rden) - u0;
-      }
-      if (c.y + 1 < A.H) {
-        Cell cn = c;
-        cn.y += 1;
-        g[1] = u_final<NDIM>(ul, bl, idx + A.W, cn, A.W, A.H, A.D, A.inv_st, A.rden) - u0;
-      }
-      if (NDIM == 3 && c.z + 1 < A.D) {
-        Cell cn = c;
-        cn.z += 1;
-        g[2] = u_final<NDIM>(ul, bl, idx + sz, cn, A.W, A.H, A.D, A.inv_st, A.rden) - u0;
-      }
-      // q = q-bar - tau grad u;  z_q = P_alpha(2q - q-bar);  q-bar += rho (z_q - q)
-      TS* q = A.qb + (long long)(NDIM * l) * A.P;
-      float qbv[3], qv[3], zv[3];
+      for (int l = 0; l < NL; l++) {
+        const float* ul = A.u + (long long)l * A.P;
+        const float u0 = ul[idx];
+        usum += u0;
+        // grad u^{k+1}: forward differences, zero across the boundary
+        float g[3] = {0.f, 0.f, 0.f};
+        if (x + 1 < A.W) g[0] = ul[idx + 1] - u0;
+        if (y + 1 < A.H) g[1] = ul[idx + A.W] - u0;
+        if (NDIM == 3 && z + 1 < A.D) g[2] = ul[idx + sz] - u0;
+        // q = q-bar - tau grad u;  z_q = P_alpha(2q - q-bar);  q-bar += rho (z_q - q)
+        TS* q = A.qb + (long long)(NDIM * l) * A.P;
+        float qbv[3], qv[3], zv[3];
 #pragma unroll
-      for (int k = 0; k < NDIM; k++) {
-        qbv[k] = ld(q + (long long)k * A.P, idx);
-        qv[k] = qbv[k] - tau * g[k];
-        zv[k] = 2.f * qv[k] - qbv[k];
-      }
-      if (NDIM == 2) {
-        if (A.iso) proj2<true>(zv[0], zv[1], A.alpha);
-        else proj2<false>(zv[0], zv[1], A.alpha);
-      } else {
-        if (A.iso) proj3<true>(zv[0], zv[1], zv[2], A.alpha);
-        else proj3<false>(zv[0], zv[1], zv[2], A.alpha);
-      }
+        for (int k = 0; k < NDIM; k++) {
+          qbv[k] = ld(q + (long long)k * A.P, idx);
+          qv[k] = qbv[k] - tau * g[k];
+          zv[k] = 2.f * qv[k] - qbv[k];
+        }
+        if (NDIM == 2) {
+          if (A.iso) proj2<true>(zv[0], zv[1], A.alpha);
+          else proj2<false>(zv[0], zv[1], A.alpha);
+        } else {
+          if (A.iso) proj3<true>(zv[0], zv[1], zv[2], A.alpha);
+          else proj3<false>(zv[0], zv[1], zv[2], A.alpha);
+        }
 #pragma unroll
-      for (int k = 0; k < NDIM; k++) {
-        st(q + (long long)k * A.P, idx, qbv[k] + rho * (zv[k] - qv[k]));
-        if (A.keep_z) st(A.zq + (long long)(NDIM * l + k) * A.P, idx, zv[k]);
+        for (int k = 0; k < NDIM; k++) {
+          st(q + (long long)k * A.P, idx, qbv[k] + rho * (zv[k] - qv[k]));
+          if (A.keep_z) st(A.zq + (long long)(NDIM * l + k) * A.P, idx, zv[k]);
+        }
+        // p_i = p-bar_i + tau u_i;  z = min(C_i, 2 p_i - p-bar_i);  p-bar_i += rho (z - p_i)
+        TS* pbl = A.pb + (long long)l * A.P;
+        const float pbv = ld(pbl, idx);
+        const float pv = pbv + tau * u0;
+        const float zpv = fminf(cap_ld(A.cap, A.P, TWO ? 1 : l, idx, A.cg), 2.f * pv - pbv);
+        st(pbl, idx, pbv + rho * (zpv - pv));
+        if (A.keep_z) st(A.zp + (long long)l * A.P, idx, zpv);
       }
-      // p_i = p-bar_i + tau u_i;  z = min(C_i, 2 p_i - p-bar_i);  p-bar_i += rho (z - p_i)
-      TS* pbl = A.pb + (long long)l * A.P;
-      const float pbv = ld(pbl, idx);
-      const float pv = pbv + tau * u0;
-      const float zpv = fminf(cap_ld(A.cap, A.P, TWO ? 1 : l, idx, A.cg), 2.f * pv - pbv);
-      st(pbl, idx, pbv + rho * (zpv - pv));
-      if (A.keep_z) st(A.zp + (long long)l * A.P, idx, zpv);
+      // p_s = p-bar_s - tau sum_i u_i;  z_s = (min(C_s,) 2 p_s - p-bar_s + tau)
+      const float psbv = ld(A.psb, idx);
+      const float psv = psbv - tau * usum;
+      float zsv = (2.f * psv - psbv) + tau;
+      if (TWO) zsv = fminf(cap_ld(A.cap, A.P, 0, idx, A.cg), zsv);
+      st(A.psb, idx, psbv + rho * (zsv - psv));
+      if (A.keep_z) st(A.zs, idx, zsv);
     }
-    // p_s = p-bar_s - tau sum_i u_i;  z_s = (min(C_s,) 2 p_s - p-bar_s + tau)
-    const float psbv = ld(A.psb, idx);
-    const float psv = psbv - tau * usum;
-    float zsv = (2.f * psv - psbv) + tau;
-    if (TWO) zsv = fminf(cap_ld(A.cap, A.P, 0, idx, A.cg), zsv);
-    st(A.psb, idx, psbv + rho * (zsv - psv));
-    if (A.keep_z) st(A.zs, idx, zsv);
-    if (is_red(c)) {
-#pragma unroll
-      for (int l = 0; l < NL; l++) A.u[(long long)l * A.P + idx] = un[l];
-    }
-  }
+  });
 }
 
 template <int NL, bool TWO, int NDIM, typename TS>
@@ -304,17 +297,21 @@ static hipError_t dr_nl(const PdrqDesc& d, hipStream_t s) {
   a.keep_z = d.keep_z ? 1 : 0;
   a.done = d.done;
   a.cg = d.cg;
-  long long nb = (a.n + 255) / 256;
-  if (nb > 16384) nb = 16384;
-  // sweeps symmetric sweeps = red, black, (red, black) x (sweeps - 1), red:
-  // a red half-sweep right after a red one would repeat it exactly
-  hipLaunchKernelGGL((k_dr_r1<NL, TWO, NDIM, TS>), dim3((int)nb), dim3(256), 0, s, a);
-  hipLaunchKernelGGL((k_dr_half<NL, NDIM, TS, false>), dim3((int)nb), dim3(256), 0, s, a);
+  // x: 64-cell chunks of a row (128 for the one-colour half-sweeps); y: four
+  // rows per block, strided beyond 65535 blocks
+  const long long rows4 = ((long long)d.g.H * d.g.D + 3) / 4;
+  const int gy = (int)(rows4 < 65535 ? rows4 : 65535);
+  const dim3 g_all((d.g.W + 63) / 64, gy), g_half(((d.g.W + 1) / 2 + 63) / 64, gy);
+  // n symmetric sweeps = red, black, (red, black) x (n - 1), red: a red
+  // half-sweep right after a red one would repeat it exactly
+  hipLaunchKernelGGL((k_dr_r1<NL, TWO, NDIM, TS>), g_all, dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_dr_half<NL, NDIM, TS, false>), g_half, dim3(256), 0, s, a);
   for (int sw = 1; sw < d.sweeps; sw++) {
-    hipLaunchKernelGGL((k_dr_half<NL, NDIM, TS, true>), dim3((int)nb), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((k_dr_half<NL, NDIM, TS, false>), dim3((int)nb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_dr_half<NL, NDIM, TS, true>), g_half, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_dr_half<NL, NDIM, TS, false>), g_half, dim3(256), 0, s, a);
   }
-  hipLaunchKernelGGL((k_dr_r2f<NL, TWO, NDIM, TS>), dim3((int)nb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_dr_half<NL, NDIM, TS, true>), g_half, dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_dr_flow<NL, TWO, NDIM, TS>), g_all, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@
 // the LDS phases of label l.  Each cell's arithmetic (b with the Potts
 // coupling st (n u_i - sum_j u_j), the Gauss-Seidel value with its
 // neighbours summed in the order -x, +x, -y, +y, the flows, the reflection,
-// the label sum of the new u in label order) is that of the three in-place
+// the label sum of the new u in label order) is that of the in-place
 // launches, so both variants give the same bits.
 #pragma once
 #include "mf_kernels.h"
