@@ -298,6 +298,8 @@ def secondary(torch, maxflow, synth, np, dev, stream):
                    method="eb", relax=1.5, alpha=0.4, storage=stg)
     sweep_rate("two_3d_256_unfused_f32", vol, alg_bytes("two", 2, 3, "f32"), iters=20, model="two",
                method="eb", relax=1.5, alpha=0.4, variant="unfused")
+    sweep_rate("two_3d_256_pdrq_f32_inplace", vol, alg_bytes("two", 2, 3, "f32"), iters=20, model="two",
+               method="dr", alpha=0.4)
     del vol
     vimg = synth.config_inputs("c3")["image"][None]
     sweep_rate("two_3d_256_fused_f32_image", vimg, alg_bytes("two", 2, 3, "f32", image=True), iters=50,
