@@ -139,8 +139,10 @@ typedef struct {
   /* Preconditioner variants (section on rPDRQ; EB scheme's relaxation).
    * gs_sweeps: symmetric red-black Gauss-Seidel sweeps per rPDRQ iteration,
    *   i.e. the preconditioner M_n (n steps of the preconditioned iteration
-   *   for T u = b from u^k); 0 -> 1; 1..64; > 1 runs the in-place launches
-   *   and only applies to rPDRQ.
+   *   for T u = b from u^k); 0 -> 1; 1..64; only applies to rPDRQ.  The
+   *   fused 2-D pass takes 1..4 sweeps for two labels and 1..3 for Potts
+   *   (64 x 16 tiles beyond one sweep); more sweeps, 3-D and the unfused
+   *   variant run the in-place launches.
    * relax0, relax_ramp: rpADMMII only.  relax0 = 0: constant rho = relax.
    *   Otherwise the non-decreasing sequence rho_k = relax0 + (relax -
    *   relax0) min(k, relax_ramp) / relax_ramp for the step from iterate k,

@@ -63,6 +63,12 @@ struct Resolved {
   int nq;         // q planes per state
 };
 
+// Largest sweep count of the fused 2-D rPDRQ pass: its staged rectangle
+// grows by 2 cells per side and sweep; beyond these the LDS per workgroup
+// (and for Potts the registers) leave one wave per SIMD and the in-place
+// launches are faster (measured at 2048^2 two-label, 1024^2 n = 4).
+inline int fused_dr_sweeps(int model) { return model == MF_TWO_LABEL ? 4 : 3; }
+
 // Fill defaults and validate; returns an error message or "".
 std::string resolve(const mf_params* in, Resolved& r) {
   if (!in) return "null params";
@@ -174,7 +180,7 @@ std::string resolve(const mf_params* in, Resolved& r) {
   // owned group of a tile is one vector access whatever the width; the
   // element-wise kernels (unfused passes, in-place rPDRQ) use the dense layout.
   const bool padded = p.variant == MF_FUSED && !(p.ndim == 3 && p.model == MF_POTTS) &&
-                      (p.method != MF_RPDRQ || (p.ndim == 2 && p.gs_sweeps == 1));
+                      (p.method != MF_RPDRQ || (p.ndim == 2 && p.gs_sweeps <= fused_dr_sweeps(p.model)));
   r.g.pitch = padded ? (r.g.W + 3) / 4 * 4 : r.g.W;
   r.g.plane = (long long)align_up((size_t)r.g.nstore(), 128);
   r.esz = p.storage == MF_BF16 ? 2 : 4;
@@ -187,10 +193,12 @@ struct Layout {
   size_t state_bytes;
 };
 
-// rPDRQ as one tiled pass per iteration (2-D, one sweep, fused variant);
+// rPDRQ as one tiled pass per iteration (2-D, fused variant, up to
+// fused_dr_sweeps sweeps);
 // otherwise three in-place element-wise launches.
 bool dr_fused(const Resolved& r) {
-  return r.p.method == MF_RPDRQ && r.p.variant == MF_FUSED && r.p.ndim == 2 && r.p.gs_sweeps == 1;
+  return r.p.method == MF_RPDRQ && r.p.variant == MF_FUSED && r.p.ndim == 2 &&
+         r.p.gs_sweeps <= fused_dr_sweeps(r.p.model);
 }
 
 Layout plan(const Resolved& r) {
@@ -764,7 +772,7 @@ mf_status maxflow_tune(mf_solver* s, int32_t sweeps, int32_t what, mf_tuning* ou
   const std::vector<int> rows_l = (what & MF_TUNE_TILE) ? rows_all : std::vector<int>{p.tile_rows};
   const std::vector<int> depth_l = (what & MF_TUNE_DEPTH) ? depth_all : std::vector<int>{p.depth};
   int shape_kind = 0;   // 0: no launch-shape choice
-  if (dr && dr_fused(s->r)) shape_kind = 1;          // fused rPDRQ: 16 or 32 rows
+  if (dr && dr_fused(s->r) && p.gs_sweeps == 1) shape_kind = 1;   // fused rPDRQ, one sweep: 16 or 32 rows
   else if (!dr && fused && !d3 && two) shape_kind = 2;   // depth 1: 8/16/32 rows; depth 2: 16/32
   else if (!dr && fused && !d3) shape_kind = 3;          // Potts: 8/16/32 rows (8/16 for n > 4)
   else if (!dr && fused && d3 && two) shape_kind = 4;    // 3-D: 8/16 rows x slab depths

@@ -16,23 +16,23 @@
 //   F  : the flows y = y-bar + tau K u and the relaxed reflection
 //        y-bar += rho (prox(2y - y-bar) - y) in place (each cell touches only
 //        its own flows).
-// 2-D solves (two-label and Potts) also have a fused tiled pass (tiledr.h)
-// that runs the same per-cell arithmetic with the state read once and
-// written once into the other ping-pong buffer.
+// 2-D solves (two-label and Potts, 1 to 4 sweeps) also have a fused tiled
+// pass (tiledr.h) that runs the same per-cell arithmetic with the state read
+// once and written once into the other ping-pong buffer.
 #include "mf_kernels.h"
 #include "tiledr.h"
 
 namespace mf {
 
-template <typename TS, int TY, int NL, bool TWO>
+template <typename TS, int TY, int NL, bool TWO, int NS>
 __global__ __launch_bounds__(256) void k_dr_fused2d(const KDF<TS> A) {
-  __shared__ SmemDR<TY, TWO> S;
+  __shared__ SmemDR<TY, TWO, NS> S;
   if (A.done && *A.done) return;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % A.tiles_x) * 64;
   const int y0 = (tile / A.tiles_x) * TY;
-  if (dr_interior<TY>(x0, y0, A.W, A.H)) tile_dr2d<TS, TY, NL, TWO, false>(A, x0, y0, S);
-  else tile_dr2d<TS, TY, NL, TWO, true>(A, x0, y0, S);
+  if (dr_interior<TY, NS>(x0, y0, A.W, A.H)) tile_dr2d<TS, TY, NL, TWO, false, NS>(A, x0, y0, S);
+  else tile_dr2d<TS, TY, NL, TWO, true, NS>(A, x0, y0, S);
 }
 
 template <typename TS, int NL, bool TWO>
@@ -65,10 +65,23 @@ static hipError_t dr_fused_nl(const PdrqDesc& d, hipStream_t s) {
   a.keep_z = d.keep_z ? 1 : 0;
   a.done = d.done;
   a.cg = d.cg;
-  if (d.tile_rows == 32) {
-    hipLaunchKernelGGL((k_dr_fused2d<TS, 32, NL, TWO>), dim3(a.tiles_x * ((d.g.H + 31) / 32)), dim3(256), 0, s, a);
-  } else {
-    hipLaunchKernelGGL((k_dr_fused2d<TS, 16, NL, TWO>), dim3(a.tiles_x * ((d.g.H + 15) / 16)), dim3(256), 0, s, a);
+  // one sweep: 64 x 32 or 64 x 16 tiles; M_2 .. M_4: 64 x 16 tiles
+  const dim3 g16(a.tiles_x * ((d.g.H + 15) / 16));
+  switch (d.sweeps) {
+    case 1:
+      if (d.tile_rows == 32)
+        hipLaunchKernelGGL((k_dr_fused2d<TS, 32, NL, TWO, 1>), dim3(a.tiles_x * ((d.g.H + 31) / 32)), dim3(256), 0,
+                           s, a);
+      else
+        hipLaunchKernelGGL((k_dr_fused2d<TS, 16, NL, TWO, 1>), g16, dim3(256), 0, s, a);
+      break;
+    case 2: hipLaunchKernelGGL((k_dr_fused2d<TS, 16, NL, TWO, 2>), g16, dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_dr_fused2d<TS, 16, NL, TWO, 3>), g16, dim3(256), 0, s, a); break;
+    case 4:   // two labels only (resolve)
+      if (!TWO) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((k_dr_fused2d<TS, 16, NL, TWO, TWO ? 4 : 1>), g16, dim3(256), 0, s, a);
+      break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
@@ -330,7 +343,7 @@ static hipError_t dr_ts(const PdrqDesc& d, hipStream_t s) {
 hipError_t launch_pdrq_iter(const PdrqDesc& d, hipStream_t s) {
   if (d.sweeps < 1) return hipErrorInvalidValue;
   if (d.fused) {
-    if (d.g.ndim != 2 || d.g.pitch % 4 != 0 || d.sweeps != 1) return hipErrorInvalidValue;
+    if (d.g.ndim != 2 || d.g.pitch % 4 != 0 || d.sweeps > 4) return hipErrorInvalidValue;
     return d.bf16 ? dr_fused_ts<bf16_t>(d, s) : dr_fused_ts<float>(d, s);
   }
   if (d.g.pitch != d.g.W) return hipErrorInvalidValue;   // element-wise sweeps use the dense layout

@@ -84,7 +84,7 @@ struct PdrqDesc {
   float* b;            // NL planes of the right-hand side b^k
   float sigma, tau, rho, inv_st, alpha;
   bool keep_z;
-  bool fused;          // one tiled pass (2-D, padded rows, tile_rows 16 or 32, one sweep)
+  bool fused;          // one tiled pass (2-D, padded rows, 1 to 4 sweeps; tile_rows 16 or 32 for one)
   int tile_rows;
   int sweeps = 1;      // symmetric red-black GS sweeps (in-place launches; the fused pass runs 1)
   const int* done;

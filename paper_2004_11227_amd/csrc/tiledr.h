@@ -12,7 +12,10 @@
 // half-sweeps of the symmetric Gauss-Seidel step on the shrinking regions in
 // LDS, then the label's flows, relaxed reflection and stores on the tile;
 // p-bar_s follows the last label.  The loads of label l+1 are issued before
-// the LDS phases of label l.  Each cell's arithmetic (b with the Potts
+// the LDS phases of label l.  With NS sweeps (the preconditioner M_NS) the
+// 2 NS + 1 half-sweeps run on T+[-2NS,+2NS+1] down to T+[0,+1], b on the
+// first of them and the staged rectangle is T+[-(2NS+1),+(2NS+2)].  Each
+// cell's arithmetic (b with the Potts
 // coupling st (n u_i - sum_j u_j), the Gauss-Seidel value with its
 // neighbours summed in the order -x, +x, -y, +y, the flows, the reflection,
 // the label sum of the new u in label order) is that of the in-place
@@ -65,10 +68,19 @@ struct KDF {
   CapGen cg;            // cg.img: `cap` is one image plane
 };
 
-template <int TY, bool TWO>
+// Staged rectangle of a pass with NS symmetric sweeps (2 NS + 1 half-sweeps):
+// rows -OY .. TY+OY, cols -OX .. 63+OX (whole 4-element groups).
+template <int NS>
+struct DrHalo {
+  static constexpr int OY = 2 * NS + 1;
+  static constexpr int OX = (2 * NS + 1 + 3) / 4 * 4;
+  static constexpr int GPR = (64 + 2 * OX) / 4;   // 4-element groups per staged row
+};
+
+template <int TY, bool TWO, int NS = 1>
 struct SmemDR {
-  static constexpr int SW = 72;       // cols -4 .. 67
-  static constexpr int SH = TY + 7;   // rows -3 .. TY+3
+  static constexpr int SW = 64 + 2 * DrHalo<NS>::OX;       // cols -OX .. 63+OX
+  static constexpr int SH = TY + 2 * DrHalo<NS>::OY + 1;   // rows -OY .. TY+OY
   __align__(16) float su[SH][SW];
   __align__(16) float sqx[SH][SW];
   __align__(16) float sqy[SH][SW];
@@ -78,24 +90,27 @@ struct SmemDR {
   __align__(16) float sus[TWO ? 1 : SH][TWO ? 1 : SW];   // Potts: sum over labels of u^k
 };
 
-// A tile whose b and half-sweep cells (rows -2 .. TY+2, cols -2 .. 66) all
-// have their four neighbours inside the grid.
-template <int TY>
+// A tile whose b and half-sweep cells (rows -2 NS .. TY-1+2 NS, cols
+// -2 NS .. 63+2 NS) all have their four neighbours inside the grid.
+template <int TY, int NS>
 __device__ __forceinline__ bool dr_interior(int x0, int y0, int W, int H) {
-  return x0 > 0 && y0 > 0 && x0 + 64 + 3 < W && y0 + TY + 3 < H;
+  return x0 > 0 && y0 > 0 && x0 + 64 + 2 * NS + 1 < W && y0 + TY + 2 * NS + 1 < H;
 }
 
 // EDGE false: an interior tile (dr_interior), whose every boundary test is
-// true and folds away; the arithmetic is unchanged.
-template <typename TS, int TY, int NL, bool TWO, bool EDGE = true>
-__device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, SmemDR<TY, TWO>& S) {
+// true and folds away; the arithmetic is unchanged.  NS: symmetric sweeps
+// per iteration (the preconditioner M_NS), 2 NS + 1 half-sweeps on regions
+// shrinking by one cell per side.
+template <typename TS, int TY, int NL, bool TWO, bool EDGE = true, int NS = 1>
+__device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, SmemDR<TY, TWO, NS>& S) {
   constexpr int TX = 64, V = 4, TPR = TX / V, RSTEP = 256 / TPR, RPT = TY / RSTEP;
-  constexpr int OX = 4, OY = 3;
-  constexpr int GPR = 18;
-  constexpr int NG = (TY + 7) * GPR;
+  constexpr int OX = DrHalo<NS>::OX, OY = DrHalo<NS>::OY;
+  constexpr int GPR = DrHalo<NS>::GPR;
+  constexpr int NG = SmemDR<TY, TWO, NS>::SH * GPR;
   constexpr int KG = (NG + 255) / 256;
   static_assert(RPT >= 1, "tile height must be a multiple of 16");
   static_assert(!TWO || NL == 1, "the two-label model carries one label");
+  static_assert(NS >= 1 && NS <= 4 && 2 * NS < TY, "1 to 4 sweeps; the halo stays inside one tile row");
   auto& su = S.su;
   auto& sqx = S.sqx;
   auto& sqy = S.sqy;
@@ -111,7 +126,7 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
   auto yp = [&](int y) { return !EDGE || y + 1 < H; };
   auto ym = [&](int y) { return !EDGE || y > 0; };
 
-  // this thread's staged groups (rows -3 .. TY+3, cols -4 .. 67)
+  // this thread's staged groups (rows -OY .. TY+OY, cols -OX .. 63+OX)
   long long gi[KG];
   int gnv[KG];
 #pragma unroll
@@ -124,7 +139,7 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
     gi[m] = nv > 0 ? (long long)gy * pitch + gx : 0;
   }
   // write staged groups into an LDS array (entries outside the grid: 0)
-  auto put = [&](float (*dst)[SmemDR<TY, TWO>::SW], int m, const float (&v)[V]) {
+  auto put = [&](float (*dst)[SmemDR<TY, TWO, NS>::SW], int m, const float (&v)[V]) {
     const int h = tid + 256 * m;
     if (h < NG) {
       const int r = h / GPR, c = (h % GPR) * 4;
@@ -232,8 +247,8 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
 
 #pragma unroll 1
   for (int l = 0; l < NL; l++) {
-    // ---- stage u, q-bar, p-bar of label l on rows -3 .. TY+3, cols -4 .. 67,
-    // then start the loads of label l+1
+    // ---- stage u, q-bar, p-bar of label l on the staged rectangle, then
+    // start the loads of label l+1
 #pragma unroll
     for (int m = 0; m < KG; m++) {
       put(su, m, nu[m]);
@@ -248,9 +263,10 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
       for (int e = 0; e < V; e++) ocl[j][e] = ncl[j][e];
     if (l + 1 < NL) fetch(l + 1);
     lds_barrier();
-    // ---- b on T+[-2,+3]: -sigma (div q-bar + p-bar - p-bar_s) (+ st (n u - sum u) for Potts)
-    for (int h = tid; h < (TY + 5) * (TX + 5); h += 256) {
-      const int r = h / (TX + 5) - 2, c = h % (TX + 5) - 2;
+    // ---- b on T+[-2NS,+2NS+1]: -sigma (div q-bar + p-bar - p-bar_s) (+ st (n u - sum u) for Potts)
+    constexpr int BW = TX + 4 * NS + 1;
+    for (int h = tid; h < (TY + 4 * NS + 1) * BW; h += 256) {
+      const int r = h / BW - 2 * NS, c = h % BW - 2 * NS;
       const int hx = x0 + c, hy = y0 + r;
       const int R = r + OY, C = c + OX;
       const float d = ((xp(hx) ? sqx[R][C] : 0.f) - (xm(hx) ? sqx[R][C - 1] : 0.f)) +
@@ -260,13 +276,13 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
       sb[R][C] = bl;
     }
     lds_barrier();
-    // ---- red cells of T+[-2,+3], black cells of T+[-1,+2], red cells of T+[0,+1]
-    half_sweep(-2, TY + 5, -2, TX + 5, 0);
-    lds_barrier();
-    half_sweep(-1, TY + 3, -1, TX + 3, 1);
-    lds_barrier();
-    half_sweep(0, TY + 1, 0, TX + 1, 0);
-    lds_barrier();
+    // ---- half-sweep j (red for even j) on T+[-(2NS-j), +(2NS+1-j)]: for one
+    // sweep red on T+[-2,+3], black on T+[-1,+2], red on T+[0,+1]
+#pragma unroll
+    for (int j = 0; j <= 2 * NS; j++) {
+      half_sweep(j - 2 * NS, TY + 4 * NS + 1 - 2 * j, j - 2 * NS, TX + 4 * NS + 1 - 2 * j, j & 1);
+      lds_barrier();
+    }
     // ---- flows y = y-bar + tau K u and the relaxed reflection on the owned groups
     TS* qx_out = A.qb_out + (long long)(2 * l) * P;
     TS* pb_out = A.pb_out + (long long)l * P;

@@ -100,15 +100,17 @@ def test_valid_preconditioner_variants_accepted():
 
 
 def test_pdrq_layout_follows_the_sweep_count():
-    """The fused rPDRQ pass (one sweep) keeps two state buffers with rows
-    padded to a multiple of 4; the in-place launches of M_n (n > 1) keep one
-    dense state, so their workspace is smaller (two-label and Potts)."""
+    """The fused rPDRQ pass (1 to 4 sweeps) keeps two state buffers with rows
+    padded to a multiple of 4; the in-place launches (M_n with n > 4, or the
+    unfused variant) keep one dense state, so their workspace is smaller
+    (two-label and Potts)."""
     from paper_2004_11227_amd import maxflow as mfx
-    for kw in (dict(model="two"), dict(model="potts", nlabels=3), dict(model="potts", nlabels=8)):
-        one = mfx.workspace_bytes(mfx.make_params((64, 1001), method="dr", gs_sweeps=1, **kw))
-        two = mfx.workspace_bytes(mfx.make_params((64, 1001), method="dr", gs_sweeps=2, **kw))
+    for kw, top in ((dict(model="two"), 4), (dict(model="potts", nlabels=3), 3), (dict(model="potts", nlabels=8), 3)):
+        ws = {n: mfx.workspace_bytes(mfx.make_params((64, 1001), method="dr", gs_sweeps=n, **kw))
+              for n in (1, 2, top, top + 1, 64)}
         unf = mfx.workspace_bytes(mfx.make_params((64, 1001), method="dr", variant="unfused", **kw))
-        assert two < one and unf == two
+        assert ws[1] == ws[2] == ws[top]
+        assert ws[top + 1] == ws[64] == unf < ws[1]
 
 
 def test_image_capacities_validation_and_workspace():

@@ -25,7 +25,7 @@ def _gpu():
     need_gpu()
 
 
-@pytest.mark.parametrize("sweeps", [2, 3])
+@pytest.mark.parametrize("sweeps", [2, 3, 4, 6])
 @pytest.mark.parametrize("case", ["two-2d", "two-3d", "potts3-2d", "potts4-3d"])
 def test_pdrq_gs_sweeps(case, sweeps):
     banner(f"pdrq M_{sweeps} {case}")
@@ -48,6 +48,31 @@ def test_pdrq_gs_sweeps(case, sweeps):
     for f in ("zq", "zs", "zp"):
         err = np.max(np.abs(g[f] - getattr(st, f)))
         assert err <= 1e-3, (f, err)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("model,n,sweeps", [("two", 2, 2), ("two", 2, 3), ("two", 2, 4), ("potts", 3, 2),
+                                            ("potts", 3, 3), ("potts", 8, 2), ("potts", 8, 3)])
+def test_pdrq_fused_sweeps_equal_inplace_bitwise(sweeps, model, n, storage):
+    """The fused 2-D pass with 2 to 4 sweeps (2 sweeps + 1 half-sweeps in LDS
+    on shrinking regions; up to 4 for two labels, 3 for Potts) against the
+    in-place launches: state and resolvent outputs bit for bit, on a ragged
+    grid with edge and interior tiles."""
+    banner(f"pdrq fused M_{sweeps} {model} n={n} {storage}")
+    img = synth.ellipse_image(75, 141, 3, 0.15, 3106 + sweeps)
+    caps = synth.two_label_caps(img) if model == "two" else synth.potts_caps(img, n)
+    kw = dict(model=model, nlabels=n, method="dr", alpha=0.5 if model == "two" else 0.3, storage=storage,
+              gs_sweeps=sweeps)
+    ref = gpu_solver(caps, variant="unfused", **kw)
+    fus = gpu_solver(caps, variant="fused", **kw)
+    for k in (1, 4):
+        ref.step(k)
+        fus.step(k)
+        a, b = gpu_fields(ref), gpu_fields(fus)
+        for f in a:
+            assert np.array_equal(a[f], b[f]), (k, f)
+    ref.close()
+    fus.close()
 
 
 def test_pdrq_one_sweep_default_unchanged_and_fused():
