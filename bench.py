@@ -67,6 +67,9 @@ PROFILE_WORKLOADS = {
     "two_3d_256": (("c3", None), dict(model="two", method="eb", relax=1.5, alpha=0.4)),
     "potts4_1024": (("c2n4", None), dict(model="potts", nlabels=4, method="eb", relax=1.5, alpha=0.3)),
     "potts8_1024": (("c2n8", None), dict(model="potts", nlabels=8, method="eb", relax=1.5, alpha=0.3)),
+    "pdrq_2048": (("c1", None), dict(model="two", method="dr", alpha=0.5)),
+    "pdrq_potts4_1024": (("c2n4", None), dict(model="potts", nlabels=4, method="dr", alpha=0.3)),
+    "pdrq_3d_256": (("c3", None), dict(model="two", method="dr", alpha=0.4)),
 }
 
 
