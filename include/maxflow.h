@@ -319,9 +319,14 @@ mf_status mf_pool_admit(mf_pool* pool, const mf_params* p, const float* cap, int
 /* Enqueue steps_per_advance super-steps (one graph replay); asynchronous. */
 mf_status mf_pool_advance(mf_pool* pool);
 
-/* Synchronise and report solves that finished since the last poll: up to
- * `cap` ids into done_ids and their gaps (iter = accepted iterate, status
- * MF_OK / MF_ENOTCONV / MF_EDIVERGED) into gaps; *ndone = count. */
+/* Report solves that finished since the last poll: up to `cap` ids into
+ * done_ids and their gaps (iter = accepted iterate, status MF_OK /
+ * MF_ENOTCONV / MF_EDIVERGED) into gaps; *ndone = count.  After an advance
+ * the poll reads the status as of the advance before it (waiting only for
+ * that one), so the device keeps the newest advance while the host reads;
+ * a poll with no advance since the last poll waits for the newest.  A
+ * finished solve is stopped, so a report one advance later changes nothing
+ * but its latency. */
 mf_status mf_pool_poll(mf_pool* pool, int64_t* done_ids, mf_gap* gaps, int32_t cap, int32_t* ndone);
 
 /* Copy a solve's u (device FP32, L planes) and/or labels (device int32) and

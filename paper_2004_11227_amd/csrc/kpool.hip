@@ -29,13 +29,17 @@ __device__ __forceinline__ int xcd_item(int n) {
   return it < (int)((long long)n * (x + 1) / 8) ? it : -1;
 }
 
-// State buffer of the slot's current iterate.
-__device__ __forceinline__ int slot_buf(const PoolSlot& sl) { return (int)((sl.iter / sl.bufdiv) & 1); }
+// A launch at step `step` of an advance takes the slot's iterate
+// sl.iter + step (sl.iter: the iterate at the start of the advance); its
+// state buffer:
+__device__ __forceinline__ int slot_buf(const PoolSlot& sl, int step) {
+  return (int)(((sl.iter + step) / sl.bufdiv) & 1);
+}
 
 template <typename TS>
-__device__ __forceinline__ K2<TS> slot_k2(const PoolSlot& sl) {
+__device__ __forceinline__ K2<TS> slot_k2(const PoolSlot& sl, int step) {
   K2<TS> a;
-  const int src = slot_buf(sl), dst = src ^ 1;
+  const int src = slot_buf(sl, step), dst = src ^ 1;
   a.W = sl.W;
   a.H = sl.H;
   a.pitch = sl.pitch;
@@ -54,7 +58,7 @@ __device__ __forceinline__ K2<TS> slot_k2(const PoolSlot& sl) {
   a.k = sl.k;
   a.acc = nullptr;
   a.done = nullptr;
-  a.write = sl.iter < sl.max_iter ? 1 : 0;
+  a.write = sl.iter + step < sl.max_iter ? 1 : 0;
   a.iso = sl.iso;
   return a;
 }
@@ -63,7 +67,7 @@ __device__ __forceinline__ K2<TS> slot_k2(const PoolSlot& sl) {
 // accumulate the (two-label, fused) gap of their input iterate, or all the
 // others.  Two specialised launches keep the common no-gap body lean.
 template <int NL, bool TWO, typename TS, int TY, bool CHECK, bool VEC>
-__global__ __launch_bounds__(256) void k_pool2d(PoolDev d, int cls) {
+__global__ __launch_bounds__(256) void k_pool2d(PoolDev d, int cls, int step) {
   __shared__ Smem2<TY, CHECK> S;
   const int it = xcd_item(d.counts[cls]);
   if (it < 0) return;
@@ -73,7 +77,7 @@ __global__ __launch_bounds__(256) void k_pool2d(PoolDev d, int cls) {
   // two-label gaps are fused into the sweep; Potts gaps run in k_pool_gap2d
   const bool check = TWO && sl->check_now != 0;
   if (check != CHECK) return;
-  const K2<TS> A = slot_k2<TS>(*sl);
+  const K2<TS> A = slot_k2<TS>(*sl, step);
   double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (d1_interior<TY>(w.x0, w.y0, A.W, A.H)) tile2d<NL, TWO, TS, CHECK, TY, VEC, CHECK, false, false>(A, w.x0, w.y0, S, g);
   else tile2d<NL, TWO, TS, CHECK, TY, VEC, CHECK, false, true>(A, w.x0, w.y0, S, g);
@@ -84,7 +88,7 @@ __global__ __launch_bounds__(256) void k_pool2d(PoolDev d, int cls) {
 // k+1 kept in LDS (the depth-2 tile body); iterate k is in buffer
 // (k / 2) & 1 and k+2 goes to the other one.
 template <typename TS, int TY, bool CHECK>
-__global__ __launch_bounds__(256) void k_pool2d_d2(PoolDev d, int cls) {
+__global__ __launch_bounds__(256) void k_pool2d_d2(PoolDev d, int cls, int step) {
   __shared__ Smem2d2<TY> S;
   const int it = xcd_item(d.counts[cls]);
   if (it < 0) return;
@@ -92,7 +96,7 @@ __global__ __launch_bounds__(256) void k_pool2d_d2(PoolDev d, int cls) {
   PoolSlot* sl = d.slots + w.slot;
   if (sl->state != SLOT_RUNNING) return;
   if ((sl->check_now != 0) != CHECK) return;
-  const K2<TS> A = slot_k2<TS>(*sl);
+  const K2<TS> A = slot_k2<TS>(*sl, step);
   double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (d2_interior<TY>(w.x0, w.y0, A.W, A.H)) tile2d_d2<TS, CHECK, TY, false, false>(A, w.x0, w.y0, S, g);
   else tile2d_d2<TS, CHECK, TY, false, true>(A, w.x0, w.y0, S, g);
@@ -100,7 +104,7 @@ __global__ __launch_bounds__(256) void k_pool2d_d2(PoolDev d, int cls) {
 }
 
 template <typename TS, bool CHECK, bool VEC>
-__global__ __launch_bounds__(256) void k_pool3d(PoolDev d, int cls) {
+__global__ __launch_bounds__(256) void k_pool3d(PoolDev d, int cls, int step) {
   __shared__ Smem3<CHECK> S;
   const int it = xcd_item(d.counts[cls]);
   if (it < 0) return;
@@ -110,7 +114,7 @@ __global__ __launch_bounds__(256) void k_pool3d(PoolDev d, int cls) {
   if ((sl->check_now != 0) != CHECK) return;
   {
     K3<TS> A;
-    const int src = slot_buf(*sl), dst = src ^ 1;
+    const int src = slot_buf(*sl, step), dst = src ^ 1;
     A.W = sl->W;
     A.H = sl->H;
     A.D = sl->D;
@@ -132,7 +136,7 @@ __global__ __launch_bounds__(256) void k_pool3d(PoolDev d, int cls) {
     A.k = sl->k;
     A.acc = nullptr;
     A.done = nullptr;
-    A.write = sl->iter < sl->max_iter ? 1 : 0;
+    A.write = sl->iter + step < sl->max_iter ? 1 : 0;
     A.iso = sl->iso;
     const int z1 = min(w.z0 + A.tz, A.D);
     double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(256) void k_pool3d(PoolDev d, int cls) {
 // Gap of iterate k of every checking Potts solve, tile by tile.  It reads
 // state buffer k & 1, which the concurrent sweep k -> k+1 does not write.
 template <int NL, typename TS, int TY>
-__global__ __launch_bounds__(256) void k_pool_gap2d(PoolDev d, int cls) {
+__global__ __launch_bounds__(256) void k_pool_gap2d(PoolDev d, int cls, int step) {
   __shared__ double sred[4 * 5];
   const int it = xcd_item(d.counts[cls]);
   if (it < 0) return;
@@ -153,7 +157,7 @@ __global__ __launch_bounds__(256) void k_pool_gap2d(PoolDev d, int cls) {
   if (sl->state != SLOT_RUNNING || !sl->check_now) return;
   {
     KG<TS> A;
-    const int src = slot_buf(*sl);
+    const int src = slot_buf(*sl, step);
     A.W = sl->W;
     A.H = sl->H;
     A.D = 1;
@@ -178,33 +182,31 @@ __global__ __launch_bounds__(256) void k_pool_gap2d(PoolDev d, int cls) {
   }
 }
 
-// One workgroup (64 threads) per slot: sum the 64 accumulator rows, decide,
-// clear them, advance the iteration counter by the slot's pass length (2 for
-// two-iteration passes, else 1) and publish the status.  `only1`: this
-// bookkeeping follows the second half of a depth-2 super-step, in which only
-// the one-iteration classes ran; the others are left alone.  Status
+// One workgroup (64 threads) per slot.  Two launches per advance:
+//   decide (after the first step, whose launches carried the gaps): sum the
+//     64 accumulator rows of every checking slot, clear them, decide
+//     (converged / cap reached / diverged / promote) and publish the gap;
+//     a slot that keeps running stops checking for the rest of the advance;
+//   advance_by > 0 (after the last step): every running slot's iterate
+//     moves on by the advance's iterations, its next check is set up and
+//     its status published.
+// A stopped or frozen slot keeps the iterate its check accepted: the first
+// step wrote only the other buffer, and later launches skip it.  Status
 // codes follow mf_status: 0 converged, 1 cap reached, -4 diverged.
-// `check_step`: this super-step ran the gap-carrying launches.  A solve whose
-// check falls on another step (cannot happen with the admission rules) waits
-// for the next check step instead of deciding on empty accumulators.
-__global__ __launch_bounds__(64) void k_pool_book(PoolDev d, int check_step, int only1) {
+__global__ __launch_bounds__(64) void k_pool_book(PoolDev d, int decide, int advance_by) {
   PoolSlot* sl = d.slots + blockIdx.x;
   const int t = threadIdx.x;
   if (sl->state != SLOT_RUNNING) return;
-  if (only1 && sl->bufdiv != 1) return;
-  const bool check = sl->check_now != 0;
-  if (check && !check_step) return;
-  double v[5];
+  if (decide) {
+    if (!sl->check_now) return;
+    double v[5];
 #pragma unroll
-  for (int j = 0; j < 5; j++) v[j] = check ? wave_sum(sl->acc[t][j]) : 0.0;
-  if (check) {
+    for (int j = 0; j < 5; j++) v[j] = wave_total(sl->acc[t][j]);
 #pragma unroll
     for (int j = 0; j < 8; j++) sl->acc[t][j] = 0.0;
-  }
-  if (t != 0) return;
-  const long long k = sl->iter;
-  int state = SLOT_RUNNING;
-  if (check) {
+    if (t != 0) return;
+    const long long k = sl->iter;
+    int state = SLOT_RUNNING;
     const double P = v[0] + sl->alpha * v[1];
     const double D = v[2];
     const double m = fmax(fmax(fabs(P), fabs(D)), 1e-300);
@@ -230,16 +232,20 @@ __global__ __launch_bounds__(64) void k_pool_book(PoolDev d, int check_step, int
                             (sl->promote_iter > 0 && k >= sl->promote_iter))) {
       state = SLOT_PROMOTE;   // frozen at k until the host moves it to FP32 storage
     }
+    sl->check_now = 0;
+    sl->state = state;
+    ps.state = state;
+    ps.status = sl->status;
+    ps.iter = k;
+    return;
   }
-  if (state == SLOT_RUNNING) {
-    const long long kn = k + sl->bufdiv;
-    sl->iter = kn;
-    sl->check_now = (kn % sl->check_every == 0 || kn >= sl->max_iter) ? 1 : 0;
-  }
-  sl->state = state;
-  d.stats[blockIdx.x].state = state;
+  if (t != 0) return;
+  const long long kn = sl->iter + advance_by;
+  sl->iter = kn;
+  sl->check_now = (kn % sl->check_every == 0 || kn >= sl->max_iter) ? 1 : 0;
+  d.stats[blockIdx.x].state = sl->state;
   d.stats[blockIdx.x].status = sl->status;
-  d.stats[blockIdx.x].iter = sl->iter;
+  d.stats[blockIdx.x].iter = kn;
 }
 
 // Kernel of one (class, gap-carrying, vector-aligned) launch.

@@ -255,12 +255,6 @@ __device__ __forceinline__ float finish_u(const Coef& k, float t, float psn) {
 }
 
 // ---------------------------------------------------------------- reductions
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 // One step of a wavefront sum: v plus v moved across lanes by the DPP control
 // CTRL; rows outside ROWS add 0.
 template <int CTRL, int ROWS>

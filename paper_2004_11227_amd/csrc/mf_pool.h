@@ -3,16 +3,16 @@
 // The pool keeps many solves resident at once.  Each solve owns a slot in a
 // device table (geometry, state buffers, iteration counter, gap
 // accumulators, decision) and its tiles are items of a per-class device work
-// list.  A super-step advances every running solve by the pool's depth d (1
-// or 2 iterations): per class, one launch of the one-iteration kernel, or
-// with d = 2 one launch of the two-iteration kernel for the two-label 2-D
-// classes -- each walks its work list, reading the solve's own buffer parity
-// and gap cadence from its slot -- then one bookkeeping launch that takes
-// every solve's convergence decision and advances its counter by its pass
-// length; with d = 2 a second half then runs the one-iteration classes
-// again, followed by a bookkeeping launch for them alone.  Because all of this state lives in
-// device memory, one captured hipGraph of the super-step sequence serves any
-// mix; admission and retirement only edit the tables between replays.
+// list.  An advance runs `steps` steps; at step h every class launch walks
+// its work list and takes each solve's iterate iter + h (iter: the iterate at
+// the start of the advance), reading the buffer parity from the slot; with
+// depth 2 the two-label 2-D classes run the two-iteration kernel at even
+// steps only.  The first step carries the gaps and is followed by one
+// bookkeeping launch that takes every checking solve's decision; the last
+// step is followed by one that moves every running solve on by `steps`.
+// Because all of this state lives in device memory, one hipGraph of the
+// advance serves any mix; admission and retirement only edit the tables
+// between replays.
 #pragma once
 #include "mf_kernels.h"
 

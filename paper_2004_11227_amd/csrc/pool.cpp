@@ -120,6 +120,7 @@ struct HostSlot {
   bool used = false;
   bool reported = false;
   int64_t id = -1;
+  long long adv0 = 0;   // first advance whose status snapshot reflects this solve's last host update
   Footprint f;
   size_t off = 0;
   StateView st[2];
@@ -140,7 +141,18 @@ struct mf_pool {
   std::vector<PoolSlot> slot_img;                       // host images for uploads
   std::vector<std::vector<WorkItem>> lists;
   std::vector<int> counts;
-  PoolStat* stats_h = nullptr;                          // pinned
+  // Status snapshots: every advance ends with a copy of the status array
+  // into snap[a & 1] (pinned) and an event.  A poll after an advance reads
+  // the snapshot of the advance before it, so the device keeps the queued
+  // advance while the host reads; a poll with no advance since the last
+  // one reads the newest.  stats_h: the snapshot the last poll read.
+  PoolStat* snap[2] = {nullptr, nullptr};
+  hipEvent_t snap_ev[2] = {nullptr, nullptr};
+  long long nadv = 0;           // advances issued
+  long long last_read = -1;     // advance whose snapshot the last poll read
+  int adv_since_poll = 0;
+  PoolStat* stats_h = nullptr;
+  PoolStat* one_stat = nullptr;                         // pinned: a single slot's status
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_mask = -1;                                  // classes the graph launches
@@ -149,8 +161,7 @@ struct mf_pool {
     const void* func;
     int cls;
     int book;    // 1: bookkeeping node (fixed grid), else sized by the class's items
-    int check;   // bookkeeping: check-step flag argument
-    int only1;   // bookkeeping: second-half flag argument
+    int step;    // class launch: the step of the advance (its input iterate is iter + step)
   };
   std::vector<Node> nodes;
   std::vector<int> node_counts;                         // counts the node grids were set for
@@ -249,44 +260,61 @@ mf_status build_graph(mf_pool* P, int mask) {
   }
   P->nodes.clear();
   PHIP(hipGraphCreate(&P->graph, 0));
-  hipGraphNode_t prev = nullptr;
   PoolDev dev = P->dev;
-  const int nhalf = P->steps;   // half-steps: one iteration of the one-iteration classes each
-  for (int h = 0; h < nhalf; h++) {
+  // Steps h = 0 .. steps-1 of one advance: every class launch of step h
+  // depends on all launches of step h-1.  The first step carries the gaps
+  // and is followed by the deciding bookkeeping; the last is followed by the
+  // bookkeeping that moves every running solve on by `steps` iterations.
+  // With depth 2 the two-label 2-D classes launch the two-iteration pass at
+  // even steps only.
+  std::vector<hipGraphNode_t> prev;
+  auto add = [&](const void* f, unsigned grid, unsigned block, void** args, hipGraphNode_t& n) -> mf_status {
+    hipKernelNodeParams kp = node_params(f, grid, block, args);
+    PHIP(hipGraphAddKernelNode(&n, P->graph, prev.empty() ? nullptr : prev.data(), prev.size(), &kp));
+    return MF_OK;
+  };
+  const void* book = pool_book_kernel();
+  for (int h = 0; h < P->steps; h++) {
     const bool cstep = h == 0;
-    const bool second = P->depth == 2 && (h & 1);   // the one-iteration classes only
+    const bool odd = P->depth == 2 && (h & 1);   // the one-iteration classes only
     std::vector<hipGraphNode_t> step_nodes;
     for (int c = 0; c < kPoolClasses; c++) {
       if (!(mask & (1 << c))) continue;
       const int model = c % kPoolModels;
       const bool d2 = P->depth == 2 && model == 0;
-      if (second && d2) continue;
+      if (odd && d2) continue;
       const bool fused_gap = model == 0 || model == 5;
       const void* fs[2] = {d2 ? pool_kernel_d2(c, cstep) : pool_kernel(c, cstep && fused_gap, true),
                            (cstep && !fused_gap) ? pool_gap_kernel(c) : nullptr};
       for (const void* f : fs) {
         if (!f) continue;
-        int cls = c;
-        void* args[] = {&dev, &cls};
-        hipKernelNodeParams kp = node_params(f, grid_for(P->counts[c]), 256, args);
+        int cls = c, step = h;
+        void* args[] = {&dev, &cls, &step};
         hipGraphNode_t n;
-        PHIP(hipGraphAddKernelNode(&n, P->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+        const mf_status ms = add(f, grid_for(P->counts[c]), 256, args, n);
+        if (ms != MF_OK) return ms;
         step_nodes.push_back(n);
-        P->nodes.push_back({n, f, c, 0, 0, 0});
+        P->nodes.push_back({n, f, c, 0, h});
       }
     }
-    // a second half with no one-iteration class has nothing to advance
-    if (second && step_nodes.empty()) continue;
-    int chk = cstep ? 1 : 0, only1 = second ? 1 : 0;
-    void* bargs[] = {&dev, &chk, &only1};
-    hipKernelNodeParams kb = node_params(pool_book_kernel(), (unsigned)P->max_slots, 64, bargs);
+    if (!step_nodes.empty()) prev = step_nodes;
+    if (cstep) {
+      int decide = 1, by = 0;
+      void* bargs[] = {&dev, &decide, &by};
+      hipGraphNode_t b;
+      const mf_status ms = add(book, (unsigned)P->max_slots, 64, bargs, b);
+      if (ms != MF_OK) return ms;
+      P->nodes.push_back({b, book, -1, 1, 0});
+      prev.assign(1, b);
+    }
+  }
+  {
+    int decide = 0, by = P->steps;
+    void* bargs[] = {&dev, &decide, &by};
     hipGraphNode_t b;
-    if (step_nodes.empty())
-      PHIP(hipGraphAddKernelNode(&b, P->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kb));
-    else
-      PHIP(hipGraphAddKernelNode(&b, P->graph, step_nodes.data(), step_nodes.size(), &kb));
-    P->nodes.push_back({b, pool_book_kernel(), -1, 1, chk, only1});
-    prev = b;
+    const mf_status ms = add(book, (unsigned)P->max_slots, 64, bargs, b);
+    if (ms != MF_OK) return ms;
+    P->nodes.push_back({b, book, -1, 1, 0});
   }
   PHIP(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
   P->graph_mask = mask;
@@ -301,8 +329,8 @@ mf_status set_grids(mf_pool* P) {
   PoolDev dev = P->dev;
   for (auto& nd : P->nodes) {
     if (nd.book) continue;
-    int cls = nd.cls;
-    void* args[] = {&dev, &cls};
+    int cls = nd.cls, step = nd.step;
+    void* args[] = {&dev, &cls, &step};
     hipKernelNodeParams kp = node_params(nd.func, grid_for(P->counts[nd.cls]), 256, args);
     PHIP(hipGraphExecKernelNodeSetParams(P->exec, nd.node, &kp));
   }
@@ -404,6 +432,7 @@ mf_status promote(mf_pool* P, int slot, long long k, bool& moved) {
   H.off = off;
   H.st[0] = n0;
   H.st[1] = n1;
+  H.adv0 = P->nadv;   // earlier snapshots still show it frozen for promotion
   fill_image(P, slot, k);
   PHIP(hipMemcpyAsync(P->dev.slots + slot, &P->slot_img[slot], sizeof(PoolSlot), hipMemcpyHostToDevice,
                       P->stream));
@@ -500,7 +529,13 @@ mf_status mf_pool_create(void* arena, size_t arena_bytes, int32_t max_slots, int
     e = hipMemcpyAsync(P->dev.counts, P->counts.data(), sizeof(int) * kPoolClasses, hipMemcpyHostToDevice,
                        P->stream);
 
-  if (e == hipSuccess) e = hipHostMalloc((void**)&P->stats_h, sizeof(PoolStat) * (size_t)max_slots, hipHostMallocDefault);
+  for (int i = 0; i < 2 && e == hipSuccess; i++) {
+    e = hipHostMalloc((void**)&P->snap[i], sizeof(PoolStat) * (size_t)max_slots, hipHostMallocDefault);
+    if (e == hipSuccess) std::memset(P->snap[i], 0, sizeof(PoolStat) * (size_t)max_slots);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&P->snap_ev[i], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipHostMalloc((void**)&P->one_stat, sizeof(PoolStat), hipHostMallocDefault);
+  P->stats_h = P->snap[0];
   if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
   if (e != hipSuccess) {
     mf_pool_destroy(P);
@@ -533,6 +568,7 @@ mf_status mf_pool_admit(mf_pool* P, const mf_params* p, const float* cap, int64_
   H.used = true;
   H.reported = false;
   H.id = P->next_id++;
+  H.adv0 = P->nadv;   // earlier snapshots show the slot's previous occupant
   H.f = f;
   H.off = off;
   char* base = P->arena + off;
@@ -569,17 +605,26 @@ mf_status mf_pool_advance(mf_pool* P) {
   else ms = set_grids(P);
   if (ms != MF_OK) return ms;
   PHIP(hipGraphLaunch(P->exec, P->stream));
+  const int b = (int)(P->nadv & 1);
+  PHIP(hipMemcpyAsync(P->snap[b], P->dev.stats, sizeof(PoolStat) * (size_t)P->max_slots, hipMemcpyDeviceToHost,
+                      P->stream));
+  PHIP(hipEventRecord(P->snap_ev[b], P->stream));
+  P->nadv++;
+  P->adv_since_poll++;
   return MF_OK;
 }
 
 mf_status mf_pool_poll(mf_pool* P, int64_t* done_ids, mf_gap* gaps, int32_t cap, int32_t* ndone) {
   if (!P || !ndone) return pfail(MF_EINVAL, "null argument");
   *ndone = 0;
-  PHIP(hipMemcpyAsync(P->stats_h, P->dev.stats, sizeof(PoolStat) * (size_t)P->max_slots, hipMemcpyDeviceToHost,
-                      P->stream));
-  PHIP(hipStreamSynchronize(P->stream));
+  const long long j = P->adv_since_poll > 0 ? P->nadv - 2 : P->nadv - 1;
+  P->adv_since_poll = 0;
+  if (j < 0 || j <= P->last_read) return MF_OK;   // nothing newer to read yet
+  PHIP(hipEventSynchronize(P->snap_ev[j & 1]));
+  P->stats_h = P->snap[j & 1];
+  P->last_read = j;
   for (int i = 0; i < P->max_slots; i++) {
-    if (P->slots[i].used && P->stats_h[i].state == SLOT_PROMOTE) {
+    if (P->slots[i].used && j >= P->slots[i].adv0 && P->stats_h[i].state == SLOT_PROMOTE) {
       bool moved;
       mf_status ms = promote(P, i, P->stats_h[i].iter, moved);
       if (ms != MF_OK) return ms;
@@ -587,7 +632,7 @@ mf_status mf_pool_poll(mf_pool* P, int64_t* done_ids, mf_gap* gaps, int32_t cap,
   }
   for (int i = 0; i < P->max_slots && *ndone < cap; i++) {
     HostSlot& H = P->slots[i];
-    if (!H.used || H.reported) continue;
+    if (!H.used || H.reported || j < H.adv0) continue;
     const PoolStat& s = P->stats_h[i];
     if (s.state != SLOT_DONE) continue;
     H.reported = true;
@@ -617,10 +662,16 @@ mf_status mf_pool_retire(mf_pool* P, int64_t solve_id, float* u_dst, int32_t* la
     }
   if (slot < 0) return pfail(MF_EINVAL, "unknown solve id");
   HostSlot& H = P->slots[slot];
-  // make the last decision visible (the solve may be retired before a poll)
-  PHIP(hipMemcpyAsync(P->stats_h + slot, P->dev.stats + slot, sizeof(PoolStat), hipMemcpyDeviceToHost, P->stream));
-  PHIP(hipStreamSynchronize(P->stream));
-  const long long it = P->stats_h[slot].iter;
+  // a reported solve is stopped: its snapshot holds the final iterate; one
+  // retired before a poll reported it is read now, after the queued work
+  long long it;
+  if (H.reported) {
+    it = P->stats_h[slot].iter;
+  } else {
+    PHIP(hipMemcpyAsync(P->one_stat, P->dev.stats + slot, sizeof(PoolStat), hipMemcpyDeviceToHost, P->stream));
+    PHIP(hipStreamSynchronize(P->stream));
+    it = P->one_stat->iter;
+  }
   const StateView& v = H.st[(it / P->slot_img[slot].bufdiv) & 1];
   const long long rows = (long long)H.f.g.H * H.f.g.D;
   if (u_dst)
@@ -665,7 +716,11 @@ mf_status mf_pool_destroy(mf_pool* P) {
   if (P->stream) hipStreamSynchronize(P->stream);
   if (P->exec) hipGraphExecDestroy(P->exec);
   if (P->graph) hipGraphDestroy(P->graph);
-  if (P->stats_h) hipHostFree(P->stats_h);
+  for (int i = 0; i < 2; i++) {
+    if (P->snap[i]) hipHostFree(P->snap[i]);
+    if (P->snap_ev[i]) hipEventDestroy(P->snap_ev[i]);
+  }
+  if (P->one_stat) hipHostFree(P->one_stat);
   delete P;
   return MF_OK;
 }
