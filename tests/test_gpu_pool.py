@@ -212,3 +212,33 @@ def test_pool_rejects_unaligned_check_cadence():
         pool.admit(caps, model="two", method="dr")
     assert pool.admit(caps, model="two", check_every=10, max_iter=100) is not None
     pool.close()
+
+
+def test_reused_slot_not_judged_by_older_snapshot():
+    """A poll after an advance reads the status as of the advance before it.
+    A solve admitted into the slot of a just-retired one must not be
+    reported from a snapshot that still shows its predecessor finished."""
+    banner("pool snapshot lag and slot reuse")
+    shape = (96, 96)
+    caps = torch.from_numpy(synth.two_label_caps(synth.ellipse_image(*shape, 3, 0.1, 11)).astype(np.float32)).cuda()
+    pool = mfx.Pool(1 << 28, max_slots=1, max_tiles=1 << 12, steps_per_advance=10)
+    first = pool.admit(caps, model="two", method="eb", alpha=0.5, tol=1e-2, max_iter=50)
+    done = []
+    while not done:
+        pool.advance()
+        done = pool.poll()
+    assert [sid for sid, _ in done] == [first]
+    pool.retire(first, want_u=False, want_labels=False)
+    second = pool.admit(caps, model="two", method="eb", alpha=0.5, tol=0.0, max_iter=200)
+    assert second is not None and second != first
+    pool.advance()
+    assert pool.poll() == []        # the snapshot read predates the admission
+    reported = []
+    for _ in range(30):
+        pool.advance()
+        reported += pool.poll()
+        if reported:
+            break
+    pool.close()
+    assert [sid for sid, _ in reported] == [second]
+    assert reported[0][1]["iter"] == 200 and reported[0][1]["status"] == 1
