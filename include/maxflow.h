@@ -275,9 +275,9 @@ const char* maxflow_last_error(void);
  * and advances all of them together.  Each solve is cut into tiles; one
  * kernel launch per model class walks a device-resident work list of
  * (solve, tile) items drawn from grids of any size (one item per workgroup),
- * and every running solve advances one iteration per super-step with its own
+ * and every running solve advances one iteration per step with its own
  * iteration counter, gap cadence and convergence decision (all on the GPU).
- * `steps_per_advance` super-steps form one hipGraph; admission and
+ * `steps_per_advance` steps form one hipGraph; admission and
  * retirement edit the device tables between replays and resize the graph's
  * kernel grids in place (the graph is rebuilt only when the set of classes
  * present changes).  A solve's iterates are bit-identical alone, in any mix,
@@ -301,12 +301,11 @@ size_t mf_pool_table_bytes(int32_t max_slots, int32_t max_tiles);
 /* `arena`: device, 256-byte aligned, caller-owned, outlives the pool;
  * `max_slots`: resident solves at most; `max_tiles`: work-list capacity per
  * class; `steps_per_advance`: iterations per mf_pool_advance; `depth`:
- * iterations per super-step, 1 or 2 (0 -> 2 when steps_per_advance is even,
- * else 1; steps_per_advance must be a multiple of it).  With depth 2 the
- * two-label 2-D classes run the two-iteration pass (iterate k+1 kept in
- * LDS, one state read and write per two iterations) and the other classes
- * two one-iteration sweeps per super-step; the iterates are the same bits
- * as with depth 1.  `hip_stream`: a created (non-default) hipStream_t. */
+ * 1 or 2 (0 -> 2 when steps_per_advance is even, else 1; steps_per_advance
+ * must be a multiple of it).  With depth 2 the two-label 2-D classes run
+ * the two-iteration pass (iterate k+1 kept in LDS, one state read and write
+ * per two iterations) every other step and the other classes one sweep per
+ * step; the iterates are the same bits as with depth 1.  `hip_stream`: a created (non-default) hipStream_t. */
 mf_status mf_pool_create(void* arena, size_t arena_bytes, int32_t max_slots, int32_t max_tiles,
                          int32_t steps_per_advance, int32_t depth, void* hip_stream, mf_pool** out);
 
@@ -316,7 +315,8 @@ mf_status mf_pool_create(void* arena, size_t arena_bytes, int32_t max_slots, int
  * (retry after retiring solves); MF_EINVAL on invalid/unsupported params. */
 mf_status mf_pool_admit(mf_pool* pool, const mf_params* p, const float* cap, int64_t* solve_id);
 
-/* Enqueue steps_per_advance super-steps (one graph replay); asynchronous. */
+/* Enqueue steps_per_advance steps (one graph replay) and a copy of the
+ * status array for mf_pool_poll; asynchronous. */
 mf_status mf_pool_advance(mf_pool* pool);
 
 /* Report solves that finished since the last poll: up to `cap` ids into

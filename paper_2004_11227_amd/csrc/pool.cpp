@@ -3,15 +3,15 @@
 // The caller hands the pool one device arena.  Its head holds the device
 // tables (slot table, per-slot status, per-class work lists and counts); the
 // rest is carved first-fit into one block per admitted solve (capacities and
-// two state buffers), so admission is decided exactly by footprint.  A
-// half-step launches, for every class as a parallel graph branch, the sweep
-// over the class work list (and, for Potts classes, the per-tile gap
-// kernel), then the bookkeeping kernel.  With depth 2 the two-label 2-D
-// classes run a two-iteration pass in every other half-step and sit out the
-// halves between.  The half-steps of one advance (steps_per_advance
-// iterations) form one hipGraph, built when the set of classes changes,
-// whose kernel grids are resized in place to the item counts, and replayed
-// by every mf_pool_advance.
+// two state buffers), so admission is decided exactly by footprint.  A step
+// launches, for every class as a parallel graph branch, the sweep over the
+// class work list (and, at the first step, the Potts classes' per-tile gap
+// kernel).  With depth 2 the two-label 2-D classes run a two-iteration pass
+// at even steps and sit out the odd ones.  Bookkeeping runs twice per
+// advance: after the first step (decisions) and after the last (counters).
+// The steps of one advance (steps_per_advance iterations) form one hipGraph,
+// built when the set of classes changes, whose kernel grids are resized in
+// place to the item counts, and replayed by every mf_pool_advance.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -133,7 +133,7 @@ struct mf_pool {
   size_t arena_bytes = 0;
   hipStream_t stream = nullptr;
   int max_slots = 0, max_tiles = 0, steps = 0;   // steps: iterations per advance
-  int depth = 1;                                  // iterations per super-step
+  int depth = 1;                                  // iterations per pass of the two-label 2-D classes
   PoolDev dev;
   size_t data_off = 0;
   std::vector<std::pair<size_t, size_t>> free_list;   // (offset, size), sorted
@@ -237,18 +237,17 @@ hipKernelNodeParams node_params(const void* func, unsigned grid, unsigned block,
   return kp;
 }
 
-// Build the super-steps of one advance for the classes in `mask` as an
-// explicit graph.  A half-step launches, per class and in parallel, the
-// sweep (the gap-carrying variant at step 0 for two-label classes) and, at
-// step 0, the per-tile Potts gap, all depending on the previous bookkeeping
-// node, then one bookkeeping node.  Depth 1: steps_per_advance half-steps.
-// Depth 2: steps_per_advance / 2 super-steps of two halves; the first runs
-// every class (the two-label 2-D classes with their two-iteration pass), the
-// second only the one-iteration classes, so a solve that stops at a check
-// keeps its iterate (no sweep past it overwrites its buffer).  Every pool
-// solve checks at multiples of check_every == steps_per_advance, starting
-// at a replay boundary, so step 0 is the check step of every solve.
-// Kernel-node grids follow the class item counts (set_grids).
+// Build the steps of one advance for the classes in `mask` as an explicit
+// graph.  Step h launches, per class and in parallel, the sweep of each
+// solve's iterate iter + h (the gap-carrying variant at step 0 for
+// two-label classes) and, at step 0, the per-tile Potts gap.  Depth 2: the
+// two-label 2-D classes launch their two-iteration pass at even steps only.
+// Every pool solve checks at multiples of check_every == steps_per_advance,
+// starting at a replay boundary, so step 0 is the check step of every
+// solve; the deciding bookkeeping follows it, so a solve that stops or is
+// frozen there keeps its iterate (step 0 wrote only its other buffer and
+// later launches skip it).  Kernel-node grids follow the class item counts
+// (set_grids).
 mf_status build_graph(mf_pool* P, int mask) {
   if (P->exec) {
     hipGraphExecDestroy(P->exec);

@@ -353,7 +353,7 @@ class Pool:
     """Continuous-batching pool over one device arena (a torch uint8 tensor
     owned here).  admit() returns a solve id, or None when the arena, the slot
     table or the class work list is full (MF_ENOMEM).  ``depth``: iterations
-    per super-step (0: 2 when steps_per_advance is even, else 1)."""
+    per two-label 2-D pass (0: 2 when steps_per_advance is even, else 1)."""
 
     def __init__(self, arena_bytes: int, max_slots: int = 256, max_tiles: int = 1 << 16,
                  steps_per_advance: int = 10, device=None, stream: torch.cuda.Stream | None = None,

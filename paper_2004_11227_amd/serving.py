@@ -68,7 +68,7 @@ def serve(requests, backend, clock=time.perf_counter, advances_per_poll: int = 1
 
     `working_set` (bytes, optional) bounds the summed footprint of the solves
     advanced together, so that they stay resident in the last-level cache
-    between super-steps; a request larger than the bound is admitted only
+    between advances; a request larger than the bound is admitted only
     into an empty pool (it then runs alone, like the one-at-a-time path).
     The backend's own arena bound still applies."""
     pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
