@@ -96,6 +96,11 @@ def parse():
     return ap.parse_args()
 
 
+def phase(msg):
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def make_solver(torch, maxflow, caps_t, stream, **kw):
     return maxflow.Solver(caps_t, stream=stream, **kw)
 
@@ -189,6 +194,7 @@ def main():
                           "sweeps": args.profile_sweeps, "shape": list(pc.shape[1:])}))
         return
 
+    phase(f"headline: {wl['name']} solves")
     s = make_solver(torch, maxflow, caps_t, stream, **kw)
 
     def one_step():
@@ -210,6 +216,7 @@ def main():
 
     # dominant kernel: the two-iteration pass, average duration over
     # back-to-back launches (step(n) issues n / 2 passes)
+    phase("headline: kernel timing")
     t_iter = time_sweeps(torch, s, stream, args.kernel_sweeps)
     t_launch = t_iter * wl["depth"]
     launch_bytes = BYTES_PER_PX["f32"] * npx
@@ -225,6 +232,7 @@ def main():
     if not args.no_extra:
         extra = secondary(torch, maxflow, synth, np, dev, stream)
         if args.serving_requests > 0:
+            phase("serving mix")
             extra["serving"] = serving_summary(args.serving_requests)
 
     out = {"metric": "pixel*label ADMM iterations/s (two-label 2048^2, rpADMMII, FP32)",
@@ -237,6 +245,7 @@ def main():
                       "tile_rows": wl["tile_rows"], "parallelism": "single GPU"},
            "roofline": roof}
     if not args.no_cpu:
+        phase("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(caps64, wl)
     if extra:
         out["extra"] = extra
@@ -251,6 +260,7 @@ def secondary(torch, maxflow, synth, np, dev, stream):
         # per-iteration time; alg_GBps = algorithmic bytes of one depth-1
         # sweep / time per iteration (a depth-2 pass moves them once per two
         # iterations, so its figure can exceed the HBM peak)
+        phase(f"secondary: {name}")
         t = torch.from_numpy(caps.astype(np.float32)).to(dev)
         s = maxflow.Solver(t, stream=stream, **kw)
         dt = time_sweeps(torch, s, stream, iters)
@@ -317,7 +327,7 @@ def serving_summary(nreq):
     request trace: solves/s at saturation and p50/p99 latency under Poisson
     arrivals at 0.7x the one-at-a-time capacity."""
     from paper_2004_11227_amd import serving
-    r = serving.benchmark(nreq=nreq, pool_storage="bf16", tol=1e-4, max_iter=1000)
+    r = serving.benchmark(nreq=nreq, pool_storage="bf16", tol=1e-4, max_iter=1000, log=phase)
     keep = ("solves_per_s", "p50_latency_s", "p99_latency_s", "mean_iters", "converged", "capped")
     out = {k: r[k] for k in ("requests", "tol", "max_iter", "total_pixels", "promotions_total",
                              "speedup_solves_per_s", "latency_rate_per_s")}

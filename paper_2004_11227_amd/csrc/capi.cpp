@@ -281,8 +281,8 @@ struct mf_solver {
   float* wbuf;
   int64_t iter;
   int off;          // iterate k lives in state buffer (k + off) & 1
-  int* host_done;       // pinned, coherent polling slots (host address)
-  int* host_done_dev;   // the same slots as the device writes them
+  int* host_done;   // pinned polling slots
+  hipEvent_t ev[8];
   int dev;
 };
 
@@ -506,15 +506,17 @@ mf_status maxflow_create(const mf_params* p, const float* cap, void* workspace, 
     delete s;
     return fail(MF_EDEVICE, "hipGetDevice failed");
   }
-  if (hipHostMalloc((void**)&s->host_done, 64 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent) !=
-      hipSuccess) {
+  if (hipHostMalloc((void**)&s->host_done, 64 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
     delete s;
     return fail(MF_EDEVICE, "pinned host allocation failed");
   }
-  if (hipHostGetDevicePointer((void**)&s->host_done_dev, s->host_done, 0) != hipSuccess) {
-    hipHostFree(s->host_done);
-    delete s;
-    return fail(MF_EDEVICE, "pinned host memory is not mapped");
+  for (int i = 0; i < 8; i++) {
+    if (hipEventCreateWithFlags(&s->ev[i], hipEventDisableTiming) != hipSuccess) {
+      for (int j = 0; j < i; j++) hipEventDestroy(s->ev[j]);
+      hipHostFree(s->host_done);
+      delete s;
+      return fail(MF_EDEVICE, "event creation failed");
+    }
   }
   hipError_t he = launch_pitch_copy(cap, false, r.g.npix(), r.g.W, s->cap, r.p.storage == MF_BF16, r.g.plane,
                                     r.g.pitch, r.g.W, (long long)r.g.H * r.g.D, r.ncp, s->stream);
@@ -589,10 +591,10 @@ mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
   // buffer offset in effect at each checked iterate: the accepted iterate's
   // buffer once later passes (which flip the offset) have been skipped
   std::vector<std::pair<int64_t, int>> off_at;
-  // polling ring: each check's bookkeeping writes 1 (running) or 2 (stopped)
-  // into pinned slot (chunk & 7), which the host cleared before issuing the
-  // chunk; no event or copy enters the stream, so the queue has no bubbles.
-  // The host keeps at most `lookahead` unobserved chunks queued.
+  // polling ring: after each chunk, `done` is copied into pinned slot
+  // (chunk & 7) and an event marks the copy; the host keeps at most
+  // `lookahead` unobserved chunks queued.  (The device never stores into
+  // host memory itself: only the runtime's copies write there.)
   int issued = 0, observed = 0;
   const int lookahead = 3;
   bool stop = false;
@@ -615,10 +617,7 @@ mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
       HIP_TRY(gap_of(s, k, done));
       if (!final_check) HIP_TRY(admm_sweep(s, k, false, true, done));
     }
-    const int slot = issued & 7;
-    if (!final_check) __atomic_store_n(&s->host_done[slot], 0, __ATOMIC_RELEASE);
-    HIP_TRY(launch_bookkeep(s->ctrl, k, p.alpha, p.tol, nres(s), final_check ? 1 : 0, 1, s->stream,
-                            final_check ? nullptr : s->host_done_dev + slot));
+    HIP_TRY(launch_bookkeep(s->ctrl, k, p.alpha, p.tol, nres(s), final_check ? 1 : 0, 1, s->stream));
     if (final_check) break;
     // ---- the rest of the chunk
     if (dr) {
@@ -635,24 +634,18 @@ mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
       }
     }
     k += n;
-    // ---- follow the decisions without stalling the queue
+    // ---- poll the decision without stalling the queue
+    const int slot = issued & 7;
+    HIP_TRY(hipMemcpyAsync(s->host_done + slot, done, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipEventRecord(s->ev[slot], s->stream));
     issued++;
-    long spins = 0;
     while (observed < issued) {
       const int os = observed & 7;
-      const int v = __atomic_load_n(&s->host_done[os], __ATOMIC_ACQUIRE);
-      if (v == 0) {
-        if (issued - observed <= lookahead) break;   // enough queued: issue the next chunk
-        if (++spins % 4096 == 0) {                   // a device error, or a flag that never comes
-          const hipError_t q = hipStreamQuery(s->stream);
-          if (q != hipSuccess && q != hipErrorNotReady)
-            return fail(MF_EDEVICE, std::string("stream: ") + hipGetErrorString(q));
-          if (q == hipSuccess && __atomic_load_n(&s->host_done[os], __ATOMIC_ACQUIRE) == 0)
-            return fail(MF_EDEVICE, "solve: decision flag not written");
-        }
-        continue;
-      }
-      if (v == 2) stop = true;
+      const hipError_t q =
+          (issued - observed > lookahead) ? hipEventSynchronize(s->ev[os]) : hipEventQuery(s->ev[os]);
+      if (q == hipErrorNotReady) break;
+      if (q != hipSuccess) return fail(MF_EDEVICE, std::string("event: ") + hipGetErrorString(q));
+      if (s->host_done[os]) stop = true;
       observed++;
     }
   }
@@ -848,6 +841,8 @@ mf_status maxflow_tune(mf_solver* s, int32_t sweeps, int32_t what, mf_tuning* ou
 mf_status maxflow_destroy(mf_solver* s) {
   if (!s) return MF_OK;
   hipStreamSynchronize(s->stream);
+  for (int i = 0; i < 8; i++)
+    if (s->ev[i]) hipEventDestroy(s->ev[i]);
   if (s->host_done) hipHostFree(s->host_done);
   delete s;
   return MF_OK;

@@ -242,20 +242,14 @@ hipError_t launch_ctrl_reset(Ctrl* c, hipStream_t s) {
 // `decide`) whether the solve stops there, and clears the accumulators.
 // Status codes follow mf_status: 0 converged, 1 cap reached, -4 diverged.
 // One wavefront, lane t reading and clearing accumulator slot t.
-// host_flag (optional): pinned host memory that receives 1 (checked, still
-// running) or 2 (stopped), so the host follows the solve without events or
-// copies on the stream.
 static_assert(kAccSlots == 64, "one lane per accumulator slot");
 __global__ __launch_bounds__(64) void k_bookkeep(Ctrl* c, long long k, double alpha, double tol, long long nres,
-                                                 int final_check, int decide, int* host_flag) {
+                                                 int final_check, int decide) {
   const int t = threadIdx.x;
   double tot[5];
 #pragma unroll
   for (int j = 0; j < 5; j++) tot[j] = c->acc[t][j];   // issued together with the read of done
-  if (c->done) {
-    if (t == 0 && host_flag) *host_flag = 2;
-    return;
-  }
+  if (c->done) return;
 #pragma unroll
   for (int j = 0; j < 5; j++) tot[j] = wave_total(tot[j]);
 #pragma unroll
@@ -288,13 +282,11 @@ __global__ __launch_bounds__(64) void k_bookkeep(Ctrl* c, long long k, double al
       c->iter = k;
     }
   }
-  // the store reaches the coherent host page before the kernel completes
-  if (host_flag) *host_flag = c->done ? 2 : 1;
 }
 
 hipError_t launch_bookkeep(Ctrl* c, long long k, double alpha, double tol, long long nres, int final_check,
-                           int decide, hipStream_t s, int* host_flag) {
-  hipLaunchKernelGGL(k_bookkeep, dim3(1), dim3(64), 0, s, c, k, alpha, tol, nres, final_check, decide, host_flag);
+                           int decide, hipStream_t s) {
+  hipLaunchKernelGGL(k_bookkeep, dim3(1), dim3(64), 0, s, c, k, alpha, tol, nres, final_check, decide);
   return hipGetLastError();
 }
 

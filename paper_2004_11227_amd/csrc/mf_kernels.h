@@ -115,6 +115,6 @@ hipError_t launch_convert_planes(const void* src, bool src_bf16, void* dst, bool
                                  long long src_stride, long long dst_stride, hipStream_t s);
 hipError_t launch_ctrl_reset(Ctrl* c, hipStream_t s);
 hipError_t launch_bookkeep(Ctrl* c, long long k, double alpha, double tol, long long nres,
-                           int final_check, int decide, hipStream_t s, int* host_flag = nullptr);
+                           int final_check, int decide, hipStream_t s);
 
 }  // namespace mf
