@@ -593,8 +593,8 @@ mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
   std::vector<std::pair<int64_t, int>> off_at;
   // polling ring: after each chunk, `done` is copied into pinned slot
   // (chunk & 7) and an event marks the copy; the host keeps at most
-  // `lookahead` unobserved chunks queued.  (The device never stores into
-  // host memory itself: only the runtime's copies write there.)
+  // `lookahead` unobserved chunks queued.  (No kernel of this library
+  // stores into host memory: only the runtime's copies write there.)
   int issued = 0, observed = 0;
   const int lookahead = 3;
   bool stop = false;
