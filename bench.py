@@ -128,7 +128,7 @@ def cpu_baseline(caps64, wl):
     oracle.step(pr, caps64, st, 1)
     n = shape[0] * shape[1]
     threads = oracle.num_threads()
-    iters = 40
+    iters = 200   # ~10 s of the host's cores at the measured ~1.5e8 pixel*label*it/s
     t0 = time.perf_counter()
     oracle.step(pr, caps64, st, iters)
     dt = time.perf_counter() - t0
