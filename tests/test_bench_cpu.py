@@ -1,5 +1,6 @@
-"""Host-side checks of bench.py (no GPU): the one-GPU refusal and the
-algorithmic bytes per pixel and iteration that the roofline divides by."""
+"""Host-side checks of bench.py (no GPU): the one-GPU refusal, progress on
+stderr only, and the algorithmic bytes per pixel and iteration that the
+roofline divides by."""
 import os
 import subprocess
 import sys
@@ -35,3 +36,11 @@ def test_algorithmic_bytes(model, n, ndim, storage, expect):
 def test_image_capacities_replace_the_planes():
     assert bench.alg_bytes("two", 2, 2, "f32", image=True) == 48 - 4
     assert bench.alg_bytes("potts", 8, 2, "f32", image=True) == 296 - 7 * 4
+
+
+def test_progress_goes_to_stderr(capsys):
+    """stdout carries only the JSON line; phase markers go to stderr."""
+    bench.phase("headline: two_label_2d_2048 solves")
+    out = capsys.readouterr()
+    assert out.out == ""
+    assert out.err == "[bench] headline: two_label_2d_2048 solves\n"
