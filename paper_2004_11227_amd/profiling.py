@@ -10,6 +10,8 @@ plain copy kernel (the counter calibration) and then runs the kernel of
 interest.  Writes OUT_PREFIX.md (human summary) and OUT_PREFIX_traffic.json
 (per-launch HBM bytes of the kernel of interest, scaled by the copy
 calibration, with the source hash of the kernel it was measured on).
+With FETCH_DIR and WRITE_DIR given as `-`, only the kernel-trace table is
+written (OUT_PREFIX.md).
 """
 from __future__ import annotations
 
@@ -63,6 +65,16 @@ def main():
     ap.add_argument("--sources", nargs="*", default=[])
     a = ap.parse_args()
     ks = kernel_stats(a.ktrace)
+    if a.fetch == "-" and a.write == "-":
+        total = sum(calls * avg for _, calls, avg, _ in ks)
+        lines = [f"# rocprofv3 kernel trace: {a.kernel}", "", f"Command: `{a.command}`", "",
+                 "| kernel | calls | average us | % time |", "|---|---|---|---|"]
+        for name, calls, avg, pct in ks[:16]:
+            lines.append(f"| `{name[:110]}` | {calls} | {avg / 1e3:.2f} | {pct:.2f} |")
+        lines += ["", f"Total kernel time {total / 1e6:.1f} ms over {sum(c for _, c, _, _ in ks)} dispatches."]
+        open(a.out + ".md", "w").write("\n".join(lines) + "\n")
+        print("\n".join(lines))
+        return
     fe, wr = counters(a.fetch), counters(a.write)
     copy_k = [k for k in fe if "copyBuffer" in k or "copy" in k.lower()]
     ck = copy_k[0]
