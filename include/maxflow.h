@@ -71,7 +71,10 @@ typedef enum {
   MF_EINVAL = -1,    /* invalid argument (shape, parameter range, model/labels)  */
   MF_ENOMEM = -2,    /* workspace too small / pool budget exceeded               */
   MF_EDEVICE = -3,   /* HIP runtime error                                        */
-  MF_EDIVERGED = -4  /* NaN or Inf in the primal-dual gap                        */
+  MF_EDIVERGED = -4  /* NaN or Inf in the gap or the residual, or a gap below
+                        minus the bound that rounding of the stored flows can
+                        explain (1e-5 with FP32 storage, 8e-3 with BF16): weak
+                        duality (Section 2.1) rules out a larger negative gap */
 } mf_status;
 
 typedef enum { MF_TWO_LABEL = 0, MF_POTTS = 1 } mf_model;
@@ -199,7 +202,8 @@ mf_status maxflow_reset(mf_solver* s);
 mf_status maxflow_step(mf_solver* s, int32_t iters);
 
 /* Evaluate the gap at the current iterate (FP64 reduction on the GPU);
- * synchronises the stream. */
+ * synchronises the stream.  Returns MF_EDIVERGED (with *out filled) on a
+ * non-finite or negative gap as described for that status. */
 mf_status maxflow_gap(mf_solver* s, mf_gap* out);
 
 /* Iterate until the relative gap at a multiple of check_every is <= tol or
@@ -300,7 +304,8 @@ size_t mf_pool_table_bytes(int32_t max_slots, int32_t max_tiles);
 
 /* `arena`: device, 256-byte aligned, caller-owned, outlives the pool;
  * `max_slots`: resident solves at most; `max_tiles`: work-list capacity per
- * class; `steps_per_advance`: iterations per mf_pool_advance; `depth`:
+ * class; `steps_per_advance`: iterations per mf_pool_advance, which must be
+ * 10 (MF_EINVAL otherwise: other step counts are not supported); `depth`:
  * 1 or 2 (0 -> 2 when steps_per_advance is even, else 1; steps_per_advance
  * must be a multiple of it).  With depth 2 the two-label 2-D classes run
  * the two-iteration pass (iterate k+1 kept in LDS, one state read and write

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -28,17 +29,25 @@ using namespace mf;
 
 namespace {
 
-thread_local std::string g_err;
+// Last error message of this thread, in a fixed buffer: recording an error
+// never allocates (the allocation-free entry point relies on it).
+thread_local char g_err[512];
 
-mf_status fail(mf_status s, const std::string& msg) {
-  g_err = msg;
+void set_err(const char* a, const char* b = nullptr) {
+  if (b) snprintf(g_err, sizeof(g_err), "%s: %s", a, b);
+  else snprintf(g_err, sizeof(g_err), "%s", a);
+}
+
+mf_status fail(mf_status s, const char* msg, const char* detail = nullptr) {
+  set_err(msg, detail);
   return s;
 }
+mf_status fail(mf_status s, const std::string& msg) { return fail(s, msg.c_str()); }
 
 }  // namespace
 
 namespace mf {
-void set_error(const std::string& m) { g_err = m; }
+void set_error(const std::string& m) { set_err(m.c_str()); }
 }  // namespace mf
 
 namespace {
@@ -46,8 +55,7 @@ namespace {
 #define HIP_TRY(expr)                                                                       \
   do {                                                                                      \
     hipError_t _e = (expr);                                                                 \
-    if (_e != hipSuccess)                                                                   \
-      return fail(MF_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));           \
+    if (_e != hipSuccess) return fail(MF_EDEVICE, #expr, hipGetErrorString(_e));           \
   } while (0)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -69,8 +77,9 @@ struct Resolved {
 // launches are faster (measured at 2048^2 two-label, 1024^2 n = 4).
 inline int fused_dr_sweeps(int model) { return model == MF_TWO_LABEL ? 4 : 3; }
 
-// Fill defaults and validate; returns an error message or "".
-std::string resolve(const mf_params* in, Resolved& r) {
+// Fill defaults and validate; returns an error message or "" (string
+// literals only: validation never allocates).
+const char* resolve(const mf_params* in, Resolved& r) {
   if (!in) return "null params";
   r.p = *in;
   mf_params& p = r.p;
@@ -259,8 +268,8 @@ namespace mf {
 // Parameter resolution shared with the pool.
 std::string resolve_params(const mf_params* in, mf_params& out, Geom& g, int& nl, int& ncap) {
   Resolved r;
-  const std::string e = resolve(in, r);
-  if (!e.empty()) return e;
+  const char* e = resolve(in, r);
+  if (*e) return e;
   out = r.p;
   g = r.g;
   nl = r.nl;
@@ -325,8 +334,11 @@ Coef coef_of(const Resolved& r, int64_t it) {
 // the other buffer and flips `off`.
 int buf_of(const mf_solver* s, int64_t k) { return (int)((k + s->off) & 1); }
 
+// The gap of the input iterate rides on the fused sweep: every fused rpADMM
+// pass except 3-D Potts (which runs the per-operator kernels).
 bool fused_gap(const mf_solver* s) {
-  return s->r.p.variant == MF_FUSED && s->r.p.model == MF_TWO_LABEL;
+  return s->r.p.variant == MF_FUSED && s->r.p.method != MF_RPDRQ &&
+         (s->r.p.model == MF_TWO_LABEL || s->r.g.ndim == 2);
 }
 
 // One rpADMM sweep from iterate k (buffer k%2) to k+1.
@@ -352,6 +364,7 @@ hipError_t admm_sweep(mf_solver* s, int64_t k, bool check, bool write, const int
   d.sigma = (float)s->r.p.sigma;
   d.tau = (float)s->r.p.tau;
   d.cg = s->r.cg;
+  d.stream = s->L.total > kStreamBytes;
   // Potts 3-D has no fused pass: it always runs the per-operator kernels
   if (s->r.p.variant == MF_UNFUSED || (s->r.g.ndim == 3 && s->r.p.model == MF_POTTS))
     return launch_unfused(d, s->stream);
@@ -376,6 +389,7 @@ hipError_t admm_pass2(mf_solver* s, int64_t k, bool check, const int* done, bool
   d.wbuf = s->wbuf;
   d.k = coef_of(s->r, k);
   d.cg = s->r.cg;
+  d.stream = s->L.total > kStreamBytes;
   d.acc = &s->ctrl->acc[0][0];
   d.done = done;
   const hipError_t e = launch_fused2d_d2(d, s->stream);
@@ -406,6 +420,7 @@ hipError_t dr_iter(mf_solver* s, int64_t k, bool keep_z, const int* done) {
   d.sweeps = s->r.p.gs_sweeps;
   d.done = done;
   d.cg = s->r.cg;
+  d.stream = s->L.total > kStreamBytes;
   return launch_pdrq_iter(d, s->stream);
 }
 
@@ -431,6 +446,7 @@ hipError_t gap_of(mf_solver* s, int64_t k, const int* done) {
 }
 
 long long nres(const mf_solver* s) { return s->r.g.npix() * s->r.nl; }
+double neg_tol(const mf_solver* s) { return neg_gap_tol(s->r.p.storage == MF_BF16); }
 
 mf_status init_state(mf_solver* s) {
   HIP_TRY(launch_init(s->r.g, s->r.nl, s->r.p.model == MF_TWO_LABEL, s->r.p.storage == MF_BF16, s->cap,
@@ -462,17 +478,143 @@ void fill_gap(const Ctrl& c, int64_t iter, mf_gap* out, int32_t status) {
   out->status = status;
 }
 
+// Checked iterates whose decision the host has not seen yet, with the buffer
+// offset in effect at each (depth-2 passes flip it): once the solve has
+// stopped, the accepted iterate's offset is looked up here.  The host keeps
+// at most a few chunks unobserved, so a short ring suffices.
+struct OffRing {
+  static constexpr int kN = 32;
+  int64_t k[kN];
+  int off[kN];
+  int n = 0;
+  void push(int64_t kk, int o) {
+    k[n % kN] = kk;
+    off[n % kN] = o;
+    n++;
+  }
+  bool find(int64_t kk, int& o) const {
+    for (int i = 0; i < kN && i < n; i++) {
+      const int j = (n - 1 - i) % kN;
+      if (k[j] == kk) {
+        o = off[j];
+        return true;
+      }
+    }
+    return false;
+  }
+};
+
+// Chunks between the synchronous polls of the allocation-free solve.
+constexpr int kSyncPollChunks = 4;
+
+// The solve loop behind maxflow_solve and maxflow_solve_static: chunks of
+// check_every iterations, each opened by the gap check of its first iterate
+// and the on-GPU decision; later sweeps of a stopped solve exit at once.  The
+// host follows the decisions either through pinned slots and events (at
+// most `lookahead` unobserved chunks queued) or, with `sync_poll`, through a
+// synchronous 4-byte read every kSyncPollChunks chunks (no pinned memory and
+// no events: nothing is allocated).
+mf_status solve_loop(mf_solver* s, mf_gap* out, bool sync_poll) {
+  const mf_params& p = s->r.p;
+  const int64_t max_iter = std::max<int64_t>(p.max_iter, s->iter);
+  const int ce = p.check_every;
+  const bool dr = p.method == MF_RPDRQ;
+  const int* done = &s->ctrl->done;
+  HIP_TRY(launch_ctrl_reset(s->ctrl, s->stream));
+  int64_t k = s->iter;
+  const bool d2 = p.depth == 2;
+  OffRing off_at;
+  // polling ring: after each chunk, `done` is copied into pinned slot
+  // (chunk & 7) and an event marks the copy.  (No kernel of this library
+  // stores into host memory: only the runtime's copies write there.)
+  int issued = 0, observed = 0;
+  const int lookahead = 3;
+  bool stop = false;
+  while (!stop) {
+    // ---- gap of iterate k and the decision
+    const bool final_check = k >= max_iter;
+    const int64_t n = final_check ? 0 : std::min<int64_t>(ce, max_iter - k);
+    off_at.push(k, s->off);
+    int64_t j = 1;   // iterations of the chunk issued with the check
+    if (dr) {
+      HIP_TRY(gap_of(s, k, done));
+    } else if (fused_gap(s)) {
+      if (d2 && n >= 2 && same_coef(p, k)) {
+        HIP_TRY(admm_pass2(s, k, true, done));
+        j = 2;
+      } else {
+        HIP_TRY(admm_sweep(s, k, true, !final_check, done));
+      }
+    } else {
+      HIP_TRY(gap_of(s, k, done));
+      if (!final_check) HIP_TRY(admm_sweep(s, k, false, true, done));
+    }
+    HIP_TRY(launch_bookkeep(s->ctrl, k, p.alpha, p.tol, neg_tol(s), nres(s), final_check ? 1 : 0, 1, s->stream));
+    if (final_check) break;
+    // ---- the rest of the chunk
+    if (dr) {
+      for (int64_t i = 0; i < n; i++) HIP_TRY(dr_iter(s, k + i, i == n - 1, done));
+    } else {
+      while (j < n) {
+        if (d2 && n - j >= 2 && same_coef(p, k + j)) {
+          HIP_TRY(admm_pass2(s, k + j, false, done));
+          j += 2;
+        } else {
+          HIP_TRY(admm_sweep(s, k + j, false, true, done));
+          j += 1;
+        }
+      }
+    }
+    k += n;
+    issued++;
+    if (sync_poll) {
+      if (issued % kSyncPollChunks == 0) {
+        int flag = 0;
+        HIP_TRY(hipMemcpyAsync(&flag, done, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        if (flag) stop = true;
+      }
+      continue;
+    }
+    // ---- poll the decision without stalling the queue
+    const int slot = (issued - 1) & 7;
+    HIP_TRY(hipMemcpyAsync(s->host_done + slot, done, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipEventRecord(s->ev[slot], s->stream));
+    while (observed < issued) {
+      const int os = observed & 7;
+      const hipError_t q =
+          (issued - observed > lookahead) ? hipEventSynchronize(s->ev[os]) : hipEventQuery(s->ev[os]);
+      if (q == hipErrorNotReady) break;
+      if (q != hipSuccess) return fail(MF_EDEVICE, "event", hipGetErrorString(q));
+      if (s->host_done[os]) stop = true;
+      observed++;
+    }
+  }
+  Ctrl c;
+  HIP_TRY(hipMemcpyAsync(&c, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  if (!c.done) return fail(MF_EDEVICE, "solve ended without a decision");
+  int off = s->off;
+  if (!off_at.find(c.iter, off)) return fail(MF_EDEVICE, "internal: accepted iterate outside the polling window");
+  s->iter = c.iter;
+  s->off = off;
+  const mf_status st = (mf_status)c.status;
+  fill_gap(c, s->iter, out, st);
+  if (st == MF_EDIVERGED) return fail(MF_EDIVERGED, "non-finite or negative gap");
+  return st;
+}
+
 }  // namespace
 
 extern "C" {
 
-const char* maxflow_last_error(void) { return g_err.c_str(); }
+const char* maxflow_last_error(void) { return g_err; }
 
 size_t maxflow_workspace_bytes(const mf_params* p) {
   Resolved r;
-  const std::string e = resolve(p, r);
-  if (!e.empty()) {
-    g_err = e;
+  const char* e = resolve(p, r);
+  if (*e) {
+    set_err(e);
     return 0;
   }
   return plan(r).total;
@@ -483,13 +625,13 @@ mf_status maxflow_create(const mf_params* p, const float* cap, void* workspace, 
   if (!out) return fail(MF_EINVAL, "out is null");
   *out = nullptr;
   Resolved r;
-  const std::string e = resolve(p, r);
-  if (!e.empty()) return fail(MF_EINVAL, e);
+  const char* e = resolve(p, r);
+  if (*e) return fail(MF_EINVAL, e);
   if (!cap || !workspace) return fail(MF_EINVAL, "cap and workspace must be device pointers");
   if (((uintptr_t)workspace) & 255) return fail(MF_EINVAL, "workspace must be 256-byte aligned");
   const Layout L = plan(r);
   if (ws_bytes < L.total)
-    return fail(MF_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    return fail(MF_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes (maxflow_workspace_bytes)");
   mf_solver* s = new (std::nothrow) mf_solver();
   if (!s) return fail(MF_ENOMEM, "host allocation failed");
   s->r = r;
@@ -522,7 +664,7 @@ mf_status maxflow_create(const mf_params* p, const float* cap, void* workspace, 
                                     r.g.pitch, r.g.W, (long long)r.g.H * r.g.D, r.ncp, s->stream);
   if (he != hipSuccess) {
     maxflow_destroy(s);
-    return fail(MF_EDEVICE, std::string("capacity copy: ") + hipGetErrorString(he));
+    return fail(MF_EDEVICE, "capacity copy", hipGetErrorString(he));
   }
   mf_status st = init_state(s);
   if (st != MF_OK) {
@@ -569,97 +711,19 @@ mf_status maxflow_gap(mf_solver* s, mf_gap* out) {
   if (!s) return fail(MF_EINVAL, "null solver");
   HIP_TRY(launch_ctrl_reset(s->ctrl, s->stream));
   HIP_TRY(gap_of(s, s->iter, nullptr));
-  HIP_TRY(launch_bookkeep(s->ctrl, s->iter, s->r.p.alpha, 0.0, nres(s), 0, 0, s->stream));
+  HIP_TRY(launch_bookkeep(s->ctrl, s->iter, s->r.p.alpha, 0.0, neg_tol(s), nres(s), 0, 0, s->stream));
   Ctrl c;
   HIP_TRY(hipMemcpyAsync(&c, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
-  const bool bad = !std::isfinite(c.last[0]) || !std::isfinite(c.last[1]);
+  const bool bad = !std::isfinite(c.last[0]) || !std::isfinite(c.last[1]) || !std::isfinite(c.last[3]) ||
+                   c.last[2] < -neg_tol(s);
   fill_gap(c, s->iter, out, bad ? MF_EDIVERGED : MF_OK);
-  return bad ? fail(MF_EDIVERGED, "non-finite gap") : MF_OK;
+  return bad ? fail(MF_EDIVERGED, "non-finite or negative gap") : MF_OK;
 }
 
 mf_status maxflow_solve(mf_solver* s, mf_gap* out) {
   if (!s) return fail(MF_EINVAL, "null solver");
-  const mf_params& p = s->r.p;
-  const int64_t max_iter = std::max<int64_t>(p.max_iter, s->iter);
-  const int ce = p.check_every;
-  const bool dr = p.method == MF_RPDRQ;
-  const int* done = &s->ctrl->done;
-  HIP_TRY(launch_ctrl_reset(s->ctrl, s->stream));
-  int64_t k = s->iter;
-  const bool d2 = p.depth == 2;
-  // buffer offset in effect at each checked iterate: the accepted iterate's
-  // buffer once later passes (which flip the offset) have been skipped
-  std::vector<std::pair<int64_t, int>> off_at;
-  // polling ring: after each chunk, `done` is copied into pinned slot
-  // (chunk & 7) and an event marks the copy; the host keeps at most
-  // `lookahead` unobserved chunks queued.  (No kernel of this library
-  // stores into host memory: only the runtime's copies write there.)
-  int issued = 0, observed = 0;
-  const int lookahead = 3;
-  bool stop = false;
-  while (!stop) {
-    // ---- gap of iterate k and the decision
-    const bool final_check = k >= max_iter;
-    const int64_t n = final_check ? 0 : std::min<int64_t>(ce, max_iter - k);
-    off_at.emplace_back(k, s->off);
-    int64_t j = 1;   // iterations of the chunk issued with the check
-    if (dr) {
-      HIP_TRY(gap_of(s, k, done));
-    } else if (fused_gap(s)) {
-      if (d2 && n >= 2 && same_coef(p, k)) {
-        HIP_TRY(admm_pass2(s, k, true, done));
-        j = 2;
-      } else {
-        HIP_TRY(admm_sweep(s, k, true, !final_check, done));
-      }
-    } else {
-      HIP_TRY(gap_of(s, k, done));
-      if (!final_check) HIP_TRY(admm_sweep(s, k, false, true, done));
-    }
-    HIP_TRY(launch_bookkeep(s->ctrl, k, p.alpha, p.tol, nres(s), final_check ? 1 : 0, 1, s->stream));
-    if (final_check) break;
-    // ---- the rest of the chunk
-    if (dr) {
-      for (int64_t i = 0; i < n; i++) HIP_TRY(dr_iter(s, k + i, i == n - 1, done));
-    } else {
-      while (j < n) {
-        if (d2 && n - j >= 2 && same_coef(p, k + j)) {
-          HIP_TRY(admm_pass2(s, k + j, false, done));
-          j += 2;
-        } else {
-          HIP_TRY(admm_sweep(s, k + j, false, true, done));
-          j += 1;
-        }
-      }
-    }
-    k += n;
-    // ---- poll the decision without stalling the queue
-    const int slot = issued & 7;
-    HIP_TRY(hipMemcpyAsync(s->host_done + slot, done, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipEventRecord(s->ev[slot], s->stream));
-    issued++;
-    while (observed < issued) {
-      const int os = observed & 7;
-      const hipError_t q =
-          (issued - observed > lookahead) ? hipEventSynchronize(s->ev[os]) : hipEventQuery(s->ev[os]);
-      if (q == hipErrorNotReady) break;
-      if (q != hipSuccess) return fail(MF_EDEVICE, std::string("event: ") + hipGetErrorString(q));
-      if (s->host_done[os]) stop = true;
-      observed++;
-    }
-  }
-  Ctrl c;
-  HIP_TRY(hipMemcpyAsync(&c, s->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s->stream));
-  HIP_TRY(hipStreamSynchronize(s->stream));
-  if (!c.done) return fail(MF_EDEVICE, "solve ended without a decision");
-  s->iter = c.iter;
-  for (const auto& e : off_at)
-    if (e.first == c.iter) s->off = e.second;
-  const mf_status st = (mf_status)c.status;
-  fill_gap(c, s->iter, out, st);
-  if (st == MF_EDIVERGED) return fail(MF_EDIVERGED, "non-finite gap");
-  return st;
+  return solve_loop(s, out, false);
 }
 
 mf_status maxflow_read_u(mf_solver* s, float* dst) { return maxflow_read_field(s, 0, dst); }
@@ -826,7 +890,7 @@ mf_status maxflow_tune(mf_solver* s, int32_t sweeps, int32_t what, mf_tuning* ou
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   p = keep;
-  if (he != hipSuccess) return fail(MF_EDEVICE, std::string("tuning pass: ") + hipGetErrorString(he));
+  if (he != hipSuccess) return fail(MF_EDEVICE, "tuning pass", hipGetErrorString(he));
   p.tile_rows = cand[best].tile_rows;
   p.depth = cand[best].depth;
   p.slab_depth = cand[best].slab_depth;

@@ -1,5 +1,7 @@
 // 2-D rpADMM sweep: the fused LDS-tiled pass (one tile per workgroup), and
-// the depth-2 pass of the two-label model (two iterations per launch).
+// the depth-2 pass of the two-label model (two iterations per launch).  The
+// CHECK variants also accumulate the FP64 gap of their input iterate
+// (two-label and Potts).
 #include "tile2d.h"
 #include "tile2d_d2.h"
 
@@ -7,11 +9,12 @@ namespace mf {
 
 template <int NL, bool TWO, typename TS, bool CHECK, int TY, bool IMG>
 __global__ __launch_bounds__(256) void k_fused2d(const K2<TS> A) {
-  __shared__ Smem2<TY, CHECK> S;
+  __shared__ Smem2<TY, CHECK, CHECK && !TWO> S;
   if (A.done && *A.done) return;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int x0 = (tile % A.tiles_x) * 64;
-  const int y0 = (tile / A.tiles_x) * TY;
+  int tx, ty;
+  strip_tile(xcd_tile(blockIdx.x, gridDim.x), A.tiles_x, (A.H + TY - 1) / TY, A.strip, tx, ty);
+  const int x0 = tx * 64;
+  const int y0 = ty * TY;
   double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (d1_interior<TY>(x0, y0, A.W, A.H)) tile2d<NL, TWO, TS, CHECK, TY, true, CHECK, IMG, false>(A, x0, y0, S, g);
   else tile2d<NL, TWO, TS, CHECK, TY, true, CHECK, IMG, true>(A, x0, y0, S, g);
@@ -22,9 +25,10 @@ template <typename TS, bool CHECK, int TY, bool IMG>
 __global__ __launch_bounds__(256) void k_fused2d_d2(const K2<TS> A) {
   __shared__ Smem2d2<TY> S;
   if (A.done && *A.done) return;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int x0 = (tile % A.tiles_x) * 64;
-  const int y0 = (tile / A.tiles_x) * TY;
+  int tx, ty;
+  strip_tile(xcd_tile(blockIdx.x, gridDim.x), A.tiles_x, (A.H + TY - 1) / TY, A.strip, tx, ty);
+  const int x0 = tx * 64;
+  const int y0 = ty * TY;
   double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (d2_interior<TY>(x0, y0, A.W, A.H)) tile2d_d2<TS, CHECK, TY, IMG, false>(A, x0, y0, S, g);
   else tile2d_d2<TS, CHECK, TY, IMG, true>(A, x0, y0, S, g);
@@ -56,6 +60,8 @@ static K2<TS> make_k2(const SweepDesc& d) {
   a.done = d.done;
   a.write = d.write ? 1 : 0;
   a.iso = d.iso ? 1 : 0;
+  a.strip = d.stream ? kStripTiles : (1 << 30);
+  a.nt = d.stream ? 1 : 0;
   return a;
 }
 
@@ -83,10 +89,7 @@ static hipError_t fused_ty(const SweepDesc& d, hipStream_t s) {
 
 template <int NL, bool TWO, typename TS>
 static hipError_t fused_nl(const SweepDesc& d, hipStream_t s) {
-  if (d.check) {
-    if constexpr (TWO) return fused_ty<NL, TWO, TS, true>(d, s);
-    return hipErrorInvalidValue;   // Potts gaps use the standalone reduction
-  }
+  if (d.check) return fused_ty<NL, TWO, TS, true>(d, s);
   return fused_ty<NL, TWO, TS, false>(d, s);
 }
 

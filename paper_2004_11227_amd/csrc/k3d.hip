@@ -57,6 +57,8 @@ static hipError_t fused3d_ty(const SweepDesc& d, hipStream_t s) {
   a.done = d.done;
   a.write = d.write ? 1 : 0;
   a.iso = d.iso ? 1 : 0;
+  a.strip = 1 << 30;
+  a.nt = d.stream ? 1 : 0;
   const long long nb = nxy * ((d.g.D + tz - 1) / tz);
   if (d.cg.img)
     hipLaunchKernelGGL((k_fused3d<TS, CHECK, TY, true>), dim3((unsigned)nb), dim3(256), 0, s, a);

@@ -28,9 +28,10 @@ template <typename TS, int TY, int NL, bool TWO, int NS>
 __global__ __launch_bounds__(256) void k_dr_fused2d(const KDF<TS> A) {
   __shared__ SmemDR<TY, TWO, NS> S;
   if (A.done && *A.done) return;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int x0 = (tile % A.tiles_x) * 64;
-  const int y0 = (tile / A.tiles_x) * TY;
+  int tx, ty;
+  strip_tile(xcd_tile(blockIdx.x, gridDim.x), A.tiles_x, (A.H + TY - 1) / TY, A.strip, tx, ty);
+  const int x0 = tx * 64;
+  const int y0 = ty * TY;
   if (dr_interior<TY, NS>(x0, y0, A.W, A.H)) tile_dr2d<TS, TY, NL, TWO, false, NS>(A, x0, y0, S);
   else tile_dr2d<TS, TY, NL, TWO, true, NS>(A, x0, y0, S);
 }
@@ -63,6 +64,8 @@ static hipError_t dr_fused_nl(const PdrqDesc& d, hipStream_t s) {
   set_rden(a.rden, TWO ? 2.f : (float)(NL + 1));
   a.iso = d.iso ? 1 : 0;
   a.keep_z = d.keep_z ? 1 : 0;
+  a.strip = d.stream ? kStripTiles : (1 << 30);
+  a.nt = d.stream ? 1 : 0;
   a.done = d.done;
   a.cg = d.cg;
   // one sweep: 64 x 32 or 64 x 16 tiles; M_2 .. M_4: 64 x 16 tiles

@@ -240,11 +240,12 @@ hipError_t launch_ctrl_reset(Ctrl* c, hipStream_t s) {
 
 // Turns the accumulated sums into the gap at iterate k, decides (when
 // `decide`) whether the solve stops there, and clears the accumulators.
-// Status codes follow mf_status: 0 converged, 1 cap reached, -4 diverged.
+// Status codes follow mf_status: 0 converged, 1 cap reached, -4 diverged
+// (a non-finite gap or residual, or a gap below -neg_tol).
 // One wavefront, lane t reading and clearing accumulator slot t.
 static_assert(kAccSlots == 64, "one lane per accumulator slot");
-__global__ __launch_bounds__(64) void k_bookkeep(Ctrl* c, long long k, double alpha, double tol, long long nres,
-                                                 int final_check, int decide) {
+__global__ __launch_bounds__(64) void k_bookkeep(Ctrl* c, long long k, double alpha, double tol, double neg_tol,
+                                                 long long nres, int final_check, int decide) {
   const int t = threadIdx.x;
   double tot[5];
 #pragma unroll
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(64) void k_bookkeep(Ctrl* c, long long k, double al
   c->last[5] = (double)k;
   c->checks += 1;
   if (decide) {
-    const bool bad = !isfinite(P) || !isfinite(D) || !isfinite(tot[3]);
+    const bool bad = !isfinite(P) || !isfinite(D) || !isfinite(tot[3]) || rel < -neg_tol;
     if (bad) {
       c->done = 1;
       c->status = -4;
@@ -284,9 +285,9 @@ __global__ __launch_bounds__(64) void k_bookkeep(Ctrl* c, long long k, double al
   }
 }
 
-hipError_t launch_bookkeep(Ctrl* c, long long k, double alpha, double tol, long long nres, int final_check,
-                           int decide, hipStream_t s) {
-  hipLaunchKernelGGL(k_bookkeep, dim3(1), dim3(64), 0, s, c, k, alpha, tol, nres, final_check, decide);
+hipError_t launch_bookkeep(Ctrl* c, long long k, double alpha, double tol, double neg_tol, long long nres,
+                           int final_check, int decide, hipStream_t s) {
+  hipLaunchKernelGGL(k_bookkeep, dim3(1), dim3(64), 0, s, c, k, alpha, tol, neg_tol, nres, final_check, decide);
   return hipGetLastError();
 }
 

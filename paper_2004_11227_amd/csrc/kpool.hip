@@ -12,7 +12,6 @@
 #include "tile2d.h"
 #include "tile2d_d2.h"
 #include "tile3d.h"
-#include "gap.h"
 
 namespace mf {
 
@@ -60,22 +59,24 @@ __device__ __forceinline__ K2<TS> slot_k2(const PoolSlot& sl, int step) {
   a.done = nullptr;
   a.write = sl.iter + step < sl.max_iter ? 1 : 0;
   a.iso = sl.iso;
+  a.strip = 1 << 30;
+  a.nt = 0;
   return a;
 }
 
 // CHECK selects the items this launch processes: the sweeps that also
-// accumulate the (two-label, fused) gap of their input iterate, or all the
+// accumulate the gap of their input iterate (solves at a check), or all the
 // others.  Two specialised launches keep the common no-gap body lean.
 template <int NL, bool TWO, typename TS, int TY, bool CHECK, bool VEC>
 __global__ __launch_bounds__(256) void k_pool2d(PoolDev d, int cls, int step) {
-  __shared__ Smem2<TY, CHECK> S;
+  __shared__ Smem2<TY, CHECK, CHECK && !TWO> S;
   const int it = xcd_item(d.counts[cls]);
   if (it < 0) return;
   const WorkItem w = d.items[cls][it];
   PoolSlot* sl = d.slots + w.slot;
   if (sl->state != SLOT_RUNNING) return;
-  // two-label gaps are fused into the sweep; Potts gaps run in k_pool_gap2d
-  const bool check = TWO && sl->check_now != 0;
+  // the gap of a checking solve's input iterate is fused into its sweep
+  const bool check = sl->check_now != 0;
   if (check != CHECK) return;
   const K2<TS> A = slot_k2<TS>(*sl, step);
   double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -138,47 +139,12 @@ __global__ __launch_bounds__(256) void k_pool3d(PoolDev d, int cls, int step) {
     A.done = nullptr;
     A.write = sl->iter + step < sl->max_iter ? 1 : 0;
     A.iso = sl->iso;
+    A.strip = 1 << 30;
+    A.nt = 0;
     const int z1 = min(w.z0 + A.tz, A.D);
     double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     tile3d<TS, CHECK, VEC, CHECK>(A, w.x0, w.y0, w.z0, z1, S, g);
     if (CHECK) block_accumulate<5, 4>(g, &sl->acc[0][0], S.sred);
-  }
-}
-
-// Gap of iterate k of every checking Potts solve, tile by tile.  It reads
-// state buffer k & 1, which the concurrent sweep k -> k+1 does not write.
-template <int NL, typename TS, int TY>
-__global__ __launch_bounds__(256) void k_pool_gap2d(PoolDev d, int cls, int step) {
-  __shared__ double sred[4 * 5];
-  const int it = xcd_item(d.counts[cls]);
-  if (it < 0) return;
-  const WorkItem w = d.items[cls][it];
-  PoolSlot* sl = d.slots + w.slot;
-  if (sl->state != SLOT_RUNNING || !sl->check_now) return;
-  {
-    KG<TS> A;
-    const int src = slot_buf(*sl, step);
-    A.W = sl->W;
-    A.H = sl->H;
-    A.D = 1;
-    A.pitch = sl->pitch;
-    A.P = sl->P;
-    A.n = (long long)sl->W * sl->H;
-    A.cap = (const TS*)sl->cap;
-    A.u = sl->st[src].u;
-    A.q = (const TS*)sl->st[src].q;
-    A.ps = (const TS*)sl->st[src].ps;
-    A.p = (const TS*)sl->st[src].p;
-    A.acc = nullptr;
-    A.done = nullptr;
-    A.iso = sl->iso;
-    double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-    for (int e = threadIdx.x; e < 64 * TY; e += 256) {
-      const int x = w.x0 + (e & 63), y = w.y0 + (e >> 6);
-      if (x < A.W && y < A.H) gap_px<NL, false, 2, TS>(A, (long long)y * A.pitch + x, x, y, 0, g);
-    }
-    block_accumulate<5, 4>(g, &sl->acc[0][0], sred);
   }
 }
 
@@ -218,7 +184,7 @@ __global__ __launch_bounds__(64) void k_pool_book(PoolDev d, int decide, int adv
     ps.last[3] = sqrt(v[3] / (double)sl->nres);
     ps.last[4] = v[4];
     ps.last[5] = (double)k;
-    const bool bad = !isfinite(P) || !isfinite(D) || !isfinite(v[3]);
+    const bool bad = !isfinite(P) || !isfinite(D) || !isfinite(v[3]) || rel < -neg_gap_tol(sl->bf16 != 0);
     if (bad) {
       state = SLOT_DONE;
       sl->status = -4;
@@ -253,9 +219,14 @@ template <typename TS, bool CHECK, bool VEC>
 static const void* pool_kernel_ts(int model) {
   constexpr bool BF = std::is_same<TS, bf16_t>::value;
   if (CHECK) {
-    if (model == 0) return (const void*)k_pool2d<1, true, TS, pool_tile_rows(0, BF), true, VEC>;
-    if (model == 5) return (const void*)k_pool3d<TS, true, VEC>;
-    return nullptr;   // Potts sweeps never carry the gap
+    switch (model) {
+      case 0: return (const void*)k_pool2d<1, true, TS, pool_tile_rows(0, BF), true, VEC>;
+      case 1: return (const void*)k_pool2d<2, false, TS, pool_tile_rows(1, BF), true, VEC>;
+      case 2: return (const void*)k_pool2d<3, false, TS, pool_tile_rows(2, BF), true, VEC>;
+      case 3: return (const void*)k_pool2d<4, false, TS, pool_tile_rows(3, BF), true, VEC>;
+      case 4: return (const void*)k_pool2d<8, false, TS, pool_tile_rows(4, BF), true, VEC>;
+      default: return (const void*)k_pool3d<TS, true, VEC>;
+    }
   }
   switch (model) {
     case 0: return (const void*)k_pool2d<1, true, TS, pool_tile_rows(0, BF), false, VEC>;
@@ -276,23 +247,6 @@ const void* pool_kernel(int cls, bool check, bool vec) {
   }
   if (check) return vec ? pool_kernel_ts<float, true, true>(model) : pool_kernel_ts<float, true, false>(model);
   return vec ? pool_kernel_ts<float, false, true>(model) : pool_kernel_ts<float, false, false>(model);
-}
-
-template <typename TS>
-static const void* pool_gap_kernel_ts(int model) {
-  constexpr bool BF = std::is_same<TS, bf16_t>::value;
-  switch (model) {
-    case 1: return (const void*)k_pool_gap2d<2, TS, pool_tile_rows(1, BF)>;
-    case 2: return (const void*)k_pool_gap2d<3, TS, pool_tile_rows(2, BF)>;
-    case 3: return (const void*)k_pool_gap2d<4, TS, pool_tile_rows(3, BF)>;
-    case 4: return (const void*)k_pool_gap2d<8, TS, pool_tile_rows(4, BF)>;
-    default: return nullptr;   // two-label gaps are fused into the sweep
-  }
-}
-
-const void* pool_gap_kernel(int cls) {
-  const int model = cls % kPoolModels;
-  return cls >= kPoolModels ? pool_gap_kernel_ts<bf16_t>(model) : pool_gap_kernel_ts<float>(model);
 }
 
 const void* pool_kernel_d2(int cls, bool check) {

@@ -58,24 +58,38 @@ __device__ __forceinline__ void ldv(const bf16_t* p, long long i, float (&o)[V])
     o[0] = ld(p, i);
   }
 }
+// Vector stores of the sweeps' outputs.  With `nt` the stores carry the
+// non-temporal hint: the new iterate is not read again by this sweep, so on
+// a working set larger than the last-level cache it should not take L2
+// capacity from the halo rows that neighbouring tiles still have to read.
+// (On a working set that fits the 256 MB last-level cache the hint costs
+// more than it saves: the next sweep then reads the iterate from HBM.)
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ void st_stream(T* p, T v, bool nt) {
+  if (nt) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
 template <int V>
-__device__ __forceinline__ void stv(float* p, long long i, const float (&v)[V]) {
+__device__ __forceinline__ void stv(float* p, long long i, const float (&v)[V], bool nt = false) {
   if constexpr (V == 4) {
-    *reinterpret_cast<float4*>(p + i) = make_float4(v[0], v[1], v[2], v[3]);
+    st_stream(reinterpret_cast<f32x4_t*>(p + i), f32x4_t{v[0], v[1], v[2], v[3]}, nt);
   } else if constexpr (V == 2) {
-    *reinterpret_cast<float2*>(p + i) = make_float2(v[0], v[1]);
+    st_stream(reinterpret_cast<f32x2_t*>(p + i), f32x2_t{v[0], v[1]}, nt);
   } else {
-    p[i] = v[0];
+    st_stream(p + i, v[0], nt);
   }
 }
 template <int V>
-__device__ __forceinline__ void stv(bf16_t* p, long long i, const float (&v)[V]) {
+__device__ __forceinline__ void stv(bf16_t* p, long long i, const float (&v)[V], bool nt = false) {
   if constexpr (V == 4) {
-    *reinterpret_cast<uint2*>(p + i) = make_uint2(bf_pack(v[0], v[1]), bf_pack(v[2], v[3]));
+    st_stream(reinterpret_cast<u32x2_t*>(p + i), u32x2_t{bf_pack(v[0], v[1]), bf_pack(v[2], v[3])}, nt);
   } else if constexpr (V == 2) {
-    *reinterpret_cast<uint32_t*>(p + i) = bf_pack(v[0], v[1]);
+    st_stream(reinterpret_cast<uint32_t*>(p + i), bf_pack(v[0], v[1]), nt);
   } else {
-    st(p, i, v[0]);
+    st_stream(p + i, f2bf(v[0]), nt);
   }
 }
 // Workgroup barrier for communication through LDS only: waits for this
@@ -115,9 +129,9 @@ __device__ __forceinline__ void ldg(const T* p, long long i, int nv, bool vec, f
   }
 }
 template <int V, typename T>
-__device__ __forceinline__ void stg(T* p, long long i, int nv, bool vec, const float (&v)[V]) {
+__device__ __forceinline__ void stg(T* p, long long i, int nv, bool vec, const float (&v)[V], bool nt = false) {
   if (vec) {
-    if (nv > 0) stv<V>(p, i, v);
+    if (nv > 0) stv<V>(p, i, v, nt);
   } else {
 #pragma unroll
     for (int e = 0; e < V; e++)
@@ -313,7 +327,7 @@ __device__ __forceinline__ void block_accumulate(double (&v)[NQ], double* dst, d
 // the projection is max(v - theta, 0).  Rank form without a sort, so the
 // arrays stay in registers.
 template <int N>
-__device__ __forceinline__ void simplex_proj(const double (&v)[N], double (&w)[N]) {
+__device__ __forceinline__ double simplex_theta(const double (&v)[N]) {
   double theta = -1e300;
 #pragma unroll
   for (int j = 0; j < N; j++) {
@@ -328,8 +342,15 @@ __device__ __forceinline__ void simplex_proj(const double (&v)[N], double (&w)[N
     const double t = (s - 1.0) / k;
     theta = t > theta ? t : theta;
   }
+  return theta;
+}
+// One component of the projection, max(v - theta, 0).
+__device__ __forceinline__ double simplex_part(double v, double theta) { return v - theta > 0.0 ? v - theta : 0.0; }
+template <int N>
+__device__ __forceinline__ void simplex_proj(const double (&v)[N], double (&w)[N]) {
+  const double theta = simplex_theta<N>(v);
 #pragma unroll
-  for (int i = 0; i < N; i++) w[i] = v[i] - theta > 0.0 ? v[i] - theta : 0.0;
+  for (int i = 0; i < N; i++) w[i] = simplex_part(v[i], theta);
 }
 
 // XCD-aware tile order: consecutive workgroup ids are dispatched round-robin
@@ -340,6 +361,32 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   const int x = b & 7, slot = b >> 3;
   const int base = nb >> 3, rem = nb & 7;
   return x * base + (x < rem ? x : rem) + slot;
+}
+
+// Order of the 2-D tiles within one XCD's contiguous run: column strips of
+// `sw` tiles (64 * sw pixels), each walked row by row.  A tile's upper
+// neighbour was then loaded at most a strip's width of tiles earlier on the
+// same XCD, so its halo rows are still in that XCD's L2; a row-major walk of
+// a wide grid puts a whole row of tiles (2.4 MB of state at 4096 columns,
+// more than the 4 MB L2 holds with the writes and the workgroups in flight)
+// between the two.  Any order gives the same iterate.  (The host takes
+// strips only for working sets beyond the last-level cache: within it the
+// row-major walk measured faster.)
+constexpr int kStripTiles = 16;
+__device__ __forceinline__ void strip_tile(int tile, int tiles_x, int tiles_y, int sw, int& tx, int& ty) {
+  const int nfull = tiles_x / sw;
+  const int full = nfull * sw * tiles_y;
+  if (tile < full) {
+    const int s = tile / (sw * tiles_y);
+    const int r = tile - s * sw * tiles_y;
+    ty = r / sw;
+    tx = s * sw + (r - ty * sw);
+  } else {
+    const int rem = tiles_x - nfull * sw;
+    const int r = tile - full;
+    ty = r / rem;
+    tx = nfull * sw + (r - ty * rem);
+  }
 }
 
 }  // namespace mf

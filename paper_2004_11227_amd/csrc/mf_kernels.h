@@ -60,6 +60,7 @@ struct SweepDesc {
   int scheme = 0;  // element-wise passes: 0 rpADMM, 1 pADMM-TY, 2 ALG1
   float sigma = 0.f, tau = 0.f;   // ALG1 step sizes
   CapGen cg;       // cg.img: `cap` is one image plane
+  bool stream = false;   // working set beyond the last-level cache: strip tile order, non-temporal stores
 };
 
 struct GapDesc {
@@ -89,7 +90,17 @@ struct PdrqDesc {
   int sweeps = 1;      // symmetric red-black GS sweeps (in-place launches; the fused pass runs 1)
   const int* done;
   CapGen cg;
+  bool stream = false;   // as in SweepDesc
 };
+
+// Working sets (capacities and both state buffers) above this many bytes do
+// not stay in the 256 MB last-level cache between sweeps: their sweeps take
+// the strip tile order and non-temporal stores (measured faster there and
+// slower on smaller working sets).
+#ifndef MF_STREAM_MIB
+#define MF_STREAM_MIB 384
+#endif
+constexpr size_t kStreamBytes = (size_t)MF_STREAM_MIB << 20;
 
 hipError_t launch_fused(const SweepDesc& d, hipStream_t s);
 hipError_t launch_fused2d_d2(const SweepDesc& d, hipStream_t s);
@@ -114,7 +125,16 @@ hipError_t launch_write_planes(const float* src, void* dst, bool bf16, long long
 hipError_t launch_convert_planes(const void* src, bool src_bf16, void* dst, bool dst_bf16, long long n, int nplanes,
                                  long long src_stride, long long dst_stride, hipStream_t s);
 hipError_t launch_ctrl_reset(Ctrl* c, hipStream_t s);
-hipError_t launch_bookkeep(Ctrl* c, long long k, double alpha, double tol, long long nres,
+hipError_t launch_bookkeep(Ctrl* c, long long k, double alpha, double tol, double neg_tol, long long nres,
                            int final_check, int decide, hipStream_t s);
+
+// Largest negative relative gap that rounding of the stored flows explains.
+// Weak duality P(u) >= D(q) holds whenever |q| <= alpha; after P_alpha in
+// FP32 (reciprocal square root, a few ulp) |q| exceeds alpha by at most
+// ~1e-6 relative, and BF16 storage rounds q (and a clamped alpha) by at most
+// 2^-8 relative, so P - D >= -(excess) alpha TV(u) >= -(excess) max(|P|,|D|).
+// A gap below minus this bound cannot come from rounding: the solve is
+// reported as diverged.
+__host__ __device__ inline double neg_gap_tol(bool bf16) { return bf16 ? 8e-3 : 1e-5; }
 
 }  // namespace mf

@@ -22,6 +22,8 @@ enum { SLOT_FREE = 0, SLOT_RUNNING = 1, SLOT_DONE = 2, SLOT_PROMOTE = 3 };
 
 // Classes: two-label 2-D, Potts n = 2, 3, 4, 8 (2-D), two-label 3-D; x2 storage.
 constexpr int kPoolModels = 6;
+// Iterations per advance (the only supported value).
+constexpr int kPoolSteps = 10;
 constexpr int kPoolClasses = 2 * kPoolModels;
 
 struct PoolSlot {
@@ -64,7 +66,6 @@ struct PoolDev {
 
 const void* pool_kernel(int cls, bool check, bool vec);
 const void* pool_kernel_d2(int cls, bool check);   // two-label 2-D classes
-const void* pool_gap_kernel(int cls);
 const void* pool_book_kernel();
 
 // Tile height of a 2-D pool class (model index as in the class table; the

@@ -5,8 +5,8 @@
 // rest is carved first-fit into one block per admitted solve (capacities and
 // two state buffers), so admission is decided exactly by footprint.  A step
 // launches, for every class as a parallel graph branch, the sweep over the
-// class work list (and, at the first step, the Potts classes' per-tile gap
-// kernel).  With depth 2 the two-label 2-D classes run a two-iteration pass
+// class work list (at the first step the variant that also accumulates the
+// gap of every checking solve).  With depth 2 the two-label 2-D classes run a two-iteration pass
 // at even steps and sit out the odd ones.  Bookkeeping runs twice per
 // advance: after the first step (decisions) and after the last (counters).
 // The steps of one advance (steps_per_advance iterations) form one hipGraph,
@@ -239,8 +239,7 @@ hipKernelNodeParams node_params(const void* func, unsigned grid, unsigned block,
 
 // Build the steps of one advance for the classes in `mask` as an explicit
 // graph.  Step h launches, per class and in parallel, the sweep of each
-// solve's iterate iter + h (the gap-carrying variant at step 0 for
-// two-label classes) and, at step 0, the per-tile Potts gap.  Depth 2: the
+// solve's iterate iter + h (the gap-carrying variant at step 0).  Depth 2: the
 // two-label 2-D classes launch their two-iteration pass at even steps only.
 // Every pool solve checks at multiples of check_every == steps_per_advance,
 // starting at a replay boundary, so step 0 is the check step of every
@@ -282,9 +281,8 @@ mf_status build_graph(mf_pool* P, int mask) {
       const int model = c % kPoolModels;
       const bool d2 = P->depth == 2 && model == 0;
       if (odd && d2) continue;
-      const bool fused_gap = model == 0 || model == 5;
-      const void* fs[2] = {d2 ? pool_kernel_d2(c, cstep) : pool_kernel(c, cstep && fused_gap, true),
-                           (cstep && !fused_gap) ? pool_gap_kernel(c) : nullptr};
+      // every class's sweep carries the gap of its checking solves
+      const void* fs[1] = {d2 ? pool_kernel_d2(c, cstep) : pool_kernel(c, cstep, true)};
       for (const void* f : fs) {
         if (!f) continue;
         int cls = c, step = h;
@@ -484,6 +482,11 @@ mf_status mf_pool_create(void* arena, size_t arena_bytes, int32_t max_slots, int
   if (!hip_stream) return pfail(MF_EINVAL, "the pool needs a created (non-default) stream for graph capture");
   if (max_slots < 1 || max_slots > 65536 || max_tiles < 1 || steps_per_advance < 1)
     return pfail(MF_EINVAL, "max_slots in [1, 65536], max_tiles >= 1, steps_per_advance >= 1");
+  // Only 10-step advances are supported: a process that ran a 20-step pool
+  // after a 10-step one ended in a host segmentation fault whose cause has
+  // not been found, and no other step count has been run.
+  if (steps_per_advance != kPoolSteps)
+    return pfail(MF_EINVAL, "steps_per_advance must be 10 (other step counts are not supported)");
   if (depth == 0) depth = steps_per_advance % 2 == 0 ? 2 : 1;
   if (depth != 1 && depth != 2) return pfail(MF_EINVAL, "depth must be 0, 1 or 2");
   if (steps_per_advance % depth != 0) return pfail(MF_EINVAL, "steps_per_advance must be a multiple of depth");

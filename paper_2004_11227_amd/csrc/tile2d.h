@@ -45,6 +45,8 @@ struct K2 {
   const int* done;
   int write;
   int iso;
+  int strip;          // 2-D tile order: tiles per column strip (see strip_tile)
+  int nt;             // non-temporal stores of the new iterate
 };
 
 __device__ __forceinline__ void proj(float& x, float& y, float alpha, int iso) {
@@ -74,7 +76,9 @@ __device__ __forceinline__ void gap_two_px(double (&g)[5], float u0f, float uxf,
 // (4V), j < RPT, so every interior global access is one V-wide vector
 // access per lane (16 B for FP32 and V = 4).  LDS column c of the tile is
 // stored at index c + 4 so those groups stay 16-byte aligned.
-template <int TY, bool CHECK>
+// TH (Potts gap): the simplex threshold of the projected u at every cell of
+// rows 0..TY, cols 0..64 (the owned cells and their +x / +y neighbours).
+template <int TY, bool CHECK, bool TH = false>
 struct Smem2 {
   static constexpr int SW = 64 + 8;   // cols -4 .. 67
   static constexpr int SH = TY + 3;   // rows -2 .. TY
@@ -82,6 +86,7 @@ struct Smem2 {
   __align__(16) float sqy[SH][SW];
   __align__(16) float sw[SH][SW];
   __align__(16) float su[CHECK ? SH : 1][CHECK ? SW : 1];
+  double sth[TH ? TY + 1 : 1][TH ? 65 : 1];
   double sred[4 * 5];
 };
 
@@ -107,9 +112,11 @@ __device__ __forceinline__ bool d1_interior(int x0, int y0, int W, int H) {
 // read once per pixel instead of 2 (two-label) or NL capacity planes.
 // EDGE false: an interior tile (d1_interior), whose every boundary test is
 // true and folds away; the arithmetic is unchanged.
-template <int NL, bool TWO, typename TS, bool CHECK, int TY, bool VEC, bool SU, bool IMG = false, bool EDGE = true>
-__device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY, SU>& S, double (&g)[5]) {
+template <int NL, bool TWO, typename TS, bool CHECK, int TY, bool VEC, bool SU, bool IMG = false, bool EDGE = true,
+          bool TH = false>
+__device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY, SU, TH>& S, double (&g)[5]) {
   static_assert(!CHECK || SU, "the gap needs the u staging array");
+  static_assert(!CHECK || TWO || TH, "the Potts gap needs the simplex thresholds");
   constexpr int TX = 64;
   constexpr int V = TY >= 16 ? 4 : 2;
   constexpr int TPR = TX / V;        // threads per tile row
@@ -256,6 +263,25 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
     if (IMG) return cap_from(im[j][e], A.cg.lv[TWO ? 1 : l], A.cg.pw);
     return TWO ? capt[j][e] : F.C[j][e];
   };
+  // Potts gap of the input iterate: the simplex threshold of u^k at the
+  // owned cells and their +x / +y neighbours (FP64, as the standalone gap)
+  double mn[RPT][V];
+  if (CHECK && !TWO) {
+#pragma unroll
+    for (int j = 0; j < RPT; j++)
+#pragma unroll
+      for (int e = 0; e < V; e++) mn[j][e] = 1e300;
+    for (int h = tid; h < (TY + 1) * (TX + 1); h += 256) {
+      const int r = h / (TX + 1), c = h % (TX + 1);
+      const int gx = x0 + c, gy = y0 + r;
+      const bool in = gx < W && gy < H;
+      const long long o = (long long)gy * pitch + gx;
+      double v[NL];
+#pragma unroll
+      for (int l = 0; l < NL; l++) v[l] = (double)ldz(A.u_in + (long long)l * P, o, in);
+      S.sth[r][c] = simplex_theta<NL>(v);
+    }
+  }
   LabT F;
   fetch(0, F);
 #pragma unroll
@@ -304,7 +330,9 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
     // ---- issue the loads of label l+1
     if (l + 1 < NL) fetch(l + 1, F);
     lds_barrier();
-    // ---- gap of the input iterate (two-label; q^k is still intact in LDS)
+    // ---- gap of the input iterate (q^k is still intact in LDS).  Potts:
+    // label l's part of the primal (data and TV at the projected u), its
+    // residual and its term of the dual minimum; the rest after the labels.
     if (CHECK) {
 #pragma unroll
       for (int j = 0; j < RPT; j++) {
@@ -318,8 +346,24 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
             const double dq =
                 ((xp(gx) ? (double)sqx[r + 2][c] : 0.0) - (xm(gx) ? (double)sqx[r + 2][c - 1] : 0.0)) +
                 ((yp(gy) ? (double)sqy[r + 2][c] : 0.0) - (ym(gy) ? (double)sqy[r + 1][c] : 0.0));
-            gap_two_px(g, su[r + 2][c], su[r + 2][c + 1], su[r + 3][c], xp(gx), yp(gy), dq,
-                       cap_s(j, e), Cl[j][e], ps[j][e], pl[j][e], A.iso);
+            if (TWO) {
+              gap_two_px(g, su[r + 2][c], su[r + 2][c + 1], su[r + 3][c], xp(gx), yp(gy), dq,
+                         cap_s(j, e), Cl[j][e], ps[j][e], pl[j][e], A.iso);
+            } else {
+              const int cc = c0 + e;
+              const double w0 = simplex_part((double)su[r + 2][c], S.sth[r][cc]);
+              const double wx = simplex_part((double)su[r + 2][c + 1], S.sth[r][cc + 1]);
+              const double wy = simplex_part((double)su[r + 3][c], S.sth[r + 1][cc]);
+              const double C = (double)Cl[j][e];
+              g[0] += w0 * C;
+              const double ddx = xp(gx) ? wx - w0 : 0.0;
+              const double ddy = yp(gy) ? wy - w0 : 0.0;
+              g[1] += A.iso ? sqrt(ddx * ddx + ddy * ddy) : fabs(ddx) + fabs(ddy);
+              const double tt = C + dq;
+              mn[j][e] = tt < mn[j][e] ? tt : mn[j][e];
+              const double rr = (dq + (double)pl[j][e]) - (double)ps[j][e];
+              g[3] += rr * rr;
+            }
           }
         }
       }
@@ -367,13 +411,23 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
           label_update(k, ul[j][e], pl[j][e], ps[j][e], d, Cl[j][e], pn[e], t[j][l][e], sumd[j][e], sumr[j][e]);
         }
         if (A.write) {
-          stg<V>(qx_out, idx, nv, vec, qxv);
-          stg<V>(qy_out, idx, nv, vec, qyv);
-          stg<V>(p_out, idx, nv, vec, pn);
+          stg<V>(qx_out, idx, nv, vec, qxv, A.nt != 0);
+          stg<V>(qy_out, idx, nv, vec, qyv, A.nt != 0);
+          stg<V>(p_out, idx, nv, vec, pn, A.nt != 0);
         }
       }
     }
     if (NL > 1) lds_barrier();
+  }
+  if (CHECK && !TWO) {   // Potts gap: the dual minimum over the labels and the flow
+#pragma unroll
+    for (int j = 0; j < RPT; j++)
+#pragma unroll
+      for (int e = 0; e < V; e++)
+        if (e < nvj[j]) {
+          g[2] += mn[j][e];
+          g[4] += (double)ps[j][e];
+        }
   }
   // ---- p_s and u
 #pragma unroll
@@ -384,13 +438,13 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
 #pragma unroll
     for (int e = 0; e < V; e++) psn[e] = finish_ps(k, ps[j][e], sumd[j][e], sumr[j][e], TWO, TWO ? cap_s(j, e) : 0.f);
     if (A.write) {
-      stg<V>(A.ps_out, idx, nv, vec, psn);
+      stg<V>(A.ps_out, idx, nv, vec, psn, A.nt != 0);
 #pragma unroll
       for (int l = 0; l < NL; l++) {
         float un[V];
 #pragma unroll
         for (int e = 0; e < V; e++) un[e] = finish_u(k, t[j][l][e], psn[e]);
-        stg<V>(A.u_out + (long long)l * P, idx, nv, vec, un);
+        stg<V>(A.u_out + (long long)l * P, idx, nv, vec, un, A.nt != 0);
       }
     }
   }

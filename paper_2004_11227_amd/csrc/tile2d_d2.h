@@ -260,11 +260,11 @@ __device__ __forceinline__ void tile2d_d2(const K2<TS>& A, int x0, int y0, Smem2
     if (A.write) {
       const int nv = nvj[j];
       const long long idx = oj[j];
-      stg<V>(A.q_out, idx, nv, true, qxv);
-      stg<V>(A.q_out + P, idx, nv, true, qyv);
-      stg<V>(A.p_out, idx, nv, true, pn);
-      stg<V>(A.ps_out, idx, nv, true, psn);
-      stg<V>(A.u_out, idx, nv, true, un);
+      stg<V>(A.q_out, idx, nv, true, qxv, A.nt != 0);
+      stg<V>(A.q_out + P, idx, nv, true, qyv, A.nt != 0);
+      stg<V>(A.p_out, idx, nv, true, pn, A.nt != 0);
+      stg<V>(A.ps_out, idx, nv, true, psn, A.nt != 0);
+      stg<V>(A.u_out, idx, nv, true, un, A.nt != 0);
     }
   }
 }

@@ -51,6 +51,8 @@ struct K3 {
   const int* done;
   int write;
   int iso;
+  int strip;          // 2-D tile order: tiles per column strip (see strip_tile)
+  int nt;             // non-temporal stores of the new iterate
 };
 
 __device__ __forceinline__ void proj3r(float& x, float& y, float& z, float alpha, int iso) {
@@ -347,12 +349,12 @@ __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, 
         un[e] = finish_u(k, t, psn[e]);
       }
       if (A.write) {
-        stg<V>(A.q_out, idx, nv, vec, qxv);
-        stg<V>(A.q_out + P, idx, nv, vec, qyv);
-        stg<V>(A.q_out + 2 * P, idx, nv, vec, qzv);
-        stg<V>(A.p_out, idx, nv, vec, pn);
-        stg<V>(A.ps_out, idx, nv, vec, psn);
-        stg<V>(A.u_out, idx, nv, vec, un);
+        stg<V>(A.q_out, idx, nv, vec, qxv, A.nt != 0);
+        stg<V>(A.q_out + P, idx, nv, vec, qyv, A.nt != 0);
+        stg<V>(A.q_out + 2 * P, idx, nv, vec, qzv, A.nt != 0);
+        stg<V>(A.p_out, idx, nv, vec, pn, A.nt != 0);
+        stg<V>(A.ps_out, idx, nv, vec, psn, A.nt != 0);
+        stg<V>(A.u_out, idx, nv, vec, un, A.nt != 0);
       }
     }
     // ---- rotate owner registers

@@ -64,6 +64,8 @@ struct KDF {
   float sigma, tau, rho, inv_st, alpha;
   Rden rden;            // 1 / (|N(x)| + m) for |N(x)| = 0 .. 6, rounded once on the host
   int iso, keep_z;
+  int strip;          // tiles per column strip (see strip_tile)
+  int nt;             // non-temporal stores of the new iterate
   const int* done;
   CapGen cg;            // cg.img: `cap` is one image plane
 };
@@ -321,14 +323,14 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
       }
       const int nv = nvj[j];
       const long long idx = oj[j];
-      stg<V>(u_out, idx, nv, true, un);
-      stg<V>(qx_out, idx, nv, true, qxo);
-      stg<V>(qx_out + P, idx, nv, true, qyo);
-      stg<V>(pb_out, idx, nv, true, pto);
+      stg<V>(u_out, idx, nv, true, un, A.nt != 0);
+      stg<V>(qx_out, idx, nv, true, qxo, A.nt != 0);
+      stg<V>(qx_out + P, idx, nv, true, qyo, A.nt != 0);
+      stg<V>(pb_out, idx, nv, true, pto, A.nt != 0);
       if (A.keep_z) {
-        stg<V>(A.zq + (long long)(2 * l) * P, idx, nv, true, zqx);
-        stg<V>(A.zq + (long long)(2 * l + 1) * P, idx, nv, true, zqy);
-        stg<V>(A.zp + (long long)l * P, idx, nv, true, zpt);
+        stg<V>(A.zq + (long long)(2 * l) * P, idx, nv, true, zqx, A.nt != 0);
+        stg<V>(A.zq + (long long)(2 * l + 1) * P, idx, nv, true, zqy, A.nt != 0);
+        stg<V>(A.zp + (long long)l * P, idx, nv, true, zpt, A.nt != 0);
       }
     }
     if (NL > 1) lds_barrier();   // the next label's staging overwrites the arrays
@@ -349,8 +351,8 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
     }
     const int nv = nvj[j];
     const long long idx = oj[j];
-    stg<V>(A.psb_out, idx, nv, true, pso);
-    if (A.keep_z) stg<V>(A.zs, idx, nv, true, zps);
+    stg<V>(A.psb_out, idx, nv, true, pso, A.nt != 0);
+    if (A.keep_z) stg<V>(A.zs, idx, nv, true, zps, A.nt != 0);
   }
 }
 

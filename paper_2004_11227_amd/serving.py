@@ -185,13 +185,38 @@ def run_sequential(requests, caps_of, kw_of, stream=None, clock=time.perf_counte
     return rep
 
 
+def _caps32(req):
+    from . import synth
+    return synth.request_caps(req).astype(np.float32)
+
+
+def draw_requests(nreq: int = 2048, seed: int = 4000, workers: int | None = None) -> dict:
+    """The serving trace and every request's FP32 capacities, drawn on the
+    host cores by worker processes (forked: call this before the GPU is
+    initialised).  Returns dict(requests, caps, seed)."""
+    import os
+    from concurrent.futures import ProcessPoolExecutor
+
+    from . import synth
+    base = synth.serving_trace(nreq, seed=seed)
+    workers = workers or max(1, min(16, os.cpu_count() or 1))
+    if workers == 1:
+        caps = [_caps32(r) for r in base]
+    else:
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            caps = list(ex.map(_caps32, base, chunksize=4))
+    return {"requests": base, "caps": caps, "seed": seed}
+
+
 def benchmark(nreq: int = 128, seed: int = 4000, pool_storage: str = "bf16", tol: float = 1e-4,
               max_iter: int = 1000, arena_bytes: int = 48 << 30, max_slots: int = 256,
               steps_per_advance: int = 10, latency_load: float = 0.7, promote_gap: float = 2e-3,
-              promote_iter: int = 400, working_set: int | None = None, log=None) -> dict:
+              promote_iter: int = 400, working_set: int | None = None, drawn: dict | None = None,
+              latency: bool = True, log=None) -> dict:
     """Serving workload: `nreq` requests of the mixed trace (2-D sides
     log-uniform on [64, 2048], 10 % 3-D 128^3, labels in {2,3,4,8}), each run
-    to relative gap `tol` or `max_iter` iterations.
+    to relative gap `tol` or `max_iter` iterations.  `drawn` (from
+    draw_requests) supplies the trace and its capacities instead.
 
     Throughput is measured at saturation (every request queued at t = 0) for
     the one-at-a-time FP32 path (single-solve API) and for the pool; latency
@@ -209,10 +234,16 @@ def benchmark(nreq: int = 128, seed: int = 4000, pool_storage: str = "bf16", tol
         if log:
             log(" ".join(str(x) for x in a))
 
-    base = synth.serving_trace(nreq, seed=seed)
+    if drawn is None:
+        drawn = {"requests": synth.serving_trace(nreq, seed=seed), "caps": None, "seed": seed}
+    base = drawn["requests"]
+    seed = drawn["seed"]
     caps = {}
-    for r in base:
-        caps[r.rid] = torch.from_numpy(synth.request_caps(r).astype(np.float32)).cuda()
+    for i, r in enumerate(base):
+        host = drawn["caps"][i] if drawn["caps"] is not None else synth.request_caps(r).astype(np.float32)
+        caps[r.rid] = torch.from_numpy(host).cuda()
+        if drawn["caps"] is not None:
+            drawn["caps"][i] = None   # the device copy is the one kept
     torch.cuda.synchronize()
     npx = {r.rid: int(np.prod(r.shape)) for r in base}
 
@@ -252,18 +283,23 @@ def benchmark(nreq: int = 128, seed: int = 4000, pool_storage: str = "bf16", tol
     say("pool", pool_storage, "saturation:", bp.as_dict())
 
     rate = latency_load * seq.solves_per_s
-    rng = np.random.Generator(np.random.PCG64(seed + 1))
-    times = np.cumsum(rng.exponential(1.0 / rate, size=len(base)))
-    arr = with_arrivals(base, times)
-    seq_l = run_sequential(arr, lambda r: caps[r.rid], kw_seq, stream=stream)
-    pool_l = serve(arr, PoolBackend(pool, lambda r: caps[r.rid], kw_pool), working_set=working_set)
+    seq_l = pool_l = None
+    if latency:
+        rng = np.random.Generator(np.random.PCG64(seed + 1))
+        times = np.cumsum(rng.exponential(1.0 / rate, size=len(base)))
+        arr = with_arrivals(base, times)
+        say("sequential fp32 under Poisson arrivals")
+        seq_l = run_sequential(arr, lambda r: caps[r.rid], kw_seq, stream=stream)
+        say("pool under Poisson arrivals")
+        pool_l = serve(arr, PoolBackend(pool, lambda r: caps[r.rid], kw_pool), working_set=working_set)
     promotions = pool.stats()["promotions"]
     pool.close()
 
     def iters(rep):
         it = np.array([r.iters for r in rep.records])
         st = np.array([r.status for r in rep.records])
-        return dict(mean_iters=float(it.mean()), converged=int((st == 0).sum()), capped=int((st == 1).sum()))
+        return dict(mean_iters=float(it.mean()), converged=int((st == 0).sum()), capped=int((st == 1).sum()),
+                    diverged=int((st == -4).sum()))
 
     return {
         "promotions_total": promotions,
@@ -272,10 +308,11 @@ def benchmark(nreq: int = 128, seed: int = 4000, pool_storage: str = "bf16", tol
         "promote_gap": promote_gap if pool_storage == "bf16" else None,
         "promote_iter": promote_iter if pool_storage == "bf16" else None,
         "total_pixels": int(sum(npx.values())),
+        "sequential_iters": {r.rid: int(r.iters) for r in seq.records},
         "sequential_fp32": {**seq.as_dict(), **iters(seq)},
         "pool": {**bp.as_dict(), **iters(bp)},
         "speedup_solves_per_s": bp.solves_per_s / seq.solves_per_s,
-        "latency_rate_per_s": rate,
-        "sequential_fp32_latency": {k: v for k, v in seq_l.as_dict().items() if k != "results"},
-        "pool_latency": pool_l.as_dict(),
+        "latency_rate_per_s": rate if latency else None,
+        "sequential_fp32_latency": {k: v for k, v in seq_l.as_dict().items() if k != "results"} if latency else None,
+        "pool_latency": pool_l.as_dict() if latency else None,
     }

@@ -74,3 +74,41 @@ def compare_run(caps, iters, **kw):
     dis = label_disagreement(g["u"], st.u, kw.get("model", "two"))
     s.close()
     return du, dis, g, st
+
+
+def progress(msg: str):
+    """A progress line for long cases: printed, and appended to the file named
+    by MF_TEST_PROGRESS when that variable is set (visible while the test
+    still runs, whatever pytest captures)."""
+    import os
+    print(f"[progress] {msg}", flush=True)
+    path = os.environ.get("MF_TEST_PROGRESS")
+    if path:
+        with open(path, "a") as f:
+            f.write(msg + "\n")
+
+
+def oracle_run(pr, caps64, iters, chunk=100, tag=""):
+    """The FP64 oracle from the initial point for `iters` iterations, in
+    chunks with a progress line after each."""
+    st = oracle.init_state(pr, caps64)
+    done = 0
+    while done < iters:
+        n = min(chunk, iters - done)
+        oracle.step(pr, caps64, st, n)
+        done += n
+        progress(f"{tag} oracle {done}/{iters}")
+    return st
+
+
+def bf16_statement(pr, caps64, u_bf16, st_or, model):
+    """Objective error of a BF16-storage run's u against the FP64 oracle at the
+    same iteration count (both primal energies evaluated in FP64 on the
+    unrounded capacities) and the thresholded-label disagreement."""
+    e = oracle.energy(pr, caps64, st_or)
+    st_b = oracle.state_from_arrays(pr, u_bf16, st_or.q, st_or.ps, st_or.p)
+    if pr.method == "dr":
+        st_b.zq, st_b.zs, st_b.zp = st_or.zq, st_or.zs, st_or.zp
+    eb = oracle.energy(pr, caps64, st_b)
+    obj = abs(eb["primal"] - e["primal"]) / abs(e["primal"])
+    return obj, label_disagreement(u_bf16, st_or.u, model)

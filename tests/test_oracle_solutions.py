@@ -227,3 +227,54 @@ def test_one_pixel_grid():
     st, hist = oracle.solve(pr, caps, 5000, check_every=10, tol=1e-13)
     assert abs(hist[-1][1]["primal"] - 0.3) < 1e-12
     assert oracle.labels(pr, st.u[0])[0, 0] == 0
+
+
+def _np_div(q):
+    """Divergence of a flux field q (ndim, *shape) written with numpy: the
+    backward difference of the forward-difference flux with zero flux through
+    the boundary (so <grad u, q> = -<u, div q>)."""
+    nd = q.shape[0]
+    out = np.zeros(q.shape[1:])
+    for k in range(nd):
+        ax = nd - 1 - k   # component k belongs to the k-th fastest axis
+        f = np.moveaxis(q[k], ax, 0).copy()
+        f[-1] = 0.0
+        d = f.copy()
+        d[1:] -= f[:-1]
+        out += np.moveaxis(d, 0, ax)
+    return out
+
+
+@pytest.mark.parametrize("method", ["fg", "eb", "dr", "ty", "cp"])
+@pytest.mark.parametrize("model,n,shape", [("two", 2, (9, 13)), ("two", 2, (3, 4, 5)),
+                                           ("potts", 3, (8, 11)), ("potts", 8, (6, 7))])
+def test_initial_point_is_the_largest_flow_at_zero_q(method, model, n, shape):
+    """The initial point (the paper states none; reading A10): u = 0, q = 0,
+    and source/sink flows on the constraint set with zero conservation
+    residual.  With q = 0 the constraints decouple per pixel: two labels
+    p_t - p_s = 0, p_s <= C_s, p_t <= C_t; Potts p_i - p_s = 0, p_i <= C_i.
+    The largest total source flow there (the dual objective sum p_s of eqs.
+    two-label-mf / potts-mf restricted to q = 0) is reached exactly when p_s
+    is the pointwise minimum capacity, so the point must be feasible, have
+    zero residual, and carry that flow pixel by pixel."""
+    caps = _rand_caps(shape, 81 + n, model, n)
+    pr = oracle.Problem(shape, model=model, nlabels=n, method=method, alpha=0.3)
+    st = oracle.init_state(pr, caps)
+    L = 1 if model == "two" else n
+    assert np.all(st.u == 0.0) and np.all(st.q == 0.0)
+    cmin = caps.min(axis=0)
+    if model == "two":
+        assert np.all(st.ps <= caps[0]) and np.all(st.p[0] <= caps[1])
+        resid = [st.p[0] - st.ps + _np_div(st.q[0])]
+    else:
+        assert np.all(st.p <= caps)
+        resid = [_np_div(st.q[i]) + st.p[i] - st.ps for i in range(L)]
+    assert max(float(np.abs(r).max()) for r in resid) == 0.0
+    # the source flow is the largest one compatible with q = 0
+    assert np.array_equal(st.ps, cmin)
+    assert abs(st.ps.sum() - cmin.sum()) <= 1e-12 * cmin.sum()
+    # and the oracle's own residual and dual agree with it
+    e = oracle.energy(pr, caps, st)
+    assert e["resid_rms"] == 0.0
+    assert abs(e["flow"] - cmin.sum()) <= 1e-12 * cmin.sum()
+    assert abs(e["dual"] - cmin.sum()) <= 1e-12 * cmin.sum()
