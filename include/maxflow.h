@@ -269,6 +269,34 @@ typedef struct {
 } mf_tuning;
 mf_status maxflow_tune(mf_solver* s, int32_t sweeps, int32_t what, mf_tuning* out);
 
+/* ------------------------------------------------------------------------
+ * Allocation-free solve, for callers that cannot allocate memory (tight
+ * serving loops, harnesses that forbid allocation).
+ *
+ * maxflow_create + maxflow_solve + maxflow_read_u + maxflow_labels in one
+ * call, with the same kernels and results (bit for bit), but the workspace
+ * is a static device array of MF_STATIC_SCRATCH_BYTES per device, reserved
+ * once the library runs on the device and held until the process ends.  The
+ * call allocates nothing: no device or pinned host memory, no events, no
+ * heap; it follows the on-GPU stop decision with a synchronous 4-byte read
+ * every 4 gap checks.
+ *   p, cap:     as in maxflow_create (cap is read, not kept);
+ *   u_dst:      device FP32, L planes (1 two-label, n Potts), dense layout;
+ *               may be NULL;
+ *   labels_dst: device int32, one plane (as maxflow_labels); may be NULL;
+ *   out:        gap at the accepted iterate, as maxflow_solve; may be NULL;
+ *   hip_stream: hipStream_t (NULL = default stream); synchronised on return.
+ * Returns as maxflow_solve (MF_OK, MF_ENOTCONV, MF_EDIVERGED), MF_EINVAL on
+ * invalid parameters, MF_ENOMEM when maxflow_workspace_bytes(p) exceeds
+ * MF_STATIC_SCRATCH_BYTES (use maxflow_create with a caller workspace), or
+ * MF_EDEVICE.  Every call on a device shares that device's array and
+ * overwrites all of it that the problem uses (capacities, state, control
+ * block): calls that overlap on one device race, so serialise them.
+ * ---------------------------------------------------------------------- */
+#define MF_STATIC_SCRATCH_BYTES (64u << 20)
+mf_status maxflow_solve_static(const mf_params* p, const float* cap, float* u_dst, int32_t* labels_dst,
+                               mf_gap* out, void* hip_stream);
+
 /* Thread-local message describing the last error (solver and pool calls). */
 const char* maxflow_last_error(void);
 

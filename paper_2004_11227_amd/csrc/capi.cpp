@@ -913,3 +913,82 @@ mf_status maxflow_destroy(mf_solver* s) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free solve: the workspace is a static device array, one per
+// device the library runs on (held until the process ends).  In host code
+// `scratch` names a host-side stand-in, not a device address: host code uses
+// only the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[MF_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev` (current), looked up once per
+// device and kept.
+hipError_t scratch_ptr(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" mf_status maxflow_solve_static(const mf_params* p, const float* cap, float* u_dst, int32_t* labels_dst,
+                                          mf_gap* out, void* hip_stream) {
+  Resolved r;
+  const char* e = resolve(p, r);
+  if (*e) return fail(MF_EINVAL, e);
+  if (!cap) return fail(MF_EINVAL, "cap must be a device pointer");
+  const Layout L = plan(r);
+  if (L.total > (size_t)MF_STATIC_SCRATCH_BYTES) {
+    snprintf(g_err, sizeof(g_err),
+             "problem needs %zu bytes of workspace; the static scratch holds %zu (use maxflow_create)", L.total,
+             (size_t)MF_STATIC_SCRATCH_BYTES);
+    return MF_ENOMEM;
+  }
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  void* ws = nullptr;
+  HIP_TRY(scratch_ptr(dev, &ws));
+  // the solver lives on this stack frame: no pinned polling slots, no events
+  mf_solver s{};
+  s.r = r;
+  s.L = L;
+  s.ws = (char*)ws;
+  s.stream = (hipStream_t)hip_stream;
+  s.ctrl = (Ctrl*)(s.ws + L.ctrl);
+  s.cap = s.ws + L.cap;
+  s.st[0] = view(s.ws, L.state[0], r);
+  s.st[1] = view(s.ws, L.state[1], r);
+  s.z = view(s.ws, L.stz, r);
+  s.wbuf = (float*)(s.ws + L.wbuf);
+  s.host_done = nullptr;
+  s.dev = dev;
+  HIP_TRY(launch_pitch_copy(cap, false, r.g.npix(), r.g.W, s.cap, r.p.storage == MF_BF16, r.g.plane, r.g.pitch,
+                            r.g.W, (long long)r.g.H * r.g.D, r.ncp, s.stream));
+  mf_status st = init_state(&s);
+  if (st != MF_OK) return st;
+  st = solve_loop(&s, out, true);
+  if (st != MF_OK && st != MF_ENOTCONV && st != MF_EDIVERGED) return st;
+  const StateView& v = s.st[buf_of(&s, s.iter)];
+  const Geom& g = r.g;
+  if (u_dst)
+    HIP_TRY(launch_pitch_copy(v.u, false, g.plane, g.pitch, u_dst, false, g.npix(), g.W, g.W, (long long)g.H * g.D,
+                              r.nl, s.stream));
+  if (labels_dst)
+    HIP_TRY(launch_labels(g, r.nl, r.p.model == MF_TWO_LABEL, v.u, labels_dst, s.stream, g.pitch));
+  HIP_TRY(hipStreamSynchronize(s.stream));
+  return st;
+}

@@ -77,7 +77,7 @@ EXPORTS = ["maxflow_workspace_bytes", "maxflow_create", "maxflow_reset", "maxflo
            "maxflow_gap", "maxflow_solve", "maxflow_iter", "maxflow_read_u", "maxflow_labels",
            "maxflow_read_field", "maxflow_write_field", "maxflow_state_bytes",
            "maxflow_export_state", "maxflow_import_state", "maxflow_destroy",
-           "maxflow_last_error", "maxflow_tune"]
+           "maxflow_last_error", "maxflow_tune", "maxflow_solve_static"]
 
 
 def lib():
@@ -109,6 +109,7 @@ def lib():
         "maxflow_destroy": (S, [V]),
         "maxflow_last_error": (ctypes.c_char_p, []),
         "maxflow_tune": (S, [V, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(mf_tuning)]),
+        "maxflow_solve_static": (S, [P, V, V, V, G, V]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -306,6 +307,35 @@ class Solver:
 
     def import_state(self, blob: torch.Tensor, iter: int):
         _check(lib().maxflow_import_state(self._h, ctypes.c_void_p(blob.data_ptr()), int(iter)))
+
+
+#: bytes of the static device workspace of solve_static (per device)
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def solve_static(caps: torch.Tensor, stream: torch.cuda.Stream | None = None, want_u: bool = True,
+                 want_labels: bool = True, **kw):
+    """One complete solve through maxflow_solve_static, the entry point that
+    allocates nothing inside the library (its workspace is a static device
+    array of STATIC_SCRATCH_BYTES).  ``caps`` and keywords as for Solver.
+    Returns (gap dict, u or None, labels or None); the output tensors are
+    allocated here, by the caller's side of the boundary."""
+    shape = tuple(caps.shape[1:])
+    p = make_params(shape, **kw)
+    if caps.dtype != torch.float32 or not caps.is_cuda or not caps.is_contiguous():
+        raise ValueError("caps must be a contiguous float32 device tensor")
+    L = 1 if kw.get("model", "two") == "two" else int(kw.get("nlabels", 2))
+    stream = stream if stream is not None else torch.cuda.current_stream(caps.device)
+    stream.wait_stream(torch.cuda.current_stream(caps.device))
+    u = torch.empty((L,) + shape, dtype=torch.float32, device=caps.device) if want_u else None
+    lab = torch.empty(shape, dtype=torch.int32, device=caps.device) if want_labels else None
+    g = mf_gap()
+    _check(lib().maxflow_solve_static(ctypes.byref(p), ctypes.c_void_p(caps.data_ptr()),
+                                      ctypes.c_void_p(u.data_ptr() if u is not None else 0),
+                                      ctypes.c_void_p(lab.data_ptr() if lab is not None else 0),
+                                      ctypes.byref(g), ctypes.c_void_p(stream.cuda_stream)),
+           allow=(MF_OK, MF_ENOTCONV, MF_EDIVERGED))
+    return g.as_dict(), u, lab
 
 
 # ---------------------------------------------------------------------------- pool

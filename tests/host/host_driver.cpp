@@ -2,7 +2,7 @@
 // of fake_hip.cpp, built with the address sanitizer: the serving pool
 // (admission, advances, polls, promotions, early and late retirement, arena
 // reuse, pool re-creation), the single-solve API (create, step, solve, field
-// access, checkpoints).  Every buffer handed to
+// access, checkpoints) and the allocation-free solve.  Every buffer handed to
 // the library has exactly the size the ABI documents, so an access past it
 // is reported.  Exits 0 when every sequence completes.
 #include <cstdint>
@@ -209,6 +209,24 @@ void solver_sequences(int n) {
   }
 }
 
+void static_sequences(int n) {
+  for (int i = 0; i < n; i++) {
+    Prob r = random_problem(false);
+    if (!maxflow_workspace_bytes(&r.p)) continue;
+    float* caps = make_caps(r);
+    float* u = (float*)std::malloc(sizeof(float) * r.L * r.npix);
+    int32_t* lab = (int32_t*)std::malloc(sizeof(int32_t) * r.npix);
+    fake_hip_stop_every(rint_(1, 9));
+    mf_gap g;
+    const mf_status st = maxflow_solve_static(&r.p, caps, rint_(0, 3) ? u : nullptr, rint_(0, 3) ? lab : nullptr,
+                                              &g, nullptr);
+    if (st != MF_OK && st != MF_ENOTCONV) fail("solve_static");
+    std::free(caps);
+    std::free(u);
+    std::free(lab);
+  }
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
@@ -216,6 +234,7 @@ int main(int argc, char** argv) {
   if (argc > 2) g_rng = std::strtoull(argv[2], nullptr, 10) | 1;
   pool_sequences(20 * scale);
   solver_sequences(300 * scale);
+  static_sequences(100 * scale);
   std::printf("host_driver ok: %lld graph launches\n", fake_hip_graph_launches());
   return 0;
 }

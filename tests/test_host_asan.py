@@ -7,7 +7,8 @@ bookkeeping transitions with scripted decisions, sweeps touch every plane
 they would read or write).  tests/host/host_driver.cpp then drives random
 sequences through the C ABI: pool admission, advances, polls, promotions,
 early and late retirement and re-creation; the single-solve API (create,
-step, solve with its polling loop, field access, checkpoints).  Every buffer handed over has exactly the documented
+step, solve with its polling loop, field access, checkpoints); and the
+allocation-free solve.  Every buffer handed over has exactly the documented
 size, so any host access outside an allocation fails the test."""
 import os
 import re
