@@ -223,8 +223,8 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
     for (int e = 0; e < V; e++) usn[j][e] = 0.f;
   const float tau = A.tau, rho = A.rho;
 
-  // Gauss-Seidel value of cell (r, c) from its neighbours in su
-  auto gs = [&](int r, int c) {
+  // Gauss-Seidel value of cell (r, c) from its neighbours in su and its b
+  auto gs_b = [&](int r, int c, float bv) {
     const int hx = x0 + c, hy = y0 + r;
     const int R = r + OY, C = c + OX;
     float s = 0.f;
@@ -233,8 +233,9 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
     if (xp(hx)) { s += su[R][C + 1]; nb++; }
     if (ym(hy)) { s += su[R - 1][C]; nb++; }
     if (yp(hy)) { s += su[R + 1][C]; nb++; }
-    return (sb[R][C] * A.inv_st + s) * rden_at(A.rden, nb);
+    return (bv * A.inv_st + s) * rden_at(A.rden, nb);
   };
+  auto gs = [&](int r, int c) { return gs_b(r, c, sb[r + OY][c + OX]); };
   // Half-sweep over the cells of one colour (0 red, 1 black: parity of
   // x + y; x0 and y0 are even) of rows rlo .. rlo+nr-1, cols clo .. clo+nc-1:
   // threads map onto that colour's cells only.
@@ -265,7 +266,11 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
       for (int e = 0; e < V; e++) ocl[j][e] = ncl[j][e];
     if (l + 1 < NL) fetch(l + 1);
     lds_barrier();
-    // ---- b on T+[-2NS,+2NS+1]: -sigma (div q-bar + p-bar - p-bar_s) (+ st (n u - sum u) for Potts)
+    // ---- b on T+[-2NS,+2NS+1]: -sigma (div q-bar + p-bar - p-bar_s) (+ st (n u - sum u) for Potts),
+    // and the first (red) half-sweep on the same region: a red cell's value
+    // needs its own b and the old u of its black neighbours, which no red
+    // update changes, so both run in one pass (b of a black cell reads only
+    // its own old u)
     constexpr int BW = TX + 4 * NS + 1;
     for (int h = tid; h < (TY + 4 * NS + 1) * BW; h += 256) {
       const int r = h / BW - 2 * NS, c = h % BW - 2 * NS;
@@ -276,12 +281,13 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
       float bl = -A.sigma * ((d + spt[R][C]) - sps[R][C]);
       if constexpr (!TWO) bl += (A.sigma * A.tau) * ((float)NL * su[R][C] - S.sus[R][C]);
       sb[R][C] = bl;
+      if (((r + c) & 1) == 0) su[R][C] = gs_b(r, c, bl);
     }
     lds_barrier();
     // ---- half-sweep j (red for even j) on T+[-(2NS-j), +(2NS+1-j)]: for one
-    // sweep red on T+[-2,+3], black on T+[-1,+2], red on T+[0,+1]
+    // sweep red on T+[-2,+3] (above), black on T+[-1,+2], red on T+[0,+1]
 #pragma unroll
-    for (int j = 0; j <= 2 * NS; j++) {
+    for (int j = 1; j <= 2 * NS; j++) {
       half_sweep(j - 2 * NS, TY + 4 * NS + 1 - 2 * j, j - 2 * NS, TX + 4 * NS + 1 - 2 * j, j & 1);
       lds_barrier();
     }

@@ -278,3 +278,33 @@ def test_initial_point_is_the_largest_flow_at_zero_q(method, model, n, shape):
     assert e["resid_rms"] == 0.0
     assert abs(e["flow"] - cmin.sum()) <= 1e-12 * cmin.sum()
     assert abs(e["dual"] - cmin.sum()) <= 1e-12 * cmin.sum()
+
+
+@pytest.mark.parametrize("model,n,tv,shape", [("potts", 3, "iso", (4, 5)), ("potts", 4, "aniso", (3, 5)),
+                                              ("two", 2, "iso", (6, 7))])
+def test_eb_step_keeps_a_saddle_point_found_by_fg(model, n, tv, shape):
+    """Reading A5 (coefficient 1 on p_i^{k+1} - p_s^{k+1} in the multi-label EB
+    multiplier step, as in the general EB update): a saddle point reached by
+    the FG scheme (r = 1, whose multiplier step has no such term) must be a
+    fixed point of one EB step with rho = 1.9.  With the printed coefficient
+    rho the multiplier would move by c (1 - rho)(p_i - p_s), which is not zero
+    at a saddle point (there p_i - p_s = -div q_i)."""
+    caps = _rand_caps(shape, 12, model, n)
+    alpha = 0.2
+    fg = oracle.Problem(shape, model=model, nlabels=n, method="fg", relax=1.0, tv=tv, alpha=alpha)
+    st = oracle.init_state(fg, caps)
+    for _ in range(40):
+        oracle.step(fg, caps, st, 5000)
+        s1 = st.copy()
+        oracle.step(fg, caps, s1, 1)
+        if max(float(np.max(np.abs(getattr(st, f) - getattr(s1, f)))) for f in ("u", "q", "ps", "p")) < 1e-13:
+            break
+    else:
+        raise AssertionError("FG did not reach a fixed point")
+    assert float(np.max(np.abs(st.p - st.ps))) > 1e-3   # the A5 term would be visible
+    eb = oracle.Problem(shape, model=model, nlabels=n, method="eb", relax=1.9, tv=tv, alpha=alpha)
+    s2 = oracle.state_from_arrays(eb, st.u, st.q, st.ps, st.p)
+    oracle.step(eb, caps, s2, 1)
+    for f in ("u", "q", "ps", "p"):
+        a, b = getattr(st, f), getattr(s2, f)
+        assert np.max(np.abs(a - b)) < 1e-9 * max(1.0, np.max(np.abs(a))), f
