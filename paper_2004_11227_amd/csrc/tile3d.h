@@ -12,8 +12,9 @@
 //   4. for the owned pixels of plane s-1: d = div q^{k+1}(s-1) (the q_z of
 //      plane s-2 is kept in registers), the pointwise p and u updates, and
 //      the stores.
-// Every plane is read from memory once per slab (plus two warm-up planes),
-// so z-neighbours cost no extra traffic; xy halos are shared through L2.
+// Every plane is read from memory once per slab (plus the warm-up planes
+// z0-1, z1 and the q_z component of z0-2), so z-neighbours cost no extra
+// traffic; xy halos are shared through L2.
 // The arithmetic is the same device-function sequence as the unfused 3-D
 // baseline, so the two agree bit for bit.
 #pragma once
@@ -147,33 +148,40 @@ __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, 
   // the slab load element 0 of the plane, one line for the whole wave); the
   // zeros are applied when the plane is staged, a step later, so the loads
   // stay in flight across the LDS phases.
+  // The first warm-up plane z0-2 only supplies q_z^k (for div q^k at z0-1):
+  // its other fields load element 0 (one cached line) instead of the plane;
+  // their staged values feed only w(z0-2), which no output uses.
   auto fetch = [&](int s, Plane3<V>& F) {
     const bool zin = s >= 0 && s < D && s <= z1;
+    const bool all = s > z0 - 2;
     const long long zoff = (long long)s * SZ;
     if (vec) {
       const long long i = (zin && nvxy > 0) ? zoff + own_off : 0;
-      ldv<V>(qx_in, i, F.qx);
-      ldv<V>(qy_in, i, F.qy);
+      const long long ia = all ? i : 0;
+      ldv<V>(qx_in, ia, F.qx);
+      ldv<V>(qy_in, ia, F.qy);
       ldv<V>(qz_in, i, F.qz);
-      ldv<V>(A.u_in, i, F.u);
-      ldv<V>(A.p_in, i, F.p);
-      ldv<V>(A.ps_in, i, F.ps);
+      ldv<V>(A.u_in, ia, F.u);
+      ldv<V>(A.p_in, ia, F.p);
+      ldv<V>(A.ps_in, ia, F.ps);
     } else {
 #pragma unroll
       for (int e = 0; e < V; e++) {
         const long long i = (zin && e < nvxy) ? zoff + own_off + e : 0;
-        F.qx[e] = ld(qx_in, i);
-        F.qy[e] = ld(qy_in, i);
+        const long long ia = all ? i : 0;
+        F.qx[e] = ld(qx_in, ia);
+        F.qy[e] = ld(qy_in, ia);
         F.qz[e] = ld(qz_in, i);
-        F.u[e] = ld(A.u_in, i);
-        F.p[e] = ld(A.p_in, i);
-        F.ps[e] = ld(A.ps_in, i);
+        F.u[e] = ld(A.u_in, ia);
+        F.p[e] = ld(A.p_in, ia);
+        F.ps[e] = ld(A.ps_in, ia);
       }
     }
     const long long iq = (zin && hq_xy) ? zoff + hq_off : 0;
-    const long long iw = (zin && hw_xy) ? zoff + hw_off : 0;
-    F.hqx = ld(qx_in, iq);
-    F.hqy = ld(qy_in, iq);
+    const long long iw = (zin && hw_xy && all) ? zoff + hw_off : 0;
+    const long long iqa = all ? iq : 0;
+    F.hqx = ld(qx_in, iqa);
+    F.hqy = ld(qy_in, iqa);
     F.hqz = ld(qz_in, iq);
     F.hu = ld(A.u_in, iw);
     F.hp = ld(A.p_in, iw);
