@@ -11,7 +11,11 @@ interest.  Writes OUT_PREFIX.md (human summary) and OUT_PREFIX_traffic.json
 (per-launch HBM bytes of the kernel of interest, scaled by the copy
 calibration, with the source hash of the kernel it was measured on).
 With FETCH_DIR and WRITE_DIR given as `-`, only the kernel-trace table is
-written (OUT_PREFIX.md).
+written (OUT_PREFIX.md); if KTRACE_DIR also holds the per-dispatch
+`*_kernel_trace.csv`, the dispatches of the kernel of interest are split by
+grid size, and launches that returned at once on the solver's done flag
+(under a tenth of their grid's median) are counted apart, so that one
+workload's average can be read off a program that runs several.
 """
 from __future__ import annotations
 
@@ -44,6 +48,38 @@ def kernel_stats(d):
     return [(r["Name"], int(r["Calls"]), float(r["AverageNs"]), float(r["Percentage"])) for r in rows]
 
 
+def dispatches_by_grid(d, kernel):
+    """{grid work-items: [durations ns]} of the dispatches whose name holds
+    `kernel`, from a per-dispatch kernel trace (None when absent)."""
+    files = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)
+    if not files:
+        return None
+    out = {}
+    for r in csv.DictReader(open(files[0])):
+        if kernel not in r["Kernel_Name"]:
+            continue
+        if "Grid_Size" in r:
+            g = int(r["Grid_Size"])
+        else:
+            g = int(r["Grid_Size_X"]) * int(r.get("Grid_Size_Y", 1) or 1) * int(r.get("Grid_Size_Z", 1) or 1)
+        out.setdefault(g, []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return out
+
+
+def grid_table(by_grid):
+    lines = ["", "Dispatches of the kernel of interest by grid size (launches under a tenth of their grid's "
+             "median are early exits on the done flag):", "",
+             "| grid work-items | workgroups of 256 | dispatches | early exits | average us (full) | "
+             "median us (full) |", "|---|---|---|---|---|---|"]
+    for g in sorted(by_grid, reverse=True):
+        ds = sorted(by_grid[g])
+        med = ds[len(ds) // 2]
+        full = [x for x in ds if x >= 0.1 * med]
+        lines.append(f"| {g} | {g // 256} | {len(ds)} | {len(ds) - len(full)} | "
+                     f"{sum(full) / len(full) / 1e3:.2f} | {full[len(full) // 2] / 1e3:.2f} |")
+    return lines
+
+
 def counters(d):
     rows = list(csv.DictReader(open(_one(os.path.join(d, "**", "*counter_collection.csv")))))
     agg = {}
@@ -72,6 +108,9 @@ def main():
         for name, calls, avg, pct in ks[:16]:
             lines.append(f"| `{name[:110]}` | {calls} | {avg / 1e3:.2f} | {pct:.2f} |")
         lines += ["", f"Total kernel time {total / 1e6:.1f} ms over {sum(c for _, c, _, _ in ks)} dispatches."]
+        by_grid = dispatches_by_grid(a.ktrace, a.kernel)
+        if by_grid:
+            lines += grid_table(by_grid)
         open(a.out + ".md", "w").write("\n".join(lines) + "\n")
         print("\n".join(lines))
         return
