@@ -24,8 +24,16 @@
 
 namespace mf {
 
+// Occupancy: one 64 x 16 tile with one sweep keeps its LDS within a quarter
+// of a CU's 160 KiB, so four workgroups can share a CU if the registers
+// allow it; the kernel is latency bound (barrier-separated LDS phases), so
+// those instantiations are held to 128 VGPRs (four waves per SIMD).
+template <int TY, int NS>
+constexpr int dr_waves_per_eu() { return (TY == 16 && NS == 1) ? 4 : 1; }
+
 template <typename TS, int TY, int NL, bool TWO, int NS>
-__global__ __launch_bounds__(256) void k_dr_fused2d(const KDF<TS> A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dr_waves_per_eu<TY, NS>())))
+void k_dr_fused2d(const KDF<TS> A) {
   __shared__ SmemDR<TY, TWO, NS> S;
   if (A.done && *A.done) return;
   int tx, ty;

@@ -88,15 +88,15 @@ struct SmemDR {
   __align__(16) float sqy[SH][SW];
   __align__(16) float sps[SH][SW];
   __align__(16) float spt[SH][SW];    // p-bar of the label (p-bar_t for two labels)
-  __align__(16) float sb[SH][SW];
-  __align__(16) float sus[TWO ? 1 : SH][TWO ? 1 : SW];   // Potts: sum over labels of u^k
+  __align__(16) float sb[SH][SW];       // Potts: holds the label sum of u^k until the first b
 };
 
-// A tile whose b and half-sweep cells (rows -2 NS .. TY-1+2 NS, cols
-// -2 NS .. 63+2 NS) all have their four neighbours inside the grid.
+// A tile whose staged rectangle (rows -OY .. TY+OY, cols -OX .. 63+OX) lies
+// inside the grid, so that its b and half-sweep cells (rows -2 NS ..
+// TY-1+2 NS, cols -2 NS .. 63+2 NS) all have their four neighbours inside.
 template <int TY, int NS>
 __device__ __forceinline__ bool dr_interior(int x0, int y0, int W, int H) {
-  return x0 > 0 && y0 > 0 && x0 + 64 + 2 * NS + 1 < W && y0 + TY + 2 * NS + 1 < H;
+  return x0 > 0 && y0 > 0 && x0 + 64 + DrHalo<NS>::OX <= W && y0 + TY + DrHalo<NS>::OY < H;
 }
 
 // EDGE false: an interior tile (dr_interior), whose every boundary test is
@@ -140,13 +140,14 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
     gnv[m] = nv;
     gi[m] = nv > 0 ? (long long)gy * pitch + gx : 0;
   }
-  // write staged groups into an LDS array (entries outside the grid: 0)
+  // write staged groups into an LDS array (entries outside the grid: 0; an
+  // interior tile's staged rectangle lies inside the grid)
   auto put = [&](float (*dst)[SmemDR<TY, TWO, NS>::SW], int m, const float (&v)[V]) {
     const int h = tid + 256 * m;
     if (h < NG) {
       const int r = h / GPR, c = (h % GPR) * 4;
 #pragma unroll
-      for (int e = 0; e < V; e++) dst[r][c + e] = e < gnv[m] ? v[e] : 0.f;
+      for (int e = 0; e < V; e++) dst[r][c + e] = (!EDGE || e < gnv[m]) ? v[e] : 0.f;
     }
   };
   // owned groups
@@ -181,7 +182,7 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
       ldv<V>(u_in, gi[m], nu[m]);
       ldv<V>(qx_in, gi[m], nqx[m]);
       ldv<V>(qx_in + P, gi[m], nqy[m]);
-      ldv<V>(pb_in, gi[m], npt[m]);
+      if (TWO) ldv<V>(pb_in, gi[m], npt[m]);
     }
     load_cap(TWO ? 1 : l, ncl);
   };
@@ -209,7 +210,7 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
           for (int e = 0; e < V; e++) acc[m][e] += lu[m][e];
       }
 #pragma unroll
-      for (int m = 0; m < KG; m++) put(S.sus, m, acc[m]);
+      for (int m = 0; m < KG; m++) put(sb, m, acc[m]);
     }
 #pragma unroll
     for (int m = 0; m < KG; m++) put(sps, m, lps[m]);
@@ -222,6 +223,14 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
 #pragma unroll
     for (int e = 0; e < V; e++) usn[j][e] = 0.f;
   const float tau = A.tau, rho = A.rho;
+  // b region T+[-2NS,+2NS+1]: thread tid takes cells tid + 256 k, the same
+  // cells for every label, so the Potts label sum of u^k at those cells,
+  // staged in sb, moves to registers before the first b overwrites it (a
+  // seventh LDS array would leave room for only three workgroups per CU)
+  constexpr int BW = TX + 4 * NS + 1;
+  constexpr int BN = (TY + 4 * NS + 1) * BW;
+  constexpr int NB = (BN + 255) / 256;
+  float rsus[TWO ? 1 : NB];
 
   // Gauss-Seidel value of cell (r, c) from its neighbours in su and its b
   auto gs_b = [&](int r, int c, float bv) {
@@ -252,6 +261,12 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
   for (int l = 0; l < NL; l++) {
     // ---- stage u, q-bar, p-bar of label l on the staged rectangle, then
     // start the loads of label l+1
+    // (Potts: p-bar of the label is loaded here, not a label ahead, which
+    // keeps the registers within four waves per SIMD)
+    if constexpr (!TWO) {
+#pragma unroll
+      for (int m = 0; m < KG; m++) ldv<V>(A.pb_in + (long long)l * P, gi[m], npt[m]);
+    }
 #pragma unroll
     for (int m = 0; m < KG; m++) {
       put(su, m, nu[m]);
@@ -271,15 +286,20 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
     // needs its own b and the old u of its black neighbours, which no red
     // update changes, so both run in one pass (b of a black cell reads only
     // its own old u)
-    constexpr int BW = TX + 4 * NS + 1;
-    for (int h = tid; h < (TY + 4 * NS + 1) * BW; h += 256) {
+#pragma unroll
+    for (int k = 0; k < NB; k++) {
+      const int h = tid + 256 * k;
+      if (k == NB - 1 && h >= BN) continue;
       const int r = h / BW - 2 * NS, c = h % BW - 2 * NS;
       const int hx = x0 + c, hy = y0 + r;
       const int R = r + OY, C = c + OX;
       const float d = ((xp(hx) ? sqx[R][C] : 0.f) - (xm(hx) ? sqx[R][C - 1] : 0.f)) +
                       ((yp(hy) ? sqy[R][C] : 0.f) - (ym(hy) ? sqy[R - 1][C] : 0.f));
       float bl = -A.sigma * ((d + spt[R][C]) - sps[R][C]);
-      if constexpr (!TWO) bl += (A.sigma * A.tau) * ((float)NL * su[R][C] - S.sus[R][C]);
+      if constexpr (!TWO) {
+        if (l == 0) rsus[k] = sb[R][C];
+        bl += (A.sigma * A.tau) * ((float)NL * su[R][C] - rsus[k]);
+      }
       sb[R][C] = bl;
       if (((r + c) & 1) == 0) su[R][C] = gs_b(r, c, bl);
     }
