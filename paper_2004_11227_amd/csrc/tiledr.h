@@ -247,13 +247,17 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
   auto gs = [&](int r, int c) { return gs_b(r, c, sb[r + OY][c + OX]); };
   // Half-sweep over the cells of one colour (0 red, 1 black: parity of
   // x + y; x0 and y0 are even) of rows rlo .. rlo+nr-1, cols clo .. clo+nc-1:
-  // threads map onto that colour's cells only.
+  // threads map onto that colour's cells only, lane pairs onto the j-th
+  // such cell of two consecutive rows (the two rows' cells alternate in
+  // column parity, so a wave's LDS accesses fall in distinct banks).
   auto half_sweep = [&](int rlo, int nr, int clo, int nc, int colour) {
     const int nch = (nc + 1) / 2;
-    for (int h = tid; h < nr * nch; h += 256) {
-      const int r = rlo + h / nch;
-      const int c = clo + 2 * (h % nch) + ((colour - r - clo) & 1);
-      if (c < clo + nc) su[r + OY][c + OX] = gs(r, c);
+    const int npr = (nr + 1) / 2;
+    for (int h = tid; h < 2 * npr * nch; h += 256) {
+      const int pr = h >> 1;
+      const int r = rlo + 2 * (pr / nch) + (h & 1);
+      const int c = clo + 2 * (pr % nch) + ((colour - r - clo) & 1);
+      if (r < rlo + nr && c < clo + nc) su[r + OY][c + OX] = gs(r, c);
     }
   };
 
@@ -320,18 +324,37 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
       const int r = rr0 + RSTEP * j;
       const int gy = y0 + r;
       float un[V], qxo[V], qyo[V], zqx[V], zqy[V], pto[V], zpt[V];
+      // the group's row of u (and its right neighbour), the row below, and
+      // q-bar, p-bar: 16-byte LDS reads, one group per lane
+      float lu[V + 1], lud[V], lqx[V], lqy[V], lpt[V];
+      {
+        const int R = r + OY, C = c0 + OX;
+        const f32x4_t a = *reinterpret_cast<const f32x4_t*>(&su[R][C]);
+        const f32x4_t b = *reinterpret_cast<const f32x4_t*>(&su[R + 1][C]);
+        const f32x4_t x = *reinterpret_cast<const f32x4_t*>(&sqx[R][C]);
+        const f32x4_t y = *reinterpret_cast<const f32x4_t*>(&sqy[R][C]);
+        const f32x4_t t = *reinterpret_cast<const f32x4_t*>(&spt[R][C]);
+#pragma unroll
+        for (int e = 0; e < V; e++) {
+          lu[e] = a[e];
+          lud[e] = b[e];
+          lqx[e] = x[e];
+          lqy[e] = y[e];
+          lpt[e] = t[e];
+        }
+        lu[V] = su[R][C + V];
+      }
 #pragma unroll
       for (int e = 0; e < V; e++) {
         const int gx = gx0 + e;
-        const int R = r + OY, C = c0 + e + OX;
-        const float u0 = su[R][C];
+        const float u0 = lu[e];
         un[e] = u0;
         usn[j][e] += u0;
         float g0 = 0.f, g1 = 0.f;
-        if (xp(gx)) g0 = su[R][C + 1] - u0;
-        if (yp(gy)) g1 = su[R + 1][C] - u0;
+        if (xp(gx)) g0 = lu[e + 1] - u0;
+        if (yp(gy)) g1 = lud[e] - u0;
         // q = q-bar - tau grad u;  z_q = P_alpha(2q - q-bar);  q-bar += rho (z_q - q)
-        const float qb0 = sqx[R][C], qb1 = sqy[R][C];
+        const float qb0 = lqx[e], qb1 = lqy[e];
         const float q0 = qb0 - tau * g0, q1 = qb1 - tau * g1;
         float z0 = 2.f * q0 - qb0, z1 = 2.f * q1 - qb1;
         if (A.iso) proj2<true>(z0, z1, A.alpha);
@@ -341,7 +364,7 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
         zqx[e] = z0;
         zqy[e] = z1;
         // p = p-bar + tau u;  z = min(C, 2p - p-bar);  p-bar += rho (z - p)
-        const float pbv = spt[R][C];
+        const float pbv = lpt[e];
         const float pv = pbv + tau * u0;
         const float zpv = fminf(cap_val(ocl[j][e], TWO ? 1 : l), 2.f * pv - pbv);
         pto[e] = pbv + rho * (zpv - pv);

@@ -80,6 +80,35 @@ def grid_table(by_grid):
     return lines
 
 
+def counter_table(dirs, kernel):
+    """Per-dispatch averages of every counter collected in `dirs` for the
+    kernel of interest, with the ratios read off them."""
+    agg = {}
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if kernel in r["Kernel_Name"]:
+                    agg.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    avg = {k: sum(v) / len(v) for k, v in agg.items()}
+    lines = ["", "## Instruction and wait counters (--pmc, one pass per group; per dispatch)", "",
+             "| counter | average per dispatch |", "|---|---|"]
+    for k in sorted(avg):
+        lines.append(f"| {k} | {avg[k]:.0f} |")
+    w = avg.get("SQ_WAVES")
+    if w:
+        lines += ["", "Per wave: " + ", ".join(f"{k[9:] if k.startswith('SQ_INSTS_') else k} {avg[k] / w:.0f}"
+                                           for k in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS",
+                                                     "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR") if k in avg) + "."]
+    if "SQ_LDS_BANK_CONFLICT" in avg and avg.get("SQ_ACTIVE_INST_LDS"):
+        lines.append(f"LDS bank-conflict cycles per LDS-active cycle: "
+                     f"{avg['SQ_LDS_BANK_CONFLICT'] / avg['SQ_ACTIVE_INST_LDS']:.2f}.")
+    if avg.get("SQ_WAVE_CYCLES"):
+        for k in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS"):
+            if k in avg:
+                lines.append(f"{k} / SQ_WAVE_CYCLES: {avg[k] / avg['SQ_WAVE_CYCLES']:.2f}.")
+    return lines
+
+
 def counters(d):
     rows = list(csv.DictReader(open(_one(os.path.join(d, "**", "*counter_collection.csv")))))
     agg = {}
@@ -99,6 +128,8 @@ def main():
     ap.add_argument("--launch-bytes", type=int, default=0)
     ap.add_argument("--command", default="")
     ap.add_argument("--sources", nargs="*", default=[])
+    ap.add_argument("--pmc-dirs", nargs="*", default=[],
+                    help="directories of further --pmc runs (SQ_ counters) of the same program")
     a = ap.parse_args()
     ks = kernel_stats(a.ktrace)
     if a.fetch == "-" and a.write == "-":
@@ -141,6 +172,8 @@ def main():
     if a.launch_bytes:
         lines.append(f"(algorithmic {a.launch_bytes / 1e6:.2f} MB per launch; ratio "
                      f"{(fetch_b + write_b) / a.launch_bytes:.3f})")
+    if a.pmc_dirs:
+        lines += counter_table(a.pmc_dirs, a.kernel)
     open(a.out + ".md", "w").write("\n".join(lines) + "\n")
     json.dump({"kernel": target, "kernel_hash": source_hash(a.sources) if a.sources else None,
                "bytes_per_launch": fetch_b + write_b, "fetch_bytes": fetch_b, "write_bytes": write_b,
