@@ -102,6 +102,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
     ap.add_argument("--serving-requests", type=int, default=2048,
                     help="requests of the serving mix in the secondary measurements (0: skip)")
+    ap.add_argument("--serving-child", default=None, metavar="OUT",
+                    help="(internal) run only the serving mix and write its summary to OUT as JSON")
     ap.add_argument("--profile-sweeps", type=int, default=200, help="iterations run in --profile-mode")
     ap.add_argument("--profile-mode", nargs="?", const="two_3d_256", default=None,
                     choices=sorted(PROFILE_WORKLOADS))
@@ -254,13 +256,17 @@ def main():
     from paper_2004_11227_amd import maxflow, synth
 
     wl = WORKLOAD
-    serving_caps = None
+    if args.serving_child:
+        serving_child(args)
+        return
+    serving_reqs, serving_out = None, None
     if not args.no_extra and args.serving_requests > 0 and not args.profile_mode:
-        # the serving mix's capacities are drawn on the host cores before the
-        # GPU is touched (worker processes)
-        from paper_2004_11227_amd import serving
-        phase(f"serving mix: drawing {args.serving_requests} requests")
-        serving_caps = serving.draw_requests(args.serving_requests)
+        # The serving mix runs first, in a child process started before this
+        # one touches the GPU: a failure there (the pool has ended a process
+        # in a host segmentation fault whose cause is not known) costs only
+        # the serving lines.
+        serving_reqs = synth.serving_trace(args.serving_requests, seed=SERVING_SEED)
+        serving_out = run_serving_child(args.serving_requests)
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -352,9 +358,10 @@ def main():
     serving_iters = None
     if not args.no_extra:
         extra = secondary(torch, maxflow, synth, np, dev, stream)
-        if serving_caps is not None:
-            phase("serving mix")
-            extra["serving"], serving_iters = serving_summary(serving_caps)
+        if serving_out is not None:
+            extra["serving"] = serving_out.get("summary")
+            if serving_out.get("sequential_iters"):
+                serving_iters = {int(k): v for k, v in serving_out["sequential_iters"].items()}
 
     out = {"metric": "pixel*label ADMM iterations/s (two-label 256^3, rpADMMII, FP32, solve to gap 1e-4)",
            "value": value, "unit": "pixel*label*iterations/s", "n_gpus": 1, "steps": args.steps,
@@ -368,8 +375,7 @@ def main():
            "roofline": roof, "gates": gates}
     if not args.no_cpu:
         phase("cpu baseline (oracle)")
-        reqs = serving_caps["requests"] if serving_caps is not None else None
-        out["cpu_baseline"] = cpu_baseline(caps64, wl, reqs, serving_iters)
+        out["cpu_baseline"] = cpu_baseline(caps64, wl, serving_reqs, serving_iters)
     if extra:
         out["extra"] = extra
     print(json.dumps(out), flush=True)
@@ -442,6 +448,40 @@ def secondary(torch, maxflow, synth, np, dev, stream):
                model="two", method="eb", relax=1.5, alpha=0.4, cap_source="image", cap_power=1, levels=(0.2, 0.8))
     del vimg
     return res
+
+
+SERVING_SEED = 4000
+
+
+def run_serving_child(nreq):
+    """The serving summary from a child run of this script (see main); on a
+    failed child, a record of the failure instead of the summary."""
+    import subprocess
+    import tempfile
+    fd, path = tempfile.mkstemp(prefix="serving_", suffix=".json")
+    os.close(fd)
+    try:
+        phase(f"serving mix: {nreq} requests in a child process")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--serving-child", path,
+                            "--serving-requests", str(nreq)], timeout=900)
+        if r.returncode != 0:
+            phase(f"serving child exited with status {r.returncode}")
+            return {"summary": {"error": f"serving child process exited with status {r.returncode}"}}
+        return json.load(open(path))
+    except subprocess.TimeoutExpired:
+        return {"summary": {"error": "serving child process timed out"}}
+    finally:
+        os.unlink(path)
+
+
+def serving_child(args):
+    from paper_2004_11227_amd import serving
+    phase(f"serving mix: drawing {args.serving_requests} requests")
+    drawn = serving.draw_requests(args.serving_requests, seed=SERVING_SEED)
+    phase("serving mix")
+    summary, iters = serving_summary(drawn)
+    json.dump({"summary": summary, "sequential_iters": {str(k): v for k, v in iters.items()}},
+              open(args.serving_child, "w"))
 
 
 def serving_summary(drawn):

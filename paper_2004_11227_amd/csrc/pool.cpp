@@ -9,9 +9,15 @@
 // gap of every checking solve).  With depth 2 the two-label 2-D classes run a two-iteration pass
 // at even steps and sit out the odd ones.  Bookkeeping runs twice per
 // advance: after the first step (decisions) and after the last (counters).
-// The steps of one advance (steps_per_advance iterations) form one hipGraph,
-// built when the set of classes changes, whose kernel grids are resized in
-// place to the item counts, and replayed by every mf_pool_advance.
+// The steps of one advance (steps_per_advance iterations) form one hipGraph
+// per set of classes, replayed by every mf_pool_advance while that set is
+// running.  A class node's grid is a per-class capacity that only grows
+// (doubling when the class's item count passes it); workgroups past the
+// count return at once.  Admission and retirement therefore change only the
+// device work lists: a graph is never edited, and graphs are destroyed only
+// with the pool.  A set whose graph was built with a smaller capacity than
+// a class now needs gets a new graph; the old one is kept until the pool is
+// destroyed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -153,18 +159,15 @@ struct mf_pool {
   int adv_since_poll = 0;
   PoolStat* stats_h = nullptr;
   PoolStat* one_stat = nullptr;                         // pinned: a single slot's status
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  int graph_mask = -1;                                  // classes the graph launches
-  struct Node {
-    hipGraphNode_t node;
-    const void* func;
-    int cls;
-    int book;    // 1: bookkeeping node (fixed grid), else sized by the class's items
-    int step;    // class launch: the step of the advance (its input iterate is iter + step)
+  struct Graph {
+    int mask = 0;                  // classes the graph launches
+    std::vector<unsigned> grid;    // per class: workgroups of its nodes
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
   };
-  std::vector<Node> nodes;
-  std::vector<int> node_counts;                         // counts the node grids were set for
+  std::vector<Graph> graphs;       // one per class set in use (cached)
+  std::vector<Graph> retired;      // superseded graphs, destroyed with the pool
+  std::vector<unsigned> cap;       // per class: grid capacity (grow-only)
   long long promotions = 0;
   int64_t next_id = 1;
   size_t in_use = 0;
@@ -245,19 +248,11 @@ hipKernelNodeParams node_params(const void* func, unsigned grid, unsigned block,
 // starting at a replay boundary, so step 0 is the check step of every
 // solve; the deciding bookkeeping follows it, so a solve that stops or is
 // frozen there keeps its iterate (step 0 wrote only its other buffer and
-// later launches skip it).  Kernel-node grids follow the class item counts
-// (set_grids).
-mf_status build_graph(mf_pool* P, int mask) {
-  if (P->exec) {
-    hipGraphExecDestroy(P->exec);
-    P->exec = nullptr;
-  }
-  if (P->graph) {
-    hipGraphDestroy(P->graph);
-    P->graph = nullptr;
-  }
-  P->nodes.clear();
-  PHIP(hipGraphCreate(&P->graph, 0));
+// later launches skip it).  Class nodes take the capacities in P->cap.
+mf_status build_graph(mf_pool* P, int mask, mf_pool::Graph& G) {
+  G.mask = mask;
+  G.grid.assign(kPoolClasses, 0);
+  PHIP(hipGraphCreate(&G.graph, 0));
   PoolDev dev = P->dev;
   // Steps h = 0 .. steps-1 of one advance: every class launch of step h
   // depends on all launches of step h-1.  The first step carries the gaps
@@ -265,12 +260,14 @@ mf_status build_graph(mf_pool* P, int mask) {
   // bookkeeping that moves every running solve on by `steps` iterations.
   // With depth 2 the two-label 2-D classes launch the two-iteration pass at
   // even steps only.
-  std::vector<hipGraphNode_t> prev;
+  std::vector<hipGraphNode_t> prev;   // the nodes the next step depends on
   auto add = [&](const void* f, unsigned grid, unsigned block, void** args, hipGraphNode_t& n) -> mf_status {
     hipKernelNodeParams kp = node_params(f, grid, block, args);
-    PHIP(hipGraphAddKernelNode(&n, P->graph, prev.empty() ? nullptr : prev.data(), prev.size(), &kp));
+    PHIP(hipGraphAddKernelNode(&n, G.graph, prev.empty() ? nullptr : prev.data(), prev.size(), &kp));
     return MF_OK;
   };
+  for (int c = 0; c < kPoolClasses; c++)
+    if (mask & (1 << c)) G.grid[c] = P->cap[c];
   const void* book = pool_book_kernel();
   for (int h = 0; h < P->steps; h++) {
     const bool cstep = h == 0;
@@ -282,17 +279,14 @@ mf_status build_graph(mf_pool* P, int mask) {
       const bool d2 = P->depth == 2 && model == 0;
       if (odd && d2) continue;
       // every class's sweep carries the gap of its checking solves
-      const void* fs[1] = {d2 ? pool_kernel_d2(c, cstep) : pool_kernel(c, cstep, true)};
-      for (const void* f : fs) {
-        if (!f) continue;
-        int cls = c, step = h;
-        void* args[] = {&dev, &cls, &step};
-        hipGraphNode_t n;
-        const mf_status ms = add(f, grid_for(P->counts[c]), 256, args, n);
-        if (ms != MF_OK) return ms;
-        step_nodes.push_back(n);
-        P->nodes.push_back({n, f, c, 0, h});
-      }
+      const void* f = d2 ? pool_kernel_d2(c, cstep) : pool_kernel(c, cstep, true);
+      if (!f) continue;
+      int cls = c, step = h;
+      void* args[] = {&dev, &cls, &step};
+      hipGraphNode_t n;
+      const mf_status ms = add(f, G.grid[c], 256, args, n);
+      if (ms != MF_OK) return ms;
+      step_nodes.push_back(n);
     }
     if (!step_nodes.empty()) prev = step_nodes;
     if (cstep) {
@@ -301,7 +295,6 @@ mf_status build_graph(mf_pool* P, int mask) {
       hipGraphNode_t b;
       const mf_status ms = add(book, (unsigned)P->max_slots, 64, bargs, b);
       if (ms != MF_OK) return ms;
-      P->nodes.push_back({b, book, -1, 1, 0});
       prev.assign(1, b);
     }
   }
@@ -311,27 +304,45 @@ mf_status build_graph(mf_pool* P, int mask) {
     hipGraphNode_t b;
     const mf_status ms = add(book, (unsigned)P->max_slots, 64, bargs, b);
     if (ms != MF_OK) return ms;
-    P->nodes.push_back({b, book, -1, 1, 0});
   }
-  PHIP(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
-  P->graph_mask = mask;
-  P->node_counts = P->counts;
+  PHIP(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
   return MF_OK;
 }
 
-// Resize the class kernel nodes of the instantiated graph to the current
-// item counts (no re-instantiation).
-mf_status set_grids(mf_pool* P) {
-  if (P->node_counts == P->counts) return MF_OK;
-  PoolDev dev = P->dev;
-  for (auto& nd : P->nodes) {
-    if (nd.book) continue;
-    int cls = nd.cls, step = nd.step;
-    void* args[] = {&dev, &cls, &step};
-    hipKernelNodeParams kp = node_params(nd.func, grid_for(P->counts[nd.cls]), 256, args);
-    PHIP(hipGraphExecKernelNodeSetParams(P->exec, nd.node, &kp));
+// The graph for the running class set, with node grids at least the current
+// item counts: the cached one, else a new one (capacities grown first).
+mf_status graph_for(mf_pool* P, int mask, hipGraphExec_t& exec) {
+  for (int c = 0; c < kPoolClasses; c++) {
+    if (!(mask & (1 << c))) continue;
+    const unsigned need = grid_for(P->counts[c]);
+    if (P->cap[c] < need) P->cap[c] = std::max(need, 2 * P->cap[c]);
   }
-  P->node_counts = P->counts;
+  auto fits = [&](const mf_pool::Graph& G) {
+    for (int c = 0; c < kPoolClasses; c++)
+      if ((mask & (1 << c)) && G.grid[c] < grid_for(P->counts[c])) return false;
+    return true;
+  };
+  int found = -1;
+  for (size_t i = 0; i < P->graphs.size(); i++)
+    if (P->graphs[i].mask == mask) found = (int)i;
+  if (found >= 0 && fits(P->graphs[found])) {
+    exec = P->graphs[found].exec;
+    return MF_OK;
+  }
+  mf_pool::Graph G;
+  const mf_status ms = build_graph(P, mask, G);
+  if (ms != MF_OK) {
+    if (G.exec) hipGraphExecDestroy(G.exec);
+    if (G.graph) hipGraphDestroy(G.graph);
+    return ms;
+  }
+  if (found >= 0) {
+    P->retired.push_back(P->graphs[found]);
+    P->graphs[found] = G;
+  } else {
+    P->graphs.push_back(G);
+  }
+  exec = G.exec;
   return MF_OK;
 }
 
@@ -519,6 +530,7 @@ mf_status mf_pool_create(void* arena, size_t arena_bytes, int32_t max_slots, int
   P->lists.resize(kPoolClasses);
   for (auto& l : P->lists) l.reserve(1024);
   P->counts.assign(kPoolClasses, 0);
+  P->cap.assign(kPoolClasses, 8);
   std::vector<PoolSlot> zero(max_slots);
   std::memset(zero.data(), 0, zero.size() * sizeof(PoolSlot));
   std::vector<PoolStat> zs(max_slots);
@@ -601,12 +613,10 @@ mf_status mf_pool_admit(mf_pool* P, const mf_params* p, const float* cap, int64_
 
 mf_status mf_pool_advance(mf_pool* P) {
   if (!P) return pfail(MF_EINVAL, "null pool");
-  const int mask = class_mask(P);
-  mf_status ms = MF_OK;
-  if (!P->exec || mask != P->graph_mask) ms = build_graph(P, mask);
-  else ms = set_grids(P);
+  hipGraphExec_t exec = nullptr;
+  const mf_status ms = graph_for(P, class_mask(P), exec);
   if (ms != MF_OK) return ms;
-  PHIP(hipGraphLaunch(P->exec, P->stream));
+  PHIP(hipGraphLaunch(exec, P->stream));
   const int b = (int)(P->nadv & 1);
   PHIP(hipMemcpyAsync(P->snap[b], P->dev.stats, sizeof(PoolStat) * (size_t)P->max_slots, hipMemcpyDeviceToHost,
                       P->stream));
@@ -716,8 +726,11 @@ mf_status mf_pool_stats(mf_pool* P, int32_t* active, size_t* bytes_in_use, size_
 mf_status mf_pool_destroy(mf_pool* P) {
   if (!P) return MF_OK;
   if (P->stream) hipStreamSynchronize(P->stream);
-  if (P->exec) hipGraphExecDestroy(P->exec);
-  if (P->graph) hipGraphDestroy(P->graph);
+  for (auto* gs : {&P->graphs, &P->retired})
+    for (auto& G : *gs) {
+      if (G.exec) hipGraphExecDestroy(G.exec);
+      if (G.graph) hipGraphDestroy(G.graph);
+    }
   for (int i = 0; i < 2; i++) {
     if (P->snap[i]) hipHostFree(P->snap[i]);
     if (P->snap_ev[i]) hipEventDestroy(P->snap_ev[i]);
