@@ -17,7 +17,9 @@
 // device work lists: a graph is never edited, and graphs are destroyed only
 // with the pool.  A set whose graph was built with a smaller capacity than
 // a class now needs gets a new graph; the old one is kept until the pool is
-// destroyed.
+// destroyed.  Each graph is instantiated twice and the two are launched in
+// turn, each only after the status snapshot of its previous launch's advance
+// has arrived.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -163,7 +165,13 @@ struct mf_pool {
     int mask = 0;                  // classes the graph launches
     std::vector<unsigned> grid;    // per class: workgroups of its nodes
     hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // two instantiations used in turn, each relaunched only after the
+    // snapshot event of the advance that last launched it (recorded after
+    // that launch) has completed: no executable graph is launched while an
+    // earlier launch of it may still run
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    long long adv[2] = {-1, -1};   // advance that last launched exec[e]
+    int next = 0;
   };
   std::vector<Graph> graphs;       // one per class set in use (cached)
   std::vector<Graph> retired;      // superseded graphs, destroyed with the pool
@@ -305,13 +313,23 @@ mf_status build_graph(mf_pool* P, int mask, mf_pool::Graph& G) {
     const mf_status ms = add(book, (unsigned)P->max_slots, 64, bargs, b);
     if (ms != MF_OK) return ms;
   }
-  PHIP(hipGraphInstantiate(&G.exec, G.graph, nullptr, nullptr, 0));
+  for (int e = 0; e < 2; e++) PHIP(hipGraphInstantiate(&G.exec[e], G.graph, nullptr, nullptr, 0));
   return MF_OK;
 }
 
-// The graph for the running class set, with node grids at least the current
-// item counts: the cached one, else a new one (capacities grown first).
-mf_status graph_for(mf_pool* P, int mask, hipGraphExec_t& exec) {
+void destroy_graph(mf_pool::Graph& G) {
+  for (int e = 0; e < 2; e++) {
+    if (G.exec[e]) hipGraphExecDestroy(G.exec[e]);
+    G.exec[e] = nullptr;
+  }
+  if (G.graph) hipGraphDestroy(G.graph);
+  G.graph = nullptr;
+}
+
+// The graph for the running class set (its index in P->graphs), with node
+// grids at least the current item counts: the cached one, else a new one
+// (capacities grown first).
+mf_status graph_for(mf_pool* P, int mask, int& index) {
   for (int c = 0; c < kPoolClasses; c++) {
     if (!(mask & (1 << c))) continue;
     const unsigned need = grid_for(P->counts[c]);
@@ -326,23 +344,23 @@ mf_status graph_for(mf_pool* P, int mask, hipGraphExec_t& exec) {
   for (size_t i = 0; i < P->graphs.size(); i++)
     if (P->graphs[i].mask == mask) found = (int)i;
   if (found >= 0 && fits(P->graphs[found])) {
-    exec = P->graphs[found].exec;
+    index = found;
     return MF_OK;
   }
   mf_pool::Graph G;
   const mf_status ms = build_graph(P, mask, G);
   if (ms != MF_OK) {
-    if (G.exec) hipGraphExecDestroy(G.exec);
-    if (G.graph) hipGraphDestroy(G.graph);
+    destroy_graph(G);
     return ms;
   }
   if (found >= 0) {
     P->retired.push_back(P->graphs[found]);
     P->graphs[found] = G;
+    index = found;
   } else {
     P->graphs.push_back(G);
+    index = (int)P->graphs.size() - 1;
   }
-  exec = G.exec;
   return MF_OK;
 }
 
@@ -613,10 +631,17 @@ mf_status mf_pool_admit(mf_pool* P, const mf_params* p, const float* cap, int64_
 
 mf_status mf_pool_advance(mf_pool* P) {
   if (!P) return pfail(MF_EINVAL, "null pool");
-  hipGraphExec_t exec = nullptr;
-  const mf_status ms = graph_for(P, class_mask(P), exec);
+  int gi = -1;
+  const mf_status ms = graph_for(P, class_mask(P), gi);
   if (ms != MF_OK) return ms;
-  PHIP(hipGraphLaunch(exec, P->stream));
+  mf_pool::Graph& G = P->graphs[gi];
+  const int e = G.next;
+  // the snapshot event of that parity was last recorded at or after the
+  // advance that launched exec[e], and behind it on the stream
+  if (G.adv[e] >= 0) PHIP(hipEventSynchronize(P->snap_ev[G.adv[e] & 1]));
+  PHIP(hipGraphLaunch(G.exec[e], P->stream));
+  G.adv[e] = P->nadv;
+  G.next = e ^ 1;
   const int b = (int)(P->nadv & 1);
   PHIP(hipMemcpyAsync(P->snap[b], P->dev.stats, sizeof(PoolStat) * (size_t)P->max_slots, hipMemcpyDeviceToHost,
                       P->stream));
@@ -727,10 +752,7 @@ mf_status mf_pool_destroy(mf_pool* P) {
   if (!P) return MF_OK;
   if (P->stream) hipStreamSynchronize(P->stream);
   for (auto* gs : {&P->graphs, &P->retired})
-    for (auto& G : *gs) {
-      if (G.exec) hipGraphExecDestroy(G.exec);
-      if (G.graph) hipGraphDestroy(G.graph);
-    }
+    for (auto& G : *gs) destroy_graph(G);
   for (int i = 0; i < 2; i++) {
     if (P->snap[i]) hipHostFree(P->snap[i]);
     if (P->snap_ev[i]) hipEventDestroy(P->snap_ev[i]);
