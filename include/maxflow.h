@@ -122,7 +122,8 @@ typedef struct {
   int32_t tile_rows;     /* fused tile height (8, 16 or 32 rows of 64 columns; the fused
                             3-D sweep tiles 8 rows for 8 and 16 rows for 16 or 32);
                             0 -> 16, except 8 for BF16 Potts with n >= 8 and for the
-                            BF16 3-D sweep; maxflow_tune chooses per problem          */
+                            BF16 3-D sweep, and 32 for the fused Potts rPDRQ pass
+                            with one sweep; maxflow_tune chooses per problem          */
   /* Pool only, BF16 storage: a solve whose gap at a check is <= promote_gap,
    * or that reaches iteration promote_iter, is frozen at that iterate and
    * continued with FP32 flows (BF16 rounding floors the reachable gap near

@@ -136,10 +136,15 @@ const char* resolve(const mf_params* in, Resolved& r) {
   if (p.check_every == 0) p.check_every = 10;
   if (p.check_every < 1) return "check_every must be >= 1";
   // default tile height: 16 rows, except 8 for BF16 Potts with n >= 8 and
-  // for the BF16 3-D sweep (the measured fastest on gfx950 at 1024^2 and
-  // 256^3; maxflow_tune picks per problem)
-  if (p.tile_rows == 0)
-    p.tile_rows = (p.storage == MF_BF16 && ((!two && p.nlabels >= 8) || (two && p.ndim == 3))) ? 8 : 16;
+  // for the BF16 3-D sweep, and 32 for the fused Potts rPDRQ pass with one
+  // sweep (the measured fastest on gfx950 at 1024^2 and 256^3;
+  // maxflow_tune picks per problem)
+  if (p.tile_rows == 0) {
+    if (p.method == MF_RPDRQ)
+      p.tile_rows = (!two && p.ndim == 2 && p.gs_sweeps <= 1) ? 32 : 16;
+    else
+      p.tile_rows = (p.storage == MF_BF16 && ((!two && p.nlabels >= 8) || (two && p.ndim == 3))) ? 8 : 16;
+  }
   if (p.tile_rows != 8 && p.tile_rows != 16 && p.tile_rows != 32) return "tile_rows must be 8, 16 or 32";
   if (!(p.promote_gap >= 0.0) || p.promote_iter < 0) return "promote_gap and promote_iter must be >= 0";
   if (p.slab_depth != 0 && p.slab_depth < 4) return "slab_depth must be 0 or >= 4";

@@ -24,15 +24,22 @@
 
 namespace mf {
 
-// Occupancy: one 64 x 16 tile with one sweep keeps its LDS within a quarter
-// of a CU's 160 KiB, so four workgroups can share a CU if the registers
-// allow it; the kernel is latency bound (barrier-separated LDS phases), so
-// those instantiations are held to 128 VGPRs (four waves per SIMD).
-template <int TY, int NS>
-constexpr int dr_waves_per_eu() { return (TY == 16 && NS == 1) ? 4 : 1; }
+// Threads of a workgroup: 256 for 64 x 16 tiles, 512 for 64 x 32 (the
+// larger tile amortises each barrier-separated phase over twice the cells
+// and shrinks the halo from 1.41 to 1.25 times the tile).
+template <int TY>
+constexpr int dr_threads() { return TY == 32 ? 512 : 256; }
 
-template <typename TS, int TY, int NL, bool TWO, int NS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(dr_waves_per_eu<TY, NS>())))
+// Occupancy: a one-sweep tile of 64 x 16 (256 threads) or 64 x 32 (512)
+// keeps its LDS within a quarter or a half of a CU's 160 KiB, so four or
+// two workgroups can share a CU if the registers allow it; the kernel is
+// latency bound (barrier-separated LDS phases), so those instantiations are
+// held to 128 VGPRs (four waves per SIMD).
+template <int TY, int NS, int NT>
+constexpr int dr_waves_per_eu() { return (TY * 256 == 16 * NT && NS == 1) ? 4 : 1; }
+
+template <typename TS, int TY, int NL, bool TWO, int NS, int NT = dr_threads<TY>()>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(dr_waves_per_eu<TY, NS, NT>())))
 void k_dr_fused2d(const KDF<TS> A) {
   __shared__ SmemDR<TY, TWO, NS> S;
   if (A.done && *A.done) return;
@@ -40,8 +47,8 @@ void k_dr_fused2d(const KDF<TS> A) {
   strip_tile(xcd_tile(blockIdx.x, gridDim.x), A.tiles_x, (A.H + TY - 1) / TY, A.strip, tx, ty);
   const int x0 = tx * 64;
   const int y0 = ty * TY;
-  if (dr_interior<TY, NS>(x0, y0, A.W, A.H)) tile_dr2d<TS, TY, NL, TWO, false, NS>(A, x0, y0, S);
-  else tile_dr2d<TS, TY, NL, TWO, true, NS>(A, x0, y0, S);
+  if (dr_interior<TY, NS>(x0, y0, A.W, A.H)) tile_dr2d<TS, TY, NL, TWO, false, NS, NT>(A, x0, y0, S);
+  else tile_dr2d<TS, TY, NL, TWO, true, NS, NT>(A, x0, y0, S);
 }
 
 template <typename TS, int NL, bool TWO>
@@ -81,8 +88,8 @@ static hipError_t dr_fused_nl(const PdrqDesc& d, hipStream_t s) {
   switch (d.sweeps) {
     case 1:
       if (d.tile_rows == 32)
-        hipLaunchKernelGGL((k_dr_fused2d<TS, 32, NL, TWO, 1>), dim3(a.tiles_x * ((d.g.H + 31) / 32)), dim3(256), 0,
-                           s, a);
+        hipLaunchKernelGGL((k_dr_fused2d<TS, 32, NL, TWO, 1>), dim3(a.tiles_x * ((d.g.H + 31) / 32)),
+                           dim3(dr_threads<32>()), 0, s, a);
       else
         hipLaunchKernelGGL((k_dr_fused2d<TS, 16, NL, TWO, 1>), g16, dim3(256), 0, s, a);
       break;

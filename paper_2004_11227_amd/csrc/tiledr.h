@@ -103,13 +103,13 @@ __device__ __forceinline__ bool dr_interior(int x0, int y0, int W, int H) {
 // true and folds away; the arithmetic is unchanged.  NS: symmetric sweeps
 // per iteration (the preconditioner M_NS), 2 NS + 1 half-sweeps on regions
 // shrinking by one cell per side.
-template <typename TS, int TY, int NL, bool TWO, bool EDGE = true, int NS = 1>
+template <typename TS, int TY, int NL, bool TWO, bool EDGE = true, int NS = 1, int NT = 256>
 __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, SmemDR<TY, TWO, NS>& S) {
-  constexpr int TX = 64, V = 4, TPR = TX / V, RSTEP = 256 / TPR, RPT = TY / RSTEP;
+  constexpr int TX = 64, V = 4, TPR = TX / V, RSTEP = NT / TPR, RPT = TY / RSTEP;
   constexpr int OX = DrHalo<NS>::OX, OY = DrHalo<NS>::OY;
   constexpr int GPR = DrHalo<NS>::GPR;
   constexpr int NG = SmemDR<TY, TWO, NS>::SH * GPR;
-  constexpr int KG = (NG + 255) / 256;
+  constexpr int KG = (NG + NT - 1) / NT;
   static_assert(RPT >= 1, "tile height must be a multiple of 16");
   static_assert(!TWO || NL == 1, "the two-label model carries one label");
   static_assert(NS >= 1 && NS <= 4 && 2 * NS < TY, "1 to 4 sweeps; the halo stays inside one tile row");
@@ -133,7 +133,7 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
   int gnv[KG];
 #pragma unroll
   for (int m = 0; m < KG; m++) {
-    const int h = tid + 256 * m;
+    const int h = tid + NT * m;
     const int r = h / GPR - OY, c = (h % GPR) * 4 - OX;
     const int gy = y0 + r, gx = x0 + c;
     const int nv = (h < NG && gy >= 0 && gy < H && gx >= 0) ? (W - gx >= V ? V : (W - gx > 0 ? W - gx : 0)) : 0;
@@ -143,7 +143,7 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
   // write staged groups into an LDS array (entries outside the grid: 0; an
   // interior tile's staged rectangle lies inside the grid)
   auto put = [&](float (*dst)[SmemDR<TY, TWO, NS>::SW], int m, const float (&v)[V]) {
-    const int h = tid + 256 * m;
+    const int h = tid + NT * m;
     if (h < NG) {
       const int r = h / GPR, c = (h % GPR) * 4;
 #pragma unroll
@@ -223,13 +223,13 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
 #pragma unroll
     for (int e = 0; e < V; e++) usn[j][e] = 0.f;
   const float tau = A.tau, rho = A.rho;
-  // b region T+[-2NS,+2NS+1]: thread tid takes cells tid + 256 k, the same
+  // b region T+[-2NS,+2NS+1]: thread tid takes cells tid + NT k, the same
   // cells for every label, so the Potts label sum of u^k at those cells,
   // staged in sb, moves to registers before the first b overwrites it (a
   // seventh LDS array would leave room for only three workgroups per CU)
   constexpr int BW = TX + 4 * NS + 1;
   constexpr int BN = (TY + 4 * NS + 1) * BW;
-  constexpr int NB = (BN + 255) / 256;
+  constexpr int NB = (BN + NT - 1) / NT;
   float rsus[TWO ? 1 : NB];
 
   // Gauss-Seidel value of cell (r, c) from its neighbours in su and its b
@@ -253,7 +253,7 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
   auto half_sweep = [&](int rlo, int nr, int clo, int nc, int colour) {
     const int nch = (nc + 1) / 2;
     const int npr = (nr + 1) / 2;
-    for (int h = tid; h < 2 * npr * nch; h += 256) {
+    for (int h = tid; h < 2 * npr * nch; h += NT) {
       const int pr = h >> 1;
       const int r = rlo + 2 * (pr / nch) + (h & 1);
       const int c = clo + 2 * (pr % nch) + ((colour - r - clo) & 1);
@@ -292,7 +292,7 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
     // its own old u)
 #pragma unroll
     for (int k = 0; k < NB; k++) {
-      const int h = tid + 256 * k;
+      const int h = tid + NT * k;
       if (k == NB - 1 && h >= BN) continue;
       const int r = h / BW - 2 * NS, c = h % BW - 2 * NS;
       const int hx = x0 + c, hy = y0 + r;
