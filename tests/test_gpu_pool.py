@@ -267,3 +267,46 @@ def test_reused_slot_not_judged_by_older_snapshot():
     pool.close()
     assert [sid for sid, _ in reported] == [second]
     assert reported[0][1]["iter"] == 200 and reported[0][1]["status"] == 1
+
+
+def test_graphs_follow_growing_lists_and_changing_class_sets():
+    """Admissions in the middle of running solves: a class whose item count
+    passes its graph's grid (a 64^2 solve joined by a 1024x768 one: 4 -> 772
+    tiles), a new class joining and leaving (Potts n = 3), retirements in
+    between.  Every solve still equals the single-solve API bit for bit."""
+    banner("pool graphs: growing lists, changing class sets")
+    specs = [((64, 64), "two", 2, 0), ((1024, 768), "two", 2, 3), ((90, 97), "potts", 3, 5),
+             ((200, 130), "two", 2, 9), ((40, 300), "potts", 3, 14)]
+    items = []
+    for i, (shape, model, n, at) in enumerate(specs):
+        if model == "two":
+            caps = synth.two_label_caps(synth.ellipse_image(*shape, 5, 0.12, 700 + i))
+        else:
+            img, _ = synth.voronoi_image(*shape, n, 0.12, 700 + i, ncells=12)
+            caps = synth.potts_caps(img, n)
+        kw = dict(model=model, nlabels=n, method="eb", alpha=0.35, storage="f32", tol=1e-4, max_iter=300,
+                  check_every=10)
+        items.append((torch.from_numpy(caps.astype(np.float32)).cuda(), kw, at))
+    pool = mfx.Pool(1 << 30, max_slots=16, max_tiles=1 << 14, steps_per_advance=10)
+    sids, res, adv = {}, {}, 0
+    while len(res) < len(items):
+        for k, (t, kw, at) in enumerate(items):
+            if at == adv and k not in sids:
+                sids[k] = pool.admit(t, **kw)
+                assert sids[k] is not None
+        pool.advance()
+        adv += 1
+        for sid, g in pool.poll():
+            u, lab = pool.retire(sid)
+            res[sid] = (g, u.cpu().numpy(), lab.cpu().numpy())
+    pool.close()
+    for k, (t, kw, _) in enumerate(items):
+        g, u, lab = res[sids[k]]
+        s = mfx.Solver(t, **kw)
+        gs = s.solve()
+        us = s.u().cpu().numpy()
+        ls = s.labels().cpu().numpy()
+        s.close()
+        assert gs["iter"] == g["iter"] and gs["status"] == g["status"], (k, gs, g)
+        assert np.array_equal(us, u), k
+        assert np.array_equal(ls, lab), k
