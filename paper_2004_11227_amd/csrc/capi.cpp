@@ -196,7 +196,7 @@ const char* resolve(const mf_params* in, Resolved& r) {
   const bool padded = p.variant == MF_FUSED && !(p.ndim == 3 && p.model == MF_POTTS) &&
                       (p.method != MF_RPDRQ || (p.ndim == 2 && p.gs_sweeps <= fused_dr_sweeps(p.model)));
   r.g.pitch = padded ? (r.g.W + 3) / 4 * 4 : r.g.W;
-  r.g.plane = (long long)align_up((size_t)r.g.nstore(), 128);
+  r.g.plane = plane_stride(r.g.nstore(), r.g.ndim);
   r.esz = p.storage == MF_BF16 ? 2 : 4;
   r.nq = r.nl * p.ndim;
   return "";

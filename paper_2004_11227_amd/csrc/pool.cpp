@@ -82,8 +82,7 @@ std::string plan_solve(const mf_params* in, Footprint& f) {
   // rows padded to a multiple of 4 elements: every tile group is one vector access
   f.pitch = (f.g.W + 3) / 4 * 4;
   f.g.pitch = f.pitch;
-  f.g.plane = (long long)al((size_t)f.pitch * f.g.H * f.g.D * 4) / 4;
-  f.g.plane = (f.g.plane + 127) / 128 * 128;
+  f.g.plane = plane_stride((long long)f.pitch * f.g.H * f.g.D, f.g.ndim);
   const size_t P = (size_t)f.g.plane;
   f.cap_bytes = al((size_t)f.ncap * P * f.esz);
   f.state_bytes = al((size_t)f.nl * P * 4) + al((size_t)f.nl * f.g.ndim * P * f.esz) + al(P * f.esz) +

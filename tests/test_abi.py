@@ -37,7 +37,7 @@ def test_workspace_bytes_and_validation_without_gpu():
     from paper_2004_11227_amd import maxflow as mfx
     p = mfx.make_params((2048, 2048), model="two", method="eb")
     n = mfx.workspace_bytes(p)
-    plane = 2048 * 2048 * 4
+    plane = (2048 * 2048 + 2176) * 4     # 2-D planes are padded by 2176 elements
     # ctrl + 2 caps + 2 states of (u, qx, qy, ps, pt) planes
     assert 12 * plane <= n <= 12 * plane + 64 * 1024
     pb = mfx.make_params((2048, 2048), model="two", method="eb", storage="bf16")
@@ -65,8 +65,8 @@ def test_workspace_layout_reserves_every_region(shape):
 
     H, W = shape
     pitch = (W + 3) // 4 * 4
-    P = (pitch * H + 127) // 128 * 128          # plane of the padded layout (elements)
-    Pd = (W * H + 127) // 128 * 128              # plane of the dense layout
+    P = (pitch * H + 127) // 128 * 128 + 2176   # plane of the padded layout (elements; 2-D pad)
+    Pd = (W * H + 127) // 128 * 128 + 2176       # plane of the dense layout
 
     def al(b):
         return (b + 255) // 256 * 256
@@ -122,7 +122,7 @@ def test_image_capacities_validation_and_workspace():
         planes = mfx.workspace_bytes(mfx.make_params((256, 256), model=model, nlabels=n))
         image = mfx.workspace_bytes(mfx.make_params((256, 256), model=model, nlabels=n, cap_source="image",
                                                     levels=[0.1 * i for i in range(n)]))
-        assert planes - image == (n - 1) * 256 * 256 * 4
+        assert planes - image == (n - 1) * (256 * 256 + 2176) * 4     # padded 2-D planes
     with pytest.raises(mfx.MaxflowError):
         mfx.workspace_bytes(mfx.make_params((16, 16), cap_source="image", cap_power=3, levels=[0.2, 0.8]))
     with pytest.raises(mfx.MaxflowError):
