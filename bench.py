@@ -54,13 +54,15 @@ def alg_bytes(model: str, n: int, ndim: int, storage: str, image: bool = False) 
 
 
 SRC = "paper_2004_11227_amd/csrc/"
-# Sources of each gate kernel, and the counter profile whose traffic is
-# reported while the sources still hash to what was profiled.
+# Sources of each gate kernel (mf_kernels.h holds the workspace's plane
+# stride), and the counter profile whose traffic is reported while the
+# sources still hash to what was profiled.
 GATE_KERNELS = {
-    "two_label_3d_256": dict(sources=[SRC + "k3d.hip", SRC + "tile3d.h", SRC + "mf_device.h"],
+    "two_label_3d_256": dict(sources=[SRC + "k3d.hip", SRC + "tile3d.h", SRC + "mf_device.h", SRC + "mf_kernels.h"],
                              traffic="fused3d_two_label_256_traffic.json",
                              kernel="k_fused3d<float, false, 16, false> (one iteration per launch)"),
-    "two_label_2d_4096": dict(sources=[SRC + "k2d.hip", SRC + "tile2d.h", SRC + "tile2d_d2.h", SRC + "mf_device.h"],
+    "two_label_2d_4096": dict(sources=[SRC + "k2d.hip", SRC + "tile2d.h", SRC + "tile2d_d2.h", SRC + "mf_device.h",
+                                       SRC + "mf_kernels.h"],
                               traffic="fused2d_two_label_4096_depth1_traffic.json",
                               kernel="k_fused2d<1, true, float, false, 16, false> (one iteration per launch)"),
 }
