@@ -6,10 +6,11 @@
 //   1. stages q^k(s) (x, y, z components) and v(s) = (p_t - p_s) - u/c on
 //      the tile plus its xy halo, into ring slot s & 1;
 //   2. forms w(s) = div q^k(s) + v(s) (needs q_z^k(s-1), still in the other
-//      slot);
-//   3. forms q^{k+1}(s-1) = P_alpha(q^k(s-1) + grad w / a) in place (needs
-//      w(s-1) in-plane and w(s) for the z difference);
-//   4. for the owned pixels of plane s-1: d = div q^{k+1}(s-1) (the q_z of
+//      slot) and, on the same cells in the same LDS phase, q^{k+1}(s-1) =
+//      P_alpha(q^k(s-1) + grad w / a) in place (needs w(s-1) of the cell
+//      and its +x, +y neighbours, formed a step earlier, and the cell's own
+//      w(s) for the z difference);
+//   3. for the owned pixels of plane s-1: d = div q^{k+1}(s-1) (the q_z of
 //      plane s-2 is kept in registers), the pointwise p and u updates, and
 //      the stores.
 // Every plane is read from memory once per slab (plus the warm-up planes
@@ -59,6 +60,23 @@ struct K3 {
 __device__ __forceinline__ void proj3r(float& x, float& y, float& z, float alpha, int iso) {
   if (iso) proj3<true>(x, y, z, alpha);
   else proj3<false>(x, y, z, alpha);
+}
+
+// proj3r with selects in place of the isotropic case's branch: the same
+// operations on the same values (the scale is formed for every cell and
+// applied where |q| > alpha), so a loop over several cells stays one basic
+// block and its LDS reads can all be in flight together.
+__device__ __forceinline__ void proj3s(float& x, float& y, float& z, float alpha, int iso) {
+  if (iso) {
+    const float n2 = (x * x + y * y) + z * z;
+    const bool out = n2 > alpha * alpha;
+    const float sc = alpha * rsq(n2);
+    x = out ? x * sc : x;
+    y = out ? y * sc : y;
+    z = out ? z * sc : z;
+  } else {
+    proj3<false>(x, y, z, alpha);
+  }
 }
 
 template <bool SU, int TY = 8>
@@ -300,17 +318,9 @@ __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, 
         }
       }
     }
-    // ---- 2. w(s) = div q^k(s) + v(s) on rows -1..TY, cols -1..TX
-    for (int h = tid; h < (TY + 2) * (TX + 2); h += 256) {
-      const int r = h / (TX + 2) - 1, c = h % (TX + 2) - 1;
-      const int hx = x0 + c, hy = y0 + r;
-      const float d = div3(sqx[sl][r + 2][c + OX], sqx[sl][r + 2][c + OX - 1], sqy[sl][r + 2][c + OX],
-                           sqy[sl][r + 1][c + OX], sqz[sl][r + 2][c + OX], sqz[pl][r + 2][c + OX],
-                           hx + 1 < W, hx > 0, hy + 1 < H, hy > 0, s + 1 < D, s > 0);
-      sw[sl][r + 2][c + OX] = wterm(d, sw[sl][r + 2][c + OX]);
-    }
     // FP64 div q^k at the owned pixels of plane s, for the next step's gap
-    // (q_z^k(s-1) is still intact in the other slot until step 3)
+    // (step 2 overwrites q_z^k(s-1) in place: the gap variant waits until
+    // every thread has read it)
     if (CHECK) {
 #pragma unroll
       for (int e = 0; e < V; e++) {
@@ -319,25 +329,61 @@ __device__ __forceinline__ void tile3d(const K3<TS>& A, int x0, int y0, int z0, 
                   (((gy + 1 < H) ? (double)sqy[sl][r0 + 2][c] : 0.0) - ((gy > 0) ? (double)sqy[sl][r0 + 1][c] : 0.0)) +
                   (((s + 1 < D) ? (double)sqz[sl][r0 + 2][c] : 0.0) - ((s > 0) ? (double)sqz[pl][r0 + 2][c] : 0.0));
       }
+      lds_barrier();
     }
-    lds_barrier();
-    // ---- 3. q^{k+1}(s-1) in place, rows -1..TY-1, cols -1..TX-1
-    if (s - 1 >= z0 - 1) {
-      for (int h = tid; h < (TY + 1) * (TX + 1); h += 256) {
-        const int r = h / (TX + 1) - 1, c = h % (TX + 1) - 1;
+    // ---- 2. w(s) = div q^k(s) + v(s) on rows -1..TY, cols -1..TX, and, on
+    // the same cells where they lie in rows -1..TY-1, cols -1..TX-1,
+    // q^{k+1}(s-1) = P_alpha(q^k(s-1) + grad w / a) in place.  A cell's q
+    // step needs w(s-1) of its +x and +y neighbours (the previous step's,
+    // complete) and its own w(s), which the same thread has just formed, so
+    // the two need no barrier between them.  Each thread takes cells
+    // tid + 256 k; all its reads come before its writes (a cell reads no
+    // other cell's w(s) or q^k(s-1)), so the LDS reads of all its cells are
+    // in flight together; the last, partial round recomputes a valid cell in
+    // its idle threads and stores nothing.
+    {
+      constexpr int NC = (TY + 2) * (TX + 2), KC = (NC + 255) / 256;
+      const bool qon = s - 1 >= z0 - 1;
+      float wv[KC], qxv[KC], qyv[KC], qzv[KC];
+#pragma unroll
+      for (int kk = 0; kk < KC; kk++) {
+        int h = tid + 256 * kk;
+        if (kk == KC - 1) h = h < NC ? h : NC - 1;
+        const int r = h / (TX + 2) - 1, c = h % (TX + 2) - 1;
         const int hx = x0 + c, hy = y0 + r;
-        const float w0 = sw[pl][r + 2][c + OX];
-        float qx = qstep(sqx[pl][r + 2][c + OX], sw[pl][r + 2][c + OX + 1], w0, hx + 1 < W, k.inv_a);
-        float qy = qstep(sqy[pl][r + 2][c + OX], sw[pl][r + 3][c + OX], w0, hy + 1 < H, k.inv_a);
-        float qz = qstep(sqz[pl][r + 2][c + OX], sw[sl][r + 2][c + OX], w0, s < D, k.inv_a);
-        proj3r(qx, qy, qz, k.alpha, A.iso);
-        sqx[pl][r + 2][c + OX] = quant3<TS>(qx);
-        sqy[pl][r + 2][c + OX] = quant3<TS>(qy);
-        sqz[pl][r + 2][c + OX] = quant3<TS>(qz);
+        const float d = div3(sqx[sl][r + 2][c + OX], sqx[sl][r + 2][c + OX - 1], sqy[sl][r + 2][c + OX],
+                             sqy[sl][r + 1][c + OX], sqz[sl][r + 2][c + OX], sqz[pl][r + 2][c + OX],
+                             hx + 1 < W, hx > 0, hy + 1 < H, hy > 0, s + 1 < D, s > 0);
+        const float wn = wterm(d, sw[sl][r + 2][c + OX]);
+        wv[kk] = wn;
+        // cells in row TY or column TX have no q step: they form a copy at
+        // an in-range cell, which is not stored
+        const int rq = r < TY ? r : TY - 1, cq = c < TX ? c : TX - 1;
+        const float w0 = sw[pl][rq + 2][cq + OX];
+        float qx = qstep(sqx[pl][rq + 2][cq + OX], sw[pl][rq + 2][cq + OX + 1], w0, x0 + cq + 1 < W, k.inv_a);
+        float qy = qstep(sqy[pl][rq + 2][cq + OX], sw[pl][rq + 3][cq + OX], w0, y0 + rq + 1 < H, k.inv_a);
+        float qz = qstep(sqz[pl][rq + 2][cq + OX], wn, w0, s < D, k.inv_a);
+        proj3s(qx, qy, qz, k.alpha, A.iso);
+        qxv[kk] = quant3<TS>(qx);
+        qyv[kk] = quant3<TS>(qy);
+        qzv[kk] = quant3<TS>(qz);
+      }
+#pragma unroll
+      for (int kk = 0; kk < KC; kk++) {
+        const int h = tid + 256 * kk;
+        if (kk < KC - 1 || h < NC) {
+          const int r = h / (TX + 2) - 1, c = h % (TX + 2) - 1;
+          sw[sl][r + 2][c + OX] = wv[kk];
+          if (qon && r < TY && c < TX) {
+            sqx[pl][r + 2][c + OX] = qxv[kk];
+            sqy[pl][r + 2][c + OX] = qyv[kk];
+            sqz[pl][r + 2][c + OX] = qzv[kk];
+          }
+        }
       }
     }
     lds_barrier();
-    // ---- 4. owned pixels of plane s-1: divergence, updates, stores
+    // ---- 3. owned pixels of plane s-1: divergence, updates, stores
     if (s - 1 >= z0 && s - 1 < z1) {
       const int zz = s - 1;
       const int nv = nvxy;
