@@ -137,8 +137,9 @@ typedef struct {
    * iteration counts finish with one depth-1 sweep. */
   int32_t depth;
   /* Fused 3-D sweep: planes per z-slab of a workgroup (each slab re-reads
-   * 3 warm-up planes).  0 -> 16 (capped at D); otherwise >= 4.  Never
-   * changes the iterates. */
+   * 3 warm-up planes).  0 -> the deepest of 16 and 8 planes that gives the
+   * launch at least 2048 workgroups, else 4 (capped at D); otherwise >= 4.
+   * Never changes the iterates. */
   int32_t slab_depth;
   /* Preconditioner variants (section on rPDRQ; EB scheme's relaxation).
    * gs_sweeps: symmetric red-black Gauss-Seidel sweeps per rPDRQ iteration,

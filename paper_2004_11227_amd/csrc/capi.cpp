@@ -835,7 +835,7 @@ mf_status maxflow_tune(mf_solver* s, int32_t sweeps, int32_t what, mf_tuning* ou
   // the candidate list: the free knobs range over their values, the others
   // keep the solver's
   std::vector<mf_tune_cand> cand;
-  const std::vector<int> rows_all = {8, 16, 32}, depth_all = {1, 2}, slab_all = {8, 16, 32};
+  const std::vector<int> rows_all = {8, 16, 32}, depth_all = {1, 2}, slab_all = {4, 8, 16, 32};
   const std::vector<int> rows_l = (what & MF_TUNE_TILE) ? rows_all : std::vector<int>{p.tile_rows};
   const std::vector<int> depth_l = (what & MF_TUNE_DEPTH) ? depth_all : std::vector<int>{p.depth};
   int shape_kind = 0;   // 0: no launch-shape choice

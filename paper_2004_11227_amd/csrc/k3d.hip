@@ -34,12 +34,27 @@ static hipError_t fused3d_ty(const SweepDesc& d, hipStream_t s) {
   a.SZ = (long long)d.g.pitch * d.g.H;
   a.tiles_x = (d.g.W + 63) / 64;
   a.tiles_y = (d.g.H + TY - 1) / TY;
-  // Slab depth: each slab re-reads 3 warm-up planes; 16 planes measured
-  // fastest at 256^3, 128 x 512^2 and 512 x 128 x 256 (slab counts that are
-  // multiples of the 8 XCDs keep each XCD's run of workgroups on whole
-  // slabs, so xy neighbours share its L2).  slab_depth overrides it.
+  // Slab depth: each slab re-reads 3 warm-up planes, but a launch needs
+  // enough workgroups to keep every CU busy to the end: the deepest of 16
+  // and 8 planes that still gives at least 2048 workgroups (8 per CU), else
+  // 4.  Measured (FP32, µs per sweep, slabs of 4 / 8 / 16 planes): 256^3
+  // 205.9 / 194.1 / 196.5; 128^3 31.6 / 33.8 / 52.9; 128 x 512^2 452.6 /
+  // 406.5 / 390.3; 64 x 1024^2 924 / 836 / 797; 200 x 300 x 260 255.8 /
+  // 264.6 / 279.7; the rule's choice is the fastest or within 3% of it, for
+  // BF16 (8-row tiles) as well.  Depths that give a slab count off a
+  // multiple of the 8 XCDs are slower (256^3: 12 planes 210.9, 20 planes
+  // 231.3), as each XCD's run of workgroups then splits slabs.  slab_depth
+  // overrides the rule.
   const long long nxy = (long long)a.tiles_x * a.tiles_y;
-  int tz = d.slab_depth > 0 ? d.slab_depth : 16;
+  int tz = d.slab_depth;
+  if (tz <= 0) {
+    tz = 4;
+    for (int c = 16; c >= 8; c /= 2)
+      if (nxy * ((d.g.D + c - 1) / c) >= 2048) {
+        tz = c;
+        break;
+      }
+  }
   if (tz > d.g.D) tz = d.g.D;
   a.tz = tz;
   a.cap = (const TS*)d.cap;

@@ -405,7 +405,7 @@ def test_autotune_keeps_state_and_caches(tmp_path, monkeypatch):
     v.step(3)
     before = gpu_fields(v)
     best, cands = v.tune(sweeps=3)
-    assert {(c["tile_rows"], c["slab_depth"]) for c in cands} == {(r, z) for r in (8, 16) for z in (8, 16, 32)}
+    assert {(c["tile_rows"], c["slab_depth"]) for c in cands} == {(r, z) for r in (8, 16) for z in (4, 8, 16, 32)}
     assert v.iter == 3 and best["slab_depth"] == v.params.slab_depth
     # with the slab depth given, only the tile height is free
     _, c2 = v.tune(sweeps=2, what=mfx.MF_TUNE_TILE)
