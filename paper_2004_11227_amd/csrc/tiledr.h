@@ -171,7 +171,13 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
   };
   auto cap_val = [&](float raw, int lv) { return img ? cap_from(raw, A.cg.lv[lv], A.cg.pw) : raw; };
   // u, q-bar, p-bar of one label on the staged groups and its capacities on
-  // the owned groups, fetched into registers one label ahead of their use
+  // the owned groups, fetched into registers one label ahead of their use.
+  // Potts loads p-bar when the label is staged instead, except BF16 with
+  // n >= 4: a label ahead it spills registers under the four-waves-per-SIMD
+  // limit and runs slower (FP32 n = 4 1024^2 38.2 -> 40.0 us, BF16 n = 2
+  // 21.7 -> 24.3 us), but BF16 n = 4 and 8 gain (37.2 -> 36.2, 69.8 ->
+  // 68.0 us).
+  constexpr bool PF_PB = TWO || (sizeof(TS) == 2 && NL >= 4);
   float nu[KG][V], nqx[KG][V], nqy[KG][V], npt[KG][V], ncl[RPT][V];
   auto fetch = [&](int l) {
     const float* u_in = A.u_in + (long long)l * P;
@@ -182,7 +188,7 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
       ldv<V>(u_in, gi[m], nu[m]);
       ldv<V>(qx_in, gi[m], nqx[m]);
       ldv<V>(qx_in + P, gi[m], nqy[m]);
-      if (TWO) ldv<V>(pb_in, gi[m], npt[m]);
+      if (PF_PB) ldv<V>(pb_in, gi[m], npt[m]);
     }
     load_cap(TWO ? 1 : l, ncl);
   };
@@ -265,9 +271,9 @@ __device__ __forceinline__ void tile_dr2d(const KDF<TS>& A, int x0, int y0, Smem
   for (int l = 0; l < NL; l++) {
     // ---- stage u, q-bar, p-bar of label l on the staged rectangle, then
     // start the loads of label l+1
-    // (Potts: p-bar of the label is loaded here, not a label ahead, which
-    // keeps the registers within four waves per SIMD)
-    if constexpr (!TWO) {
+    // (Potts other than BF16 n >= 4: p-bar of the label is loaded here, not
+    // a label ahead, which keeps the registers within four waves per SIMD)
+    if constexpr (!PF_PB) {
 #pragma unroll
       for (int m = 0; m < KG; m++) ldv<V>(A.pb_in + (long long)l * P, gi[m], npt[m]);
     }
