@@ -54,6 +54,21 @@ __device__ __forceinline__ void proj(float& x, float& y, float alpha, int iso) {
   else proj2<false>(x, y, alpha);
 }
 
+// proj with selects in place of the isotropic case's branch (the same
+// operations on the same values), so a loop over several cells stays one
+// basic block.
+__device__ __forceinline__ void projs(float& x, float& y, float alpha, int iso) {
+  if (iso) {
+    const float n2 = x * x + y * y;
+    const bool out = n2 > alpha * alpha;
+    const float sc = alpha * rsq(n2);
+    x = out ? x * sc : x;
+    y = out ? y * sc : y;
+  } else {
+    proj2<false>(x, y, alpha);
+  }
+}
+
 // FP64 gap terms of the two-label model at one pixel:
 // data (1-u)C_s + u C_t and TV at u = clip(u,0,1), dual min(C_s, C_t + div q),
 // residual p_t - p_s + div q, flow p_s.
@@ -126,6 +141,12 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
   constexpr int NHQ = 3 * (TX + 3) + 3 * TY;   // q halo: rows {-2,-1,TY} x cols -2..TX, cols {-2,-1,TX} x rows 0..TY-1
   constexpr int NHW = 2 * (TX + 2) + 2 * TY;   // v halo: rows {-1,TY} x cols -1..TX, cols {-1,TX} x rows 0..TY-1
   constexpr int KQ = (NHQ + 255) / 256, KW = (NHW + 255) / 256;
+  // Potts with n = 8, and n = 3 on 16- and 32-row tiles, forms each
+  // phase's cells in a batch (see the w and q phases below): n = 8 1024^2
+  // FP32 67.3 -> 65.8 us, BF16 41.3 -> 39.3 us, n = 3 2% faster.  Elsewhere
+  // the batch's registers cost a wave per SIMD (FP32 n = 4: 11% slower) or
+  // gain nothing (two labels, n = 2).
+  constexpr bool BATCH = !TWO && (NL == 8 || (NL == 3 && TY >= 16));
   auto& sqx = S.sqx;
   auto& sqy = S.sqy;
   auto& sw = S.sw;
@@ -368,27 +389,84 @@ __device__ __forceinline__ void tile2d(const K2<TS>& A, int x0, int y0, Smem2<TY
         }
       }
     }
-    // ---- w = div q^k + v on rows -1..TY, cols -1..TX
-    for (int h = tid; h < (TY + 2) * (TX + 2); h += 256) {
-      const int r = h / (TX + 2) - 1, c = h % (TX + 2) - 1;
-      const int hx = x0 + c, hy = y0 + r;
-      const float d = div2(sqx[r + 2][c + OX], sqx[r + 2][c + OX - 1], sqy[r + 2][c + OX],
-                           sqy[r + 1][c + OX], xp(hx), xm(hx), yp(hy), ym(hy));
-      sw[r + 2][c + OX] = wterm(d, sw[r + 2][c + OX]);
+    if constexpr (BATCH) {
+      // ---- w = div q^k + v on rows -1..TY, cols -1..TX; then q^{k+1} =
+      // P_alpha(q^k + grad(w)/a) on rows -1..TY-1, cols -1..TX-1 in place.
+      // Each thread takes cells tid + 256 k and forms all of them before
+      // writing any (a cell reads no other cell's output of the same
+      // phase), so their LDS reads are in flight together; the last,
+      // partial round forms a copy of the last cell in its idle threads and
+      // stores nothing.
+      {
+        constexpr int NC = (TY + 2) * (TX + 2), KC = (NC + 255) / 256;
+        float wv[KC];
+#pragma unroll
+        for (int kk = 0; kk < KC; kk++) {
+          int h = tid + 256 * kk;
+          if (kk == KC - 1) h = h < NC ? h : NC - 1;
+          const int r = h / (TX + 2) - 1, c = h % (TX + 2) - 1;
+          const int hx = x0 + c, hy = y0 + r;
+          const float d = div2(sqx[r + 2][c + OX], sqx[r + 2][c + OX - 1], sqy[r + 2][c + OX],
+                               sqy[r + 1][c + OX], xp(hx), xm(hx), yp(hy), ym(hy));
+          wv[kk] = wterm(d, sw[r + 2][c + OX]);
+        }
+#pragma unroll
+        for (int kk = 0; kk < KC; kk++) {
+          const int h = tid + 256 * kk;
+          if (kk < KC - 1 || h < NC) sw[h / (TX + 2) + 1][h % (TX + 2) - 1 + OX] = wv[kk];
+        }
+      }
+      lds_barrier();
+      {
+        constexpr int NC = (TY + 1) * (TX + 1), KC = (NC + 255) / 256;
+        float qxv[KC], qyv[KC];
+#pragma unroll
+        for (int kk = 0; kk < KC; kk++) {
+          int h = tid + 256 * kk;
+          if (kk == KC - 1) h = h < NC ? h : NC - 1;
+          const int r = h / (TX + 1) - 1, c = h % (TX + 1) - 1;
+          const int hx = x0 + c, hy = y0 + r;
+          const float w0 = sw[r + 2][c + OX];
+          float qx = qstep(sqx[r + 2][c + OX], sw[r + 2][c + OX + 1], w0, xp(hx), k.inv_a);
+          float qy = qstep(sqy[r + 2][c + OX], sw[r + 3][c + OX], w0, yp(hy), k.inv_a);
+          projs(qx, qy, k.alpha, A.iso);
+          qxv[kk] = quant<TS>(qx);
+          qyv[kk] = quant<TS>(qy);
+        }
+#pragma unroll
+        for (int kk = 0; kk < KC; kk++) {
+          const int h = tid + 256 * kk;
+          if (kk < KC - 1 || h < NC) {
+            const int r = h / (TX + 1) - 1, c = h % (TX + 1) - 1;
+            sqx[r + 2][c + OX] = qxv[kk];
+            sqy[r + 2][c + OX] = qyv[kk];
+          }
+        }
+      }
+      lds_barrier();
+    } else {
+      // ---- w = div q^k + v on rows -1..TY, cols -1..TX
+      for (int h = tid; h < (TY + 2) * (TX + 2); h += 256) {
+        const int r = h / (TX + 2) - 1, c = h % (TX + 2) - 1;
+        const int hx = x0 + c, hy = y0 + r;
+        const float d = div2(sqx[r + 2][c + OX], sqx[r + 2][c + OX - 1], sqy[r + 2][c + OX],
+                             sqy[r + 1][c + OX], xp(hx), xm(hx), yp(hy), ym(hy));
+        sw[r + 2][c + OX] = wterm(d, sw[r + 2][c + OX]);
+      }
+      lds_barrier();
+      // ---- q^{k+1} = P_alpha(q^k + grad(w)/a) on rows -1..TY-1, cols -1..TX-1 (in place)
+      for (int h = tid; h < (TY + 1) * (TX + 1); h += 256) {
+        const int r = h / (TX + 1) - 1, c = h % (TX + 1) - 1;
+        const int hx = x0 + c, hy = y0 + r;
+        const float w0 = sw[r + 2][c + OX];
+        float qx = qstep(sqx[r + 2][c + OX], sw[r + 2][c + OX + 1], w0, xp(hx), k.inv_a);
+        float qy = qstep(sqy[r + 2][c + OX], sw[r + 3][c + OX], w0, yp(hy), k.inv_a);
+        proj(qx, qy, k.alpha, A.iso);
+        sqx[r + 2][c + OX] = quant<TS>(qx);
+        sqy[r + 2][c + OX] = quant<TS>(qy);
+      }
+      lds_barrier();
     }
-    lds_barrier();
-    // ---- q^{k+1} = P_alpha(q^k + grad(w)/a) on rows -1..TY-1, cols -1..TX-1 (in place)
-    for (int h = tid; h < (TY + 1) * (TX + 1); h += 256) {
-      const int r = h / (TX + 1) - 1, c = h % (TX + 1) - 1;
-      const int hx = x0 + c, hy = y0 + r;
-      const float w0 = sw[r + 2][c + OX];
-      float qx = qstep(sqx[r + 2][c + OX], sw[r + 2][c + OX + 1], w0, xp(hx), k.inv_a);
-      float qy = qstep(sqy[r + 2][c + OX], sw[r + 3][c + OX], w0, yp(hy), k.inv_a);
-      proj(qx, qy, k.alpha, A.iso);
-      sqx[r + 2][c + OX] = quant<TS>(qx);
-      sqy[r + 2][c + OX] = quant<TS>(qy);
-    }
-    lds_barrier();
     // ---- owned groups: d = div q^{k+1}, store q^{k+1}, per-label p and u parts
     {
       TS* qx_out = A.q_out + (long long)(2 * l) * P;
