@@ -3,8 +3,11 @@
 
 namespace mf {
 
+// The gap-carrying 8-row sweep is held to 128 VGPRs (four workgroups per
+// CU, as its LDS allows), which it meets without spills.
 template <typename TS, bool CHECK, int TY, bool IMG>
-__global__ __launch_bounds__(256) void k_fused3d(const K3<TS> A) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CHECK && TY == 8 ? 4 : 1)))
+void k_fused3d(const K3<TS> A) {
   __shared__ Smem3<CHECK, TY> S;
   if (A.done && *A.done) return;
   const int nxy = A.tiles_x * A.tiles_y;
