@@ -1,8 +1,9 @@
 // Pool kernels: one launch per class walks that class's work list of
-// (solve, tile) items drawn from many grids of different sizes (one item per
-// workgroup when the grid is sized to the list, grid-stride otherwise), and
-// advances every running solve by one iteration; the bookkeeping launch then
-// takes each solve's gap decision and advances its counter.  The tile bodies
+// (solve, tile) items drawn from many grids of different sizes, one item per
+// workgroup, and advances every running solve by one iteration; two
+// bookkeeping launches per advance take the solves' gap decisions (after the
+// first step, whose sweeps carry the gaps) and move their counters on (after
+// the last).  The tile bodies
 // are the same device functions as the single-solve kernels, so a solve
 // produces the same bits in the pool, alone or in any mix, and through the
 // single-solve API with the same tile shape.
@@ -18,10 +19,12 @@ namespace mf {
 // Work item of this workgroup, or -1.  The list is cut into 8 contiguous
 // chunks and the workgroups dispatched to one XCD (block b runs on XCD b & 7)
 // take the items of one chunk, so neighbouring tiles of a grid share that
-// XCD's L2.  The host sizes the grid to 8 * ceil(n / 8) workgroups, one item
-// each: a loop over several items per workgroup doubles the register
-// footprint of the tile bodies (the compiler keeps the next item's state
-// live) and costs occupancy.
+// XCD's L2.  The launch's grid is a capacity of at least 8 * ceil(n / 8)
+// workgroups that only grows (the pool's graphs are cached per class set);
+// workgroups past the items return at once.  One item per workgroup: a loop
+// over several items per workgroup doubles the register footprint of the
+// tile bodies (the compiler keeps the next item's state live) and costs
+// occupancy.
 __device__ __forceinline__ int xcd_item(int n) {
   const int b = blockIdx.x, x = b & 7;
   const int it = (int)((long long)n * x / 8) + (b >> 3);
