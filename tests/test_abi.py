@@ -82,6 +82,30 @@ def test_workspace_layout_reserves_every_region(shape):
         (al(8 * Pd) - al(8 * P)) + 2 * (state_dense - state_pad) + al(4 * Pd)
 
 
+@pytest.mark.parametrize("shape", [(256, 256, 256), (40, 48, 70)])
+def test_workspace_layout_3d(shape):
+    """3-D fused two-label workspace: control block, 2 capacity planes and
+    two state buffers of (u, q_x, q_y, q_z, p_s, p_t), each plane padded to
+    128 elements plus 128 (the 3-D plane pad), rows to 4 elements."""
+    if not os.path.exists(LIB):
+        pytest.skip("libmaxflow.so not built")
+    from paper_2004_11227_amd import maxflow as mfx
+    D, H, W = shape
+    pitch = (W + 3) // 4 * 4
+    P = (pitch * H * D + 127) // 128 * 128 + 128
+
+    def al(b):
+        return (b + 255) // 256 * 256
+
+    state = al(4 * P) + al(12 * P) + al(4 * P) + al(4 * P)
+    caps = al(8 * P)
+    n = mfx.workspace_bytes(mfx.make_params(shape, model="two", method="eb"))
+    assert 0 <= n - (caps + 2 * state) <= 64 * 1024      # the control block
+    bf = mfx.workspace_bytes(mfx.make_params(shape, model="two", method="eb", storage="bf16"))
+    state_bf = al(4 * P) + al(6 * P) + al(2 * P) + al(2 * P)
+    assert bf - (al(4 * P) + 2 * state_bf) == n - (caps + 2 * state)
+
+
 @pytest.mark.parametrize("bad", [dict(method="eb", gs_sweeps=2), dict(method="dr", gs_sweeps=65),
                                  dict(method="fg", relax0=0.5, relax_ramp=5),
                                  dict(method="eb", relax=1.5, relax0=1.6, relax_ramp=5),
