@@ -538,7 +538,14 @@ mf_status solve_loop(mf_solver* s, mf_gap* out, bool sync_poll) {
   // (chunk & 7) and an event marks the copy.  (No kernel of this library
   // stores into host memory: only the runtime's copies write there.)
   int issued = 0, observed = 0;
-  const int lookahead = 3;
+  // Unobserved chunks kept queued: enough to cover the host's turnaround
+  // between a chunk's end and its successor's launches, and no more, since
+  // every sweep queued past the stop still dispatches its grid (to exit at
+  // once, ~10 us for a 256^3 sweep).  A chunk's length is estimated from
+  // its state traffic (one state read and write per iteration, ~5 TB/s):
+  // one chunk ahead from ~0.5 ms per chunk, two from ~0.15 ms, else three.
+  const double chunk_us = (double)ce * 2.0 * (double)s->L.state_bytes / 5.0e6;
+  const int lookahead = chunk_us >= 500.0 ? 1 : (chunk_us >= 150.0 ? 2 : 3);
   bool stop = false;
   while (!stop) {
     // ---- gap of iterate k and the decision
