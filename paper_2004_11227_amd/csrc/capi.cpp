@@ -534,18 +534,21 @@ mf_status solve_loop(mf_solver* s, mf_gap* out, bool sync_poll) {
   int64_t k = s->iter;
   const bool d2 = p.depth == 2;
   OffRing off_at;
-  // polling ring: after each chunk, `done` is copied into pinned slot
-  // (chunk & 7) and an event marks the copy.  (No kernel of this library
-  // stores into host memory: only the runtime's copies write there.)
+  // polling ring: the decision of each chunk's check sits in pinned slot
+  // (chunk & 7), its copy marked by an event
   int issued = 0, observed = 0;
-  // Unobserved chunks kept queued: enough to cover the host's turnaround
-  // between a chunk's end and its successor's launches, and no more, since
-  // every sweep queued past the stop still dispatches its grid (to exit at
-  // once, ~10 us for a 256^3 sweep).  A chunk's length is estimated from
-  // its state traffic (one state read and write per iteration, ~5 TB/s):
-  // one chunk ahead from ~0.5 ms per chunk, two from ~0.15 ms, else three.
+  // Each chunk's decision is copied out right after its gap-carrying sweep,
+  // ahead of the chunk's other sweeps.  Unobserved decisions kept in
+  // flight: enough that the GPU still has queued work while the host turns
+  // around to launch the next chunk, and no more, since every sweep queued
+  // past the stop still dispatches its grid (to exit at once, ~10 us for a
+  // 256^3 sweep).  A chunk's length is estimated from its state traffic (one
+  // state read and write per iteration, ~5 TB/s): from ~0.2 ms per chunk the
+  // host waits for the current chunk's decision while the GPU runs the
+  // chunk's other sweeps; from ~60 us it keeps one decision more in flight,
+  // below that three.
   const double chunk_us = (double)ce * 2.0 * (double)s->L.state_bytes / 5.0e6;
-  const int lookahead = chunk_us >= 500.0 ? 1 : (chunk_us >= 150.0 ? 2 : 3);
+  const int lookahead = chunk_us >= 200.0 ? 0 : (chunk_us >= 60.0 ? 1 : 3);
   bool stop = false;
   while (!stop) {
     // ---- gap of iterate k and the decision
@@ -568,6 +571,15 @@ mf_status solve_loop(mf_solver* s, mf_gap* out, bool sync_poll) {
     }
     HIP_TRY(launch_bookkeep(s->ctrl, k, p.alpha, p.tol, neg_tol(s), nres(s), final_check ? 1 : 0, 1, s->stream));
     if (final_check) break;
+    issued++;
+    if (!sync_poll) {
+      // the decision at k, copied into pinned slot (chunk & 7) and marked by
+      // an event (no kernel of this library stores into host memory: only
+      // the runtime's copies write there)
+      const int slot = (issued - 1) & 7;
+      HIP_TRY(hipMemcpyAsync(s->host_done + slot, done, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+      HIP_TRY(hipEventRecord(s->ev[slot], s->stream));
+    }
     // ---- the rest of the chunk
     if (dr) {
       for (int64_t i = 0; i < n; i++) HIP_TRY(dr_iter(s, k + i, i == n - 1, done));
@@ -583,7 +595,6 @@ mf_status solve_loop(mf_solver* s, mf_gap* out, bool sync_poll) {
       }
     }
     k += n;
-    issued++;
     if (sync_poll) {
       if (issued % kSyncPollChunks == 0) {
         int flag = 0;
@@ -593,10 +604,7 @@ mf_status solve_loop(mf_solver* s, mf_gap* out, bool sync_poll) {
       }
       continue;
     }
-    // ---- poll the decision without stalling the queue
-    const int slot = (issued - 1) & 7;
-    HIP_TRY(hipMemcpyAsync(s->host_done + slot, done, sizeof(int), hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipEventRecord(s->ev[slot], s->stream));
+    // ---- follow the decisions without stalling the queue
     while (observed < issued) {
       const int os = observed & 7;
       const hipError_t q =
