@@ -298,6 +298,7 @@ struct mf_solver {
   int* host_done;   // pinned polling slots
   hipEvent_t ev[8];
   int dev;
+  bool fresh;       // the state is the initial point as init_state stored it
 };
 
 namespace {
@@ -474,6 +475,7 @@ mf_status init_state(mf_solver* s) {
   HIP_TRY(launch_ctrl_reset(s->ctrl, s->stream));
   s->iter = 0;
   s->off = 0;
+  s->fresh = true;
   return MF_OK;
 }
 
@@ -554,10 +556,21 @@ mf_status solve_loop(mf_solver* s, mf_gap* out, bool sync_poll) {
     // ---- gap of iterate k and the decision
     const bool final_check = k >= max_iter;
     const int64_t n = final_check ? 0 : std::min<int64_t>(ce, max_iter - k);
+    // the solve's first check on the initial point of a two-label rpADMM
+    // solve with capacity planes runs pointwise (see k_first_two): 256^3
+    // solve 4.30 -> 4.22 ms.  Not with depth-2 passes, where it would replace
+    // a two-iteration pass and add a launch (2048^2 0.572 -> 0.583 ms).
+    const bool first = k == 0 && s->fresh && p.model == MF_TWO_LABEL && p.variant == MF_FUSED &&
+                       (p.method == MF_RPADMM_FG || p.method == MF_RPADMM_EB) && !s->r.cg.img && !d2;
+    s->fresh = false;
     off_at.push(k, s->off);
     int64_t j = 1;   // iterations of the chunk issued with the check
     if (dr) {
       HIP_TRY(gap_of(s, k, done));
+    } else if (first && !final_check) {
+      // the first iteration from the initial point is pointwise (q stays 0)
+      HIP_TRY(launch_first_two(s->r.g, p.storage == MF_BF16, s->cap, s->st[buf_of(s, k)], s->st[buf_of(s, k) ^ 1],
+                               coef_of(s->r, k), &s->ctrl->acc[0][0], s->stream));
     } else if (fused_gap(s)) {
       if (d2 && n >= 2 && same_coef(p, k)) {
         HIP_TRY(admm_pass2(s, k, true, done));
@@ -715,6 +728,7 @@ int64_t maxflow_iter(const mf_solver* s) { return s ? s->iter : -1; }
 mf_status maxflow_step(mf_solver* s, int32_t iters) {
   if (!s) return fail(MF_EINVAL, "null solver");
   if (iters < 0) return fail(MF_EINVAL, "iters must be >= 0");
+  if (iters > 0) s->fresh = false;
   const bool d2 = s->r.p.depth == 2;
   for (int32_t i = 0; i < iters;) {
     if (s->r.p.method == MF_RPDRQ) {
@@ -795,6 +809,7 @@ mf_status maxflow_read_field(mf_solver* s, int32_t field, float* dst) {
 
 mf_status maxflow_write_field(mf_solver* s, int32_t field, const float* src) {
   if (!s || !src) return fail(MF_EINVAL, "null argument");
+  s->fresh = false;
   void* ptr;
   int np;
   bool is_u;
@@ -827,6 +842,7 @@ mf_status maxflow_export_state(mf_solver* s, void* dst) {
 mf_status maxflow_import_state(mf_solver* s, const void* src, int64_t iter) {
   if (!s || !src) return fail(MF_EINVAL, "null argument");
   if (iter < 0) return fail(MF_EINVAL, "iter must be >= 0");
+  s->fresh = false;
   const bool dr = s->r.p.method == MF_RPDRQ;
   s->iter = iter;
   const size_t off = s->L.state[buf_of(s, iter)];
