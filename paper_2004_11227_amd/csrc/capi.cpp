@@ -359,9 +359,9 @@ hipError_t admm_sweep(mf_solver* s, int64_t k, bool check, bool write, const int
   d.write = write;
   d.tile_rows = s->r.p.tile_rows;
   // the gap-carrying 3-D sweep runs 8-row tiles: at 16 rows its FP64 terms
-  // and u staging take 181 VGPRs and 55 KB of LDS (two workgroups per CU),
-  // at 8 rows 106 VGPRs and 32 KB (four); 256^3 check sweep ~300 -> ~270 us.
-  // The tile height never changes the iterate.
+  // and u staging take 214 VGPRs and 55 KB of LDS (two workgroups per CU),
+  // at 8 rows 128 VGPRs and 32 KB (four).  The tile height never changes
+  // the iterate.
   if (check && s->r.g.ndim == 3) d.tile_rows = 8;
   d.slab_depth = s->r.p.slab_depth;
   d.cap = s->cap;
