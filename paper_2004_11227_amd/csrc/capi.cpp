@@ -298,7 +298,8 @@ struct mf_solver {
   int* host_done;   // pinned polling slots
   hipEvent_t ev[8];
   int dev;
-  bool fresh;       // the state is the initial point as init_state stored it
+  bool fresh;       // the state is the initial point init_state set up
+  bool pending;     // ... and iterate 0 is not in memory yet (see materialize)
 };
 
 namespace {
@@ -459,9 +460,33 @@ hipError_t gap_of(mf_solver* s, int64_t k, const int* done) {
 long long nres(const mf_solver* s) { return s->r.g.npix() * s->r.nl; }
 double neg_tol(const mf_solver* s) { return neg_gap_tol(s->r.p.storage == MF_BF16); }
 
-mf_status init_state(mf_solver* s) {
+// Two-label fused rpADMM with capacity planes and depth-1 sweeps: a solve's
+// first iteration from the initial point runs pointwise (k_first_two) and
+// needs neither iterate 0 in memory nor a sweep.
+bool first_pointwise(const mf_solver* s) {
+  const mf_params& p = s->r.p;
+  return p.model == MF_TWO_LABEL && p.variant == MF_FUSED &&
+         (p.method == MF_RPADMM_FG || p.method == MF_RPADMM_EB) && !s->r.cg.img && p.depth != 2;
+}
+
+// Store iterate 0 if init_state left it out.
+mf_status materialize(mf_solver* s) {
+  if (!s->pending) return MF_OK;
   HIP_TRY(launch_init(s->r.g, s->r.nl, s->r.p.model == MF_TWO_LABEL, s->r.p.storage == MF_BF16, s->cap,
                       s->r.cg, s->st[0], s->stream));
+  s->pending = false;
+  return MF_OK;
+}
+
+// The initial point.  Where a solve's first iteration runs pointwise, iterate
+// 0 is stored only when something else needs it (any entry point but a
+// solve, or a solve that stops at iterate 0): the 256^3 solve then skips a
+// 105 us pass.
+mf_status init_state(mf_solver* s) {
+  s->pending = first_pointwise(s);
+  if (!s->pending)
+    HIP_TRY(launch_init(s->r.g, s->r.nl, s->r.p.model == MF_TWO_LABEL, s->r.p.storage == MF_BF16, s->cap,
+                        s->r.cg, s->st[0], s->stream));
   if (s->r.p.method == MF_RPDRQ) {
     if (s->L.wbuf_bytes < (size_t)s->r.nl * (size_t)s->r.g.plane * 4)
       return fail(MF_EDEVICE, "internal: rPDRQ layout without its scratch planes");
@@ -532,6 +557,11 @@ mf_status solve_loop(mf_solver* s, mf_gap* out, bool sync_poll) {
   const int ce = p.check_every;
   const bool dr = p.method == MF_RPDRQ;
   const int* done = &s->ctrl->done;
+  // iterate 0 must be in memory unless the first check runs pointwise
+  if (!(s->fresh && s->iter == 0 && max_iter > 0 && first_pointwise(s))) {
+    const mf_status ms = materialize(s);
+    if (ms != MF_OK) return ms;
+  }
   HIP_TRY(launch_ctrl_reset(s->ctrl, s->stream));
   int64_t k = s->iter;
   const bool d2 = p.depth == 2;
@@ -560,17 +590,16 @@ mf_status solve_loop(mf_solver* s, mf_gap* out, bool sync_poll) {
     // solve with capacity planes runs pointwise (see k_first_two): 256^3
     // solve 4.30 -> 4.22 ms.  Not with depth-2 passes, where it would replace
     // a two-iteration pass and add a launch (2048^2 0.572 -> 0.583 ms).
-    const bool first = k == 0 && s->fresh && p.model == MF_TWO_LABEL && p.variant == MF_FUSED &&
-                       (p.method == MF_RPADMM_FG || p.method == MF_RPADMM_EB) && !s->r.cg.img && !d2;
+    const bool first = k == 0 && s->fresh && first_pointwise(s) && !final_check;
     s->fresh = false;
     off_at.push(k, s->off);
     int64_t j = 1;   // iterations of the chunk issued with the check
     if (dr) {
       HIP_TRY(gap_of(s, k, done));
-    } else if (first && !final_check) {
+    } else if (first) {
       // the first iteration from the initial point is pointwise (q stays 0)
-      HIP_TRY(launch_first_two(s->r.g, p.storage == MF_BF16, s->cap, s->st[buf_of(s, k)], s->st[buf_of(s, k) ^ 1],
-                               coef_of(s->r, k), &s->ctrl->acc[0][0], s->stream));
+      HIP_TRY(launch_first_two(s->r.g, p.storage == MF_BF16, s->cap, s->st[buf_of(s, k) ^ 1], coef_of(s->r, k),
+                               &s->ctrl->acc[0][0], s->stream));
     } else if (fused_gap(s)) {
       if (d2 && n >= 2 && same_coef(p, k)) {
         HIP_TRY(admm_pass2(s, k, true, done));
@@ -636,6 +665,14 @@ mf_status solve_loop(mf_solver* s, mf_gap* out, bool sync_poll) {
   if (!off_at.find(c.iter, off)) return fail(MF_EDEVICE, "internal: accepted iterate outside the polling window");
   s->iter = c.iter;
   s->off = off;
+  if (s->pending) {   // a stop at iterate 0 keeps it; any later one has overwritten its buffer
+    if (c.iter == 0) {
+      const mf_status ms = materialize(s);
+      if (ms != MF_OK) return ms;
+      HIP_TRY(hipStreamSynchronize(s->stream));
+    }
+    s->pending = false;
+  }
   const mf_status st = (mf_status)c.status;
   fill_gap(c, s->iter, out, st);
   if (st == MF_EDIVERGED) return fail(MF_EDIVERGED, "non-finite or negative gap");
@@ -728,6 +765,10 @@ int64_t maxflow_iter(const mf_solver* s) { return s ? s->iter : -1; }
 mf_status maxflow_step(mf_solver* s, int32_t iters) {
   if (!s) return fail(MF_EINVAL, "null solver");
   if (iters < 0) return fail(MF_EINVAL, "iters must be >= 0");
+  {
+    const mf_status ms = materialize(s);
+    if (ms != MF_OK) return ms;
+  }
   if (iters > 0) s->fresh = false;
   const bool d2 = s->r.p.depth == 2;
   for (int32_t i = 0; i < iters;) {
@@ -748,6 +789,10 @@ mf_status maxflow_step(mf_solver* s, int32_t iters) {
 
 mf_status maxflow_gap(mf_solver* s, mf_gap* out) {
   if (!s) return fail(MF_EINVAL, "null solver");
+  {
+    const mf_status ms = materialize(s);
+    if (ms != MF_OK) return ms;
+  }
   HIP_TRY(launch_ctrl_reset(s->ctrl, s->stream));
   HIP_TRY(gap_of(s, s->iter, nullptr));
   HIP_TRY(launch_bookkeep(s->ctrl, s->iter, s->r.p.alpha, 0.0, neg_tol(s), nres(s), 0, 0, s->stream));
@@ -769,6 +814,10 @@ mf_status maxflow_read_u(mf_solver* s, float* dst) { return maxflow_read_field(s
 
 mf_status maxflow_labels(mf_solver* s, int32_t* dst) {
   if (!s || !dst) return fail(MF_EINVAL, "null argument");
+  {
+    const mf_status ms = materialize(s);
+    if (ms != MF_OK) return ms;
+  }
   const StateView& v = s->st[buf_of(s, s->iter)];
   HIP_TRY(launch_labels(s->r.g, s->r.nl, s->r.p.model == MF_TWO_LABEL, v.u, dst, s->stream, s->r.g.pitch));
   HIP_TRY(hipStreamSynchronize(s->stream));
@@ -795,6 +844,10 @@ static mf_status field_ptr(mf_solver* s, int32_t field, void** ptr, int* np, boo
 
 mf_status maxflow_read_field(mf_solver* s, int32_t field, float* dst) {
   if (!s || !dst) return fail(MF_EINVAL, "null argument");
+  {
+    const mf_status ms = materialize(s);
+    if (ms != MF_OK) return ms;
+  }
   void* ptr;
   int np;
   bool is_u;
@@ -809,6 +862,10 @@ mf_status maxflow_read_field(mf_solver* s, int32_t field, float* dst) {
 
 mf_status maxflow_write_field(mf_solver* s, int32_t field, const float* src) {
   if (!s || !src) return fail(MF_EINVAL, "null argument");
+  {
+    const mf_status ms = materialize(s);
+    if (ms != MF_OK) return ms;
+  }
   s->fresh = false;
   void* ptr;
   int np;
@@ -829,6 +886,10 @@ size_t maxflow_state_bytes(const mf_solver* s) {
 
 mf_status maxflow_export_state(mf_solver* s, void* dst) {
   if (!s || !dst) return fail(MF_EINVAL, "null argument");
+  {
+    const mf_status ms = materialize(s);
+    if (ms != MF_OK) return ms;
+  }
   const bool dr = s->r.p.method == MF_RPDRQ;
   const size_t off = s->L.state[buf_of(s, s->iter)];
   HIP_TRY(hipMemcpyAsync(dst, s->ws + off, s->L.state_bytes, hipMemcpyDeviceToDevice, s->stream));
@@ -843,6 +904,7 @@ mf_status maxflow_import_state(mf_solver* s, const void* src, int64_t iter) {
   if (!s || !src) return fail(MF_EINVAL, "null argument");
   if (iter < 0) return fail(MF_EINVAL, "iter must be >= 0");
   s->fresh = false;
+  s->pending = false;   // the import overwrites the state it would have held
   const bool dr = s->r.p.method == MF_RPDRQ;
   s->iter = iter;
   const size_t off = s->L.state[buf_of(s, iter)];
@@ -856,6 +918,10 @@ mf_status maxflow_import_state(mf_solver* s, const void* src, int64_t iter) {
 
 mf_status maxflow_tune(mf_solver* s, int32_t sweeps, int32_t what, mf_tuning* out) {
   if (!s || !out) return fail(MF_EINVAL, "null solver or out");
+  {
+    const mf_status ms = materialize(s);
+    if (ms != MF_OK) return ms;
+  }
   if (sweeps < 1 || sweeps > 10000) return fail(MF_EINVAL, "sweeps must be in 1..10000");
   mf_params& p = s->r.p;
   *out = mf_tuning{};

@@ -115,21 +115,25 @@ hipError_t launch_init(const Geom& g, int nl, bool two, bool bf16, const void* c
 // as k_init stores it (u = 0, q = 0, p_s = p_t): v = (p_t - p_s) - u/c and
 // div q are both +0, so w = 0 and q^1 = P_alpha(0 + 0) = +0 exactly, and the
 // iteration is pointwise.  It runs the sweeps' device functions on those
-// values (div q^1 = +0, u = +0, p_t and p_s as stored), so iterate 1 has the
-// sweeps' bits, and adds the FP64 gap terms of iterate 0 (u = 0: data C_s,
+// values (div q^1 = +0, u = +0, p_t and p_s as k_init stores them), so
+// iterate 1 has the sweeps' bits, and adds the FP64 gap terms of iterate 0 (u = 0: data C_s,
 // TV 0, dual min(C_s, C_t), residual (p_t - p_s)^2, flow p_s) to the gap
 // accumulators as the gap-carrying sweep does.  Pad columns are neither
 // written nor counted.
 template <typename TS>
 __global__ __launch_bounds__(256) void k_first_two(long long n, long long P, int pitch, int W, int ndim,
-                                                   const TS* cap, const TS* ps_in, const TS* p_in, Coef k,
-                                                   float* u_out, TS* q_out, TS* ps_out, TS* p_out, double* acc) {
+                                                   const TS* cap, Coef k, float* u_out, TS* q_out, TS* ps_out,
+                                                   TS* p_out, double* acc) {
   __shared__ double sred[4 * 5];
   double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
     if ((int)(i % pitch) >= W) continue;
     const float cs = ld(cap, i), ct = ld(cap + P, i);
-    const float ps = ld(ps_in, i), pt = ld(p_in, i);
+    // p_t^0 = p_s^0 = min(C_s, C_t) in the storage type, as k_init stores
+    // them (iterate 0 itself need not be in memory)
+    const float m = fminf(cs, ct);
+    const float ps = sizeof(TS) == 2 ? __uint_as_float((uint32_t)__builtin_bit_cast(uint16_t, f2bf(m)) << 16) : m;
+    const float pt = ps;
     float pn, t, sd = 0.f, sr = 0.f;
     label_update(k, 0.f, pt, ps, 0.f, ct, pn, t, sd, sr);
     const float psn = finish_ps(k, ps, sd, sr, true, cs);
@@ -146,17 +150,15 @@ __global__ __launch_bounds__(256) void k_first_two(long long n, long long P, int
   block_accumulate<5, 4>(g, acc, sred);
 }
 
-hipError_t launch_first_two(const Geom& g, bool bf16, const void* cap, const StateView& in, const StateView& out,
-                            const Coef& k, double* acc, hipStream_t s) {
+hipError_t launch_first_two(const Geom& g, bool bf16, const void* cap, const StateView& out, const Coef& k,
+                            double* acc, hipStream_t s) {
   const long long n = g.nstore();
   if (bf16)
     hipLaunchKernelGGL(k_first_two<bf16_t>, dim3(blocks_for(n)), dim3(256), 0, s, n, g.plane, g.pitch, g.W, g.ndim,
-                       (const bf16_t*)cap, (const bf16_t*)in.ps, (const bf16_t*)in.p, k, out.u, (bf16_t*)out.q,
-                       (bf16_t*)out.ps, (bf16_t*)out.p, acc);
+                       (const bf16_t*)cap, k, out.u, (bf16_t*)out.q, (bf16_t*)out.ps, (bf16_t*)out.p, acc);
   else
     hipLaunchKernelGGL(k_first_two<float>, dim3(blocks_for(n)), dim3(256), 0, s, n, g.plane, g.pitch, g.W, g.ndim,
-                       (const float*)cap, (const float*)in.ps, (const float*)in.p, k, out.u, (float*)out.q,
-                       (float*)out.ps, (float*)out.p, acc);
+                       (const float*)cap, k, out.u, (float*)out.q, (float*)out.ps, (float*)out.p, acc);
   return hipGetLastError();
 }
 

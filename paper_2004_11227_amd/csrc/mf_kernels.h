@@ -125,8 +125,8 @@ hipError_t launch_pdrq_iter(const PdrqDesc& d, hipStream_t s);
 // misc kernels
 hipError_t launch_init(const Geom& g, int nl, bool two, bool bf16, const void* cap, const CapGen& cg,
                        StateView st, hipStream_t s);
-hipError_t launch_first_two(const Geom& g, bool bf16, const void* cap, const StateView& in, const StateView& out,
-                            const Coef& k, double* acc, hipStream_t s);
+hipError_t launch_first_two(const Geom& g, bool bf16, const void* cap, const StateView& out, const Coef& k,
+                            double* acc, hipStream_t s);
 hipError_t launch_convert_caps(const float* src, void* dst, long long n_per_plane, int nplanes,
                                long long plane, bool bf16, hipStream_t s);
 hipError_t launch_labels(const Geom& g, int nl, bool two, const float* u, int32_t* lab,

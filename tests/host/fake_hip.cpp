@@ -243,12 +243,10 @@ hipError_t launch_unfused(const SweepDesc& d, hipStream_t) {
   if (d.wbuf) touch_w(d.wbuf, ((size_t)(d.nl - 1) * d.g.plane + (size_t)d.g.nstore()) * 4);
   return sweep_desc(d);
 }
-hipError_t launch_first_two(const Geom& g, bool bf16, const void* cap, const StateView& in, const StateView& out,
-                            const Coef&, double* acc, hipStream_t) {
+hipError_t launch_first_two(const Geom& g, bool bf16, const void* cap, const StateView& out, const Coef&,
+                            double* acc, hipStream_t) {
   const size_t e = bf16 ? 2 : 4, n = (size_t)g.nstore(), P = (size_t)g.plane;
   touch(cap, (P + n) * e);
-  touch(in.ps, n * e);
-  touch(in.p, n * e);
   touch_w(out.u, n * 4);
   touch_w(out.q, ((size_t)(g.ndim - 1) * P + n) * e);
   touch_w(out.ps, n * e);

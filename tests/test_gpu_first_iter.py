@@ -82,3 +82,35 @@ def test_first_check_gives_the_same_stop():
         assert np.array_equal(fa[f], fb[f]), f
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("shape,storage", [((70, 131), "f32"), ((20, 37, 50), "bf16")])
+def test_initial_point_appears_where_needed(shape, storage):
+    """The initial point is stored only when something needs it: fields read
+    right after creation, and a solve that stops at its first check (a
+    tolerance every iterate meets), give u = 0, q = 0, p_t = p_s =
+    min(C_s, C_t) in the storage type."""
+    need_gpu()
+    banner(f"initial point on demand {shape} {storage}")
+    if len(shape) == 2:
+        caps = synth.two_label_caps(synth.ellipse_image(*shape, 6, 0.1, 94))
+    else:
+        caps = synth.two_label_caps(synth.ellipsoid_volume(*shape, 5, 0.1, 95))
+    kw = dict(model="two", method="eb", relax=1.5, alpha=0.45, storage=storage, check_every=10, max_iter=100)
+    ref = gpu_solver(caps, depth=1, **kw) if len(shape) == 2 else gpu_solver(caps, **kw)
+    f0 = gpu_fields(ref)
+    m = np.minimum(caps[0], caps[1]).astype(np.float32)
+    if storage == "bf16":   # round to nearest even, as the store does
+        b = m.view(np.uint32).astype(np.uint64)
+        b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+        m = b.astype(np.uint32).view(np.float32)
+    assert np.all(f0["u"] == 0) and np.all(f0["q"] == 0)
+    assert np.array_equal(f0["ps"], m.astype(np.float64)) and np.array_equal(f0["p"][0], m.astype(np.float64))
+    s = gpu_solver(caps, tol=1e3, **kw) if len(shape) == 3 else gpu_solver(caps, tol=1e3, depth=1, **kw)
+    g = s.solve()
+    assert g["iter"] == 0 and g["status"] == 0
+    f1 = gpu_fields(s)
+    for f in f0:
+        assert np.array_equal(f0[f], f1[f]), f
+    s.close()
+    ref.close()
